@@ -1,0 +1,340 @@
+"""FP64 reference implementation of a0 -> chi0 -> W (test infrastructure only).
+
+What the method computes, in the paper's notation (energies in Hartree):
+
+* Pair vertex, Section 7.A (closed form of chi0 below eq. subsetof_vef's
+  preamble): V_mu^{EF} = X_a^E V_mu^{ab} X_b^F for an occupied state E and an
+  empty state F (Section 3: E < 0 occupied, E > 0 empty).
+* Spectral function of the free response, Section 5.A eq. chi_by_spectra: for
+  s > 0 it is the density of electron-hole pair weights; a(-s) = -a(s); chi0 is
+  its Cauchy transform.  With the closed form of Section 7.A this is
+  a_{mu nu}(s) = 2 sum_p V_mu^p V_nu^p delta(s - Delta_p), Delta_p = F - E,
+  the 2 being the spin sum (Section 2, eq. more_screening).
+* Discretisation on a uniform mesh, Section 5 (mesh spacing somewhat smaller
+  than the broadening) and Section 5.B (eps = 1.5 domega by default).
+* Screening, Section 2 eq. Coulombscreening / Section 3 eq.
+  tensorform-scr-inter: W = (1 - v chi0)^{-1} v, frequency by frequency.
+* Compression, Section 7.B eqs. subspace_chi0 and chi_RPA.
+
+Readings where the paper is silent (each also listed in the design notes):
+
+1. Grid: omega_j = omega_min + j*domega, domega = (omega_max-omega_min)/N
+   (omega_max excluded).  This is what reproduces the 0.234375 eV the paper
+   prints for N = 1024 on [-80, 80] eV with eps = 1.5 domega (Section 6).
+   domega must be a power of two so that Delta/domega is exact.
+2. Deposition: linear (two-bin) split of each pole onto the mesh, in int64
+   fixed point with 2^-s resolution so the sum is exact and order-free.
+3. Retarded response at every omega: chi0(-omega) = conj chi0(omega).
+4. Spectral bins are m = 0 .. nhb-1 (s = m*domega >= 0); bin 0 is stored but,
+   by a(-s) = -a(s), contributes nothing to chi0.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "grid_spacing",
+    "grid_omegas",
+    "grid_shift_bits",
+    "pair_vectors",
+    "pair_bins",
+    "hist_bins",
+    "frac_bits",
+    "histogram",
+    "histogram_c",
+    "packed_index",
+    "unpack_upper",
+    "chi0_from_hist",
+    "chi0_poles",
+    "screened_W",
+    "compress_basis",
+    "screened_W_compressed",
+    "project_pairs",
+]
+
+
+# ----------------------------------------------------------------------------
+# grid (Section 5, Section 5.B, Section 6)
+
+
+def grid_spacing(n_omega: int, omega_min: float, omega_max: float) -> float:
+    """domega = (omega_max - omega_min) / N (reading 1)."""
+    return (omega_max - omega_min) / n_omega
+
+
+def grid_omegas(n_omega: int, omega_min: float, omega_max: float) -> np.ndarray:
+    d = grid_spacing(n_omega, omega_min, omega_max)
+    return omega_min + d * np.arange(n_omega, dtype=np.float64)
+
+
+def grid_shift_bits(domega: float) -> int:
+    """k with domega = 2^-k; raises unless domega is an exact power of two."""
+    m, e = math.frexp(domega)
+    if m != 0.5:
+        raise ValueError("domega must be a power of two")
+    return 1 - e
+
+
+# ----------------------------------------------------------------------------
+# pair vertex (Section 7.A closed form; Section 3 eq. VertexDefinition sparsity)
+
+
+def pair_vectors(mol) -> np.ndarray:
+    """P[mu, p] = V_mu^{EF} = sum_a X_a^E sum_b V_mu^{ab} X_b^F, p = E*N_virt + (F - N_occ).
+
+    The contraction runs over the atom-local orbital set O of mu only (the
+    vertex vanishes elsewhere).  The order is fixed: first T[a, F] = sum over b
+    ascending of V^{ab} X_b^F, then sum over a ascending of X_a^E T[a, F],
+    every product and every addition rounded separately.
+    """
+    n_occ, n_orb = mol.n_occ, mol.n_orb
+    n_virt = n_orb - n_occ
+    X = mol.X
+    P = np.zeros((mol.n_prod, n_occ * n_virt))
+    for b in range(mol.n_blk):
+        p0, nprod, orbs, mats = mol.block_of(b)
+        Xv = X[orbs][:, n_occ:]  # [|O|, N_virt]
+        Xo = X[orbs][:, :n_occ]  # [|O|, N_occ]
+        for i, V in enumerate(mats):
+            n = len(orbs)
+            T = np.zeros((n, n_virt))
+            for bb in range(n):
+                T = T + V[:, bb][:, None] * Xv[bb][None, :]
+            acc = np.zeros((n_occ, n_virt))
+            for aa in range(n):
+                acc = acc + Xo[aa][:, None] * T[aa][None, :]
+            P[p0 + i] = acc.ravel()
+    return P
+
+
+# ----------------------------------------------------------------------------
+# binning (Section 5 mesh; Section 5.A spectral function of the response)
+
+
+def pair_bins(eig: np.ndarray, n_occ: int, domega: float):
+    """Delta_p = E_F - E_E; x = Delta_p / domega (exact: domega = 2^-k);
+    m_p = floor(x); frac_p = x - m_p in [0, 1)."""
+    k = grid_shift_bits(domega)
+    e_occ = eig[:n_occ]
+    e_vir = eig[n_occ:]
+    delta = (e_vir[None, :] - e_occ[:, None]).ravel()
+    x = np.ldexp(delta, k)
+    m = np.floor(x)
+    frac = x - m
+    return m.astype(np.int64), frac
+
+
+def hist_bins(eig: np.ndarray, n_omega: int, domega: float) -> int:
+    """Number of stored spectral bins: enough for the largest pair energy plus
+    its upper neighbour, at most n_omega/2 (s < omega_max)."""
+    k = grid_shift_bits(domega)
+    dmax = float(eig[-1] - eig[0])
+    mmax = int(math.floor(math.ldexp(dmax, k)))
+    return int(min(n_omega // 2, mmax + 2))
+
+
+def frac_bits(P: np.ndarray, n_pairs: int) -> int:
+    """Fixed-point exponent s (weights are integers times 2^-s).
+
+    With vmax = max |V_mu^p| < 2^e and 2*n_pairs < 2^c, every rounded weight
+    stays below 2^(61-c) and below 2^50, so every histogram entry fits in
+    int64 with a bit to spare.  s = min(61 - c - 2e, 50 - 2e), clamped to
+    [-200, 960].
+    """
+    vmax = float(np.max(np.abs(P))) if P.size else 0.0
+    _, e = math.frexp(vmax)
+    c = int(2 * n_pairs).bit_length()
+    s = min(61 - c - 2 * e, 50 - 2 * e)
+    return int(max(-200, min(960, s)))
+
+
+def packed_index(mu: np.ndarray, nu: np.ndarray, n: int) -> np.ndarray:
+    """Row-major index of (mu, nu), mu <= nu, in the packed upper triangle."""
+    mu = np.asarray(mu, dtype=np.int64)
+    nu = np.asarray(nu, dtype=np.int64)
+    return mu * n - (mu * (mu - 1)) // 2 + (nu - mu)
+
+
+def histogram(P: np.ndarray, m: np.ndarray, frac: np.ndarray, s: int, nhb: int) -> np.ndarray:
+    """Exact int64 spectral histogram H[bin, packed (mu<=nu)].
+
+    For each pair p and mu <= nu (Section 5.A eq. chi_by_spectra with the
+    closed form of Section 7.A):
+      t    = RNE(2^s * fl(V_mu^p * V_nu^p))
+      t_hi = RNE(fl(fl(V_mu^p * 2^s frac_p) * V_nu^p))
+      bin m_p   += 2 (t - t_hi)   (the 2 is the spin sum)
+      bin m_p+1 += 2 t_hi
+    Pairs whose upper bin m_p + 1 >= nhb are dropped.  Plain loop over pairs;
+    for tiny inputs only.
+    """
+    n_prod, n_pairs = P.shape
+    iu, ju = np.triu_indices(n_prod)
+    H = np.zeros((nhb, len(iu)), dtype=np.int64)
+    for p in range(n_pairs):
+        mp = int(m[p])
+        if mp + 1 >= nhb:
+            continue
+        vm = P[iu, p]
+        vn = P[ju, p]
+        t = np.rint(np.ldexp(vm * vn, s)).astype(np.int64)
+        w = math.ldexp(float(frac[p]), s)
+        th = np.rint((vm * w) * vn).astype(np.int64)
+        H[mp] += 2 * (t - th)
+        H[mp + 1] += 2 * th
+    return H
+
+
+_CLIB = None
+
+
+def _clib():
+    global _CLIB
+    if _CLIB is None:
+        here = os.path.dirname(os.path.abspath(__file__))
+        path = os.path.join(here, "libhist_ref.so")
+        if not os.path.exists(path):
+            build_c()
+        lib = ctypes.CDLL(path)
+        lib.hist_ref_entries.restype = ctypes.c_int
+        lib.hist_ref_entries.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        _CLIB = lib
+    return _CLIB
+
+
+def build_c() -> str:
+    """Compile the plain C histogram (no FMA contraction, OpenMP over entries)."""
+    import subprocess
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "hist_ref.c")
+    out = os.path.join(here, "libhist_ref.so")
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(
+        ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+         "-fno-fast-math", "-std=c99", src, "-o", tmp, "-lm"]
+    )
+    os.replace(tmp, out)
+    return out
+
+
+def histogram_c(P: np.ndarray, m: np.ndarray, frac: np.ndarray, s: int, nhb: int,
+                mu: Optional[np.ndarray] = None, nu: Optional[np.ndarray] = None):
+    """Same definition as histogram(), in plain C, for chosen (mu, nu) entries
+    (all of mu <= nu by default).  Returns (H[nhb, n_entries], n_dropped)."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    n_prod, n_pairs = P.shape
+    if mu is None:
+        mu, nu = np.triu_indices(n_prod)
+    mu = np.ascontiguousarray(mu, dtype=np.int64)
+    nu = np.ascontiguousarray(nu, dtype=np.int64)
+    if np.any(mu > nu):
+        raise ValueError("entries must have mu <= nu")
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    frac = np.ascontiguousarray(frac, dtype=np.float64)
+    H = np.zeros((nhb, len(mu)), dtype=np.int64)
+    dropped = np.zeros(1, dtype=np.int64)
+    rc = _clib().hist_ref_entries(
+        P.ctypes.data, n_prod, n_pairs, m.ctypes.data, frac.ctypes.data, int(s),
+        mu.ctypes.data, nu.ctypes.data, len(mu), nhb, H.ctypes.data, dropped.ctypes.data,
+    )
+    if rc != 0:
+        raise RuntimeError("hist_ref_entries failed: %d" % rc)
+    return H, int(dropped[0])
+
+
+def unpack_upper(packed: np.ndarray, n: int) -> np.ndarray:
+    """[..., n(n+1)/2] packed upper triangle -> [..., n, n] symmetric."""
+    iu, ju = np.triu_indices(n)
+    out = np.zeros(packed.shape[:-1] + (n, n), dtype=packed.dtype)
+    out[..., iu, ju] = packed
+    out[..., ju, iu] = packed
+    return out
+
+
+# ----------------------------------------------------------------------------
+# chi0 (Section 5.A eq. chi_by_spectra: Cauchy transform of the odd-extended a)
+
+
+def chi0_from_hist(H: np.ndarray, s: int, n_omega: int, omega_min: float, omega_max: float,
+                   eps: float, js: Optional[Sequence[int]] = None,
+                   omegas: Optional[np.ndarray] = None) -> np.ndarray:
+    """chi0[j, entry] = sum_{m>=1} 2^-s H[m, entry] *
+        (1/(omega_j - m domega + i eps) - 1/(omega_j + m domega + i eps)).
+
+    Direct summation over bins (no FFT).  The second term is the a(-s) = -a(s)
+    half of the spectral function.  By default omega_j are grid points j (all,
+    or the listed js); explicit omegas may be given instead."""
+    d = grid_spacing(n_omega, omega_min, omega_max)
+    if omegas is None:
+        om = grid_omegas(n_omega, omega_min, omega_max)
+        if js is None:
+            js = range(n_omega)
+        js = np.asarray(list(js), dtype=np.int64)
+        om = om[js]
+    else:
+        om = np.asarray(omegas, dtype=np.float64)
+    nhb = H.shape[0]
+    mvals = np.arange(1, nhb, dtype=np.float64) * d
+    w = om[:, None]
+    K = 1.0 / (w - mvals[None, :] + 1j * eps) - 1.0 / (w + mvals[None, :] + 1j * eps)
+    h = np.ldexp(H[1:].astype(np.float64), -s)
+    return K @ h
+
+
+def chi0_poles(P: np.ndarray, eig: np.ndarray, n_occ: int, omegas: np.ndarray, eps: float) -> np.ndarray:
+    """Closed form of Section 7.A with the poles where they really are:
+    chi0_{mu nu}(w) = 2 sum_p V_mu^p V_nu^p (1/(w - Delta_p + i eps) - 1/(w + Delta_p + i eps)).
+    Full [n_omega, n_prod, n_prod]; for convergence checks on small inputs."""
+    delta = (eig[n_occ:][None, :] - eig[:n_occ][:, None]).ravel()
+    out = np.empty((len(omegas), P.shape[0], P.shape[0]), dtype=np.complex128)
+    for i, w in enumerate(omegas):
+        g = 1.0 / (w - delta + 1j * eps) - 1.0 / (w + delta + 1j * eps)
+        out[i] = 2.0 * (P * g[None, :]) @ P.T
+    return out
+
+
+# ----------------------------------------------------------------------------
+# screening (Section 2 eq. Coulombscreening, Section 3 eq. tensorform-scr-inter)
+
+
+def screened_W(v: np.ndarray, chi0: np.ndarray) -> np.ndarray:
+    """W = (1 - v chi0)^{-1} v by dense LU (LAPACK gesv)."""
+    n = v.shape[0]
+    A = np.eye(n, dtype=np.complex128) - v.astype(np.complex128) @ chi0
+    return np.linalg.solve(A, v.astype(np.complex128))
+
+
+def compress_basis(v: np.ndarray, k: int):
+    """Top-k eigenpairs of the Coulomb metric, eigenvalues descending."""
+    lam, U = np.linalg.eigh(v)
+    order = np.argsort(lam)[::-1][:k]
+    return U[:, order], lam[order]
+
+
+def project_pairs(P: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Pair vectors in the compressed basis: U^T V^p (so that the histogram of
+    the projected vectors is U^T chi0 U, Section 7.B eq. subspace_chi0)."""
+    return U.T @ P
+
+
+def screened_W_compressed(v: np.ndarray, chi0: np.ndarray, k: int) -> np.ndarray:
+    """Section 7.B with the subspace spanned by the top-k eigenvectors of v:
+    with v_k = U_k L_k U_k^T, chi_hat = U_k^T chi0 U_k,
+      W = U_k (1 - L_k chi_hat)^{-1} L_k U_k^T  ( = (1 - v_k chi0)^{-1} v_k ).
+    No square root of L_k is needed, so zero or slightly negative kept
+    eigenvalues are harmless."""
+    U, lam = compress_basis(v, k)
+    chat = U.T @ chi0 @ U
+    A = np.eye(k, dtype=np.complex128) - lam[:, None] * chat
+    Xk = np.linalg.solve(A, np.diag(lam).astype(np.complex128))
+    return U @ Xk @ U.T

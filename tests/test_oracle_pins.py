@@ -1,0 +1,390 @@
+"""Pins of the CPU oracle to facts fixed by the paper or by mathematics.
+
+None of these re-types an oracle formula and compares it with itself: each
+checks a printed number, a closed form, a conservation law, a brute-force
+contraction, a symmetry or a limit that a plausible mistake (wrong sign, lost
+factor 2, swapped bins, transposed operand, off-by-one grid) would break.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gw_synth as gs
+import oracle as o
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = [x.strip() for x in line.split("=")]
+                out[k] = float(v)
+    return out
+
+
+def _pipeline(mol, grid):
+    P = o.pair_vectors(mol)
+    d = grid.domega
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+    nhb = o.hist_bins(mol.eig, grid.n_omega, d)
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, nhb)
+    return P, m, fr, nhb, s, H
+
+
+def _tiny(eig, n_occ, V, X=None):
+    """Hand-built molecule with one product block spanning all orbitals."""
+    n = len(eig)
+    if X is None:
+        X = np.eye(n)
+    if V.ndim == 2:
+        V = V[None]
+    nprod = V.shape[0]
+    centres = np.zeros((nprod, 3))
+    centres[:, 0] = np.arange(nprod)
+    d2 = (centres[:, None, 0] - centres[None, :, 0]) ** 2
+    return gs.Molecule(
+        n_orb=n, n_occ=n_occ, eig=np.asarray(eig, float), X=np.asarray(X, float),
+        blk_prod=np.array([0, nprod], np.int32), blk_orb=np.array([0, n], np.int32),
+        orb_idx=np.arange(n, dtype=np.int32), blk_val=np.array([0, nprod * n * n], np.int64),
+        vals=np.ascontiguousarray(V, float).ravel(), centres=centres, atoms=np.zeros((1, 3)),
+        v=1.0 / np.sqrt(d2 + 2.0),
+    )
+
+
+# --------------------------------------------------------------------------- grid
+
+
+def test_grid_reproduces_printed_benzene_broadening():
+    """Section 6 prints eps = 1.5*domega = 0.234375 eV for 1024 points on
+    [-80, 80] eV; only domega = range/N (omega_max excluded) gives it."""
+    g = _read_golden("benzene_grid.txt")
+    d = o.grid_spacing(int(g["n_omega"]), g["omega_min_eV"], g["omega_max_eV"])
+    assert g["eps_factor"] * d == g["eps_eV"]
+    d_alt = (g["omega_max_eV"] - g["omega_min_eV"]) / (g["n_omega"] - 1)
+    assert abs(g["eps_factor"] * d_alt - g["eps_eV"]) > 1e-4
+    om = o.grid_omegas(int(g["n_omega"]), g["omega_min_eV"], g["omega_max_eV"])
+    assert om[0] == g["omega_min_eV"] and om[-1] < g["omega_max_eV"]
+    assert om[int(g["n_omega"]) // 2] == 0.0
+
+
+def test_grid_requires_power_of_two_spacing():
+    assert o.grid_shift_bits(2.0 ** -6) == 6
+    with pytest.raises(ValueError):
+        o.grid_shift_bits(0.03)
+
+
+# --------------------------------------------------------------------------- pair vertex
+
+
+@pytest.mark.parametrize("which", ["c0", "chain8"])
+def test_pair_vectors_match_dense_bruteforce(which):
+    """V^{EF} = X^T V_mu X restricted to occupied x empty, built from the dense
+    (assembled) vertex: pins the block indexing and the E/F roles."""
+    if which == "c0":
+        mol = gs.make_config(0)
+    else:
+        mol = gs.chain_molecule(8, 7, orb_per_atom=4, occ_per_atom=2, prod_per_atom=10,
+                                prod_per_bond=8, bond_cutoff=None)
+    P = o.pair_vectors(mol)
+    n = mol.n_orb
+    dense = np.zeros((mol.n_prod, n, n))
+    for b in range(mol.n_blk):
+        p0, npr, orbs, mats = mol.block_of(b)
+        for i, M in enumerate(mats):
+            dense[p0 + i][np.ix_(orbs, orbs)] = M
+    full = np.einsum("aE,mab,bF->mEF", mol.X, dense, mol.X)
+    ref = full[:, : mol.n_occ, mol.n_occ :].reshape(mol.n_prod, -1)
+    assert np.abs(P - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+    # orthogonal X: sum over ALL (E, F) of (V^EF)^2 equals ||V_mu||_F^2; the
+    # occupied-empty block is part of it and never exceeds it
+    fro = (dense ** 2).sum(axis=(1, 2))
+    assert np.allclose((full ** 2).sum(axis=(1, 2)), fro, rtol=1e-12)
+    assert np.all((P ** 2).sum(axis=1) <= fro * (1 + 1e-12))
+
+
+def test_pair_vectors_identity_eigenvectors():
+    """X = 1: V^{EF} is the vertex entry V^{EF} itself."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((4, 4))
+    A = A + A.T
+    mol = _tiny([-0.5, -0.25, 0.25, 0.5], 2, A)
+    P = o.pair_vectors(mol)
+    assert np.array_equal(P[0], A[:2, 2:].ravel())
+
+
+# --------------------------------------------------------------------------- bins
+
+
+def test_pair_bins_on_and_between_grid_points():
+    d = 2.0 ** -5
+    eig = np.array([-10 * d, -3 * d, 4 * d, 6.5 * d])
+    m, fr = o.pair_bins(eig, 2, d)
+    # pairs (E,F): (0,2) 14, (0,3) 16.5, (1,2) 7, (1,3) 9.5
+    assert list(m) == [14, 16, 7, 9]
+    assert list(fr) == [0.0, 0.5, 0.0, 0.5]
+    assert o.hist_bins(eig, 64, d) == 16 + 2
+    assert o.hist_bins(eig, 32, d) == 16  # capped at n_omega / 2
+
+
+def test_frac_bits_rule_bounds():
+    for vmax, npairs in [(1.4737, 64), (0.28, 57600), (2.0 ** -3, 518400), (3.0, 1)]:
+        P = np.array([[vmax, -vmax / 3]])
+        s = o.frac_bits(P, npairs)
+        x = math.ldexp(vmax * vmax, s)
+        assert x <= 2.0 ** 50
+        assert 2 * npairs * 2 * x < 2.0 ** 63
+        # the rule bounds vmax by the next power of two, so it is within three
+        # bits of the largest safe exponent
+        x3 = 8 * x
+        assert x3 > 2.0 ** 50 or 2 * npairs * 2 * x3 >= 2.0 ** 61
+
+
+# --------------------------------------------------------------------------- histogram
+
+
+def test_histogram_sum_rule_and_first_moment():
+    """Zeroth moment: integral of a0_{mu nu} = 2 sum_p V_mu^p V_nu^p (the sum
+    rule; on the diagonal it is 2 sum_p |V_mu^p|^2).  First moment: linear
+    deposition keeps the pole position, sum_m m domega H_m = 2 sum_p Delta_p
+    V_mu V_nu.  A lost spin factor, swapped lo/hi bins, nearest-bin deposition
+    or an off-by-one bin all fail one of the two."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    iu, ju = np.triu_indices(mol.n_prod)
+    lsb = 2.0 ** -s
+    pair = P[iu] * P[ju]
+    zeroth = np.ldexp(H.sum(axis=0).astype(float), -s)
+    ref0 = 2.0 * pair.sum(axis=1)
+    assert np.abs(zeroth - ref0).max() <= mol.n_pairs * (2 * lsb + 1e-15 * np.abs(pair).max())
+    diag = [o.packed_index(i, i, mol.n_prod) for i in range(mol.n_prod)]
+    assert np.allclose(zeroth[diag], 2.0 * (P ** 2).sum(axis=1), rtol=1e-12)
+    d = grid.domega
+    delta = (mol.eig[mol.n_occ:][None, :] - mol.eig[: mol.n_occ][:, None]).ravel()
+    first = d * np.ldexp((np.arange(nhb)[:, None] * H).sum(axis=0).astype(float), -s)
+    ref1 = 2.0 * (pair * delta[None, :]).sum(axis=1)
+    tol1 = mol.n_pairs * nhb * d * 4 * lsb + 1e-13 * np.abs(ref1).max()
+    assert np.abs(first - ref1).max() <= tol1
+    # the first moment is far more sensitive than the tolerance: nearest-bin
+    # deposition would miss it by ~ domega * |V V| per pair
+    assert np.abs(pair).sum(axis=1).max() * d * 0.05 > tol1
+
+
+def test_histogram_order_free_and_c_matches():
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    perm = np.random.default_rng(5).permutation(mol.n_pairs)
+    H2 = o.histogram(P[:, perm], m[perm], fr[perm], s, nhb)
+    assert np.array_equal(H, H2)
+    Hc, dropped = o.histogram_c(P, m, fr, s, nhb)
+    assert dropped == 0 and np.array_equal(H, Hc)
+    sel = np.array([3, 17, 40]), np.array([3, 50, 63])
+    Hs, _ = o.histogram_c(P, m, fr, s, nhb, sel[0], sel[1])
+    assert np.array_equal(Hs, H[:, o.packed_index(sel[0], sel[1], mol.n_prod)])
+
+
+def test_histogram_drops_pairs_beyond_grid():
+    d = 2.0 ** -3
+    eig = np.array([-1.0, 0.25, 2.0])  # pair energies 1.25 (m=10), 3.0 (m=24)
+    V = np.array([[0.0, 0.3, 0.2], [0.3, 0.0, 0.0], [0.2, 0.0, 0.0]])
+    mol = _tiny(eig, 1, V)
+    P = o.pair_vectors(mol)
+    m, fr = o.pair_bins(eig, 1, d)
+    nhb = o.hist_bins(eig, 32, d)  # 16 bins: m=24 does not fit
+    assert nhb == 16
+    s = o.frac_bits(P, 2)
+    H = o.histogram(P, m, fr, s, nhb)
+    _, dropped = o.histogram_c(P, m, fr, s, nhb)
+    assert dropped == 1
+    assert H[10, 0] == 2 * int(np.rint(math.ldexp(0.09, s)))
+
+
+# --------------------------------------------------------------------------- chi0
+
+
+def test_chi0_single_pole_closed_form():
+    """One product, one pair: chi0 = 2 V^2 [1/(w - D + i eps) - 1/(w + D + i eps)]
+    when D sits on a grid point, and the average of the two neighbouring poles
+    when it sits half way (linear deposition)."""
+    grid = gs.config_grid(0)
+    d = grid.domega
+    om = grid.omegas()
+    for D, parts in [(24 * d, [(24, 1.0)]), (24.5 * d, [(24, 0.5), (25, 0.5)])]:
+        eig = np.array([-D / 2, D / 2])
+        V = np.array([[0.0, 0.7], [0.7, 0.0]])
+        mol = _tiny(eig, 1, V)
+        P, m, fr, nhb, s, H = _pipeline(mol, grid)
+        chi = o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)[:, 0]
+        ref = sum(w * 2 * 0.49 * (1 / (om - k * d + 1j * grid.eps) - 1 / (om + k * d + 1j * grid.eps))
+                  for k, w in parts)
+        assert np.abs(chi - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_chi0_symmetries():
+    """chi0 is complex-symmetric in (mu, nu) (Section 5: real basis),
+    chi0(-w) = conj chi0(w) (retarded reading), -Im chi0(w>0) is PSD."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min,
+                                          grid.omega_max, grid.eps), mol.n_prod)
+    N = grid.n_omega
+    for j in [1, 37, 100, 127]:
+        a, b = chi[N - j], chi[j]
+        assert np.abs(a - np.conj(b)).max() <= 1e-13 * np.abs(b).max()
+    for j in [N // 2 + 5, N // 2 + 40, N // 2 + 100]:
+        ev = np.linalg.eigvalsh(-chi[j].imag)
+        assert ev.min() > -1e-10 * ev.max()
+    assert np.abs(chi[N // 2].imag).max() < 1e-12 * np.abs(chi).max()
+
+
+def test_chi0_converges_to_true_poles_second_order():
+    """Refining the mesh at fixed eps, the binned chi0 approaches the closed
+    form with the poles at their true energies (Section 7.A) as domega^2."""
+    mol = gs.make_config(0)
+    P = o.pair_vectors(mol)
+    eps = 0.05
+    errs = []
+    test_w = np.array([0.45, 0.8, 1.3, 2.1])
+    ref = o.chi0_poles(P, mol.eig, mol.n_occ, test_w, eps)
+    iu, ju = np.triu_indices(mol.n_prod)
+    for n in [256, 512, 1024]:
+        d = 8.0 / n
+        m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+        nhb = o.hist_bins(mol.eig, n, d)
+        s = o.frac_bits(P, mol.n_pairs)
+        H = o.histogram(P, m, fr, s, nhb)
+        chi = o.chi0_from_hist(H, s, n, -4.0, 4.0, eps, omegas=test_w)
+        errs.append(np.linalg.norm(chi - ref[:, iu, ju]) / np.linalg.norm(ref[:, iu, ju]))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
+
+
+def test_chi0_kramers_kronig():
+    """Re chi0 is the Hilbert transform of Im chi0 (analytic in the upper half
+    plane): checks signs, the factor pi and the odd extension a(-s) = -a(s)."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    e = o.packed_index(5, 5, mol.n_prod)
+    h = grid.eps / 10
+    L = 60.0
+    w = np.arange(-L, L, h)
+    chi = o.chi0_from_hist(H[:, [e]], s, grid.n_omega, grid.omega_min, grid.omega_max,
+                           grid.eps, omegas=w)[:, 0]
+    im = chi.imag
+    for w0_idx in [len(w) // 2 + 40, len(w) // 2 + 400, len(w) // 2 - 700]:
+        k = np.arange(len(w)) - w0_idx
+        odd = (k % 2) != 0
+        # Maclaurin rule for the principal value: sum over odd offsets, weight 2h
+        re_kk = (2 * h / np.pi) * np.sum(im[odd] / (w[odd] - w[w0_idx]))
+        assert abs(re_kk - chi.real[w0_idx]) < 2e-3 * np.abs(chi).max()
+
+
+# --------------------------------------------------------------------------- W
+
+
+def test_W_reduces_to_v_without_vertex():
+    """V -> 0 removes all screening: W = v exactly; and W - v scales as t^2
+    under V -> tV (chi0 is quadratic in V)."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    z = mol.scaled_vertex(0.0)
+    P, m, fr, nhb, s, H = _pipeline(z, grid)
+    assert not H.any()
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max,
+                                          grid.eps, js=[140]), mol.n_prod)[0]
+    W = o.screened_W(mol.v, chi)
+    assert np.array_equal(W, mol.v.astype(complex))
+    dev = []
+    for t in [1e-3, 2e-3]:
+        P, m, fr, nhb, s, H = _pipeline(mol.scaled_vertex(t), grid)
+        chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min,
+                                              grid.omega_max, grid.eps, js=[140]), mol.n_prod)[0]
+        dev.append(np.linalg.norm(o.screened_W(mol.v, chi) - mol.v))
+    assert abs(dev[1] / dev[0] - 4.0) < 0.01
+
+
+def test_W_one_by_one_closed_form():
+    grid = gs.config_grid(0)
+    d = grid.domega
+    eig = np.array([-10 * d, 14.25 * d])
+    mol = _tiny(eig, 1, np.array([[0.1, 0.9], [0.9, -0.2]]))
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    chi = o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    v = mol.v[0, 0]
+    for j in [128, 150, 151, 200, 20]:
+        W = o.screened_W(mol.v, chi[j].reshape(1, 1))[0, 0]
+        assert abs(W - v / (1 - v * chi[j, 0])) < 1e-14 * abs(W)
+
+
+def test_W_symmetric_and_series():
+    """W^T = W in a real basis (Section 5); for weak response W matches the
+    series v + v chi0 v + v chi0 v chi0 v of Section 7.B eq. W-series."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max,
+                                          grid.eps, js=[150]), mol.n_prod)[0]
+    W = o.screened_W(mol.v, chi)
+    assert np.abs(W - W.T).max() < 1e-10 * np.abs(W).max()
+    weak = mol.scaled_vertex(0.01)
+    P, m, fr, nhb, s, H = _pipeline(weak, grid)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max,
+                                          grid.eps, js=[150]), mol.n_prod)[0]
+    v = mol.v
+    W = o.screened_W(v, chi)
+    vc = v @ chi
+    series = v + vc @ v + vc @ vc @ v
+    nxt = np.linalg.norm(vc @ vc @ vc @ v)
+    assert np.linalg.norm(W - series) < 3 * nxt
+    assert np.linalg.norm(W - v - vc @ v) > 0.3 * np.linalg.norm(vc @ vc @ v)
+
+
+def test_compressed_W_equals_full_when_rank_fits():
+    """Section 7.B: if chi0 acts inside the kept subspace nothing is lost.  The
+    synthetic v has rank = number of distinct centres (7 for the tiny chain),
+    so k = 16 reproduces the full W, k = 4 does not, and the compressed form
+    equals (1 - v_k chi0)^{-1} v_k with v_k the rank-k truncation of v."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max,
+                                          grid.eps, js=[150]), mol.n_prod)[0]
+    Wf = o.screened_W(mol.v, chi)
+    Wk = o.screened_W_compressed(mol.v, chi, 16)
+    assert np.linalg.norm(Wk - Wf) < 1e-9 * np.linalg.norm(Wf)
+    W4 = o.screened_W_compressed(mol.v, chi, 4)
+    U, lam = o.compress_basis(mol.v, 4)
+    vk = (U * lam) @ U.T
+    alt = np.linalg.solve(np.eye(mol.n_prod) - vk @ chi, vk.astype(complex))
+    assert np.linalg.norm(W4 - alt) < 1e-10 * np.linalg.norm(alt)
+    assert np.linalg.norm(W4 - Wf) > 1e-3 * np.linalg.norm(Wf)
+
+
+def test_projected_histogram_is_projected_chi0():
+    """Histogram of U^T V^p equals U^T chi0 U up to fixed-point rounding
+    (Section 8.A: compress the response as soon as it is formed)."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    U, lam = o.compress_basis(mol.v, 10)
+    Pt = o.project_pairs(P, U)
+    st = o.frac_bits(Pt, mol.n_pairs)
+    Ht = o.histogram(Pt, m, fr, st, nhb)
+    js = [150, 170]
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max,
+                                          grid.eps, js=js), mol.n_prod)
+    chit = o.unpack_upper(o.chi0_from_hist(Ht, st, grid.n_omega, grid.omega_min,
+                                           grid.omega_max, grid.eps, js=js), 10)
+    for i in range(len(js)):
+        ref = U.T @ chi[i] @ U
+        assert np.abs(chit[i] - ref).max() < 1e-9 * np.abs(ref).max()
