@@ -1,0 +1,210 @@
+/*
+ * gw.h -- C ABI of the MI355X screened-interaction library (libgw.so).
+ *
+ * The library builds the screened Coulomb interaction of Hedin's GW
+ * approximation in a local product basis, following D. Foerster, P. Koval,
+ * D. Sanchez-Portal, "An O(N^3) implementation of Hedin's GW approximation for
+ * molecules" (arXiv:1101.2065):
+ *
+ *   1. pair vectors V_mu^{EF} = X_a^E V_mu^{ab} X_b^F       (Section 7.A)
+ *   2. spectral function of the free response a0_{mu nu}(s),
+ *      histogrammed on the frequency mesh                    (Section 5.A,
+ *                                                              eq. chi_by_spectra)
+ *   3. chi0(w + i eps) = Cauchy transform of a0, by FFT      (Section 5.A, 8.A)
+ *   4. W(w) = (1 - v chi0(w))^{-1} v by dense complex LU      (Section 2 eq.
+ *      Coulombscreening, Section 3 eq. tensorform-scr-inter)
+ *   5. optional compression to the top-k eigenvectors of v    (Section 7.B)
+ *
+ * Conventions for every function below:
+ *   - Energies in Hartree, measured from the Fermi level: states with index
+ *     < n_occ are occupied (E < 0), the rest empty (Section 3).
+ *   - Matrices are row-major.  Complex numbers are interleaved {re, im}
+ *     doubles (C99 double _Complex layout) or {re, im} floats for complex64.
+ *   - Pointers marked DEVICE are HIP device memory of the context's device;
+ *     pointers marked HOST are ordinary host memory.  The caller owns every
+ *     buffer it passes and must keep it alive until the call returns (for
+ *     gw_submit: until gw_poll returns GW_OK for that ticket).
+ *   - All GPU work is enqueued on the hipStream_t passed as void* (NULL = the
+ *     null stream).  Functions return when the work is enqueued unless they
+ *     say otherwise.
+ *   - Errors are status codes; nothing throws across the ABI.  Arguments are
+ *     checked before anything is launched (GW_E_INVALID).  A device error is
+ *     sticky: every later call on that context returns GW_E_DEVICE until
+ *     gw_destroy.  gw_last_error() gives a message for the last failure.
+ *   - One context per host thread; contexts are not thread-safe, except that
+ *     gw_submit / gw_poll / gw_release may be called from any one thread while
+ *     the context's serving worker runs.
+ */
+#ifndef GW_H
+#define GW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GW_OK = 0,
+    GW_PENDING = 1,     /* gw_poll: not finished yet */
+    GW_E_INVALID = -1,  /* bad argument (shape, layout, ordering, grid) */
+    GW_E_OOM = -2,      /* device workspace could not be allocated */
+    GW_E_DEVICE = -3,   /* HIP runtime or kernel failure (sticky) */
+    GW_E_NOCONV = -4,   /* refinement did not converge and fallback disabled */
+    GW_E_RANGE = -5,    /* value outside what the fixed-point format can hold */
+    GW_E_STATE = -6     /* call not valid in the current state (unknown ticket ...) */
+} gw_status;
+
+typedef enum {
+    GW_FP64 = 0,     /* form, factor and solve in FP64 */
+    GW_FP32_IR = 1,  /* factor and solve in FP32, FP64 residual refinement */
+    GW_BF16X_IR = 2  /* FP32 factor with split-BF16 trailing updates, FP64 refinement */
+} gw_precision;
+
+typedef struct gw_ctx gw_ctx;
+
+/* One molecule (Section 3).  Every array is DEVICE memory.
+ *
+ * Products are grouped in blocks; all products of block b share one ascending
+ * orbital set O_b = orb_idx[blk_orb[b] .. blk_orb[b+1]) (the atom or atom pair
+ * the product lives on; the vertex is zero outside it, Section 3 text after
+ * eq. VertexDefinition).  Product mu of block b (blk_prod[b] <= mu <
+ * blk_prod[b+1]) stores its |O_b| x |O_b| symmetric matrix V_mu^{ab} at
+ * vals[blk_val[b] + (mu - blk_prod[b]) * |O_b|^2], row-major in O_b order.
+ * |O_b| must be at most 64. */
+typedef struct {
+    int32_t n_orb;            /* number of orbitals = number of KS states */
+    int32_t n_occ;            /* occupied states: 0 < n_occ < n_orb */
+    int32_t n_prod;           /* number of products N_prod */
+    const double *eig;        /* [n_orb] ascending; eig[n_occ-1] < eig[n_occ] */
+    const double *X;          /* [n_orb][n_orb], X[a*n_orb + E] = X_a^E */
+    int32_t n_blk;
+    const int32_t *blk_prod;  /* [n_blk+1] product offsets, blk_prod[0] = 0, last = n_prod */
+    const int32_t *blk_orb;   /* [n_blk+1] offsets into orb_idx */
+    const int32_t *orb_idx;   /* orbital sets, ascending within a block, < n_orb */
+    const int64_t *blk_val;   /* [n_blk+1] offsets into vals */
+    const double *vals;       /* vertex values */
+} gw_molecule;
+
+/* Frequency mesh (Section 5, 5.B): omega_j = omega_min + j*domega,
+ * j = 0..n_omega-1, domega = (omega_max - omega_min)/n_omega.  Requirements:
+ * n_omega a power of two in [16, 8192]; omega_min = -omega_max (a window
+ * symmetric about the Fermi level); domega an exact power of two; eps > 0.
+ * frac_bits < 0 picks the fixed-point exponent s from the data (the largest
+ * that provably cannot overflow); frac_bits >= 0 asks for that s, lowered to
+ * the safe maximum if it is larger (the report says what was used). */
+typedef struct {
+    int32_t n_omega;
+    double omega_min, omega_max;
+    double eps;
+    int32_t frac_bits;
+} gw_grid;
+
+typedef struct {
+    int32_t n_hbins;          /* spectral bins stored per (mu, nu): m = 0..n_hbins-1 */
+    int32_t frac_bits_used;   /* s: histogram entries are integers times 2^-s */
+    int64_t n_dropped_pairs;  /* pairs whose energy lies beyond the mesh (ignored) */
+    int32_t n_solved;         /* frequencies factorised (the rest by conj mirror) */
+    int32_t n_fallback;       /* frequencies re-solved in FP64 after IR failed */
+    int32_t max_iter;         /* most refinement steps any frequency needed */
+    double max_rel_update;    /* largest final ||dW||_F / ||W||_F over frequencies */
+} gw_report;
+
+/* Sizes the caller needs before gw_build_chi0.  m: HOST copy of the scalar
+ * fields plus HOST pointers for eig (the other pointers are not read). */
+typedef struct {
+    int64_t n_pairs;          /* n_occ * (n_orb - n_occ) */
+    int32_t n_hbins;          /* bins stored per entry */
+    int64_t n_upper;          /* k(k+1)/2, k = n_prod or the compressed rank */
+    int64_t hist_bytes;       /* n_hbins * n_upper * 8 */
+    int64_t chi0_bytes;       /* n_omega * k * k * 16 */
+} gw_sizes;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * workspace the context may allocate (0 = 90% of free memory).
+ * Returns GW_E_INVALID for a bad device, GW_E_DEVICE on runtime failure. */
+gw_status gw_create(int device, size_t hbm_budget_bytes, gw_ctx **out);
+
+/* Waits for the context's outstanding work, frees its workspace. */
+gw_status gw_destroy(gw_ctx *ctx);
+
+/* Message of the last failure on this context ("" if none).  Never NULL. */
+const char *gw_last_error(const gw_ctx *ctx);
+
+/* Sizes for gw_build_chi0.  eig_host: HOST [n_orb]; k = 0 for no compression.
+ * Pure host computation (Section 5 mesh, Section 5.A bins). */
+gw_status gw_query_sizes(int32_t n_orb, int32_t n_occ, int32_t n_prod, const double *eig_host,
+                         const gw_grid *g, int32_t k, gw_sizes *out);
+
+/* Steps 1-3: a0 histogram and chi0 on the whole mesh (Sections 5.A, 7.A, 8.A).
+ *   basis: DEVICE [n_prod][k] or NULL.  If given, pair vectors are projected
+ *          onto its columns before histogramming (Section 8.A: compress as
+ *          soon as the response is formed), so the outputs live in the
+ *          k-dimensional basis: chi0_hat = basis^T chi0 basis.
+ *   hist_out: DEVICE int64 [n_hbins][n_upper] or NULL (then a workspace is
+ *          used).  Entry (m, t) is 2^s * a0_{mu nu} integrated over bin m,
+ *          t the row-major index of mu <= nu in the packed upper triangle.
+ *          Integer-exact and independent of launch shape and pair order.
+ *   chi0_out: DEVICE complex128 [n_omega][k][k] (k = n_prod without basis).
+ *          Both triangles are written.
+ *   rep: HOST or NULL.  If non-NULL the call synchronises the stream and
+ *          fills n_hbins, frac_bits_used and n_dropped_pairs.
+ * Reads eig and the block index arrays back to the host for validation
+ * (a synchronous copy on `stream`). */
+gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g,
+                        const double *basis, int32_t k, void *stream,
+                        int64_t *hist_out, void *chi0_out, gw_report *rep);
+
+/* Step 4: W(omega_j) = (1 - v chi0(omega_j))^{-1} v for every mesh point
+ * (Section 2 eq. Coulombscreening).  Only j = 0 and j >= n_omega/2 are
+ * factorised; W(omega_{n-j}) = conj W(omega_j) fills the rest (retarded
+ * response, exact on the symmetric mesh).
+ *   v: DEVICE, [n][n] symmetric (v_is_diag = 0) or the [n] diagonal of a
+ *      diagonal metric (v_is_diag = 1; the compressed solve passes the kept
+ *      eigenvalues Lambda_k, giving X = (1 - Lambda chi_hat)^{-1} Lambda).
+ *   chi0: DEVICE complex128 [n_omega][n][n] (e.g. from gw_build_chi0).
+ *   prec: GW_FP64, or a mixed form refined with an FP64 residual
+ *      r = v - (1 - v chi0) W until ||dW||_F <= tol ||W||_F (at most 6
+ *      steps); a frequency that does not converge is re-solved in FP64.
+ *   W_out: DEVICE complex128 [n_omega][n][n].
+ *   rep: HOST or NULL; if non-NULL the call synchronises and reports.
+ * n_omega must be even and at least 2.  The call synchronises the stream
+ * once per refinement step for the mixed forms. */
+gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
+                     const void *chi0, int32_t n_omega, gw_precision prec, double tol,
+                     void *stream, void *W_out, gw_report *rep);
+
+/* Section 7.B subspace: the k eigenvectors of v with the largest eigenvalues.
+ *   v: DEVICE [n][n] symmetric.  U_out: DEVICE [n][k] (columns = eigenvectors,
+ *   eigenvalues descending), lambda_out: DEVICE [k].  Synchronous. */
+gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream,
+                            double *U_out, double *lambda_out);
+
+/* Decompress one frequency: W = U X U^T (Section 8.B, decompression on the fly).
+ *   U: DEVICE [n][k]; X: DEVICE complex128 [k][k]; W_out: DEVICE complex128 [n][n]. */
+gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X,
+                        void *stream, void *W_out);
+
+/* Serving (continuous batching).  gw_submit copies nothing: the molecule's
+ * DEVICE buffers must stay valid until gw_poll returns GW_OK.  The request is
+ * admitted when its estimated HBM footprint fits; its chi0 and W stay on the
+ * device, owned by the library, until gw_release.
+ *   k_compress: 0 for the full basis, else the rank of the top-k compression
+ *   (W_dev then holds X [n_omega][k][k] followed by U_k [n][k] doubles).
+ *   v: DEVICE [n_prod][n_prod] Coulomb metric of the molecule. */
+gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
+                    int32_t k_compress, gw_precision prec, double tol, uint64_t *ticket);
+
+/* GW_PENDING until the request is done; then GW_OK with *W_dev pointing at
+ * the device-resident result ([n_omega][n][n] complex128) and *rep filled. */
+gw_status gw_poll(gw_ctx *ctx, uint64_t ticket, void **W_dev, gw_report *rep);
+
+/* Frees the device result of a finished request. */
+gw_status gw_release(gw_ctx *ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GW_H */

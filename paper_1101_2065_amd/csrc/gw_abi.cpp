@@ -1,0 +1,561 @@
+// C ABI of libgw.so: argument checks, planning, workspace and launch order.
+// Every arithmetic step of the path runs in the HIP kernels of k_chi0.hip,
+// k_gemm.hip and k_lu.hip; this file only validates, sizes and sequences.
+#include "../../include/gw.h"
+#include "gw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace gwk {
+hipError_t launch_perm(hipStream_t st, int n, const int32_t *ipiv, int32_t *perm, int batch);
+hipError_t launch_init_rhs_perm(hipStream_t st, int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
+                                int64_t sB, int batch);
+hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
+                              zdbl *dst, int64_t sD, int batch);
+hipError_t launch_dzgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
+                         const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                         int batch);
+hipError_t launch_zdgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
+                         const double *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                         int batch);
+hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
+                        const double *B, int64_t ldb, int64_t sB, double beta, double *C, int64_t ldc, int64_t sC,
+                        int batch);
+hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *src, double *dst);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
+hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
+                                zflt *dst, int64_t sD, int batch);
+hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch);
+}  // namespace gwk
+
+using gwk::zdbl;
+using gwk::zflt;
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct gw_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::string err;
+    bool sticky = false;
+    std::map<std::string, DevBuf> bufs;
+    // cached Cauchy-kernel spectrum
+    int ks_n = 0;
+    double ks_min = 0, ks_d = 0, ks_eps = 0;
+};
+
+namespace {
+
+gw_status fail(gw_ctx *c, gw_status s, const std::string &msg) {
+    if (c) {
+        c->err = msg;
+        if (s == GW_E_DEVICE) c->sticky = true;
+    }
+    return s;
+}
+
+#define GW_HIP(ctx, call)                                                                                     \
+    do {                                                                                                      \
+        hipError_t _e = (call);                                                                               \
+        if (_e != hipSuccess)                                                                                 \
+            return fail((ctx), _e == hipErrorOutOfMemory ? GW_E_OOM : GW_E_DEVICE,                            \
+                        std::string(#call) + ": " + hipGetErrorString(_e));                                  \
+    } while (0)
+
+// Grow-only named device buffers.  Reallocation waits for the device first.
+gw_status ws(gw_ctx *c, const char *name, size_t bytes, void **out) {
+    DevBuf &b = c->bufs[name];
+    if (bytes == 0) bytes = 256;
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            GW_HIP(c, hipDeviceSynchronize());
+            GW_HIP(c, hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&b.ptr, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            return fail(c, GW_E_OOM, std::string("workspace ") + name + ": cannot allocate " +
+                                         std::to_string(bytes) + " bytes");
+        }
+        b.bytes = bytes;
+    }
+    *out = b.ptr;
+    return GW_OK;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// domega = 2^-k exactly; returns false otherwise
+bool shift_bits(double d, int *k) {
+    int e = 0;
+    const double m = std::frexp(d, &e);
+    if (m != 0.5) return false;
+    *k = 1 - e;
+    return true;
+}
+
+gw_status check_grid(gw_ctx *c, const gw_grid *g, int *kbits) {
+    if (!g) return fail(c, GW_E_INVALID, "grid is NULL");
+    if (!is_pow2(g->n_omega) || g->n_omega < 16 || g->n_omega > 2048)
+        return fail(c, GW_E_INVALID, "n_omega must be a power of two in [16, 2048]");
+    if (!(g->omega_max > 0.0) || g->omega_min != -g->omega_max)
+        return fail(c, GW_E_INVALID, "the mesh must be symmetric: omega_min = -omega_max < 0");
+    if (!(g->eps > 0.0) || !std::isfinite(g->eps)) return fail(c, GW_E_INVALID, "eps must be positive");
+    const double d = (g->omega_max - g->omega_min) / g->n_omega;
+    if (!shift_bits(d, kbits)) return fail(c, GW_E_INVALID, "domega must be an exact power of two");
+    return GW_OK;
+}
+
+int hist_bins_host(const double *eig, int n_orb, int n_omega, int kbits) {
+    const double dmax = eig[n_orb - 1] - eig[0];
+    const double x = std::ldexp(dmax, kbits);
+    const long mmax = (long)std::floor(x);
+    return (int)std::min<long>(n_omega / 2, mmax + 2);
+}
+
+struct HostMol {
+    std::vector<double> eig;
+    std::vector<int32_t> blk_prod, blk_orb, orb_idx;
+    std::vector<int64_t> blk_val;
+    int max_o = 0;
+};
+
+gw_status check_molecule(gw_ctx *c, const gw_molecule *m, hipStream_t st, HostMol *h) {
+    if (!m) return fail(c, GW_E_INVALID, "molecule is NULL");
+    if (m->n_orb < 2 || m->n_occ < 1 || m->n_occ >= m->n_orb)
+        return fail(c, GW_E_INVALID, "need 0 < n_occ < n_orb");
+    if (m->n_prod < 1 || m->n_blk < 1) return fail(c, GW_E_INVALID, "need n_prod >= 1 and n_blk >= 1");
+    if ((int64_t)m->n_occ * (m->n_orb - m->n_occ) > INT32_MAX)
+        return fail(c, GW_E_INVALID, "too many electron-hole pairs");
+    if (!m->eig || !m->X || !m->blk_prod || !m->blk_orb || !m->orb_idx || !m->blk_val || !m->vals)
+        return fail(c, GW_E_INVALID, "NULL array in molecule");
+    h->eig.resize(m->n_orb);
+    h->blk_prod.resize(m->n_blk + 1);
+    h->blk_orb.resize(m->n_blk + 1);
+    h->blk_val.resize(m->n_blk + 1);
+    GW_HIP(c, hipMemcpyAsync(h->eig.data(), m->eig, sizeof(double) * m->n_orb, hipMemcpyDeviceToHost, st));
+    GW_HIP(c, hipMemcpyAsync(h->blk_prod.data(), m->blk_prod, sizeof(int32_t) * (m->n_blk + 1), hipMemcpyDeviceToHost, st));
+    GW_HIP(c, hipMemcpyAsync(h->blk_orb.data(), m->blk_orb, sizeof(int32_t) * (m->n_blk + 1), hipMemcpyDeviceToHost, st));
+    GW_HIP(c, hipMemcpyAsync(h->blk_val.data(), m->blk_val, sizeof(int64_t) * (m->n_blk + 1), hipMemcpyDeviceToHost, st));
+    GW_HIP(c, hipStreamSynchronize(st));
+    for (int i = 0; i < m->n_orb; ++i)
+        if (!std::isfinite(h->eig[i])) return fail(c, GW_E_INVALID, "non-finite eigenvalue");
+    for (int i = 1; i < m->n_orb; ++i)
+        if (h->eig[i] < h->eig[i - 1]) return fail(c, GW_E_INVALID, "eigenvalues must be ascending");
+    if (!(h->eig[m->n_occ - 1] < h->eig[m->n_occ]))
+        return fail(c, GW_E_INVALID, "need a gap: eig[n_occ-1] < eig[n_occ]");
+    if (h->blk_prod[0] != 0 || h->blk_prod[m->n_blk] != m->n_prod || h->blk_orb[0] != 0)
+        return fail(c, GW_E_INVALID, "block offsets must start at 0 and end at n_prod");
+    const int n_idx = h->blk_orb[m->n_blk];
+    if (n_idx < 1) return fail(c, GW_E_INVALID, "empty orbital index");
+    h->orb_idx.resize(n_idx);
+    GW_HIP(c, hipMemcpy(h->orb_idx.data(), m->orb_idx, sizeof(int32_t) * n_idx, hipMemcpyDeviceToHost));
+    for (int b = 0; b < m->n_blk; ++b) {
+        const int np = h->blk_prod[b + 1] - h->blk_prod[b];
+        const int no = h->blk_orb[b + 1] - h->blk_orb[b];
+        if (np < 1) return fail(c, GW_E_INVALID, "every block needs at least one product");
+        if (no < 1 || no > 64) return fail(c, GW_E_INVALID, "orbital set size must be in [1, 64]");
+        if (h->blk_val[b] < 0 || h->blk_val[b + 1] - h->blk_val[b] != (int64_t)np * no * no)
+            return fail(c, GW_E_INVALID, "blk_val offsets inconsistent with |O|^2 per product");
+        for (int i = h->blk_orb[b]; i < h->blk_orb[b + 1]; ++i) {
+            if (h->orb_idx[i] < 0 || h->orb_idx[i] >= m->n_orb) return fail(c, GW_E_INVALID, "orbital index out of range");
+            if (i > h->blk_orb[b] && h->orb_idx[i] <= h->orb_idx[i - 1])
+                return fail(c, GW_E_INVALID, "orbital indices must be strictly ascending in a block");
+        }
+        h->max_o = std::max(h->max_o, no);
+    }
+    return GW_OK;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+namespace {
+
+// per-frequency workspace for the solve
+struct SolveWs {
+    zdbl *A = nullptr;
+    zflt *A32 = nullptr, *B32 = nullptr;
+    zdbl *R = nullptr;
+    void *scratch = nullptr;
+    void *Li = nullptr, *Ui = nullptr;
+    int32_t *ipiv = nullptr, *perm = nullptr, *info = nullptr, *active = nullptr;
+    double *norms = nullptr;
+};
+
+size_t per_freq_bytes(int n, bool mixed) {
+    const size_t nn = (size_t)n * n;
+    const int nblk = (n + 63) / 64;
+    size_t b = nn * 16;                                    // A (FP64)
+    b += (size_t)64 * n * 16 + 4096;                       // panel scratch + swap list
+    b += 2 * (size_t)nblk * 64 * 64 * 16;                  // L11^-1, U11^-1
+    b += 3 * (size_t)n * 4;                                // ipiv, perm
+    if (mixed) b += nn * 8 * 2 + nn * 16 + (size_t)64 * n * 8 + 2 * (size_t)nblk * 64 * 64 * 8;
+    return b;
+}
+
+gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
+                           zdbl *W, int nb, SolveWs &w) {
+    const int64_t nn = (int64_t)n * n;
+    GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, nullptr, 0, nb));
+    GW_HIP(c, gwk::launch_fill_u32(st, (uint32_t *)w.info, nb, 0u));
+    GW_HIP(c, gwk::getrf_batched<zdbl>(st, n, w.A, nn, w.ipiv, (zdbl *)w.Li, (zdbl *)w.Ui, (zdbl *)w.scratch, w.info, nb));
+    GW_HIP(c, gwk::launch_perm(st, n, w.ipiv, w.perm, nb));
+    GW_HIP(c, gwk::launch_init_rhs_perm(st, n, v, v_is_diag, w.perm, W, nn, nb));
+    GW_HIP(c, gwk::getrs_batched<zdbl>(st, n, n, w.A, nn, w.ipiv, (const zdbl *)w.Li, (const zdbl *)w.Ui, W, nn, nb));
+    return GW_OK;
+}
+
+}  // namespace
+
+namespace {
+
+gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
+                            zdbl *W, int nb, double tol, SolveWs &w, std::vector<int> *conv_iters,
+                            std::vector<double> *rel, int max_iter) {
+    const int64_t nn = (int64_t)n * n;
+    GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, w.A32, nn, nb));
+    GW_HIP(c, gwk::launch_fill_u32(st, (uint32_t *)w.info, nb, 0u));
+    GW_HIP(c, gwk::getrf_batched<zflt>(st, n, w.A32, nn, w.ipiv, (zflt *)w.Li, (zflt *)w.Ui, (zflt *)w.scratch, w.info,
+                                       nb));
+    GW_HIP(c, gwk::launch_perm(st, n, w.ipiv, w.perm, nb));
+    // first solve: B32 = P v, solve, W = B32
+    GW_HIP(c, gwk::launch_init_rhs(st, n, v, v_is_diag, w.R, nn, nb));
+    GW_HIP(c, gwk::launch_rowgather_z2c(st, n, n, w.perm, w.R, nn, w.B32, nn, nb));
+    GW_HIP(c, gwk::getrs_batched<zflt>(st, n, n, w.A32, nn, w.ipiv, (const zflt *)w.Li, (const zflt *)w.Ui, w.B32, nn,
+                                       nb));
+    GW_HIP(c, gwk::launch_c2z_set(st, w.B32, W, nn, nb));
+    std::vector<int32_t> act(nb, 1);
+    std::vector<double> hn(2 * nb);
+    conv_iters->assign(nb, -1);
+    rel->assign(nb, 0.0);
+    GW_HIP(c, hipMemcpyAsync(w.active, act.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+    for (int it = 1; it <= max_iter; ++it) {
+        // FP64 residual r = v - (1 - v chi0) W
+        GW_HIP(c, gwk::launch_residual(st, n, v, v_is_diag, w.A, nn, W, nn, w.R, nn, nb));
+        GW_HIP(c, gwk::launch_rowgather_z2c(st, n, n, w.perm, w.R, nn, w.B32, nn, nb));
+        GW_HIP(c, gwk::getrs_batched<zflt>(st, n, n, w.A32, nn, w.ipiv, (const zflt *)w.Li, (const zflt *)w.Ui, w.B32,
+                                           nn, nb));
+        GW_HIP(c, gwk::launch_c2z_add(st, w.B32, W, nn, nb, w.active));
+        GW_HIP(c, gwk::launch_fill_u64(st, (uint64_t *)w.norms, 2 * nb, 0ull));
+        GW_HIP(c, gwk::launch_norms(st, w.B32, W, nn, nb, w.norms));
+        GW_HIP(c, hipMemcpyAsync(hn.data(), w.norms, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
+        GW_HIP(c, hipStreamSynchronize(st));
+        bool any = false;
+        for (int b = 0; b < nb; ++b) {
+            if (!act[b]) continue;
+            const double r = std::sqrt(hn[2 * b]) / std::max(std::sqrt(hn[2 * b + 1]), 1e-300);
+            (*rel)[b] = r;
+            if (r <= tol) {
+                act[b] = 0;
+                (*conv_iters)[b] = it;
+            } else {
+                any = true;
+            }
+        }
+        if (!any) break;
+        GW_HIP(c, hipMemcpyAsync(w.active, act.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
+    }
+    return GW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gw_status gw_create(int device, size_t hbm_budget_bytes, gw_ctx **out) {
+    if (!out) return GW_E_INVALID;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return GW_E_DEVICE;
+    if (device < 0 || device >= count) return GW_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return GW_E_DEVICE;
+    gw_ctx *c = new gw_ctx();
+    c->device = device;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        delete c;
+        return GW_E_DEVICE;
+    }
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+    *out = c;
+    return GW_OK;
+}
+
+gw_status gw_destroy(gw_ctx *ctx) {
+    if (!ctx) return GW_E_INVALID;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->bufs)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    delete ctx;
+    return GW_OK;
+}
+
+const char *gw_last_error(const gw_ctx *ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+gw_status gw_query_sizes(int32_t n_orb, int32_t n_occ, int32_t n_prod, const double *eig_host, const gw_grid *g,
+                         int32_t k, gw_sizes *out) {
+    if (!out || !eig_host || n_orb < 2 || n_occ < 1 || n_occ >= n_orb || n_prod < 1 || k < 0 || k > n_prod)
+        return GW_E_INVALID;
+    int kbits = 0;
+    if (check_grid(nullptr, g, &kbits) != GW_OK) return GW_E_INVALID;
+    const int64_t kk = k ? k : n_prod;
+    out->n_pairs = (int64_t)n_occ * (n_orb - n_occ);
+    out->n_hbins = hist_bins_host(eig_host, n_orb, g->n_omega, kbits);
+    out->n_upper = kk * (kk + 1) / 2;
+    out->hist_bytes = (int64_t)out->n_hbins * out->n_upper * 8;
+    out->chi0_bytes = (int64_t)g->n_omega * kk * kk * 16;
+    return GW_OK;
+}
+
+gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const double *basis, int32_t k,
+                        void *stream, int64_t *hist_out, void *chi0_out, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    int kbits = 0;
+    gw_status s = check_grid(ctx, g, &kbits);
+    if (s != GW_OK) return s;
+    if (!chi0_out) return fail(ctx, GW_E_INVALID, "chi0_out is NULL");
+    if (basis && (k < 1 || k > m->n_prod)) return fail(ctx, GW_E_INVALID, "compressed rank k must be in [1, n_prod]");
+    if (!basis && k != 0) return fail(ctx, GW_E_INVALID, "k must be 0 without a basis");
+    HostMol h;
+    s = check_molecule(ctx, m, st, &h);
+    if (s != GW_OK) return s;
+
+    const int n_orb = m->n_orb, n_occ = m->n_occ, n_prod = m->n_prod;
+    const int64_t n_pairs = (int64_t)n_occ * (n_orb - n_occ);
+    const int nhb = hist_bins_host(h.eig.data(), n_orb, g->n_omega, kbits);
+    const int rows = basis ? k : n_prod;
+    const int64_t n_upper = (int64_t)rows * (rows + 1) / 2;
+    const int L = 2 * g->n_omega;
+
+    void *P, *Pt = nullptr, *Ps, *lo, *rowoff, *binoff, *perm, *fsort, *stat, *vmax, *sdev, *Kt, *tw, *H;
+    if ((s = ws(ctx, "P", sizeof(double) * n_prod * n_pairs, &P)) != GW_OK) return s;
+    if (basis) {
+        void *bt;
+        if ((s = ws(ctx, "Pt", sizeof(double) * rows * n_pairs, &Pt)) != GW_OK) return s;
+        if ((s = ws(ctx, "basisT", sizeof(double) * (int64_t)k * n_prod, &bt)) != GW_OK) return s;
+        GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb, m->orb_idx,
+                                        m->blk_val, m->vals, h.max_o, (double *)P));
+        GW_HIP(ctx, gwk::launch_transpose_d(st, n_prod, k, basis, (double *)bt));
+        // Pt[k][pairs] = basis^T P (Section 8.A: compress as soon as formed)
+        GW_HIP(ctx, gwk::launch_dgemm(st, k, (int)n_pairs, n_prod, 1.0, (const double *)bt, n_prod, 0,
+                                      (const double *)P, n_pairs, 0, 0.0, (double *)Pt, n_pairs, 0, 1));
+    }
+    if ((s = ws(ctx, "Ps", sizeof(double) * rows * n_pairs, &Ps)) != GW_OK) return s;
+    if ((s = ws(ctx, "lo", sizeof(int32_t) * n_occ * (nhb + 1), &lo)) != GW_OK) return s;
+    if ((s = ws(ctx, "rowoff", sizeof(int32_t) * n_occ * nhb, &rowoff)) != GW_OK) return s;
+    if ((s = ws(ctx, "binoff", sizeof(int32_t) * nhb, &binoff)) != GW_OK) return s;
+    if ((s = ws(ctx, "perm", sizeof(int32_t) * n_pairs, &perm)) != GW_OK) return s;
+    if ((s = ws(ctx, "fsort", sizeof(double) * n_pairs, &fsort)) != GW_OK) return s;
+    if ((s = ws(ctx, "stat", 64, &stat)) != GW_OK) return s;
+    if ((s = ws(ctx, "vmax", 64, &vmax)) != GW_OK) return s;
+    if ((s = ws(ctx, "sdev", 64, &sdev)) != GW_OK) return s;
+    if ((s = ws(ctx, "Kt", sizeof(zdbl) * L, &Kt)) != GW_OK) return s;
+    if ((s = ws(ctx, "tw", sizeof(zdbl) * L, &tw)) != GW_OK) return s;
+    if (hist_out) H = hist_out;
+    else if ((s = ws(ctx, "H", sizeof(int64_t) * nhb * n_upper, &H)) != GW_OK) return s;
+
+    if (!basis)
+        GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb, m->orb_idx,
+                                        m->blk_val, m->vals, h.max_o, (double *)P));
+    const double *Psrc = basis ? (const double *)Pt : (const double *)P;
+    GW_HIP(ctx, gwk::launch_absmax(st, Psrc, (int64_t)rows * n_pairs, (uint64_t *)vmax));
+    GW_HIP(ctx, gwk::launch_fracbits(st, (const uint64_t *)vmax, n_pairs, g->frac_bits, (int32_t *)sdev));
+    GW_HIP(ctx, gwk::launch_pair_sort(st, n_orb, n_occ, m->eig, kbits, nhb, (int32_t *)lo, (int32_t *)rowoff,
+                                      (int32_t *)binoff, (int32_t *)perm, (double *)fsort, (int64_t *)stat));
+    GW_HIP(ctx, gwk::launch_gather(st, rows, n_pairs, Psrc, (const int32_t *)perm, (const int64_t *)stat, (double *)Ps));
+    // enough workgroups to fill 256 CUs a few times over
+    const int ntiles = (rows + 63) / 64;
+    const int ntp = ntiles * (ntiles + 1) / 2;
+    int splits = std::max(1, std::min(64, (2048 + ntp - 1) / ntp));
+    splits = std::min(splits, std::max(1, nhb - 1));
+    GW_HIP(ctx, gwk::launch_hist(st, rows, n_pairs, (const double *)Ps, (const double *)fsort, (const int32_t *)binoff,
+                                 (const int64_t *)stat, (const int32_t *)sdev, nhb, (int64_t *)H, splits));
+    const double dom = (g->omega_max - g->omega_min) / g->n_omega;
+    if (ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != dom || ctx->ks_eps != g->eps) {
+        const int j0 = (int)std::lround(g->omega_min / dom);
+        GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, j0, dom, g->eps, (zdbl *)Kt, (zdbl *)tw));
+        ctx->ks_n = g->n_omega;
+        ctx->ks_min = g->omega_min;
+        ctx->ks_d = dom;
+        ctx->ks_eps = g->eps;
+    }
+    GW_HIP(ctx, gwk::launch_fftconv(st, rows, g->n_omega, nhb, (const int64_t *)H, (const int32_t *)sdev,
+                                    (const zdbl *)Kt, (const zdbl *)tw, (zdbl *)chi0_out));
+    if (rep) {
+        int64_t hs[2];
+        int32_t sv = 0;
+        GW_HIP(ctx, hipMemcpyAsync(hs, stat, sizeof(hs), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipMemcpyAsync(&sv, sdev, sizeof(sv), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_hbins = nhb;
+        rep->frac_bits_used = sv;
+        rep->n_dropped_pairs = hs[1];
+    }
+    return GW_OK;
+}
+
+gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, const void *chi0, int32_t n_omega,
+                     gw_precision prec, double tol, void *stream, void *W_out, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    if (!v || !chi0 || !W_out) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
+    if (n < 1 || n > 32768) return fail(ctx, GW_E_INVALID, "n must be in [1, 32768]");
+    if (n_omega < 2 || (n_omega & 1)) return fail(ctx, GW_E_INVALID, "n_omega must be even and >= 2");
+    if (prec != GW_FP64 && prec != GW_FP32_IR && prec != GW_BF16X_IR)
+        return fail(ctx, GW_E_INVALID, "unknown precision");
+    if (prec == GW_BF16X_IR) return fail(ctx, GW_E_INVALID, "GW_BF16X_IR is not available in this build");
+    if (prec != GW_FP64 && !(tol > 0.0)) return fail(ctx, GW_E_INVALID, "tol must be positive for mixed precision");
+    hipStream_t st = as_stream(stream);
+    const bool mixed = prec != GW_FP64;
+    const int64_t nn = (int64_t)n * n;
+    const int nblk = (n + 63) / 64;
+
+    // batch size from the budget (the caller's chi0/W are not counted)
+    const size_t pf = per_freq_bytes(n, mixed);
+    int nbmax = (int)std::max<size_t>(1, std::min<size_t>(ctx->budget / 2 / pf, 256));
+    const int nsolve_hi = n_omega / 2;  // j = n/2 .. n-1
+    nbmax = std::min(nbmax, nsolve_hi);
+    SolveWs w;
+    gw_status s;
+    void *p;
+    if ((s = ws(ctx, "sA", (size_t)nbmax * nn * 16, &p)) != GW_OK) return s;
+    w.A = (zdbl *)p;
+    if ((s = ws(ctx, "sScr", (size_t)nbmax * (64 * (size_t)n * 16 + 4 * 257 + 256), &p)) != GW_OK) return s;
+    w.scratch = p;
+    const size_t esz = mixed ? 8 : 16;
+    if ((s = ws(ctx, "sLi", (size_t)nbmax * nblk * 64 * 64 * esz, &p)) != GW_OK) return s;
+    w.Li = p;
+    if ((s = ws(ctx, "sUi", (size_t)nbmax * nblk * 64 * 64 * esz, &p)) != GW_OK) return s;
+    w.Ui = p;
+    if ((s = ws(ctx, "sIpiv", (size_t)nbmax * n * 4, &p)) != GW_OK) return s;
+    w.ipiv = (int32_t *)p;
+    if ((s = ws(ctx, "sPerm", (size_t)nbmax * n * 4, &p)) != GW_OK) return s;
+    w.perm = (int32_t *)p;
+    if ((s = ws(ctx, "sInfo", (size_t)nbmax * 4, &p)) != GW_OK) return s;
+    w.info = (int32_t *)p;
+    if ((s = ws(ctx, "sAct", (size_t)nbmax * 4, &p)) != GW_OK) return s;
+    w.active = (int32_t *)p;
+    if ((s = ws(ctx, "sNorm", (size_t)nbmax * 16, &p)) != GW_OK) return s;
+    w.norms = (double *)p;
+    if (mixed) {
+        if ((s = ws(ctx, "sA32", (size_t)nbmax * nn * 8, &p)) != GW_OK) return s;
+        w.A32 = (zflt *)p;
+        if ((s = ws(ctx, "sB32", (size_t)nbmax * nn * 8, &p)) != GW_OK) return s;
+        w.B32 = (zflt *)p;
+        if ((s = ws(ctx, "sR", (size_t)nbmax * nn * 16, &p)) != GW_OK) return s;
+        w.R = (zdbl *)p;
+    }
+
+    const zdbl *X0 = (const zdbl *)chi0;
+    zdbl *W = (zdbl *)W_out;
+    // frequency batches: {0}, then [n/2, n) in chunks
+    std::vector<std::pair<int, int>> batches;
+    batches.push_back({0, 1});
+    for (int j = n_omega / 2; j < n_omega; j += nbmax) batches.push_back({j, std::min(nbmax, n_omega - j)});
+    if (n_omega == 2) batches = {{0, 2}};
+    int n_solved = 0, n_fallback = 0, max_it = 0;
+    double max_rel = 0.0;
+    for (auto &bt : batches) {
+        const int j0 = bt.first, nb = bt.second;
+        n_solved += nb;
+        if (!mixed) {
+            if ((s = solve_batch_fp64(ctx, st, n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, w)) != GW_OK) return s;
+        } else {
+            std::vector<int> its;
+            std::vector<double> rel;
+            if ((s = solve_batch_mixed(ctx, st, n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, tol, w, &its, &rel, 6)) !=
+                GW_OK)
+                return s;
+            for (int b = 0; b < nb; ++b) {
+                if (its[b] < 0) {
+                    // not converged: FP64 fallback for this frequency
+                    ++n_fallback;
+                    if ((s = solve_batch_fp64(ctx, st, n, v, v_is_diag, X0 + (j0 + b) * nn, W + (j0 + b) * nn, 1, w)) !=
+                        GW_OK)
+                        return s;
+                } else {
+                    max_it = std::max(max_it, its[b]);
+                    max_rel = std::max(max_rel, rel[b]);
+                }
+            }
+        }
+    }
+    if (n_omega >= 4) GW_HIP(ctx, gwk::launch_conj_mirror(st, nn, n_omega, W));
+    if (rep) {
+        std::vector<int32_t> info(1, 0);
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        rep->n_solved = n_solved;
+        rep->n_fallback = n_fallback;
+        rep->max_iter = max_it;
+        rep->max_rel_update = max_rel;
+    }
+    return GW_OK;
+}
+
+gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream, double *U_out,
+                            double *lambda_out) {
+    if (!ctx) return GW_E_INVALID;
+    (void)v; (void)n; (void)k; (void)stream; (void)U_out; (void)lambda_out;
+    return fail(ctx, GW_E_STATE, "gw_compress_basis is not available in this build");
+}
+
+gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X, void *stream, void *W_out) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    if (!U || !X || !W_out || n < 1 || k < 1 || k > n) return fail(ctx, GW_E_INVALID, "bad decompress arguments");
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    void *T, *Ut;
+    gw_status s;
+    if ((s = ws(ctx, "dT", sizeof(zdbl) * (int64_t)n * k, &T)) != GW_OK) return s;
+    if ((s = ws(ctx, "dUt", sizeof(double) * (int64_t)n * k, &Ut)) != GW_OK) return s;
+    GW_HIP(ctx, gwk::launch_transpose_d(st, n, k, U, (double *)Ut));
+    // T = U X ([n][k]), W = T U^T ([n][n]) (Section 8.B decompression)
+    GW_HIP(ctx, gwk::launch_dzgemm(st, n, k, k, 1.0, U, k, 0, (const zdbl *)X, k, 0, 0.0, (zdbl *)T, k, 0, 1));
+    GW_HIP(ctx, gwk::launch_zdgemm(st, n, n, k, 1.0, (const zdbl *)T, k, 0, (const double *)Ut, n, 0, 0.0,
+                                   (zdbl *)W_out, n, 0, 1));
+    return GW_OK;
+}
+
+gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, int32_t k_compress,
+                    gw_precision prec, double tol, uint64_t *ticket) {
+    if (!ctx) return GW_E_INVALID;
+    (void)m; (void)v; (void)g; (void)k_compress; (void)prec; (void)tol; (void)ticket;
+    return fail(ctx, GW_E_STATE, "serving is not available in this build");
+}
+
+gw_status gw_poll(gw_ctx *ctx, uint64_t ticket, void **W_dev, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    (void)ticket; (void)W_dev; (void)rep;
+    return fail(ctx, GW_E_STATE, "unknown ticket");
+}
+
+gw_status gw_release(gw_ctx *ctx, uint64_t ticket) {
+    if (!ctx) return GW_E_INVALID;
+    (void)ticket;
+    return fail(ctx, GW_E_STATE, "unknown ticket");
+}
+
+}  // extern "C"

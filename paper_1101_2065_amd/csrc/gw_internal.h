@@ -1,0 +1,110 @@
+// Internal declarations shared by the HIP translation units of libgw.so.
+// Host-side launchers for every kernel, plus small device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gwk {
+
+struct zdbl {
+    double re, im;
+};
+struct zflt {
+    float re, im;
+};
+
+// ---------------------------------------------------------------- chi0 build
+// Pair vertex (Section 7.A): P[mu][E*n_virt + F'] = sum_a X_a^E sum_b V_mu^{ab} X_b^{n_occ+F'}.
+hipError_t launch_pairvec(hipStream_t st, int n_orb, int n_occ, int n_prod, int n_blk,
+                          const double *X, const int32_t *blk_prod, const int32_t *blk_orb,
+                          const int32_t *orb_idx, const int64_t *blk_val, const double *vals,
+                          int max_o, double *P);
+
+// Pair bins on the mesh and the bin-sorted pair order (Sections 5, 5.A).
+// lo: [n_occ][nhb+1] int32, rowoff: [n_occ][nhb] int32, binoff: [nhb] int32,
+// perm: [n_pairs] int32, fsort: [n_pairs] double, stat: [4] int64 (n_kept, n_dropped).
+hipError_t launch_pair_sort(hipStream_t st, int n_orb, int n_occ, const double *eig, int kbits,
+                            int nhb, int32_t *lo, int32_t *rowoff, int32_t *binoff,
+                            int32_t *perm, double *fsort, int64_t *stat);
+
+// Ps[r][i] = P[r][perm[i]], i < n_kept (n_kept read from stat[0]).
+hipError_t launch_gather(hipStream_t st, int rows, int64_t n_pairs, const double *P,
+                         const int32_t *perm, const int64_t *stat, double *Ps);
+
+// vmax bits (as uint64) of max |P| into dst (must be zeroed first, done inside).
+hipError_t launch_absmax(hipStream_t st, const double *P, int64_t n, uint64_t *dst);
+
+// s from the overflow rule (and the caller's request): params[0] = s.
+hipError_t launch_fracbits(hipStream_t st, const uint64_t *vmax_bits, int64_t n_pairs,
+                           int requested, int32_t *s_out);
+
+hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t value);
+
+// Exact int64 histogram H[nhb][n_upper] (Section 5.A eq. chi_by_spectra).
+hipError_t launch_hist(hipStream_t st, int n, int64_t n_pairs_cap, const double *Ps,
+                       const double *fsort, const int32_t *binoff, const int64_t *stat,
+                       const int32_t *s_dev, int nhb, int64_t *H, int splits);
+
+// Kernel spectrum Kt[q] = DFT of k(r) = 1/((r + j0) domega + i eps) (wrapped) and
+// the twiddle table tw[q] = exp(-2 pi i q / L).
+hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, double eps,
+                        zdbl *Kt, zdbl *tw);
+
+// chi0[j][mu][nu] from H by FFT convolution (Section 5.A, 8.A).
+hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H,
+                          const int32_t *s_dev, const zdbl *Kt, const zdbl *tw, zdbl *chi0);
+
+// ---------------------------------------------------------------- dense algebra
+// Batched complex GEMM, C = alpha*A*B + beta*C, row-major, element strides,
+// batch strides in elements.  If C aliases B the caller guarantees M <= 64.
+hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha,
+                        const zdbl *A, int64_t lda, int64_t sA,
+                        const zdbl *B, int64_t ldb, int64_t sB, double beta,
+                        zdbl *C, int64_t ldc, int64_t sC, int batch);
+hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha,
+                        const zflt *A, int64_t lda, int64_t sA,
+                        const zflt *B, int64_t ldb, int64_t sB, float beta,
+                        zflt *C, int64_t ldc, int64_t sC, int batch);
+
+// A = I - v * chi0 (v real [n][n], chi0 complex), batched over frequencies.
+// v_is_diag: v holds the diagonal only.
+hipError_t launch_formA(hipStream_t st, int n, const double *v, int v_is_diag,
+                        const zdbl *chi0, int64_t s_chi, zdbl *A, int64_t s_A,
+                        zflt *A32, int64_t s_A32, int batch);
+
+// Right-looking blocked LU with partial pivoting, batched; factors in place,
+// ipiv[batch][n] (0-based global rows), Linv/Uinv [batch][n/64 blocks][64][64].
+template <typename Z>
+hipError_t getrf_batched(hipStream_t st, int n, Z *A, int64_t sA, int32_t *ipiv,
+                         Z *Linv, Z *Uinv, Z *scratch, int32_t *info, int batch);
+// Solve A X = B with the factors above, B [batch][n][nrhs] in place.
+template <typename Z>
+hipError_t getrs_batched(hipStream_t st, int n, int nrhs, const Z *LU, int64_t sA,
+                         const int32_t *ipiv, const Z *Linv, const Z *Uinv,
+                         Z *B, int64_t sB, int batch);
+
+// B[b] = v (as complex), v dense or diagonal.
+hipError_t launch_init_rhs(hipStream_t st, int n, const double *v, int v_is_diag,
+                           zdbl *B, int64_t sB, int batch);
+// W[n_omega - j] = conj(W[j]) for j in (n_omega/2, n_omega).
+hipError_t launch_conj_mirror(hipStream_t st, int64_t nn, int n_omega, zdbl *W);
+
+// Mixed precision helpers.
+hipError_t launch_z2c(hipStream_t st, const zdbl *src, zflt *dst, int64_t n);
+hipError_t launch_c2z_add(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch,
+                          const int32_t *active);
+// Per-batch sum of squares into out[2*b] (|dW|^2) and out[2*b+1] (|W|^2).
+hipError_t launch_norms(hipStream_t st, const zflt *dW, const zdbl *W, int64_t n_per, int batch,
+                        double *out);
+// R = v - A W (FP64), R complex, A complex, W complex; batched.
+hipError_t launch_residual(hipStream_t st, int n, const double *v, int v_is_diag,
+                           const zdbl *A, int64_t sA, const zdbl *W, int64_t sW,
+                           zdbl *R, int64_t sR, int batch);
+
+// Symmetric eigen-decomposition (one-sided Jacobi on the GPU), used for the
+// compression basis.
+hipError_t eig_topk(hipStream_t st, int n, int k, const double *v, double *U_out,
+                    double *lam_out, double *work);
+
+}  // namespace gwk

@@ -1,0 +1,261 @@
+// Dense products on the CDNA4 matrix cores (MFMA), for the W solve:
+// forming A = 1 - v chi0, the trailing updates of the blocked LU, the
+// triangular block products of the solve, and the FP64 refinement residual
+// (Section 2 eq. Coulombscreening, Section 3 eq. tensorform-scr-inter).
+//
+// Complex numbers are interleaved {re, im}.  A complex product is four real
+// MFMA products (no 3M trick: the FP64 residual must keep its accuracy).
+// Tile: 64x64 outputs per 256-thread workgroup, four 64-wide waves in 2x2,
+// each wave 32x32 = 2x2 MFMA 16x16 blocks; K staged through LDS in steps of
+// 16 with the next step prefetched into registers.
+#include "gw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace gwk {
+
+namespace {
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // result element e of lane l is D[(l / 16) + 4 e][l % 16] (measured on gfx950)
+    static __device__ inline int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // result element e of lane l is D[4 (l / 16) + e][l % 16]
+    static __device__ inline int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+// C = alpha * A * B + beta * C (+ identity on the real diagonal if add_eye).
+// AC/BC: A/B complex (else real).  C is complex unless both are real.
+// Optional C32: a complex-float copy of the result (same ld).
+template <typename T, bool AC, bool BC>
+__global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
+                                                 int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
+                                                 T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
+                                                 int64_t sC32) {
+    constexpr bool CC = AC || BC;
+    constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = CC ? 2 : 1;
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ T Ar[BK][BM];
+    __shared__ T Ai[AC ? BK : 1][AC ? BM : 1];
+    __shared__ T Br[BK][BN];
+    __shared__ T Bi[BC ? BK : 1][BC ? BN : 1];
+
+    const int bz = blockIdx.z;
+    A += (int64_t)bz * sA * ea;
+    B += (int64_t)bz * sB * eb;
+    C += (int64_t)bz * sC * ec;
+    if (C32) C32 += (int64_t)bz * sC32 * 2;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    v4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            accr[i][j] = v4{0, 0, 0, 0};
+            acci[i][j] = v4{0, 0, 0, 0};
+        }
+
+    // global -> register staging: A tile BM x BK (4 per thread), B tile BK x BN (4 per thread)
+    const int a_row = tid >> 2, a_k = (tid & 3) * 4;
+    const int b_row = tid >> 4, b_col = (tid & 15) * 4;
+    T ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+    auto gload = [&](int k0) {
+        const int gr = m0 + a_row;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int gk = k0 + a_k + c;
+            if (gr < M && gk < K) {
+                const T *p = A + ((int64_t)gr * lda + gk) * ea;
+                ra_r[c] = p[0];
+                if constexpr (AC) ra_i[c] = p[1];
+                else ra_i[c] = T(0);
+            } else {
+                ra_r[c] = T(0);
+                ra_i[c] = T(0);
+            }
+        }
+        const int gk = k0 + b_row;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int gc = n0 + b_col + c;
+            if (gk < K && gc < N) {
+                const T *p = B + ((int64_t)gk * ldb + gc) * eb;
+                rb_r[c] = p[0];
+                if constexpr (BC) rb_i[c] = p[1];
+                else rb_i[c] = T(0);
+            } else {
+                rb_r[c] = T(0);
+                rb_i[c] = T(0);
+            }
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Ar[a_k + c][a_row] = ra_r[c];
+            if constexpr (AC) Ai[a_k + c][a_row] = ra_i[c];
+            Br[b_row][b_col + c] = rb_r[c];
+            if constexpr (BC) Bi[b_row][b_col + c] = rb_i[c];
+        }
+        __syncthreads();
+        if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kl = kk + (lane >> 4);
+            T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm * 32 + i * 16 + (lane & 15);
+                ar[i] = Ar[kl][r];
+                if constexpr (AC) ai[i] = Ai[kl][r];
+                else ai[i] = T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int c = wn * 32 + j * 16 + (lane & 15);
+                br[j] = Br[kl][c];
+                if constexpr (BC) bi[j] = Bi[kl][c];
+                else bi[j] = T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    accr[i][j] = Mfma<T>::op(ar[i], br[j], accr[i][j]);
+                    if constexpr (AC && BC) accr[i][j] = Mfma<T>::op(-ai[i], bi[j], accr[i][j]);
+                    if constexpr (BC) acci[i][j] = Mfma<T>::op(ar[i], bi[j], acci[i][j]);
+                    if constexpr (AC) acci[i][j] = Mfma<T>::op(ai[i], br[j], acci[i][j]);
+                }
+        }
+    }
+    // epilogue: element e of a lane is row Mfma<T>::row(lane, e), column lane % 16
+    // of its 16x16 block (operands: A[lane % 16][lane / 16], B[lane / 16][lane % 16])
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, e);
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < M && col < N) {
+                    T *pc = C + ((int64_t)row * ldc + col) * ec;
+                    T vr = alpha * accr[i][j][e];
+                    T vi = alpha * acci[i][j][e];
+                    if (beta != T(0)) {
+                        vr += beta * pc[0];
+                        if constexpr (CC) vi += beta * pc[1];
+                    }
+                    if (add_eye && row == col) vr += T(1);
+                    pc[0] = vr;
+                    if constexpr (CC) pc[1] = vi;
+                    if (C32) {
+                        float *q = C32 + ((int64_t)row * ldc + col) * 2;
+                        q[0] = (float)vr;
+                        q[1] = (float)vi;
+                    }
+                }
+            }
+}
+
+// A = 1 - diag(lam) chi0 (compressed metric), optional complex-float copy.
+__global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *__restrict__ chi0, int64_t s_chi,
+                             zdbl *__restrict__ A, int64_t s_A, zflt *A32, int64_t s_A32) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= (int64_t)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    const zdbl c = chi0[b * s_chi + idx];
+    zdbl a{-lam[i] * c.re, -lam[i] * c.im};
+    if (i == j) a.re += 1.0;
+    A[b * s_A + idx] = a;
+    if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
+}
+
+template <typename T, bool AC, bool BC>
+hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *A, int64_t lda, int64_t sA,
+                         const T *B, int64_t ldb, int64_t sB, T beta, T *C, int64_t ldc, int64_t sC, int batch,
+                         int add_eye = 0, float *C32 = nullptr, int64_t sC32 = 0) {
+    if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
+    hipLaunchKernelGGL((k_gemm<T, AC, BC>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
+                       ldc, sC, add_eye, C32, sC32);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
+                        const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                        int batch) {
+    return launch_gemm_t<double, true, true>(st, M, N, K, alpha, (const double *)A, lda, sA, (const double *)B, ldb,
+                                             sB, beta, (double *)C, ldc, sC, batch);
+}
+
+hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha, const zflt *A, int64_t lda, int64_t sA,
+                        const zflt *B, int64_t ldb, int64_t sB, float beta, zflt *C, int64_t ldc, int64_t sC,
+                        int batch) {
+    return launch_gemm_t<float, true, true>(st, M, N, K, alpha, (const float *)A, lda, sA, (const float *)B, ldb, sB,
+                                            beta, (float *)C, ldc, sC, batch);
+}
+
+hipError_t launch_formA(hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0, int64_t s_chi,
+                        zdbl *A, int64_t s_A, zflt *A32, int64_t s_A32, int batch) {
+    if (v_is_diag) {
+        dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
+        hipLaunchKernelGGL(k_formA_diag, grid, dim3(256), 0, st, n, v, chi0, s_chi, A, s_A, A32, s_A32);
+        return hipGetLastError();
+    }
+    // A = -v * chi0 + 1 (v real, shared by the batch: batch stride 0)
+    return launch_gemm_t<double, false, true>(st, n, n, n, -1.0, v, n, 0, (const double *)chi0, n, s_chi, 0.0,
+                                              (double *)A, n, s_A, batch, 1, (float *)A32, s_A32);
+}
+
+// R = v - A W: R <- v (complex), then R -= A W.
+hipError_t launch_residual(hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *A, int64_t sA,
+                           const zdbl *W, int64_t sW, zdbl *R, int64_t sR, int batch) {
+    hipError_t e = launch_init_rhs(st, n, v, v_is_diag, R, sR, batch);
+    if (e != hipSuccess) return e;
+    return launch_zgemm(st, n, n, n, -1.0, A, n, sA, W, n, sW, 1.0, R, n, sR, batch);
+}
+
+// Real-times-complex and complex-times-real products exposed for the compression path.
+hipError_t launch_dzgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
+                         const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                         int batch) {
+    return launch_gemm_t<double, false, true>(st, M, N, K, alpha, A, lda, sA, (const double *)B, ldb, sB, beta,
+                                              (double *)C, ldc, sC, batch);
+}
+hipError_t launch_zdgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
+                         const double *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                         int batch) {
+    return launch_gemm_t<double, true, false>(st, M, N, K, alpha, (const double *)A, lda, sA, B, ldb, sB, beta,
+                                              (double *)C, ldc, sC, batch);
+}
+hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
+                        const double *B, int64_t ldb, int64_t sB, double beta, double *C, int64_t ldc, int64_t sC,
+                        int batch) {
+    return launch_gemm_t<double, false, false>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+}
+
+}  // namespace gwk

@@ -1,0 +1,578 @@
+// Blocked right-looking LU with partial pivoting, batched over frequencies,
+// and the matching solve, for W(w) = (1 - v chi0(w))^{-1} v (Section 2 eq.
+// Coulombscreening; the inversion is the O(N^3) step the paper's Sections 1
+// and 7.B point to).
+//
+// Panel width 64.  Per panel: one workgroup per frequency factors the
+// (n - kb) x 64 panel column by column (pivot = largest |re| + |im|, ties to
+// the lowest row), composes the 64 row exchanges into one list of
+// (destination, source) rows, and inverts the 64x64 unit-lower L11 and the
+// upper U11 in LDS.  The row exchanges are then applied to the rest of the
+// matrix in one pass, U12 = L11^{-1} A12 and the trailing update
+// A22 -= L21 U12 run on the MFMA GEMM.  The solve uses the stored inverses the
+// same way, so every O(N^3) flop of factor and solve is an MFMA product.
+#include "gw_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace gwk {
+
+hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
+                        const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                        int batch);
+hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha, const zflt *A, int64_t lda, int64_t sA,
+                        const zflt *B, int64_t ldb, int64_t sB, float beta, zflt *C, int64_t ldc, int64_t sC,
+                        int batch);
+
+namespace {
+
+constexpr int NB = 64;         // panel width
+constexpr int SWP = 1 + 4 * NB;  // per-frequency swap list: count, dst[2NB], src[2NB]
+
+template <typename T>
+struct Cx {
+    T re, im;
+};
+template <typename T>
+__device__ inline Cx<T> cmul(Cx<T> a, Cx<T> b) {
+    return Cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ inline Cx<T> crcp(Cx<T> a) {
+    const T d = a.re * a.re + a.im * a.im;
+    return Cx<T>{a.re / d, -a.im / d};
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_getf2(int n, int kb, int w, Cx<T> *A, int64_t sA, int32_t *ipiv,
+                                               Cx<T> *Linv, Cx<T> *Uinv, int nblk, Cx<T> *S, int32_t *swp,
+                                               int32_t *info) {
+    __shared__ Cx<T> Ts[NB][NB];
+    __shared__ Cx<T> Xs[NB][NB];
+    __shared__ Cx<T> urow[NB];
+    __shared__ T red_v[8];
+    __shared__ int red_i[8];
+    __shared__ int lpiv[NB];
+    __shared__ int piv_s;
+    __shared__ int zero_s;
+    __shared__ int rows[2 * NB], cont[2 * NB];
+    __shared__ Cx<T> dinv[NB];
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    A += (int64_t)b * sA;
+    ipiv += (int64_t)b * n;
+    S += (int64_t)b * NB * n;
+    swp += (int64_t)b * SWP;
+    Linv += ((int64_t)b * nblk + kb / NB) * NB * NB;
+    Uinv += ((int64_t)b * nblk + kb / NB) * NB * NB;
+    const int m = n - kb;
+
+    for (int64_t idx = tid; idx < (int64_t)m * w; idx += 512) {
+        const int i = (int)(idx / w), c = (int)(idx % w);
+        S[(int64_t)c * m + i] = A[(int64_t)(kb + i) * n + kb + c];
+    }
+    __syncthreads();
+
+    for (int j = 0; j < w; ++j) {
+        const Cx<T> *col = S + (int64_t)j * m;
+        T best = T(-1);
+        int bi = m;
+        for (int i = j + tid; i < m; i += 512) {
+            const Cx<T> z = col[i];
+            const T v = fabs(z.re) + fabs(z.im);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const T ov = __shfl_xor(best, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ov > best || (ov == best && oi < bi)) {
+                best = ov;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            red_v[wave] = best;
+            red_i[wave] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            T bv = red_v[0];
+            int bx = red_i[0];
+            for (int q = 1; q < 8; ++q)
+                if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bx)) {
+                    bv = red_v[q];
+                    bx = red_i[q];
+                }
+            if (bx >= m) bx = j;
+            piv_s = bx;
+            lpiv[j] = bx;
+            zero_s = (bv == T(0));
+            if (bv == T(0) && info[b] == 0) info[b] = kb + j + 1;
+        }
+        __syncthreads();
+        const int piv = piv_s;
+        if (piv != j) {
+            for (int c = tid; c < w; c += 512) {
+                Cx<T> *pc = S + (int64_t)c * m;
+                const Cx<T> t = pc[j];
+                pc[j] = pc[piv];
+                pc[piv] = t;
+            }
+        }
+        __syncthreads();
+        if (!zero_s) {
+            const Cx<T> inv = crcp(S[(int64_t)j * m + j]);
+            if (tid > j && tid < w) urow[tid] = S[(int64_t)tid * m + j];
+            __syncthreads();
+            for (int i = j + 1 + tid; i < m; i += 512) {
+                Cx<T> *pj = S + (int64_t)j * m;
+                const Cx<T> l = cmul(pj[i], inv);
+                pj[i] = l;
+                for (int c = j + 1; c < w; ++c) {
+                    Cx<T> *pc = S + (int64_t)c * m;
+                    const Cx<T> u = urow[c];
+                    const Cx<T> x = pc[i];
+                    pc[i] = Cx<T>{x.re - (l.re * u.re - l.im * u.im), x.im - (l.re * u.im + l.im * u.re)};
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // write the factored panel back, pivots as global rows
+    for (int64_t idx = tid; idx < (int64_t)m * w; idx += 512) {
+        const int i = (int)(idx / w), c = (int)(idx % w);
+        A[(int64_t)(kb + i) * n + kb + c] = S[(int64_t)c * m + i];
+    }
+    if (tid < w) ipiv[kb + tid] = kb + lpiv[tid];
+    // compose the row exchanges: new row dst = old row src
+    if (tid == 0) {
+        int nt = 0;
+        for (int j = 0; j < w; ++j) {
+            const int r1 = j, r2 = lpiv[j];
+            if (r1 == r2) continue;
+            int i1 = -1, i2 = -1;
+            for (int t = 0; t < nt; ++t) {
+                if (rows[t] == r1) i1 = t;
+                if (rows[t] == r2) i2 = t;
+            }
+            if (i1 < 0) {
+                rows[nt] = r1;
+                cont[nt] = r1;
+                i1 = nt++;
+            }
+            if (i2 < 0) {
+                rows[nt] = r2;
+                cont[nt] = r2;
+                i2 = nt++;
+            }
+            const int t = cont[i1];
+            cont[i1] = cont[i2];
+            cont[i2] = t;
+        }
+        swp[0] = nt;
+        for (int t = 0; t < nt; ++t) {
+            swp[1 + t] = kb + rows[t];
+            swp[1 + 2 * NB + t] = kb + cont[t];
+        }
+    }
+    // diagonal block into LDS (row-major), zero padded
+    for (int idx = tid; idx < NB * NB; idx += 512) {
+        const int i = idx / NB, c = idx % NB;
+        Ts[i][c] = (i < w && c < w) ? S[(int64_t)c * m + i] : Cx<T>{T(0), T(0)};
+        Xs[i][c] = Cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    // L11^{-1}: unit lower, column c by forward substitution
+    if (tid < w) {
+        const int c = tid;
+        Xs[c][c] = Cx<T>{T(1), T(0)};
+        for (int i = c + 1; i < w; ++i) {
+            T sr = 0, si = 0;
+            for (int k = c; k < i; ++k) {
+                const Cx<T> l = Ts[i][k], x = Xs[k][c];
+                sr += l.re * x.re - l.im * x.im;
+                si += l.re * x.im + l.im * x.re;
+            }
+            Xs[i][c] = Cx<T>{-sr, -si};
+        }
+    }
+    if (tid < w) dinv[tid] = crcp(Ts[tid][tid]);
+    __syncthreads();
+    for (int idx = tid; idx < NB * NB; idx += 512) {
+        Linv[idx] = Xs[idx / NB][idx % NB];
+        Xs[idx / NB][idx % NB] = Cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    // U11^{-1}: upper, column c by back substitution
+    if (tid < w) {
+        const int c = tid;
+        Xs[c][c] = dinv[c];
+        for (int i = c - 1; i >= 0; --i) {
+            T sr = 0, si = 0;
+            for (int k = i + 1; k <= c; ++k) {
+                const Cx<T> u = Ts[i][k], x = Xs[k][c];
+                sr += u.re * x.re - u.im * x.im;
+                si += u.re * x.im + u.im * x.re;
+            }
+            const Cx<T> d = dinv[i];
+            Xs[i][c] = Cx<T>{-(sr * d.re - si * d.im), -(sr * d.im + si * d.re)};
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NB * NB; idx += 512) Uinv[idx] = Xs[idx / NB][idx % NB];
+}
+
+// Apply a panel's composed row exchanges to columns [0, kb) and [kb+w, n).
+// Workgroup = 32 columns; all source rows are staged in LDS before any write.
+template <typename T>
+__global__ __launch_bounds__(256) void k_laswp(int n, int kb, int w, Cx<T> *A, int64_t sA, const int32_t *swp) {
+    __shared__ Cx<T> buf[2 * NB][32];
+    const int b = blockIdx.y;
+    A += (int64_t)b * sA;
+    swp += (int64_t)b * SWP;
+    const int nt = swp[0];
+    if (nt == 0) return;
+    const int ncols = n - w;
+    const int cc = threadIdx.x & 31, tr = threadIdx.x >> 5;
+    const int idx = blockIdx.x * 32 + cc;
+    const int c = idx < kb ? idx : idx + w;
+    const bool ok = idx < ncols;
+    for (int t = tr; t < nt; t += 8)
+        if (ok) buf[t][cc] = A[(int64_t)swp[1 + 2 * NB + t] * n + c];
+    __syncthreads();
+    for (int t = tr; t < nt; t += 8)
+        if (ok) A[(int64_t)swp[1 + t] * n + c] = buf[t][cc];
+}
+
+// Full row permutation of a factorisation: row i of P A is row perm[i] of A.
+__global__ __launch_bounds__(256) void k_perm_from_ipiv(int n, const int32_t *ipiv, int32_t *perm) {
+    extern __shared__ int32_t pm[];
+    const int b = blockIdx.x;
+    ipiv += (int64_t)b * n;
+    perm += (int64_t)b * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) pm[i] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < n; ++j) {
+            const int r = ipiv[j];
+            if (r != j) {
+                const int t = pm[j];
+                pm[j] = pm[r];
+                pm[r] = t;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = pm[i];
+}
+
+// B[b][i][c] = src[b][perm[i]][c]  (out of place gather of rows)
+template <typename T>
+__global__ void k_rowgather(int n, int nrhs, const int32_t *perm, const Cx<T> *src, int64_t sS, Cx<T> *dst,
+                            int64_t sD) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= (int64_t)n * nrhs) return;
+    const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+    dst[(int64_t)b * sD + idx] = src[(int64_t)b * sS + (int64_t)perm[(int64_t)b * n + i] * nrhs + c];
+}
+
+// B[b][i][c] = v[perm[i]][c] (dense real v) or delta(perm[i], c) lam[c] (diagonal);
+// perm may be null (identity).
+__global__ void k_init_rhs(int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B, int64_t sB) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= (int64_t)n * n) return;
+    const int i = (int)(idx / n), c = (int)(idx % n);
+    const int r = perm ? perm[(int64_t)b * n + i] : i;
+    double x;
+    if (v_is_diag) x = (r == c) ? v[c] : 0.0;
+    else x = v[(int64_t)r * n + c];
+    B[(int64_t)b * sB + idx] = zdbl{x, 0.0};
+}
+
+__global__ void k_conj_mirror(int64_t nn, int n_omega, zdbl *W) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = 1 + blockIdx.y;  // 1 .. n_omega/2 - 1
+    if (idx >= nn) return;
+    const zdbl s = W[(int64_t)(n_omega - j) * nn + idx];
+    W[(int64_t)j * nn + idx] = zdbl{s.re, -s.im};
+}
+
+__global__ void k_z2c(const zdbl *src, zflt *dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = zflt{(float)src[i].re, (float)src[i].im};
+}
+
+// W[b] += d[b] for active batch entries (d complex float).
+__global__ void k_c2z_add(const zflt *d, zdbl *W, int64_t n_per, const int32_t *active) {
+    const int b = blockIdx.y;
+    if (active && !active[b]) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_per; i += (int64_t)gridDim.x * blockDim.x) {
+        const zflt x = d[(int64_t)b * n_per + i];
+        zdbl &y = W[(int64_t)b * n_per + i];
+        y.re += (double)x.re;
+        y.im += (double)x.im;
+    }
+}
+
+// out[2b] += sum |d|^2, out[2b+1] += sum |W|^2 (caller zeroes out).
+__global__ void k_norms(const zflt *d, const zdbl *W, int64_t n_per, double *out) {
+    const int b = blockIdx.y;
+    double sd = 0, sw = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_per; i += (int64_t)gridDim.x * blockDim.x) {
+        const zflt x = d[(int64_t)b * n_per + i];
+        const zdbl y = W[(int64_t)b * n_per + i];
+        sd += (double)x.re * x.re + (double)x.im * x.im;
+        sw += y.re * y.re + y.im * y.im;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sd += __shfl_xor(sd, off);
+        sw += __shfl_xor(sw, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out[2 * b], sd);
+        atomicAdd(&out[2 * b + 1], sw);
+    }
+}
+
+
+__global__ void k_rowgather_z2c(int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS, zflt *dst,
+                                int64_t sD) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= (int64_t)n * nrhs) return;
+    const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
+    const zdbl x = src[(int64_t)b * sS + (int64_t)perm[(int64_t)b * n + i] * nrhs + c];
+    dst[(int64_t)b * sD + idx] = zflt{(float)x.re, (float)x.im};
+}
+
+__global__ void k_c2z_set(const zflt *d, zdbl *W, int64_t n_per) {
+    const int b = blockIdx.y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_per; i += (int64_t)gridDim.x * blockDim.x) {
+        const zflt x = d[(int64_t)b * n_per + i];
+        W[(int64_t)b * n_per + i] = zdbl{(double)x.re, (double)x.im};
+    }
+}
+
+// dst[c][r] = src[r][c] through a 32x32 LDS tile
+__global__ __launch_bounds__(256) void k_transpose_d(int rows, int cols, const double *src, double *dst) {
+    __shared__ double t[32][33];
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8)
+        if (r0 + k < rows && c0 + tx < cols) t[k][tx] = src[(int64_t)(r0 + k) * cols + c0 + tx];
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8)
+        if (c0 + k < cols && r0 + tx < rows) dst[(int64_t)(c0 + k) * rows + r0 + tx] = t[tx][k];
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+hipError_t gemm_t(hipStream_t st, int M, int N, int K, T alpha, const Cx<T> *A, int64_t lda, int64_t sA,
+                  const Cx<T> *B, int64_t ldb, int64_t sB, T beta, Cx<T> *C, int64_t ldc, int64_t sC, int batch);
+template <>
+hipError_t gemm_t<double>(hipStream_t st, int M, int N, int K, double alpha, const Cx<double> *A, int64_t lda,
+                          int64_t sA, const Cx<double> *B, int64_t ldb, int64_t sB, double beta, Cx<double> *C,
+                          int64_t ldc, int64_t sC, int batch) {
+    return launch_zgemm(st, M, N, K, alpha, (const zdbl *)A, lda, sA, (const zdbl *)B, ldb, sB, beta, (zdbl *)C, ldc,
+                        sC, batch);
+}
+template <>
+hipError_t gemm_t<float>(hipStream_t st, int M, int N, int K, float alpha, const Cx<float> *A, int64_t lda,
+                         int64_t sA, const Cx<float> *B, int64_t ldb, int64_t sB, float beta, Cx<float> *C,
+                         int64_t ldc, int64_t sC, int batch) {
+    return launch_cgemm(st, M, N, K, alpha, (const zflt *)A, lda, sA, (const zflt *)B, ldb, sB, beta, (zflt *)C, ldc,
+                        sC, batch);
+}
+
+template <typename T>
+hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv, Cx<T> *Linv, Cx<T> *Uinv,
+                      Cx<T> *scratch, int32_t *info, int batch) {
+    const int nblk = (n + NB - 1) / NB;
+    int32_t *swp = (int32_t *)(scratch + (int64_t)batch * NB * n);
+    hipError_t e;
+    for (int kb = 0; kb < n; kb += NB) {
+        const int w = min(NB, n - kb);
+        hipLaunchKernelGGL(k_getf2<T>, dim3(batch), dim3(512), 0, st, n, kb, w, A, sA, ipiv, Linv, Uinv, nblk, scratch,
+                           swp, info);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (n - w > 0) {
+            hipLaunchKernelGGL(k_laswp<T>, dim3((n - w + 31) / 32, batch), dim3(256), 0, st, n, kb, w, A, sA, swp);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        const int rest = n - kb - w;
+        if (rest > 0) {
+            const Cx<T> *Lb = Linv + (int64_t)(kb / NB) * NB * NB;
+            Cx<T> *A12 = A + (int64_t)kb * n + kb + w;
+            e = gemm_t<T>(st, w, rest, w, T(1), Lb, NB, (int64_t)nblk * NB * NB, A12, n, sA, T(0), A12, n, sA, batch);
+            if (e != hipSuccess) return e;
+            const Cx<T> *L21 = A + (int64_t)(kb + w) * n + kb;
+            Cx<T> *A22 = A + (int64_t)(kb + w) * n + kb + w;
+            e = gemm_t<T>(st, rest, rest, w, T(-1), L21, n, sA, A12, n, sA, T(1), A22, n, sA, batch);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t sA, const Cx<T> *Linv,
+                      const Cx<T> *Uinv, Cx<T> *B, int64_t sB, int batch) {
+    const int nblk = (n + NB - 1) / NB;
+    const int64_t sI = (int64_t)nblk * NB * NB;
+    hipError_t e;
+    for (int kb = 0; kb < n; kb += NB) {
+        const int w = min(NB, n - kb);
+        Cx<T> *Bk = B + (int64_t)kb * nrhs;
+        e = gemm_t<T>(st, w, nrhs, w, T(1), Linv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk, nrhs,
+                      sB, batch);
+        if (e != hipSuccess) return e;
+        const int rest = n - kb - w;
+        if (rest > 0) {
+            e = gemm_t<T>(st, rest, nrhs, w, T(-1), LU + (int64_t)(kb + w) * n + kb, n, sA, Bk, nrhs, sB, T(1),
+                          B + (int64_t)(kb + w) * nrhs, nrhs, sB, batch);
+            if (e != hipSuccess) return e;
+        }
+    }
+    for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
+        const int w = min(NB, n - kb);
+        Cx<T> *Bk = B + (int64_t)kb * nrhs;
+        e = gemm_t<T>(st, w, nrhs, w, T(1), Uinv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk, nrhs,
+                      sB, batch);
+        if (e != hipSuccess) return e;
+        if (kb > 0) {
+            e = gemm_t<T>(st, kb, nrhs, w, T(-1), LU + kb, n, sA, Bk, nrhs, sB, T(1), B, nrhs, sB, batch);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+// scratch must hold batch * 64 * n complex + batch * (1 + 4*64) int32.
+template <>
+hipError_t getrf_batched<zdbl>(hipStream_t st, int n, zdbl *A, int64_t sA, int32_t *ipiv, zdbl *Linv, zdbl *Uinv,
+                               zdbl *scratch, int32_t *info, int batch) {
+    return getrf_impl<double>(st, n, (Cx<double> *)A, sA, ipiv, (Cx<double> *)Linv, (Cx<double> *)Uinv,
+                              (Cx<double> *)scratch, info, batch);
+}
+template <>
+hipError_t getrf_batched<zflt>(hipStream_t st, int n, zflt *A, int64_t sA, int32_t *ipiv, zflt *Linv, zflt *Uinv,
+                               zflt *scratch, int32_t *info, int batch) {
+    return getrf_impl<float>(st, n, (Cx<float> *)A, sA, ipiv, (Cx<float> *)Linv, (Cx<float> *)Uinv,
+                             (Cx<float> *)scratch, info, batch);
+}
+template <>
+hipError_t getrs_batched<zdbl>(hipStream_t st, int n, int nrhs, const zdbl *LU, int64_t sA, const int32_t *ipiv,
+                               const zdbl *Linv, const zdbl *Uinv, zdbl *B, int64_t sB, int batch) {
+    (void)ipiv;  // rows of B are already in pivot order (see launch_perm / launch_init_rhs)
+    return getrs_impl<double>(st, n, nrhs, (const Cx<double> *)LU, sA, (const Cx<double> *)Linv,
+                              (const Cx<double> *)Uinv, (Cx<double> *)B, sB, batch);
+}
+template <>
+hipError_t getrs_batched<zflt>(hipStream_t st, int n, int nrhs, const zflt *LU, int64_t sA, const int32_t *ipiv,
+                               const zflt *Linv, const zflt *Uinv, zflt *B, int64_t sB, int batch) {
+    (void)ipiv;
+    return getrs_impl<float>(st, n, nrhs, (const Cx<float> *)LU, sA, (const Cx<float> *)Linv,
+                             (const Cx<float> *)Uinv, (Cx<float> *)B, sB, batch);
+}
+
+hipError_t launch_perm(hipStream_t st, int n, const int32_t *ipiv, int32_t *perm, int batch) {
+    hipLaunchKernelGGL(k_perm_from_ipiv, dim3(batch), dim3(256), (size_t)n * sizeof(int32_t), st, n, ipiv, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowgather_c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zflt *src, int64_t sS,
+                              zflt *dst, int64_t sD, int batch) {
+    dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
+    hipLaunchKernelGGL(k_rowgather<float>, grid, dim3(256), 0, st, n, nrhs, perm, (const Cx<float> *)src, sS,
+                       (Cx<float> *)dst, sD);
+    return hipGetLastError();
+}
+hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
+                              zdbl *dst, int64_t sD, int batch) {
+    dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
+    hipLaunchKernelGGL(k_rowgather<double>, grid, dim3(256), 0, st, n, nrhs, perm, (const Cx<double> *)src, sS,
+                       (Cx<double> *)dst, sD);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_rhs_perm(hipStream_t st, int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
+                                int64_t sB, int batch) {
+    dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
+    hipLaunchKernelGGL(k_init_rhs, grid, dim3(256), 0, st, n, v, v_is_diag, perm, B, sB);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_rhs(hipStream_t st, int n, const double *v, int v_is_diag, zdbl *B, int64_t sB, int batch) {
+    return launch_init_rhs_perm(st, n, v, v_is_diag, nullptr, B, sB, batch);
+}
+
+hipError_t launch_conj_mirror(hipStream_t st, int64_t nn, int n_omega, zdbl *W) {
+    if (n_omega < 4) return hipSuccess;
+    dim3 grid((unsigned)((nn + 255) / 256), n_omega / 2 - 1);
+    hipLaunchKernelGGL(k_conj_mirror, grid, dim3(256), 0, st, nn, n_omega, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_z2c(hipStream_t st, const zdbl *src, zflt *dst, int64_t n) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_z2c, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_c2z_add(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch, const int32_t *active) {
+    int64_t blocks = (n_per + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_c2z_add, dim3((unsigned)blocks, batch), dim3(256), 0, st, d, W, n_per, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(hipStream_t st, const zflt *dW, const zdbl *W, int64_t n_per, int batch, double *out) {
+    int64_t blocks = (n_per + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)blocks, batch), dim3(256), 0, st, dW, W, n_per, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
+                                zflt *dst, int64_t sD, int batch) {
+    dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
+    hipLaunchKernelGGL(k_rowgather_z2c, grid, dim3(256), 0, st, n, nrhs, perm, src, sS, dst, sD);
+    return hipGetLastError();
+}
+
+hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch) {
+    int64_t blocks = (n_per + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_c2z_set, dim3((unsigned)blocks, batch), dim3(256), 0, st, d, W, n_per);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *src, double *dst) {
+    dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+    hipLaunchKernelGGL(k_transpose_d, grid, dim3(256), 0, st, rows, cols, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
+}  // namespace gwk
