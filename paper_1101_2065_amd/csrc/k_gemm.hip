@@ -6,8 +6,8 @@
 // Complex numbers are interleaved {re, im}.  A complex product is four real
 // MFMA products (no 3M trick: the FP64 residual must keep its accuracy).
 // Tile: 64x64 outputs per 256-thread workgroup, four 64-wide waves in 2x2,
-// each wave 32x32 = 2x2 MFMA 16x16 blocks; K staged through LDS in steps of
-// 16 with the next step prefetched into registers.
+// each wave 32x32 = 2x2 MFMA 16x16 blocks; K staged through a double-buffered
+// LDS tile in steps of 16, the next step prefetched into registers.
 #include "gw_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -50,10 +50,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
     constexpr bool CC = AC || BC;
     constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = CC ? 2 : 1;
     typedef typename Mfma<T>::v4 v4;
-    __shared__ T Ar[BK][BM];
-    __shared__ T Ai[AC ? BK : 1][AC ? BM : 1];
-    __shared__ T Br[BK][BN];
-    __shared__ T Bi[BC ? BK : 1][BC ? BN : 1];
+    __shared__ T Ar[2][BK][BM];
+    __shared__ T Ai[2][AC ? BK : 1][AC ? BM : 1];
+    __shared__ T Br[2][BK][BN];
+    __shared__ T Bi[2][BC ? BK : 1][BC ? BN : 1];
 
     const int bz = blockIdx.z;
     A += (int64_t)bz * sA * ea;
@@ -107,18 +107,24 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
             }
         }
     };
-    gload(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        __syncthreads();
+    auto lstore = [&](int b) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            Ar[a_k + c][a_row] = ra_r[c];
-            if constexpr (AC) Ai[a_k + c][a_row] = ra_i[c];
-            Br[b_row][b_col + c] = rb_r[c];
-            if constexpr (BC) Bi[b_row][b_col + c] = rb_i[c];
+            Ar[b][a_k + c][a_row] = ra_r[c];
+            if constexpr (AC) Ai[b][a_k + c][a_row] = ra_i[c];
+            Br[b][b_row][b_col + c] = rb_r[c];
+            if constexpr (BC) Bi[b][b_row][b_col + c] = rb_i[c];
         }
-        __syncthreads();
-        if (k0 + BK < K) gload(k0 + BK);
+    };
+    // LDS double buffer: compute on one buffer while the next K step is
+    // written into the other; one barrier per K step.
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const bool more = k0 + BK < K;
+        if (more) gload(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kl = kk + (lane >> 4);
@@ -126,15 +132,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int r = wm * 32 + i * 16 + (lane & 15);
-                ar[i] = Ar[kl][r];
-                if constexpr (AC) ai[i] = Ai[kl][r];
+                ar[i] = Ar[cur][kl][r];
+                if constexpr (AC) ai[i] = Ai[cur][kl][r];
                 else ai[i] = T(0);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int c = wn * 32 + j * 16 + (lane & 15);
-                br[j] = Br[kl][c];
-                if constexpr (BC) bi[j] = Bi[kl][c];
+                br[j] = Br[cur][kl][c];
+                if constexpr (BC) bi[j] = Bi[cur][kl][c];
                 else bi[j] = T(0);
             }
 #pragma unroll
@@ -147,6 +153,9 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
                     if constexpr (AC) acci[i][j] = Mfma<T>::op(ai[i], br[j], acci[i][j]);
                 }
         }
+        if (more) lstore(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
     // epilogue: element e of a lane is row Mfma<T>::row(lane, e), column lane % 16
     // of its 16x16 block (operands: A[lane % 16][lane / 16], B[lane / 16][lane % 16])

@@ -3,7 +3,8 @@
 // Coulombscreening; the inversion is the O(N^3) step the paper's Sections 1
 // and 7.B point to).
 //
-// Panel width 64.  Per panel: one workgroup per frequency factors the
+// Panel width 64 (inside 256-wide blocks, see getrf_impl).  Per panel: one
+// workgroup per frequency factors the
 // (n - kb) x 64 panel column by column (pivot = largest |re| + |im|, ties to
 // the lowest row), composes the 64 row exchanges into one list of
 // (destination, source) rows, and inverts the 64x64 unit-lower L11 and the
@@ -227,6 +228,290 @@ __global__ __launch_bounds__(512) void k_getf2(int n, int kb, int w, Cx<T> *A, i
     for (int idx = tid; idx < NB * NB; idx += 512) Uinv[idx] = Xs[idx / NB][idx % NB];
 }
 
+// Left-looking panel factorisation with the active rows in registers.
+// 512 threads; thread t owns panel rows i = t + 512 r (r < R), so the panel
+// height m = n - kb must be at most 512 R.  The 64 columns are processed in
+// blocks of 4: (1) the U rows of the block (rows < j0) by forward
+// substitution with the unit-lower L above it, one wave per column; (2) the
+// block's rows >= j0 loaded into registers and updated with
+// L[:, 0:j0] U[0:j0, block] (left-looking: the panel's L part is read once
+// per block instead of being rewritten after every column); (3) the block
+// factorised column by column in registers (pivot = largest |re| + |im|,
+// ties to the lowest row; row exchanges applied at once to the other panel
+// columns in memory); (4) written back.  The diagonal-block inverses and the
+// composed row exchange list are produced as in k_getf2.
+constexpr int GF_NT = 512;
+
+template <typename T, int R>
+__global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A, int64_t sA, int32_t *ipiv,
+                                                 Cx<T> *Linv, Cx<T> *Uinv, int nblk, int32_t *swp, int32_t *info) {
+    constexpr int BW = 4;
+    __shared__ Cx<T> Ts[NB][NB];
+    __shared__ Cx<T> Xs[NB][NB];
+    __shared__ Cx<T> Ux[NB][BW];
+    __shared__ Cx<T> prow[BW];
+    __shared__ Cx<T> xch[2][BW];
+    __shared__ T red_v[GF_NT / 64];
+    __shared__ int red_i[GF_NT / 64];
+    __shared__ int lpiv[NB];
+    __shared__ int piv_s, zero_s;
+    __shared__ int rows[2 * NB], cont[2 * NB];
+    __shared__ Cx<T> dinv[NB];
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    A += (int64_t)b * sA;
+    ipiv += (int64_t)b * n;
+    swp += (int64_t)b * SWP;
+    Linv += ((int64_t)b * nblk + kb / NB) * NB * NB;
+    Uinv += ((int64_t)b * nblk + kb / NB) * NB * NB;
+    const int m = n - kb;
+    Cx<T> *P = A + (int64_t)kb * n + kb;  // panel origin, row stride n
+    const Cx<T> zero{T(0), T(0)};
+
+    for (int j0 = 0; j0 < w; j0 += BW) {
+        const int bw = min(BW, w - j0);
+        // (1) U rows of the block: x_i = a_i - sum_{k<i} L_ik x_k, i < j0
+        if (j0 > 0 && wave < bw) {
+            const int c = j0 + wave;
+            Cx<T> xl = zero;  // lane k keeps x_k
+            for (int i = 0; i < j0; ++i) {
+                T pr = 0, pi = 0;
+                if (lane < i) {
+                    const Cx<T> l = P[(int64_t)i * n + lane];
+                    pr = l.re * xl.re - l.im * xl.im;
+                    pi = l.re * xl.im + l.im * xl.re;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    pr += __shfl_xor(pr, off);
+                    pi += __shfl_xor(pi, off);
+                }
+                const Cx<T> a = P[(int64_t)i * n + c];
+                const Cx<T> x{a.re - pr, a.im - pi};
+                if (lane == i) xl = x;
+                if (lane == 0) {
+                    Ux[i][wave] = x;
+                    P[(int64_t)i * n + c] = x;
+                }
+            }
+        }
+        __syncthreads();
+        // (2) rows >= j0 of the block into registers, left-looking update
+        Cx<T> a[R][BW];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = tid + GF_NT * r;
+#pragma unroll
+            for (int c = 0; c < BW; ++c) a[r][c] = zero;
+            if (i >= j0 && i < m) {
+                const Cx<T> *row = P + (int64_t)i * n;
+#pragma unroll
+                for (int c = 0; c < BW; ++c)
+                    if (c < bw) a[r][c] = row[j0 + c];
+                for (int k = 0; k < j0; ++k) {
+                    const Cx<T> l = row[k];
+#pragma unroll
+                    for (int c = 0; c < BW; ++c) {
+                        const Cx<T> u = Ux[k][c];
+                        a[r][c].re -= l.re * u.re - l.im * u.im;
+                        a[r][c].im -= l.re * u.im + l.im * u.re;
+                    }
+                }
+            }
+        }
+        // (3) factor the block column by column (c compile-time: a[][] stays in registers)
+#pragma unroll
+        for (int c = 0; c < BW; ++c) {
+            if (c >= bw) break;
+            const int j = j0 + c;
+            T best = T(-1);
+            int bi = m;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = tid + GF_NT * r;
+                if (i >= j && i < m) {
+                    const T v = fabs(a[r][c].re) + fabs(a[r][c].im);
+                    if (v > best) {
+                        best = v;
+                        bi = i;
+                    }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const T ov = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ov > best || (ov == best && oi < bi)) {
+                    best = ov;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                red_v[wave] = best;
+                red_i[wave] = bi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                T bv = red_v[0];
+                int bx = red_i[0];
+                for (int q = 1; q < GF_NT / 64; ++q)
+                    if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bx)) {
+                        bv = red_v[q];
+                        bx = red_i[q];
+                    }
+                if (bx >= m) bx = j;
+                piv_s = bx;
+                lpiv[j] = bx;
+                zero_s = (bv == T(0));
+                if (bv == T(0) && info[b] == 0) info[b] = kb + j + 1;
+            }
+            __syncthreads();
+            const int piv = piv_s;
+            // exchange rows j and piv of the block through LDS
+            if (piv != j) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = tid + GF_NT * r;
+                    if (i == j)
+#pragma unroll
+                        for (int cc = 0; cc < BW; ++cc) xch[0][cc] = a[r][cc];
+                    if (i == piv)
+#pragma unroll
+                        for (int cc = 0; cc < BW; ++cc) xch[1][cc] = a[r][cc];
+                }
+                // the other panel columns, in memory
+                if (tid < w && (tid < j0 || tid >= j0 + bw)) {
+                    Cx<T> *p1 = P + (int64_t)j * n + tid;
+                    Cx<T> *p2 = P + (int64_t)piv * n + tid;
+                    const Cx<T> t = *p1;
+                    *p1 = *p2;
+                    *p2 = t;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = tid + GF_NT * r;
+                    if (i == j)
+#pragma unroll
+                        for (int cc = 0; cc < BW; ++cc) a[r][cc] = xch[1][cc];
+                    if (i == piv)
+#pragma unroll
+                        for (int cc = 0; cc < BW; ++cc) a[r][cc] = xch[0][cc];
+                }
+            }
+            // pivot row to LDS
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (tid + GF_NT * r == j)
+#pragma unroll
+                    for (int cc = 0; cc < BW; ++cc) prow[cc] = a[r][cc];
+            __syncthreads();
+            if (!zero_s) {
+                const Cx<T> inv = crcp(prow[c]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = tid + GF_NT * r;
+                    if (i > j && i < m) {
+                        const Cx<T> l = cmul(a[r][c], inv);
+                        a[r][c] = l;
+#pragma unroll
+                        for (int cc = 0; cc < BW; ++cc)
+                            if (cc > c) {
+                                const Cx<T> u = prow[cc];
+                                a[r][cc].re -= l.re * u.re - l.im * u.im;
+                                a[r][cc].im -= l.re * u.im + l.im * u.re;
+                            }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // (4) write the block back
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = tid + GF_NT * r;
+            if (i >= j0 && i < m)
+#pragma unroll
+                for (int c = 0; c < BW; ++c)
+                    if (c < bw) P[(int64_t)i * n + j0 + c] = a[r][c];
+        }
+        __syncthreads();
+    }
+
+    if (tid < w) ipiv[kb + tid] = kb + lpiv[tid];
+    if (tid == 0) {
+        int nt = 0;
+        for (int j = 0; j < w; ++j) {
+            const int r1 = j, r2 = lpiv[j];
+            if (r1 == r2) continue;
+            int i1 = -1, i2 = -1;
+            for (int t = 0; t < nt; ++t) {
+                if (rows[t] == r1) i1 = t;
+                if (rows[t] == r2) i2 = t;
+            }
+            if (i1 < 0) {
+                rows[nt] = r1;
+                cont[nt] = r1;
+                i1 = nt++;
+            }
+            if (i2 < 0) {
+                rows[nt] = r2;
+                cont[nt] = r2;
+                i2 = nt++;
+            }
+            const int t = cont[i1];
+            cont[i1] = cont[i2];
+            cont[i2] = t;
+        }
+        swp[0] = nt;
+        for (int t = 0; t < nt; ++t) {
+            swp[1 + t] = kb + rows[t];
+            swp[1 + 2 * NB + t] = kb + cont[t];
+        }
+    }
+    for (int idx = tid; idx < NB * NB; idx += GF_NT) {
+        const int i = idx / NB, c = idx % NB;
+        Ts[i][c] = (i < w && c < w) ? P[(int64_t)i * n + c] : zero;
+        Xs[i][c] = zero;
+    }
+    __syncthreads();
+    if (tid < w) {
+        const int c = tid;
+        Xs[c][c] = Cx<T>{T(1), T(0)};
+        for (int i = c + 1; i < w; ++i) {
+            T sr = 0, si = 0;
+            for (int k = c; k < i; ++k) {
+                const Cx<T> l = Ts[i][k], x = Xs[k][c];
+                sr += l.re * x.re - l.im * x.im;
+                si += l.re * x.im + l.im * x.re;
+            }
+            Xs[i][c] = Cx<T>{-sr, -si};
+        }
+    }
+    if (tid < w) dinv[tid] = crcp(Ts[tid][tid]);
+    __syncthreads();
+    for (int idx = tid; idx < NB * NB; idx += GF_NT) {
+        Linv[idx] = Xs[idx / NB][idx % NB];
+        Xs[idx / NB][idx % NB] = zero;
+    }
+    __syncthreads();
+    if (tid < w) {
+        const int c = tid;
+        Xs[c][c] = dinv[c];
+        for (int i = c - 1; i >= 0; --i) {
+            T sr = 0, si = 0;
+            for (int k = i + 1; k <= c; ++k) {
+                const Cx<T> u = Ts[i][k], x = Xs[k][c];
+                sr += u.re * x.re - u.im * x.im;
+                si += u.re * x.im + u.im * x.re;
+            }
+            const Cx<T> d = dinv[i];
+            Xs[i][c] = Cx<T>{-(sr * d.re - si * d.im), -(sr * d.im + si * d.re)};
+        }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NB * NB; idx += GF_NT) Uinv[idx] = Xs[idx / NB][idx % NB];
+}
+
 // Apply a panel's composed row exchanges to columns [0, kb) and [kb+w, n).
 // Workgroup = 32 columns; all source rows are staged in LDS before any write.
 template <typename T>
@@ -395,30 +680,84 @@ hipError_t gemm_t<float>(hipStream_t st, int M, int N, int K, float alpha, const
                         sC, batch);
 }
 
+// Two-level blocking: 64-wide panels inside 256-wide blocks.  Inside a block
+// each panel updates only the block's remaining columns (narrow GEMMs); the
+// block then computes its U12 rows and updates the trailing matrix with one
+// rank-256 GEMM, so the large updates stream the trailing matrix a quarter as
+// often as rank-64 updates would.  Row exchanges of every panel are applied at
+// once to all columns outside the panel (the columns right of the block have
+// received no update from this block yet, so the order is the same as
+// applying them all before the block's triangular solve).
+constexpr int NBO = 256;
+
 template <typename T>
 hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv, Cx<T> *Linv, Cx<T> *Uinv,
                       Cx<T> *scratch, int32_t *info, int batch) {
     const int nblk = (n + NB - 1) / NB;
+    const int64_t sI = (int64_t)nblk * NB * NB;
     int32_t *swp = (int32_t *)(scratch + (int64_t)batch * NB * n);
     hipError_t e;
-    for (int kb = 0; kb < n; kb += NB) {
-        const int w = min(NB, n - kb);
-        hipLaunchKernelGGL(k_getf2<T>, dim3(batch), dim3(512), 0, st, n, kb, w, A, sA, ipiv, Linv, Uinv, nblk, scratch,
-                           swp, info);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (n - w > 0) {
-            hipLaunchKernelGGL(k_laswp<T>, dim3((n - w + 31) / 32, batch), dim3(256), 0, st, n, kb, w, A, sA, swp);
+    for (int KB = 0; KB < n; KB += NBO) {
+        const int WO = min(NBO, n - KB);
+        for (int kb = KB; kb < KB + WO; kb += NB) {
+            const int w = min(NB, n - kb);
+            const int m = n - kb;
+            if (m <= 512)
+                hipLaunchKernelGGL((k_getf2r<T, 1>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                                   Uinv, nblk, swp, info);
+            else if (m <= 1024)
+                hipLaunchKernelGGL((k_getf2r<T, 2>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                                   Uinv, nblk, swp, info);
+            else if (m <= 2048)
+                hipLaunchKernelGGL((k_getf2r<T, 4>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                                   Uinv, nblk, swp, info);
+            else if (m <= 3072)
+                hipLaunchKernelGGL((k_getf2r<T, 6>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                                   Uinv, nblk, swp, info);
+            else if (m <= 4096)
+                hipLaunchKernelGGL((k_getf2r<T, 8>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                                   Uinv, nblk, swp, info);
+            else
+                hipLaunchKernelGGL(k_getf2<T>, dim3(batch), dim3(512), 0, st, n, kb, w, A, sA, ipiv, Linv, Uinv, nblk,
+                                   scratch, swp, info);
             if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (n - w > 0) {
+                hipLaunchKernelGGL(k_laswp<T>, dim3((n - w + 31) / 32, batch), dim3(256), 0, st, n, kb, w, A, sA, swp);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
+            const int rb = KB + WO - kb - w;  // columns of this block right of the panel
+            if (rb > 0) {
+                const Cx<T> *Lb = Linv + (int64_t)(kb / NB) * NB * NB;
+                Cx<T> *A12 = A + (int64_t)kb * n + kb + w;
+                e = gemm_t<T>(st, w, rb, w, T(1), Lb, NB, sI, A12, n, sA, T(0), A12, n, sA, batch);
+                if (e != hipSuccess) return e;
+                if (n - kb - w > 0) {
+                    e = gemm_t<T>(st, n - kb - w, rb, w, T(-1), A + (int64_t)(kb + w) * n + kb, n, sA, A12, n, sA, T(1),
+                                  A + (int64_t)(kb + w) * n + kb + w, n, sA, batch);
+                    if (e != hipSuccess) return e;
+                }
+            }
         }
-        const int rest = n - kb - w;
+        const int rest = n - KB - WO;
         if (rest > 0) {
-            const Cx<T> *Lb = Linv + (int64_t)(kb / NB) * NB * NB;
-            Cx<T> *A12 = A + (int64_t)kb * n + kb + w;
-            e = gemm_t<T>(st, w, rest, w, T(1), Lb, NB, (int64_t)nblk * NB * NB, A12, n, sA, T(0), A12, n, sA, batch);
-            if (e != hipSuccess) return e;
-            const Cx<T> *L21 = A + (int64_t)(kb + w) * n + kb;
-            Cx<T> *A22 = A + (int64_t)(kb + w) * n + kb + w;
-            e = gemm_t<T>(st, rest, rest, w, T(-1), L21, n, sA, A12, n, sA, T(1), A22, n, sA, batch);
+            // U12 rows of the block: blocked forward substitution over its panels
+            for (int kb = KB; kb < KB + WO; kb += NB) {
+                const int w = min(NB, n - kb);
+                Cx<T> *Ak = A + (int64_t)kb * n + KB + WO;
+                e = gemm_t<T>(st, w, rest, w, T(1), Linv + (int64_t)(kb / NB) * NB * NB, NB, sI, Ak, n, sA, T(0), Ak,
+                              n, sA, batch);
+                if (e != hipSuccess) return e;
+                const int r2 = KB + WO - kb - w;
+                if (r2 > 0) {
+                    e = gemm_t<T>(st, r2, rest, w, T(-1), A + (int64_t)(kb + w) * n + kb, n, sA, Ak, n, sA, T(1),
+                                  A + (int64_t)(kb + w) * n + KB + WO, n, sA, batch);
+                    if (e != hipSuccess) return e;
+                }
+            }
+            // trailing update, rank WO
+            e = gemm_t<T>(st, rest, rest, WO, T(-1), A + (int64_t)(KB + WO) * n + KB, n, sA,
+                          A + (int64_t)KB * n + KB + WO, n, sA, T(1), A + (int64_t)(KB + WO) * n + KB + WO, n, sA,
+                          batch);
             if (e != hipSuccess) return e;
         }
     }
@@ -431,27 +770,48 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
     const int nblk = (n + NB - 1) / NB;
     const int64_t sI = (int64_t)nblk * NB * NB;
     hipError_t e;
-    for (int kb = 0; kb < n; kb += NB) {
-        const int w = min(NB, n - kb);
-        Cx<T> *Bk = B + (int64_t)kb * nrhs;
-        e = gemm_t<T>(st, w, nrhs, w, T(1), Linv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk, nrhs,
-                      sB, batch);
-        if (e != hipSuccess) return e;
-        const int rest = n - kb - w;
+    // forward: L Y = P B
+    for (int KB = 0; KB < n; KB += NBO) {
+        const int WO = min(NBO, n - KB);
+        for (int kb = KB; kb < KB + WO; kb += NB) {
+            const int w = min(NB, n - kb);
+            Cx<T> *Bk = B + (int64_t)kb * nrhs;
+            e = gemm_t<T>(st, w, nrhs, w, T(1), Linv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk,
+                          nrhs, sB, batch);
+            if (e != hipSuccess) return e;
+            const int r2 = KB + WO - kb - w;
+            if (r2 > 0) {
+                e = gemm_t<T>(st, r2, nrhs, w, T(-1), LU + (int64_t)(kb + w) * n + kb, n, sA, Bk, nrhs, sB, T(1),
+                              B + (int64_t)(kb + w) * nrhs, nrhs, sB, batch);
+                if (e != hipSuccess) return e;
+            }
+        }
+        const int rest = n - KB - WO;
         if (rest > 0) {
-            e = gemm_t<T>(st, rest, nrhs, w, T(-1), LU + (int64_t)(kb + w) * n + kb, n, sA, Bk, nrhs, sB, T(1),
-                          B + (int64_t)(kb + w) * nrhs, nrhs, sB, batch);
+            e = gemm_t<T>(st, rest, nrhs, WO, T(-1), LU + (int64_t)(KB + WO) * n + KB, n, sA, B + (int64_t)KB * nrhs,
+                          nrhs, sB, T(1), B + (int64_t)(KB + WO) * nrhs, nrhs, sB, batch);
             if (e != hipSuccess) return e;
         }
     }
-    for (int kb = ((n - 1) / NB) * NB; kb >= 0; kb -= NB) {
-        const int w = min(NB, n - kb);
-        Cx<T> *Bk = B + (int64_t)kb * nrhs;
-        e = gemm_t<T>(st, w, nrhs, w, T(1), Uinv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk, nrhs,
-                      sB, batch);
-        if (e != hipSuccess) return e;
-        if (kb > 0) {
-            e = gemm_t<T>(st, kb, nrhs, w, T(-1), LU + kb, n, sA, Bk, nrhs, sB, T(1), B, nrhs, sB, batch);
+    // backward: U X = Y
+    for (int KB = ((n - 1) / NBO) * NBO; KB >= 0; KB -= NBO) {
+        const int WO = min(NBO, n - KB);
+        for (int kb = KB + ((WO - 1) / NB) * NB; kb >= KB; kb -= NB) {
+            const int w = min(NB, n - kb);
+            Cx<T> *Bk = B + (int64_t)kb * nrhs;
+            e = gemm_t<T>(st, w, nrhs, w, T(1), Uinv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk,
+                          nrhs, sB, batch);
+            if (e != hipSuccess) return e;
+            const int r2 = kb - KB;
+            if (r2 > 0) {
+                e = gemm_t<T>(st, r2, nrhs, w, T(-1), LU + (int64_t)KB * n + kb, n, sA, Bk, nrhs, sB, T(1),
+                              B + (int64_t)KB * nrhs, nrhs, sB, batch);
+                if (e != hipSuccess) return e;
+            }
+        }
+        if (KB > 0) {
+            e = gemm_t<T>(st, KB, nrhs, WO, T(-1), LU + KB, n, sA, B + (int64_t)KB * nrhs, nrhs, sB, T(1), B, nrhs, sB,
+                          batch);
             if (e != hipSuccess) return e;
         }
     }
