@@ -5,9 +5,10 @@
 //
 // Complex numbers are interleaved {re, im}.  A complex product is four real
 // MFMA products (no 3M trick: the FP64 residual must keep its accuracy).
-// Tile: 64x64 outputs per 256-thread workgroup, four 64-wide waves in 2x2,
-// each wave 32x32 = 2x2 MFMA 16x16 blocks; K staged through a double-buffered
-// LDS tile in steps of 16, the next step prefetched into registers.
+// Tiles: 256-thread workgroups, four 64-wide waves in 2x2; 64x64 outputs
+// (each wave 2x2 MFMA 16x16 blocks, K steps of 16) or 128x64 (4x2 blocks per
+// wave, K steps of 8).  K is staged through a double-buffered LDS tile, the
+// next step prefetched into registers.
 #include "gw_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -37,18 +38,23 @@ struct Mfma<float> {
     static __device__ inline int row(int lane, int e) { return 4 * (lane >> 4) + e; }
 };
 
-constexpr int BM = 64, BN = 64, BK = 16;
-
 // C = alpha * A * B + beta * C (+ identity on the real diagonal if add_eye).
 // AC/BC: A/B complex (else real).  C is complex unless both are real.
 // Optional C32: a complex-float copy of the result (same ld).
-template <typename T, bool AC, bool BC>
+// Workgroup = 256 threads = 2x2 waves; a wave owns WM x WN MFMA blocks of
+// 16x16, so the workgroup tile is (32 WM) x (32 WN); K advances BK per
+// LDS stage.
+template <typename T, bool AC, bool BC, int WM, int WN, int BK>
 __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
                                                  int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
                                                  T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
                                                  int64_t sC32) {
+    constexpr int BM = 32 * WM, BN = 32 * WN;
     constexpr bool CC = AC || BC;
     constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = CC ? 2 : 1;
+    constexpr int EA = BM * BK / 256, TPRA = BK / EA;  // elements per thread, threads per row (A)
+    constexpr int EB = BK * BN / 256, TPRB = BN / EB;  // (B)
+    static_assert(EA >= 1 && EB >= 1 && TPRA >= 1 && TPRB >= 1, "tile too small");
     typedef typename Mfma<T>::v4 v4;
     __shared__ T Ar[2][BK][BM];
     __shared__ T Ai[2][AC ? BK : 1][AC ? BM : 1];
@@ -64,54 +70,79 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    v4 accr[2][2], acci[2][2];
+    v4 accr[WM][WN], acci[WM][WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < WN; ++j) {
             accr[i][j] = v4{0, 0, 0, 0};
             acci[i][j] = v4{0, 0, 0, 0};
         }
 
-    // global -> register staging: A tile BM x BK (4 per thread), B tile BK x BN (4 per thread)
-    const int a_row = tid >> 2, a_k = (tid & 3) * 4;
-    const int b_row = tid >> 4, b_col = (tid & 15) * 4;
-    T ra_r[4], ra_i[4], rb_r[4], rb_i[4];
+    const int a_row = tid / TPRA, a_k = (tid % TPRA) * EA;
+    const int b_row = tid / TPRB, b_col = (tid % TPRB) * EB;
+    T ra_r[EA], ra_i[EA], rb_r[EB], rb_i[EB];
+    // interior tiles take an unpredicated path
+    const bool rows_in = m0 + BM <= M;
+    const bool cols_in = n0 + BN <= N;
     auto gload = [&](int k0) {
         const int gr = m0 + a_row;
+        if (rows_in && k0 + BK <= K) {
+            const T *p = A + ((int64_t)gr * lda + k0 + a_k) * ea;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int gk = k0 + a_k + c;
-            if (gr < M && gk < K) {
-                const T *p = A + ((int64_t)gr * lda + gk) * ea;
-                ra_r[c] = p[0];
-                if constexpr (AC) ra_i[c] = p[1];
+            for (int c = 0; c < EA; ++c) {
+                ra_r[c] = p[c * ea];
+                if constexpr (AC) ra_i[c] = p[c * ea + 1];
                 else ra_i[c] = T(0);
-            } else {
-                ra_r[c] = T(0);
-                ra_i[c] = T(0);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < EA; ++c) {
+                const int gk = k0 + a_k + c;
+                if (gr < M && gk < K) {
+                    const T *p = A + ((int64_t)gr * lda + gk) * ea;
+                    ra_r[c] = p[0];
+                    if constexpr (AC) ra_i[c] = p[1];
+                    else ra_i[c] = T(0);
+                } else {
+                    ra_r[c] = T(0);
+                    ra_i[c] = T(0);
+                }
             }
         }
         const int gk = k0 + b_row;
+        if (cols_in && gk < K) {
+            const T *p = B + ((int64_t)gk * ldb + n0 + b_col) * eb;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int gc = n0 + b_col + c;
-            if (gk < K && gc < N) {
-                const T *p = B + ((int64_t)gk * ldb + gc) * eb;
-                rb_r[c] = p[0];
-                if constexpr (BC) rb_i[c] = p[1];
+            for (int c = 0; c < EB; ++c) {
+                rb_r[c] = p[c * eb];
+                if constexpr (BC) rb_i[c] = p[c * eb + 1];
                 else rb_i[c] = T(0);
-            } else {
-                rb_r[c] = T(0);
-                rb_i[c] = T(0);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < EB; ++c) {
+                const int gc = n0 + b_col + c;
+                if (gk < K && gc < N) {
+                    const T *p = B + ((int64_t)gk * ldb + gc) * eb;
+                    rb_r[c] = p[0];
+                    if constexpr (BC) rb_i[c] = p[1];
+                    else rb_i[c] = T(0);
+                } else {
+                    rb_r[c] = T(0);
+                    rb_i[c] = T(0);
+                }
             }
         }
     };
     auto lstore = [&](int b) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < EA; ++c) {
             Ar[b][a_k + c][a_row] = ra_r[c];
             if constexpr (AC) Ai[b][a_k + c][a_row] = ra_i[c];
+        }
+#pragma unroll
+        for (int c = 0; c < EB; ++c) {
             Br[b][b_row][b_col + c] = rb_r[c];
             if constexpr (BC) Bi[b][b_row][b_col + c] = rb_i[c];
         }
@@ -128,30 +159,39 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kl = kk + (lane >> 4);
-            T ar[2], ai[2], br[2], bi[2];
+            T ar[WM], ai[WM], br[WN], bi[WN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int r = wm * 32 + i * 16 + (lane & 15);
+            for (int i = 0; i < WM; ++i) {
+                const int r = wm * 16 * WM + i * 16 + (lane & 15);
                 ar[i] = Ar[cur][kl][r];
                 if constexpr (AC) ai[i] = Ai[cur][kl][r];
                 else ai[i] = T(0);
             }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int c = wn * 32 + j * 16 + (lane & 15);
+            for (int j = 0; j < WN; ++j) {
+                const int c = wn * 16 * WN + j * 16 + (lane & 15);
                 br[j] = Br[cur][kl][c];
                 if constexpr (BC) bi[j] = Bi[cur][kl][c];
                 else bi[j] = T(0);
             }
+            // two passes so that no MFMA waits on the one issued just before it
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < WN; ++j) {
                     accr[i][j] = Mfma<T>::op(ar[i], br[j], accr[i][j]);
-                    if constexpr (AC && BC) accr[i][j] = Mfma<T>::op(-ai[i], bi[j], accr[i][j]);
                     if constexpr (BC) acci[i][j] = Mfma<T>::op(ar[i], bi[j], acci[i][j]);
-                    if constexpr (AC) acci[i][j] = Mfma<T>::op(ai[i], br[j], acci[i][j]);
+                    else if constexpr (AC) acci[i][j] = Mfma<T>::op(ai[i], br[j], acci[i][j]);
                 }
+            if constexpr (AC && BC) {
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) {
+                        accr[i][j] = Mfma<T>::op(-ai[i], bi[j], accr[i][j]);
+                        acci[i][j] = Mfma<T>::op(ai[i], br[j], acci[i][j]);
+                    }
+            }
         }
         if (more) lstore(cur ^ 1);
         __syncthreads();
@@ -160,13 +200,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
     // epilogue: element e of a lane is row Mfma<T>::row(lane, e), column lane % 16
     // of its 16x16 block (operands: A[lane % 16][lane / 16], B[lane / 16][lane % 16])
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < WN; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm * 32 + i * 16 + Mfma<T>::row(lane, e);
-                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                const int row = m0 + wm * 16 * WM + i * 16 + Mfma<T>::row(lane, e);
+                const int col = n0 + wn * 16 * WN + j * 16 + (lane & 15);
                 if (row < M && col < N) {
                     T *pc = C + ((int64_t)row * ldc + col) * ec;
                     T vr = alpha * accr[i][j][e];
@@ -201,14 +241,24 @@ __global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *
     if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
 }
 
+int g_gemm_tile = -1;  // < 0: choose by shape; 0: 64x64; 1: 128x64 (for measurements)
+
 template <typename T, bool AC, bool BC>
 hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *A, int64_t lda, int64_t sA,
                          const T *B, int64_t ldb, int64_t sB, T beta, T *C, int64_t ldc, int64_t sC, int batch,
                          int add_eye = 0, float *C32 = nullptr, int64_t sC32 = 0) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
-    hipLaunchKernelGGL((k_gemm<T, AC, BC>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C,
-                       ldc, sC, add_eye, C32, sC32);
+    int tile = g_gemm_tile;
+    if (tile < 0) tile = (AC && BC && M >= 128 && K >= 64) ? 1 : 0;
+    if (tile == 1) {
+        dim3 grid((N + 63) / 64, (M + 127) / 128, batch);
+        hipLaunchKernelGGL((k_gemm<T, AC, BC, 4, 2, 8>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb,
+                           sB, beta, C, ldc, sC, add_eye, C32, sC32);
+    } else {
+        dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+        hipLaunchKernelGGL((k_gemm<T, AC, BC, 2, 2, 16>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb,
+                           sB, beta, C, ldc, sC, add_eye, C32, sC32);
+    }
     return hipGetLastError();
 }
 
@@ -268,3 +318,5 @@ hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const
 }
 
 }  // namespace gwk
+
+extern "C" void gwk_set_gemm_tile(int t) { gwk::g_gemm_tile = t; }
