@@ -89,7 +89,7 @@ typedef struct {
 
 /* Frequency mesh (Section 5, 5.B): omega_j = omega_min + j*domega,
  * j = 0..n_omega-1, domega = (omega_max - omega_min)/n_omega.  Requirements:
- * n_omega a power of two in [16, 8192]; omega_min = -omega_max (a window
+ * n_omega a power of two in [16, 2048]; omega_min = -omega_max (a window
  * symmetric about the Fermi level); domega an exact power of two; eps > 0.
  * frac_bits < 0 picks the fixed-point exponent s from the data (the largest
  * that provably cannot overflow); frac_bits >= 0 asks for that s, lowered to
@@ -111,8 +111,7 @@ typedef struct {
     double max_rel_update;    /* largest final ||dW||_F / ||W||_F over frequencies */
 } gw_report;
 
-/* Sizes the caller needs before gw_build_chi0.  m: HOST copy of the scalar
- * fields plus HOST pointers for eig (the other pointers are not read). */
+/* Sizes the caller needs before gw_build_chi0 (filled by gw_query_sizes). */
 typedef struct {
     int64_t n_pairs;          /* n_occ * (n_orb - n_occ) */
     int32_t n_hbins;          /* bins stored per entry */
@@ -161,8 +160,8 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g,
  * factorised; W(omega_{n-j}) = conj W(omega_j) fills the rest (retarded
  * response, exact on the symmetric mesh).
  *   v: DEVICE, [n][n] symmetric (v_is_diag = 0) or the [n] diagonal of a
- *      diagonal metric (v_is_diag = 1; the compressed solve passes the kept
- *      eigenvalues Lambda_k, giving X = (1 - Lambda chi_hat)^{-1} Lambda).
+ *      diagonal metric (v_is_diag = 1).  For the compressed solve pass the
+ *      metric S from gw_compress_basis and chi_hat from gw_build_chi0.
  *   chi0: DEVICE complex128 [n_omega][n][n] (e.g. from gw_build_chi0).
  *   prec: GW_FP64, or a mixed form refined with an FP64 residual
  *      r = v - (1 - v chi0) W until ||dW||_F <= tol ||W||_F (at most 6
@@ -175,14 +174,23 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
                      const void *chi0, int32_t n_omega, gw_precision prec, double tol,
                      void *stream, void *W_out, gw_report *rep);
 
-/* Section 7.B subspace: the k eigenvectors of v with the largest eigenvalues.
- *   v: DEVICE [n][n] symmetric.  U_out: DEVICE [n][k] (columns = eigenvectors,
- *   eigenvalues descending), lambda_out: DEVICE [k].  Synchronous. */
+/* Section 7.B subspace: an orthonormal basis Q of the k-dimensional dominant
+ * eigenspace of v (the span of its top-k eigenvectors; shifted subspace
+ * iteration, 4 steps) and the metric in that basis, S = Q^T v Q.  The
+ * compressed interaction depends only on that subspace:
+ *   chi_hat = Q^T chi0 Q              (gw_build_chi0 with basis = Q)
+ *   X = (1 - S chi_hat)^{-1} S        (gw_solve_W with v = S, v_is_diag = 0)
+ *   W = Q X Q^T                       (gw_decompress)
+ * which is the paper's W = v + Z chi_RPA Z of eq. chi_RPA with v replaced by
+ * its rank-k projection.
+ *   v: DEVICE [n][n] symmetric.  Q_out: DEVICE [n][k].  S_out: DEVICE [k][k].
+ * Synchronous.  GW_E_NOCONV if the iteration lost a direction (non-finite v). */
 gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream,
-                            double *U_out, double *lambda_out);
+                            double *Q_out, double *S_out);
 
-/* Decompress one frequency: W = U X U^T (Section 8.B, decompression on the fly).
- *   U: DEVICE [n][k]; X: DEVICE complex128 [k][k]; W_out: DEVICE complex128 [n][n]. */
+/* Decompress one frequency: W = Q X Q^T (Section 8.B, decompression on the fly).
+ *   U: DEVICE [n][k] (the basis Q); X: DEVICE complex128 [k][k];
+ *   W_out: DEVICE complex128 [n][n]. */
 gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X,
                         void *stream, void *W_out);
 
@@ -191,7 +199,8 @@ gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, cons
  * admitted when its estimated HBM footprint fits; its chi0 and W stay on the
  * device, owned by the library, until gw_release.
  *   k_compress: 0 for the full basis, else the rank of the top-k compression
- *   (W_dev then holds X [n_omega][k][k] followed by U_k [n][k] doubles).
+ *   (W_dev then holds X [n_omega][k][k] complex128 followed by Q [n][k]
+ *   doubles, W = Q X Q^T).
  *   v: DEVICE [n_prod][n_prod] Coulomb metric of the molecule. */
 gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
                     int32_t k_compress, gw_precision prec, double tol, uint64_t *ticket);

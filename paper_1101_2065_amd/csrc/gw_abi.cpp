@@ -31,6 +31,8 @@ hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const
                         int batch);
 hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *src, double *dst);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
+hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double *Q_out, double *S_out, double *work,
+                          int iters);
 hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
                                 zflt *dst, int64_t sD, int batch);
 hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch);
@@ -514,11 +516,20 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     return GW_OK;
 }
 
-gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream, double *U_out,
-                            double *lambda_out) {
+gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream, double *Q_out,
+                            double *S_out) {
     if (!ctx) return GW_E_INVALID;
-    (void)v; (void)n; (void)k; (void)stream; (void)U_out; (void)lambda_out;
-    return fail(ctx, GW_E_STATE, "gw_compress_basis is not available in this build");
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    if (!v || !Q_out || !S_out || n < 1 || k < 1 || k > n) return fail(ctx, GW_E_INVALID, "bad compress arguments");
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    void *work;
+    gw_status s;
+    if ((s = ws(ctx, "cWork", sizeof(double) * (3 * (size_t)k * n + k + 16), &work)) != GW_OK) return s;
+    hipError_t e = gwk::compress_basis(st, n, k, v, Q_out, S_out, (double *)work, 4);
+    if (e == hipErrorUnknown) return fail(ctx, GW_E_NOCONV, "subspace iteration lost a direction (v not finite?)");
+    GW_HIP(ctx, e);
+    return GW_OK;
 }
 
 gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X, void *stream, void *W_out) {

@@ -162,8 +162,8 @@ class Context:
         self._check(st, "gw_solve_W")
         return rep
 
-    def compress_basis(self, v, n: int, k: int, U_out, lam_out, stream=None):
-        st = lib.gw_compress_basis(self.h, _ptr(v), n, k, _stream_handle(stream), _ptr(U_out), _ptr(lam_out))
+    def compress_basis(self, v, n: int, k: int, Q_out, S_out, stream=None):
+        st = lib.gw_compress_basis(self.h, _ptr(v), n, k, _stream_handle(stream), _ptr(Q_out), _ptr(S_out))
         self._check(st, "gw_compress_basis")
 
     def decompress(self, U, n: int, k: int, X, W_out, stream=None):
