@@ -31,8 +31,6 @@ hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const
                         int batch);
 hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *src, double *dst);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
-hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double *Q_out, double *S_out, double *work,
-                          int iters);
 hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
                                 zflt *dst, int64_t sD, int batch);
 hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch);
@@ -41,21 +39,7 @@ hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per,
 using gwk::zdbl;
 using gwk::zflt;
 
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-};
-
-struct gw_ctx {
-    int device = 0;
-    size_t budget = 0;
-    std::string err;
-    bool sticky = false;
-    std::map<std::string, DevBuf> bufs;
-    // cached Cauchy-kernel spectrum
-    int ks_n = 0;
-    double ks_min = 0, ks_d = 0, ks_eps = 0;
-};
+#include "gw_ctx.h"
 
 namespace {
 
@@ -81,7 +65,9 @@ gw_status ws(gw_ctx *c, const char *name, size_t bytes, void **out) {
     if (bytes == 0) bytes = 256;
     if (b.bytes < bytes) {
         if (b.ptr) {
-            GW_HIP(c, hipDeviceSynchronize());
+            // a serving slot's context only ever uses its own stream
+            if (c->own_stream) GW_HIP(c, hipStreamSynchronize(c->own_stream));
+            else GW_HIP(c, hipDeviceSynchronize());
             GW_HIP(c, hipFree(b.ptr));
             b.ptr = nullptr;
             b.bytes = 0;
@@ -165,7 +151,8 @@ gw_status check_molecule(gw_ctx *c, const gw_molecule *m, hipStream_t st, HostMo
     const int n_idx = h->blk_orb[m->n_blk];
     if (n_idx < 1) return fail(c, GW_E_INVALID, "empty orbital index");
     h->orb_idx.resize(n_idx);
-    GW_HIP(c, hipMemcpy(h->orb_idx.data(), m->orb_idx, sizeof(int32_t) * n_idx, hipMemcpyDeviceToHost));
+    GW_HIP(c, hipMemcpyAsync(h->orb_idx.data(), m->orb_idx, sizeof(int32_t) * n_idx, hipMemcpyDeviceToHost, st));
+    GW_HIP(c, hipStreamSynchronize(st));
     for (int b = 0; b < m->n_blk; ++b) {
         const int np = h->blk_prod[b + 1] - h->blk_prod[b];
         const int no = h->blk_orb[b + 1] - h->blk_orb[b];
@@ -200,6 +187,9 @@ struct SolveWs {
     double *norms = nullptr;
 };
 
+size_t per_freq_bytes(int n, bool mixed);
+int solve_batch_max(int n, int n_omega, bool mixed, size_t budget);
+
 size_t per_freq_bytes(int n, bool mixed) {
     const size_t nn = (size_t)n * n;
     const int nblk = (n + 63) / 64;
@@ -209,6 +199,17 @@ size_t per_freq_bytes(int n, bool mixed) {
     b += 3 * (size_t)n * 4;                                // ipiv, perm
     if (mixed) b += nn * 8 * 2 + nn * 16 + (size_t)64 * n * 8 + 2 * (size_t)nblk * 64 * 64 * 8;
     return b;
+}
+
+int solve_batch_max(int n, int n_omega, bool mixed, size_t budget) {
+    const size_t pf = per_freq_bytes(n, mixed);
+    int nb = (int)std::max<size_t>(1, std::min<size_t>(budget / 2 / pf, 256));
+    return std::max(1, std::min(nb, n_omega / 2));
+}
+
+// bytes gw_solve_W allocates for a problem of this size
+size_t solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) {
+    return (size_t)solve_batch_max(n, n_omega, mixed, budget) * per_freq_bytes(n, mixed) + 4096;
 }
 
 gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
@@ -301,6 +302,7 @@ gw_status gw_create(int device, size_t hbm_budget_bytes, gw_ctx **out) {
 
 gw_status gw_destroy(gw_ctx *ctx) {
     if (!ctx) return GW_E_INVALID;
+    gwk_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     for (auto &kv : ctx->bufs)
@@ -350,17 +352,30 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, con
     const int L = 2 * g->n_omega;
 
     void *P, *Pt = nullptr, *Ps, *lo, *rowoff, *binoff, *perm, *fsort, *stat, *vmax, *sdev, *Kt, *tw, *H;
-    if ((s = ws(ctx, "P", sizeof(double) * n_prod * n_pairs, &P)) != GW_OK) return s;
+    const int n_virt = n_orb - n_occ;
     if (basis) {
+        // Compress as soon as formed (Section 8.A): pair vectors for a range of
+        // occupied states at a time, projected onto the basis, so the full
+        // N_prod x N_pairs matrix never has to exist.
+        const int64_t cap = std::max<int64_t>(1, (int64_t)(2ll << 30) / (8ll * n_prod * n_virt));
+        const int echunk = (int)std::min<int64_t>(n_occ, cap);
         void *bt;
+        if ((s = ws(ctx, "P", sizeof(double) * n_prod * (int64_t)echunk * n_virt, &P)) != GW_OK) return s;
         if ((s = ws(ctx, "Pt", sizeof(double) * rows * n_pairs, &Pt)) != GW_OK) return s;
         if ((s = ws(ctx, "basisT", sizeof(double) * (int64_t)k * n_prod, &bt)) != GW_OK) return s;
-        GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb, m->orb_idx,
-                                        m->blk_val, m->vals, h.max_o, (double *)P));
         GW_HIP(ctx, gwk::launch_transpose_d(st, n_prod, k, basis, (double *)bt));
-        // Pt[k][pairs] = basis^T P (Section 8.A: compress as soon as formed)
-        GW_HIP(ctx, gwk::launch_dgemm(st, k, (int)n_pairs, n_prod, 1.0, (const double *)bt, n_prod, 0,
-                                      (const double *)P, n_pairs, 0, 0.0, (double *)Pt, n_pairs, 0, 1));
+        for (int e0 = 0; e0 < n_occ; e0 += echunk) {
+            const int ec = std::min(echunk, n_occ - e0);
+            const int64_t cw = (int64_t)ec * n_virt;
+            GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb,
+                                            m->orb_idx, m->blk_val, m->vals, h.max_o, e0, ec, cw, (double *)P));
+            // Pt[:, chunk] = basis^T P_chunk
+            GW_HIP(ctx, gwk::launch_dgemm(st, k, (int)cw, n_prod, 1.0, (const double *)bt, n_prod, 0,
+                                          (const double *)P, cw, 0, 0.0, (double *)Pt + (int64_t)e0 * n_virt, n_pairs,
+                                          0, 1));
+        }
+    } else {
+        if ((s = ws(ctx, "P", sizeof(double) * n_prod * n_pairs, &P)) != GW_OK) return s;
     }
     if ((s = ws(ctx, "Ps", sizeof(double) * rows * n_pairs, &Ps)) != GW_OK) return s;
     if ((s = ws(ctx, "lo", sizeof(int32_t) * n_occ * (nhb + 1), &lo)) != GW_OK) return s;
@@ -378,7 +393,7 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, con
 
     if (!basis)
         GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb, m->orb_idx,
-                                        m->blk_val, m->vals, h.max_o, (double *)P));
+                                        m->blk_val, m->vals, h.max_o, 0, n_occ, n_pairs, (double *)P));
     const double *Psrc = basis ? (const double *)Pt : (const double *)P;
     GW_HIP(ctx, gwk::launch_absmax(st, Psrc, (int64_t)rows * n_pairs, (uint64_t *)vmax));
     GW_HIP(ctx, gwk::launch_fracbits(st, (const uint64_t *)vmax, n_pairs, g->frac_bits, (int32_t *)sdev));
@@ -435,10 +450,7 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     const int nblk = (n + 63) / 64;
 
     // batch size from the budget (the caller's chi0/W are not counted)
-    const size_t pf = per_freq_bytes(n, mixed);
-    int nbmax = (int)std::max<size_t>(1, std::min<size_t>(ctx->budget / 2 / pf, 256));
-    const int nsolve_hi = n_omega / 2;  // j = n/2 .. n-1
-    nbmax = std::min(nbmax, nsolve_hi);
+    const int nbmax = solve_batch_max(n, n_omega, mixed, ctx->budget);
     SolveWs w;
     gw_status s;
     void *p;
@@ -550,23 +562,18 @@ gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, cons
     return GW_OK;
 }
 
-gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, int32_t k_compress,
-                    gw_precision prec, double tol, uint64_t *ticket) {
-    if (!ctx) return GW_E_INVALID;
-    (void)m; (void)v; (void)g; (void)k_compress; (void)prec; (void)tol; (void)ticket;
-    return fail(ctx, GW_E_STATE, "serving is not available in this build");
-}
-
-gw_status gw_poll(gw_ctx *ctx, uint64_t ticket, void **W_dev, gw_report *rep) {
-    if (!ctx) return GW_E_INVALID;
-    (void)ticket; (void)W_dev; (void)rep;
-    return fail(ctx, GW_E_STATE, "unknown ticket");
-}
-
-gw_status gw_release(gw_ctx *ctx, uint64_t ticket) {
-    if (!ctx) return GW_E_INVALID;
-    (void)ticket;
-    return fail(ctx, GW_E_STATE, "unknown ticket");
-}
-
 }  // extern "C"
+
+// Free every workspace buffer of a context (serving slots do this after each
+// request so that admission can count transient memory exactly).
+void gwk_ctx_trim(gw_ctx *c) {
+    if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
+    else (void)hipDeviceSynchronize();
+    for (auto &kv : c->bufs)
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    c->bufs.clear();
+    c->ks_n = 0;
+}
+
+size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) { return solve_ws_bytes(n, n_omega, mixed, budget); }
+

@@ -1,0 +1,32 @@
+// Private definition of the context behind the opaque gw_ctx handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct GwServe;  // serving state (gw_serve.cpp)
+
+struct gw_ctx {
+    int device = 0;
+    size_t budget = 0;
+    std::string err;
+    bool sticky = false;
+    std::map<std::string, DevBuf> bufs;
+    // cached Cauchy-kernel spectrum
+    int ks_n = 0;
+    double ks_min = 0, ks_d = 0, ks_eps = 0;
+    // set for the private contexts of serving slots: the only stream they use
+    hipStream_t own_stream = nullptr;
+    GwServe *serve = nullptr;
+};
+
+void gwk_ctx_trim(gw_ctx *c);
+void gwk_serve_stop(gw_ctx *c);
+size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget);

@@ -15,11 +15,12 @@ struct zflt {
 };
 
 // ---------------------------------------------------------------- chi0 build
-// Pair vertex (Section 7.A): P[mu][E*n_virt + F'] = sum_a X_a^E sum_b V_mu^{ab} X_b^{n_occ+F'}.
+// Pair vertex (Section 7.A): P[mu][(E-e0)*n_virt + F'] = sum_a X_a^E sum_b V_mu^{ab} X_b^{n_occ+F'}
+// for occupied E in [e0, e0+ecnt); rows of P are ldp apart.
 hipError_t launch_pairvec(hipStream_t st, int n_orb, int n_occ, int n_prod, int n_blk,
                           const double *X, const int32_t *blk_prod, const int32_t *blk_orb,
                           const int32_t *orb_idx, const int64_t *blk_val, const double *vals,
-                          int max_o, double *P);
+                          int max_o, int e0, int ecnt, int64_t ldp, double *P);
 
 // Pair bins on the mesh and the bin-sorted pair order (Sections 5, 5.A).
 // lo: [n_occ][nhb+1] int32, rowoff: [n_occ][nhb] int32, binoff: [nhb] int32,
@@ -102,9 +103,9 @@ hipError_t launch_residual(hipStream_t st, int n, const double *v, int v_is_diag
                            const zdbl *A, int64_t sA, const zdbl *W, int64_t sW,
                            zdbl *R, int64_t sR, int batch);
 
-// Symmetric eigen-decomposition (one-sided Jacobi on the GPU), used for the
-// compression basis.
-hipError_t eig_topk(hipStream_t st, int n, int k, const double *v, double *U_out,
-                    double *lam_out, double *work);
+// Orthonormal basis Q [n][k] of the dominant k-dimensional eigenspace of v and
+// S = Q^T v Q [k][k] (shifted subspace iteration); work: 3 k n + k + 16 doubles.
+hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double *Q_out, double *S_out,
+                          double *work, int iters);
 
 }  // namespace gwk

@@ -1,0 +1,313 @@
+// Serving: continuous batching of molecule solves on one GPU.
+//
+// gw_submit queues a request and returns a ticket at once.  A fixed number of
+// slots (GW_SERVE_SLOTS, default 2) each own a host thread, a HIP stream and a
+// private context.  A free slot admits the request at the head of the queue
+// as soon as its estimated HBM footprint (transient workspace + results) fits
+// under the context's budget; admitted requests run concurrently on their
+// slots' streams, so work of different molecules overlaps on the device.
+// After a request finishes, its transient workspace is freed and only the
+// results stay resident (chi0 and W, plus the compression basis) until
+// gw_release.  Requests are admitted in arrival order.
+#include "../../include/gw.h"
+#include "gw_ctx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstdlib>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+enum ReqState { Q_QUEUED, Q_RUNNING, Q_DONE, Q_FAILED };
+
+struct ServeReq {
+    uint64_t ticket = 0;
+    gw_molecule mol{};
+    const double *v = nullptr;
+    gw_grid grid{};
+    int k = 0, kk = 0;
+    gw_precision prec = GW_FP64;
+    double tol = 1e-7;
+    size_t bytes_result = 0, bytes_peak = 0;
+    ReqState state = Q_QUEUED;
+    void *chi = nullptr, *res = nullptr, *Q = nullptr, *S = nullptr;
+    gw_report rep{};
+    gw_status status = GW_OK;
+    std::string err;
+};
+
+}  // namespace
+
+struct GwServe {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, std::unique_ptr<ServeReq>> reqs;
+    size_t budget = 0, in_use = 0;
+    size_t slot_ws_budget = 0;
+    std::vector<std::thread> workers;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    int device = 0;
+};
+
+namespace {
+
+size_t est_transient(const gw_molecule &m, int k, int n_omega, gw_precision prec, size_t slot_budget) {
+    const size_t n_prod = m.n_prod, n_occ = m.n_occ, n_virt = m.n_orb - m.n_occ;
+    const size_t n_pairs = n_occ * n_virt;
+    const size_t kk = k ? (size_t)k : n_prod;
+    const size_t nhb = n_omega / 2;
+    size_t b = 0;
+    if (k) {
+        const size_t chunk_rows = std::max<size_t>(1, (size_t)(2ull << 30) / (8 * n_prod * n_virt));
+        b += 8 * n_prod * std::min(n_occ, chunk_rows) * n_virt;  // pair-vector chunk
+        b += 8 * kk * n_pairs;                                   // projected pair vectors
+        b += 8 * (size_t)k * n_prod;                             // basis transpose
+        b += 8 * (3 * (size_t)k * n_prod + k + 16);              // basis iteration
+    } else {
+        b += 8 * n_prod * n_pairs;
+    }
+    b += 8 * kk * n_pairs;                                       // bin-sorted pair vectors
+    b += 4 * n_occ * (2 * nhb + 1) + 4 * nhb + 12 * n_pairs + 4096;
+    b += 8 * nhb * kk * (kk + 1) / 2;                            // histogram
+    b += 2 * 16 * 2 * (size_t)n_omega;                           // kernel spectrum, twiddles
+    b += gwk_solve_ws_bytes((int)kk, n_omega, prec != GW_FP64, slot_budget);
+    return b + (64ull << 20);
+}
+
+void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e == hipSuccess) return true;
+        r.status = e == hipErrorOutOfMemory ? GW_E_OOM : GW_E_DEVICE;
+        r.err = std::string(what) + ": " + hipGetErrorString(e);
+        return false;
+    };
+    const size_t nn = (size_t)r.kk * r.kk;
+    const size_t n = r.mol.n_prod;
+    if (r.k) {
+        if (!hip_ok(hipMalloc(&r.Q, 8 * n * r.k), "basis")) return;
+        if (!hip_ok(hipMalloc(&r.S, 8 * (size_t)r.k * r.k), "metric")) return;
+        gw_status s = gw_compress_basis(child, r.v, (int)n, r.k, st, (double *)r.Q, (double *)r.S);
+        if (s != GW_OK) {
+            r.status = s;
+            r.err = gw_last_error(child);
+            return;
+        }
+    }
+    if (!hip_ok(hipMalloc(&r.chi, 16 * nn * r.grid.n_omega), "chi0")) return;
+    const size_t res_bytes = 16 * nn * r.grid.n_omega + (r.k ? 8 * n * r.k : 0);
+    if (!hip_ok(hipMalloc(&r.res, res_bytes), "W")) return;
+    gw_report rb{}, rs{};
+    gw_status s = gw_build_chi0(child, &r.mol, &r.grid, (const double *)r.Q, r.k, st, nullptr, r.chi, &rb);
+    if (s == GW_OK)
+        s = gw_solve_W(child, r.k ? (const double *)r.S : r.v, 0, r.kk, r.chi, r.grid.n_omega, r.prec, r.tol, st,
+                       r.res, &rs);
+    if (s != GW_OK) {
+        r.status = s;
+        r.err = gw_last_error(child);
+        return;
+    }
+    if (r.k) {
+        char *tail = (char *)r.res + 16 * nn * r.grid.n_omega;
+        if (!hip_ok(hipMemcpyAsync(tail, r.Q, 8 * n * r.k, hipMemcpyDeviceToDevice, st), "copy basis")) return;
+    }
+    if (!hip_ok(hipStreamSynchronize(st), "stream")) return;
+    r.rep = rs;
+    r.rep.n_hbins = rb.n_hbins;
+    r.rep.frac_bits_used = rb.frac_bits_used;
+    r.rep.n_dropped_pairs = rb.n_dropped_pairs;
+}
+
+void free_results(ServeReq &r) {
+    for (void **p : {&r.chi, &r.res, &r.Q, &r.S})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+}
+
+void worker(GwServe *sv) {
+    (void)hipSetDevice(sv->device);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    gw_ctx *child = nullptr;
+    if (gw_create(sv->device, sv->slot_ws_budget, &child) != GW_OK) {
+        (void)hipStreamDestroy(st);
+        return;
+    }
+    child->own_stream = st;
+    for (;;) {
+        ServeReq *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv.wait(lk, [&] {
+                if (sv->stop) return true;
+                if (sv->queue.empty()) return false;
+                ServeReq *h = sv->reqs[sv->queue.front()].get();
+                return sv->in_use + h->bytes_peak <= sv->budget;
+            });
+            if (sv->stop) break;
+            r = sv->reqs[sv->queue.front()].get();
+            sv->queue.pop_front();
+            sv->in_use += r->bytes_peak;
+            r->state = Q_RUNNING;
+        }
+        run_request(child, st, *r);
+        gwk_ctx_trim(child);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (r->status != GW_OK) {
+                free_results(*r);
+                r->state = Q_FAILED;
+                sv->in_use -= r->bytes_peak;
+            } else {
+                r->state = Q_DONE;
+                sv->in_use -= r->bytes_peak - r->bytes_result;
+            }
+        }
+        sv->cv.notify_all();
+    }
+    gw_destroy(child);
+    (void)hipStreamDestroy(st);
+}
+
+GwServe *serve_of(gw_ctx *ctx) {
+    if (ctx->serve) return ctx->serve;
+    GwServe *sv = new GwServe();
+    sv->device = ctx->device;
+    sv->budget = ctx->budget;
+    int slots = 2;
+    if (const char *e = std::getenv("GW_SERVE_SLOTS")) slots = std::max(1, std::min(8, std::atoi(e)));
+    sv->slot_ws_budget = std::min<size_t>(32ull << 30, ctx->budget / (4 * slots));
+    for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv);
+    ctx->serve = sv;
+    return sv;
+}
+
+}  // namespace
+
+void gwk_serve_stop(gw_ctx *ctx) {
+    GwServe *sv = ctx->serve;
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv.notify_all();
+    for (auto &t : sv->workers) t.join();
+    for (auto &kv : sv->reqs) free_results(*kv.second);
+    delete sv;
+    ctx->serve = nullptr;
+}
+
+extern "C" {
+
+gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, int32_t k_compress,
+                    gw_precision prec, double tol, uint64_t *ticket) {
+    if (!ctx || !m || !v || !g || !ticket) return GW_E_INVALID;
+    if (ctx->sticky) return GW_E_DEVICE;
+    if (m->n_prod < 1 || m->n_orb < 2 || m->n_occ < 1 || m->n_occ >= m->n_orb) {
+        ctx->err = "gw_submit: bad molecule sizes";
+        return GW_E_INVALID;
+    }
+    if (k_compress < 0 || k_compress > m->n_prod) {
+        ctx->err = "gw_submit: k_compress must be in [0, n_prod]";
+        return GW_E_INVALID;
+    }
+    if (prec != GW_FP64 && prec != GW_FP32_IR) {
+        ctx->err = "gw_submit: precision not available for serving";
+        return GW_E_INVALID;
+    }
+    if (g->n_omega < 16 || g->n_omega > 2048 || (g->n_omega & (g->n_omega - 1))) {
+        ctx->err = "gw_submit: n_omega must be a power of two in [16, 2048]";
+        return GW_E_INVALID;
+    }
+    GwServe *sv = serve_of(ctx);
+    auto r = std::make_unique<ServeReq>();
+    r->mol = *m;
+    r->v = v;
+    r->grid = *g;
+    r->k = k_compress;
+    r->kk = k_compress ? k_compress : m->n_prod;
+    r->prec = prec;
+    r->tol = tol;
+    const size_t nn = (size_t)r->kk * r->kk;
+    r->bytes_result = 32 * nn * g->n_omega + (k_compress ? 16ull * m->n_prod * k_compress + 8ull * nn : 0);
+    r->bytes_peak = r->bytes_result + est_transient(*m, k_compress, g->n_omega, prec, sv->slot_ws_budget);
+    if (r->bytes_peak > sv->budget) {
+        ctx->err = "gw_submit: request needs " + std::to_string(r->bytes_peak) + " bytes, more than the budget";
+        return GW_E_OOM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        r->ticket = sv->next_ticket++;
+        *ticket = r->ticket;
+        sv->queue.push_back(r->ticket);
+        sv->reqs[r->ticket] = std::move(r);
+    }
+    sv->cv.notify_all();
+    return GW_OK;
+}
+
+gw_status gw_poll(gw_ctx *ctx, uint64_t ticket, void **W_dev, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    GwServe *sv = ctx->serve;
+    if (!sv) {
+        ctx->err = "gw_poll: unknown ticket";
+        return GW_E_STATE;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) {
+        ctx->err = "gw_poll: unknown ticket";
+        return GW_E_STATE;
+    }
+    ServeReq &r = *it->second;
+    if (r.state == Q_QUEUED || r.state == Q_RUNNING) return GW_PENDING;
+    if (r.state == Q_FAILED) {
+        ctx->err = "request " + std::to_string(ticket) + ": " + r.err;
+        return r.status;
+    }
+    if (W_dev) *W_dev = r.res;
+    if (rep) *rep = r.rep;
+    return GW_OK;
+}
+
+gw_status gw_release(gw_ctx *ctx, uint64_t ticket) {
+    if (!ctx) return GW_E_INVALID;
+    GwServe *sv = ctx->serve;
+    if (!sv) {
+        ctx->err = "gw_release: unknown ticket";
+        return GW_E_STATE;
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end()) {
+            ctx->err = "gw_release: unknown ticket";
+            return GW_E_STATE;
+        }
+        ServeReq &r = *it->second;
+        if (r.state == Q_QUEUED || r.state == Q_RUNNING) {
+            ctx->err = "gw_release: request still pending";
+            return GW_E_STATE;
+        }
+        if (r.state == Q_DONE) sv->in_use -= r.bytes_result;
+        free_results(r);
+        sv->reqs.erase(it);
+    }
+    sv->cv.notify_all();
+    return GW_OK;
+}
+
+}  // extern "C"

@@ -42,13 +42,13 @@ __global__ __launch_bounds__(128) void k_pairvec(int n_orb, int n_occ, int n_blk
                                                  const int32_t *__restrict__ blk_orb,
                                                  const int32_t *__restrict__ orb_idx,
                                                  const int64_t *__restrict__ blk_val,
-                                                 const double *__restrict__ vals, double *__restrict__ P) {
+                                                 const double *__restrict__ vals, int e0, int ecnt, int64_t ldp,
+                                                 double *__restrict__ P) {
 #pragma clang fp contract(off)
     __shared__ double Vs[NMAX * NMAX];
     __shared__ int Os[NMAX];
     const int mu = blockIdx.x;
     const int n_virt = n_orb - n_occ;
-    const int64_t n_pairs = (int64_t)n_occ * n_virt;
     // block of mu: largest b with blk_prod[b] <= mu
     int lo = 0, hi = n_blk - 1;
     while (lo < hi) {
@@ -72,8 +72,9 @@ __global__ __launch_bounds__(128) void k_pairvec(int n_orb, int n_occ, int n_blk
         for (int a = 0; a < NMAX; ++a)
             if (a < n) T[a] = __dadd_rn(T[a], __dmul_rn(Vs[a * n + bb], xb));
     }
-    double *Prow = P + (int64_t)mu * n_pairs + f;
-    for (int E = 0; E < n_occ; ++E) {
+    // occupied states e0 .. e0+ecnt-1 go to columns (E - e0) * n_virt + F' of row mu
+    double *Prow = P + (int64_t)mu * ldp + f - (int64_t)e0 * n_virt;
+    for (int E = e0; E < e0 + ecnt; ++E) {
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < NMAX; ++a)
@@ -320,18 +321,19 @@ __global__ __launch_bounds__(256) void k_hist(int n, int64_t ldp, const double *
 
 hipError_t launch_pairvec(hipStream_t st, int n_orb, int n_occ, int n_prod, int n_blk, const double *X,
                           const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
-                          const int64_t *blk_val, const double *vals, int max_o, double *P) {
+                          const int64_t *blk_val, const double *vals, int max_o, int e0, int ecnt, int64_t ldp,
+                          double *P) {
     const int n_virt = n_orb - n_occ;
     dim3 grid(n_prod, (n_virt + 127) / 128);
     if (max_o <= 16)
         hipLaunchKernelGGL(k_pairvec<16>, grid, dim3(128), 0, st, n_orb, n_occ, n_blk, X, blk_prod, blk_orb,
-                           orb_idx, blk_val, vals, P);
+                           orb_idx, blk_val, vals, e0, ecnt, ldp, P);
     else if (max_o <= 32)
         hipLaunchKernelGGL(k_pairvec<32>, grid, dim3(128), 0, st, n_orb, n_occ, n_blk, X, blk_prod, blk_orb,
-                           orb_idx, blk_val, vals, P);
+                           orb_idx, blk_val, vals, e0, ecnt, ldp, P);
     else if (max_o <= 64)
         hipLaunchKernelGGL(k_pairvec<64>, grid, dim3(128), 0, st, n_orb, n_occ, n_blk, X, blk_prod, blk_orb,
-                           orb_idx, blk_val, vals, P);
+                           orb_idx, blk_val, vals, e0, ecnt, ldp, P);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -1,0 +1,133 @@
+"""Serving (continuous batching): every result is the same whether the request
+ran alone or together with others, results stay on the device until released,
+and the error paths report the documented status codes."""
+import ctypes
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import gw_synth as gs
+import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_2065_amd.gw as gw
+
+    yield gw, torch
+
+
+def _wait(ctx, ticket, timeout=300.0):
+    t0 = time.time()
+    while True:
+        r = ctx.poll(ticket)
+        if r is not None:
+            return r
+        if time.time() - t0 > timeout:
+            raise TimeoutError("request %d not done after %.0fs" % (ticket, timeout))
+        time.sleep(0.002)
+
+
+_HIP = None
+
+
+def _fetch(gw, torch, ptr, n_omega, kk):
+    """Copy a library-owned device result (complex128 [n_omega][kk][kk]) to the host."""
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _HIP.hipMemcpy.restype = ctypes.c_int
+    out = np.empty((n_omega, kk, kk), dtype=np.complex128)
+    rc = _HIP.hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2)  # hipMemcpyDeviceToHost
+    assert rc == 0
+    return out
+
+
+def _workload():
+    grid = gs.config_grid(0)
+    mols = [
+        (gs.make_config(0), 0),
+        (gs.chain_molecule(8, 7, orb_per_atom=4, occ_per_atom=2, prod_per_atom=10, prod_per_bond=8,
+                           bond_cutoff=None), 0),
+        (gs.chain_molecule(6, 21), 0),
+        (gs.cluster_molecule(12, 9, radius=9.0), 60),
+    ]
+    return grid, mols
+
+
+def test_results_same_alone_and_in_the_mix(gpu):
+    gw, torch = gpu
+    grid, mols = _workload()
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    dms = [gw.DeviceMolecule(m) for m, _ in mols]
+    ctx = gw.Context(0)
+    # alone: one request at a time
+    alone = []
+    for (m, k), dm in zip(mols, dms):
+        _say("alone n_prod", m.n_prod, "k", k)
+        t = ctx.submit(dm.struct, dm.v, g, k_compress=k)
+        ptr, rep = _wait(ctx, t)
+        alone.append(_fetch(gw, torch, ptr, grid.n_omega, k or m.n_prod))
+        ctx.release(t)
+    # in the mix: all submitted at once, twice over
+    tickets = []
+    for rep_i in range(2):
+        for (m, k), dm in zip(mols, dms):
+            tickets.append((ctx.submit(dm.struct, dm.v, g, k_compress=k), len(tickets) % len(mols)))
+    _say("submitted", len(tickets))
+    for t, i in tickets:
+        ptr, rep = _wait(ctx, t)
+        m, k = mols[i]
+        got = _fetch(gw, torch, ptr, grid.n_omega, k or m.n_prod)
+        e = np.linalg.norm(got - alone[i]) / np.linalg.norm(alone[i])
+        _say("ticket", t, "molecule", i, "rel diff vs alone", e)
+        assert e <= 1e-12
+        ctx.release(t)
+    # and the tiny molecule against the oracle
+    m = mols[0][0]
+    P = o.pair_vectors(m)
+    mm, fr = o.pair_bins(m.eig, m.n_occ, grid.domega)
+    nhb = o.hist_bins(m.eig, grid.n_omega, grid.domega)
+    s = o.frac_bits(P, m.n_pairs)
+    H = o.histogram(P, mm, fr, s, nhb)
+    js = [grid.n_omega // 2 + 9, 40]
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps, js=js),
+                         m.n_prod)
+    for i, j in enumerate(js):
+        Wr = o.screened_W(m.v, chi[i])
+        assert np.linalg.norm(alone[0][j] - Wr) <= 1e-10 * np.linalg.norm(Wr)
+    ctx.close()
+
+
+def test_serving_error_paths(gpu):
+    gw, torch = gpu
+    grid, mols = _workload()
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    ctx = gw.Context(0, budget_bytes=64 << 20)  # 64 MiB: too small for the larger molecules
+    dm = gw.DeviceMolecule(mols[2][0])
+    with pytest.raises(gw.GwError) as e:
+        ctx.submit(dm.struct, dm.v, g)
+    assert e.value.status == gw.GW_E_OOM
+    with pytest.raises(gw.GwError) as e:
+        ctx.poll(12345)
+    assert e.value.status == gw.GW_E_STATE
+    with pytest.raises(gw.GwError) as e:
+        ctx.release(12345)
+    assert e.value.status == gw.GW_E_STATE
+    with pytest.raises(gw.GwError) as e:
+        ctx.submit(dm.struct, dm.v, g, k_compress=dm.n_prod + 1)
+    assert e.value.status == gw.GW_E_INVALID
+    ctx.close()
