@@ -194,6 +194,29 @@ gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, 
 gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X,
                         void *stream, void *W_out);
 
+/* Batched form: n_mol molecules of different sizes on one mesh (all
+ * frequencies of all molecules).  gw_batch_create validates every molecule,
+ * sizes the workspaces, chooses GEMM tile shapes per size class with the
+ * autotuner (timed once per class, cached in $GW_TUNE_FILE, default
+ * $HOME/.cache/gw_tune.json) and records the whole computation once into a
+ * hipGraph: every chi0 build, then the W solves on GW_BATCH_STREAMS (default
+ * 4) parallel branches.  gw_batch_run replays that graph on `stream`.
+ *   v[i]: DEVICE [n_i][n_i]; chi0_out[i], W_out[i]: DEVICE complex128
+ *   [n_omega][n_i][n_i], caller-owned, fixed for the life of the batch.
+ *   prec GW_FP64, or GW_FP32_IR with exactly n_refine (1..6) FP64 refinement
+ *   steps in the graph; gw_batch_run then re-solves in FP64 every frequency
+ *   whose last step left ||dW||_F > tol ||W||_F (counted in the report).
+ *   reps: HOST [n_mol] or NULL (then gw_batch_run does not synchronise for
+ *   FP64).  A later gw_batch_create on the same context retires earlier
+ *   batches (gw_batch_run on them returns GW_E_STATE).  Not thread-safe with
+ *   other calls on the same context. */
+typedef struct gw_batch gw_batch;
+gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, const double *const *v,
+                          const gw_grid *g, gw_precision prec, double tol, int32_t n_refine, void *stream,
+                          void *const *chi0_out, void *const *W_out, gw_batch **out);
+gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps);
+gw_status gw_batch_destroy(gw_batch *b);
+
 /* Serving (continuous batching).  gw_submit copies nothing: the molecule's
  * DEVICE buffers must stay valid until gw_poll returns GW_OK.  The request is
  * admitted when its estimated HBM footprint fits; its chi0 and W stay on the

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_exact.hip", "k_chi0.hip", "k_gemm.hip", "k_lu.hip", "k_compress.hip", "gw_abi.cpp", "gw_serve.cpp"]
+SOURCES = ["k_exact.hip", "k_chi0.hip", "k_gemm.hip", "k_lu.hip", "k_compress.hip", "gw_abi.cpp", "gw_serve.cpp", "gw_batch.cpp"]
 
 # The exact kernels (pair vertex, bins, int64 histogram) must round every
 # product and sum on its own: no FMA contraction anywhere in that file.
@@ -40,7 +40,7 @@ def _compile(src: str, objdir: str) -> str:
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs

@@ -1,8 +1,8 @@
 // C ABI of libgw.so: argument checks, planning, workspace and launch order.
-// Every arithmetic step of the path runs in the HIP kernels of k_chi0.hip,
-// k_gemm.hip and k_lu.hip; this file only validates, sizes and sequences.
-#include "../../include/gw.h"
-#include "gw_internal.h"
+// Every arithmetic step of the path runs in the HIP kernels of k_exact.hip,
+// k_chi0.hip, k_gemm.hip, k_lu.hip and k_compress.hip; this file only
+// validates, sizes and sequences.
+#include "gw_plan.h"
 
 #include <hip/hip_runtime.h>
 
@@ -18,8 +18,6 @@ namespace gwk {
 hipError_t launch_perm(hipStream_t st, int n, const int32_t *ipiv, int32_t *perm, int batch);
 hipError_t launch_init_rhs_perm(hipStream_t st, int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
                                 int64_t sB, int batch);
-hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
-                              zdbl *dst, int64_t sD, int batch);
 hipError_t launch_dzgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
                          const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
                          int batch);
@@ -38,10 +36,10 @@ hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per,
 
 using gwk::zdbl;
 using gwk::zflt;
+using gwp::fail;
+using gwp::ws;
 
-#include "gw_ctx.h"
-
-namespace {
+namespace gwp {
 
 gw_status fail(gw_ctx *c, gw_status s, const std::string &msg) {
     if (c) {
@@ -51,16 +49,8 @@ gw_status fail(gw_ctx *c, gw_status s, const std::string &msg) {
     return s;
 }
 
-#define GW_HIP(ctx, call)                                                                                     \
-    do {                                                                                                      \
-        hipError_t _e = (call);                                                                               \
-        if (_e != hipSuccess)                                                                                 \
-            return fail((ctx), _e == hipErrorOutOfMemory ? GW_E_OOM : GW_E_DEVICE,                            \
-                        std::string(#call) + ": " + hipGetErrorString(_e));                                  \
-    } while (0)
-
 // Grow-only named device buffers.  Reallocation waits for the device first.
-gw_status ws(gw_ctx *c, const char *name, size_t bytes, void **out) {
+gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out) {
     DevBuf &b = c->bufs[name];
     if (bytes == 0) bytes = 256;
     if (b.bytes < bytes) {
@@ -84,6 +74,10 @@ gw_status ws(gw_ctx *c, const char *name, size_t bytes, void **out) {
     *out = b.ptr;
     return GW_OK;
 }
+
+}  // namespace gwp
+
+namespace {
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -172,23 +166,12 @@ gw_status check_molecule(gw_ctx *c, const gw_molecule *m, hipStream_t st, HostMo
 
 hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
+
+
+
 }  // namespace
 
-namespace {
-
-// per-frequency workspace for the solve
-struct SolveWs {
-    zdbl *A = nullptr;
-    zflt *A32 = nullptr, *B32 = nullptr;
-    zdbl *R = nullptr;
-    void *scratch = nullptr;
-    void *Li = nullptr, *Ui = nullptr;
-    int32_t *ipiv = nullptr, *perm = nullptr, *info = nullptr, *active = nullptr;
-    double *norms = nullptr;
-};
-
-size_t per_freq_bytes(int n, bool mixed);
-int solve_batch_max(int n, int n_omega, bool mixed, size_t budget);
+namespace gwp {
 
 size_t per_freq_bytes(int n, bool mixed) {
     const size_t nn = (size_t)n * n;
@@ -207,11 +190,6 @@ int solve_batch_max(int n, int n_omega, bool mixed, size_t budget) {
     return std::max(1, std::min(nb, n_omega / 2));
 }
 
-// bytes gw_solve_W allocates for a problem of this size
-size_t solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) {
-    return (size_t)solve_batch_max(n, n_omega, mixed, budget) * per_freq_bytes(n, mixed) + 4096;
-}
-
 gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
                            zdbl *W, int nb, SolveWs &w) {
     const int64_t nn = (int64_t)n * n;
@@ -224,39 +202,62 @@ gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, in
     return GW_OK;
 }
 
-}  // namespace
+}  // namespace gwp
 
 namespace {
 
-gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
-                            zdbl *W, int nb, double tol, SolveWs &w, std::vector<int> *conv_iters,
-                            std::vector<double> *rel, int max_iter) {
+size_t solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) {
+    return (size_t)gwp::solve_batch_max(n, n_omega, mixed, budget) * gwp::per_freq_bytes(n, mixed) +
+           16 * (size_t)n_omega + 4096;
+}
+
+// FP32 factor + solve, first solution W = A32^{-1} v (no refinement yet).
+gw_status mixed_first_solve(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
+                            zdbl *W, int nb, gwp::SolveWs &w) {
     const int64_t nn = (int64_t)n * n;
     GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, w.A32, nn, nb));
     GW_HIP(c, gwk::launch_fill_u32(st, (uint32_t *)w.info, nb, 0u));
     GW_HIP(c, gwk::getrf_batched<zflt>(st, n, w.A32, nn, w.ipiv, (zflt *)w.Li, (zflt *)w.Ui, (zflt *)w.scratch, w.info,
                                        nb));
     GW_HIP(c, gwk::launch_perm(st, n, w.ipiv, w.perm, nb));
-    // first solve: B32 = P v, solve, W = B32
     GW_HIP(c, gwk::launch_init_rhs(st, n, v, v_is_diag, w.R, nn, nb));
     GW_HIP(c, gwk::launch_rowgather_z2c(st, n, n, w.perm, w.R, nn, w.B32, nn, nb));
     GW_HIP(c, gwk::getrs_batched<zflt>(st, n, n, w.A32, nn, w.ipiv, (const zflt *)w.Li, (const zflt *)w.Ui, w.B32, nn,
                                        nb));
     GW_HIP(c, gwk::launch_c2z_set(st, w.B32, W, nn, nb));
+    return GW_OK;
+}
+
+// One refinement step: r = v - (1 - v chi0) W in FP64, dW = A32^{-1} r, W += dW
+// (active frequencies only, active may be null = all); norms of dW and W.
+gw_status mixed_refine_step(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, zdbl *W, int nb,
+                            gwp::SolveWs &w, const int32_t *active, double *norms) {
+    const int64_t nn = (int64_t)n * n;
+    GW_HIP(c, gwk::launch_residual(st, n, v, v_is_diag, w.A, nn, W, nn, w.R, nn, nb));
+    GW_HIP(c, gwk::launch_rowgather_z2c(st, n, n, w.perm, w.R, nn, w.B32, nn, nb));
+    GW_HIP(c, gwk::getrs_batched<zflt>(st, n, n, w.A32, nn, w.ipiv, (const zflt *)w.Li, (const zflt *)w.Ui, w.B32,
+                                       nn, nb));
+    GW_HIP(c, gwk::launch_c2z_add(st, w.B32, W, nn, nb, active));
+    GW_HIP(c, gwk::launch_fill_u64(st, (uint64_t *)norms, 2 * nb, 0ull));
+    GW_HIP(c, gwk::launch_norms(st, w.B32, W, nn, nb, norms));
+    return GW_OK;
+}
+
+// Adaptive refinement: stop a frequency once ||dW|| <= tol ||W|| (reads the
+// norms back after every step).
+gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
+                            zdbl *W, int nb, double tol, gwp::SolveWs &w, std::vector<int> *conv_iters,
+                            std::vector<double> *rel, int max_iter) {
+    gw_status s = mixed_first_solve(c, st, n, v, v_is_diag, chi0, W, nb, w);
+    if (s != GW_OK) return s;
     std::vector<int32_t> act(nb, 1);
     std::vector<double> hn(2 * nb);
     conv_iters->assign(nb, -1);
     rel->assign(nb, 0.0);
     GW_HIP(c, hipMemcpyAsync(w.active, act.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
     for (int it = 1; it <= max_iter; ++it) {
-        // FP64 residual r = v - (1 - v chi0) W
-        GW_HIP(c, gwk::launch_residual(st, n, v, v_is_diag, w.A, nn, W, nn, w.R, nn, nb));
-        GW_HIP(c, gwk::launch_rowgather_z2c(st, n, n, w.perm, w.R, nn, w.B32, nn, nb));
-        GW_HIP(c, gwk::getrs_batched<zflt>(st, n, n, w.A32, nn, w.ipiv, (const zflt *)w.Li, (const zflt *)w.Ui, w.B32,
-                                           nn, nb));
-        GW_HIP(c, gwk::launch_c2z_add(st, w.B32, W, nn, nb, w.active));
-        GW_HIP(c, gwk::launch_fill_u64(st, (uint64_t *)w.norms, 2 * nb, 0ull));
-        GW_HIP(c, gwk::launch_norms(st, w.B32, W, nn, nb, w.norms));
+        s = mixed_refine_step(c, st, n, v, v_is_diag, W, nb, w, w.active, w.norms);
+        if (s != GW_OK) return s;
         GW_HIP(c, hipMemcpyAsync(hn.data(), w.norms, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
         GW_HIP(c, hipStreamSynchronize(st));
         bool any = false;
@@ -277,10 +278,187 @@ gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, i
     return GW_OK;
 }
 
+// frequency batches: {0}, then [n/2, n) in chunks of nbmax
+std::vector<std::pair<int, int>> freq_batches(int n_omega, int nbmax) {
+    std::vector<std::pair<int, int>> b;
+    if (n_omega == 2) return {{0, 2}};
+    b.push_back({0, 1});
+    for (int j = n_omega / 2; j < n_omega; j += nbmax) b.push_back({j, std::min(nbmax, n_omega - j)});
+    return b;
+}
+
 }  // namespace
 
-extern "C" {
+namespace gwp {
 
+gw_status build_plan(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const double *basis, int k, hipStream_t st,
+                     const std::string &pre, int64_t *hist_out, BuildPlan *p) {
+    int kbits = 0;
+    gw_status s = check_grid(ctx, g, &kbits);
+    if (s != GW_OK) return s;
+    if (!m) return fail(ctx, GW_E_INVALID, "molecule is NULL");
+    if (basis && (k < 1 || k > m->n_prod)) return fail(ctx, GW_E_INVALID, "compressed rank k must be in [1, n_prod]");
+    if (!basis && k != 0) return fail(ctx, GW_E_INVALID, "k must be 0 without a basis");
+    HostMol h;
+    s = check_molecule(ctx, m, st, &h);
+    if (s != GW_OK) return s;
+    p->m = *m;
+    p->g = *g;
+    p->basis = basis;
+    p->k = k;
+    p->kbits = kbits;
+    p->n_orb = m->n_orb;
+    p->n_occ = m->n_occ;
+    p->n_prod = m->n_prod;
+    p->n_virt = m->n_orb - m->n_occ;
+    p->n_pairs = (int64_t)p->n_occ * p->n_virt;
+    p->nhb = hist_bins_host(h.eig.data(), p->n_orb, g->n_omega, kbits);
+    p->rows = basis ? k : p->n_prod;
+    p->n_upper = (int64_t)p->rows * (p->rows + 1) / 2;
+    p->max_o = h.max_o;
+    p->dom = (g->omega_max - g->omega_min) / g->n_omega;
+    p->j0 = (int)std::lround(g->omega_min / p->dom);
+    const int L = 2 * g->n_omega;
+    const int64_t n_pairs = p->n_pairs;
+    const int n_prod = p->n_prod, rows = p->rows;
+    void *q;
+#define GW_WS(name, bytes, dst)                                              \
+    do {                                                                     \
+        if ((s = ws(ctx, pre + name, (bytes), &q)) != GW_OK) return s;       \
+        dst = (decltype(dst))q;                                              \
+    } while (0)
+    if (basis) {
+        // Compress as soon as formed (Section 8.A): pair vectors for a range of
+        // occupied states at a time, projected onto the basis, so the full
+        // N_prod x N_pairs matrix never has to exist.
+        const int64_t cap = std::max<int64_t>(1, (int64_t)(2ll << 30) / (8ll * n_prod * p->n_virt));
+        p->echunk = (int)std::min<int64_t>(p->n_occ, cap);
+        GW_WS("P", sizeof(double) * n_prod * (int64_t)p->echunk * p->n_virt, p->P);
+        GW_WS("Pt", sizeof(double) * rows * n_pairs, p->Pt);
+        GW_WS("basisT", sizeof(double) * (int64_t)k * n_prod, p->bt);
+    } else {
+        p->echunk = p->n_occ;
+        GW_WS("P", sizeof(double) * n_prod * n_pairs, p->P);
+    }
+    GW_WS("Ps", sizeof(double) * rows * n_pairs, p->Ps);
+    GW_WS("lo", sizeof(int32_t) * p->n_occ * (p->nhb + 1), p->lo);
+    GW_WS("rowoff", sizeof(int32_t) * p->n_occ * p->nhb, p->rowoff);
+    GW_WS("binoff", sizeof(int32_t) * p->nhb, p->binoff);
+    GW_WS("perm", sizeof(int32_t) * n_pairs, p->perm);
+    GW_WS("fsort", sizeof(double) * n_pairs, p->fsort);
+    GW_WS("stat", 64, p->stat);
+    GW_WS("vmax", 64, p->vmax);
+    GW_WS("sdev", 64, p->sdev);
+    GW_WS("Kt", sizeof(zdbl) * L, p->Kt);
+    GW_WS("tw", sizeof(zdbl) * L, p->tw);
+    if (hist_out) p->H = hist_out;
+    else GW_WS("H", sizeof(int64_t) * p->nhb * p->n_upper, p->H);
+#undef GW_WS
+    const int ntiles = (rows + 63) / 64;
+    const int ntp = ntiles * (ntiles + 1) / 2;
+    int splits = std::max(1, std::min(64, (2048 + ntp - 1) / ntp));
+    p->splits = std::min(splits, std::max(1, p->nhb - 1));
+    return GW_OK;
+}
+
+gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
+    const gw_molecule *m = &p.m;
+    if (p.basis) {
+        GW_HIP(ctx, gwk::launch_transpose_d(st, p.n_prod, p.k, p.basis, p.bt));
+        for (int e0 = 0; e0 < p.n_occ; e0 += p.echunk) {
+            const int ec = std::min(p.echunk, p.n_occ - e0);
+            const int64_t cw = (int64_t)ec * p.n_virt;
+            GW_HIP(ctx, gwk::launch_pairvec(st, p.n_orb, p.n_occ, p.n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb,
+                                            m->orb_idx, m->blk_val, m->vals, p.max_o, e0, ec, cw, p.P));
+            // Pt[:, chunk] = basis^T P_chunk
+            GW_HIP(ctx, gwk::launch_dgemm(st, p.k, (int)cw, p.n_prod, 1.0, p.bt, p.n_prod, 0, p.P, cw, 0, 0.0,
+                                          p.Pt + (int64_t)e0 * p.n_virt, p.n_pairs, 0, 1));
+        }
+    } else {
+        GW_HIP(ctx, gwk::launch_pairvec(st, p.n_orb, p.n_occ, p.n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb,
+                                        m->orb_idx, m->blk_val, m->vals, p.max_o, 0, p.n_occ, p.n_pairs, p.P));
+    }
+    const double *Psrc = p.basis ? p.Pt : p.P;
+    GW_HIP(ctx, gwk::launch_absmax(st, Psrc, (int64_t)p.rows * p.n_pairs, p.vmax));
+    GW_HIP(ctx, gwk::launch_fracbits(st, p.vmax, p.n_pairs, p.g.frac_bits, p.sdev));
+    GW_HIP(ctx, gwk::launch_pair_sort(st, p.n_orb, p.n_occ, m->eig, p.kbits, p.nhb, p.lo, p.rowoff, p.binoff, p.perm,
+                                      p.fsort, p.stat));
+    GW_HIP(ctx, gwk::launch_gather(st, p.rows, p.n_pairs, Psrc, p.perm, p.stat, p.Ps));
+    GW_HIP(ctx, gwk::launch_hist(st, p.rows, p.n_pairs, p.Ps, p.fsort, p.binoff, p.stat, p.sdev, p.nhb, p.H, p.splits));
+    if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
+    GW_HIP(ctx, gwk::launch_fftconv(st, p.rows, p.g.n_omega, p.nhb, p.H, p.sdev, p.Kt, p.tw, (zdbl *)chi0_out));
+    return GW_OK;
+}
+
+gw_status solve_plan(gw_ctx *ctx, int n, int n_omega, bool mixed, const std::string &pre, SolvePlan *p) {
+    const int64_t nn = (int64_t)n * n;
+    const int nblk = (n + 63) / 64;
+    const int nbmax = solve_batch_max(n, n_omega, mixed, ctx->budget);
+    p->n = n;
+    p->n_omega = n_omega;
+    p->nbmax = nbmax;
+    p->mixed = mixed;
+    SolveWs &w = p->w;
+    gw_status s;
+    void *q;
+    if ((s = ws(ctx, pre + "sA", (size_t)nbmax * nn * 16, &q)) != GW_OK) return s;
+    w.A = (zdbl *)q;
+    if ((s = ws(ctx, pre + "sScr", (size_t)nbmax * (64 * (size_t)n * 16 + 4 * 257 + 256), &q)) != GW_OK) return s;
+    w.scratch = q;
+    const size_t esz = mixed ? 8 : 16;
+    if ((s = ws(ctx, pre + "sLi", (size_t)nbmax * nblk * 64 * 64 * esz, &q)) != GW_OK) return s;
+    w.Li = q;
+    if ((s = ws(ctx, pre + "sUi", (size_t)nbmax * nblk * 64 * 64 * esz, &q)) != GW_OK) return s;
+    w.Ui = q;
+    if ((s = ws(ctx, pre + "sIpiv", (size_t)nbmax * n * 4, &q)) != GW_OK) return s;
+    w.ipiv = (int32_t *)q;
+    if ((s = ws(ctx, pre + "sPerm", (size_t)nbmax * n * 4, &q)) != GW_OK) return s;
+    w.perm = (int32_t *)q;
+    if ((s = ws(ctx, pre + "sInfo", (size_t)nbmax * 4, &q)) != GW_OK) return s;
+    w.info = (int32_t *)q;
+    if ((s = ws(ctx, pre + "sAct", (size_t)nbmax * 4, &q)) != GW_OK) return s;
+    w.active = (int32_t *)q;
+    if ((s = ws(ctx, pre + "sNorm", (size_t)nbmax * 16, &q)) != GW_OK) return s;
+    w.norms = (double *)q;
+    if ((s = ws(ctx, pre + "sFinal", (size_t)n_omega * 16, &q)) != GW_OK) return s;
+    p->final_norms = (double *)q;
+    if (mixed) {
+        if ((s = ws(ctx, pre + "sA32", (size_t)nbmax * nn * 8, &q)) != GW_OK) return s;
+        w.A32 = (zflt *)q;
+        if ((s = ws(ctx, pre + "sB32", (size_t)nbmax * nn * 8, &q)) != GW_OK) return s;
+        w.B32 = (zflt *)q;
+        if ((s = ws(ctx, pre + "sR", (size_t)nbmax * nn * 16, &q)) != GW_OK) return s;
+        w.R = (zdbl *)q;
+    }
+    return GW_OK;
+}
+
+gw_status solve_enqueue_nosync(gw_ctx *ctx, SolvePlan &p, hipStream_t st, const double *v, int v_is_diag,
+                               const zdbl *chi0, zdbl *W, int fixed_ir) {
+    const int64_t nn = (int64_t)p.n * p.n;
+    gw_status s;
+    for (auto &bt : freq_batches(p.n_omega, p.nbmax)) {
+        const int j0 = bt.first, nb = bt.second;
+        if (!p.mixed) {
+            s = solve_batch_fp64(ctx, st, p.n, v, v_is_diag, chi0 + j0 * nn, W + j0 * nn, nb, p.w);
+            if (s != GW_OK) return s;
+        } else {
+            s = mixed_first_solve(ctx, st, p.n, v, v_is_diag, chi0 + j0 * nn, W + j0 * nn, nb, p.w);
+            if (s != GW_OK) return s;
+            for (int it = 0; it < fixed_ir; ++it) {
+                s = mixed_refine_step(ctx, st, p.n, v, v_is_diag, W + j0 * nn, nb, p.w, nullptr,
+                                      p.final_norms + 2 * j0);
+                if (s != GW_OK) return s;
+            }
+        }
+    }
+    if (p.n_omega >= 4) GW_HIP(ctx, gwk::launch_conj_mirror(st, nn, p.n_omega, W));
+    return GW_OK;
+}
+
+}  // namespace gwp
+
+extern "C" {
 gw_status gw_create(int device, size_t hbm_budget_bytes, gw_ctx **out) {
     if (!out) return GW_E_INVALID;
     *out = nullptr;
@@ -334,98 +512,28 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, con
     if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
     GW_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
-    int kbits = 0;
-    gw_status s = check_grid(ctx, g, &kbits);
-    if (s != GW_OK) return s;
     if (!chi0_out) return fail(ctx, GW_E_INVALID, "chi0_out is NULL");
-    if (basis && (k < 1 || k > m->n_prod)) return fail(ctx, GW_E_INVALID, "compressed rank k must be in [1, n_prod]");
-    if (!basis && k != 0) return fail(ctx, GW_E_INVALID, "k must be 0 without a basis");
-    HostMol h;
-    s = check_molecule(ctx, m, st, &h);
+    gwp::BuildPlan p;
+    gw_status s = gwp::build_plan(ctx, m, g, basis, k, st, "", hist_out, &p);
     if (s != GW_OK) return s;
-
-    const int n_orb = m->n_orb, n_occ = m->n_occ, n_prod = m->n_prod;
-    const int64_t n_pairs = (int64_t)n_occ * (n_orb - n_occ);
-    const int nhb = hist_bins_host(h.eig.data(), n_orb, g->n_omega, kbits);
-    const int rows = basis ? k : n_prod;
-    const int64_t n_upper = (int64_t)rows * (rows + 1) / 2;
-    const int L = 2 * g->n_omega;
-
-    void *P, *Pt = nullptr, *Ps, *lo, *rowoff, *binoff, *perm, *fsort, *stat, *vmax, *sdev, *Kt, *tw, *H;
-    const int n_virt = n_orb - n_occ;
-    if (basis) {
-        // Compress as soon as formed (Section 8.A): pair vectors for a range of
-        // occupied states at a time, projected onto the basis, so the full
-        // N_prod x N_pairs matrix never has to exist.
-        const int64_t cap = std::max<int64_t>(1, (int64_t)(2ll << 30) / (8ll * n_prod * n_virt));
-        const int echunk = (int)std::min<int64_t>(n_occ, cap);
-        void *bt;
-        if ((s = ws(ctx, "P", sizeof(double) * n_prod * (int64_t)echunk * n_virt, &P)) != GW_OK) return s;
-        if ((s = ws(ctx, "Pt", sizeof(double) * rows * n_pairs, &Pt)) != GW_OK) return s;
-        if ((s = ws(ctx, "basisT", sizeof(double) * (int64_t)k * n_prod, &bt)) != GW_OK) return s;
-        GW_HIP(ctx, gwk::launch_transpose_d(st, n_prod, k, basis, (double *)bt));
-        for (int e0 = 0; e0 < n_occ; e0 += echunk) {
-            const int ec = std::min(echunk, n_occ - e0);
-            const int64_t cw = (int64_t)ec * n_virt;
-            GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb,
-                                            m->orb_idx, m->blk_val, m->vals, h.max_o, e0, ec, cw, (double *)P));
-            // Pt[:, chunk] = basis^T P_chunk
-            GW_HIP(ctx, gwk::launch_dgemm(st, k, (int)cw, n_prod, 1.0, (const double *)bt, n_prod, 0,
-                                          (const double *)P, cw, 0, 0.0, (double *)Pt + (int64_t)e0 * n_virt, n_pairs,
-                                          0, 1));
-        }
-    } else {
-        if ((s = ws(ctx, "P", sizeof(double) * n_prod * n_pairs, &P)) != GW_OK) return s;
-    }
-    if ((s = ws(ctx, "Ps", sizeof(double) * rows * n_pairs, &Ps)) != GW_OK) return s;
-    if ((s = ws(ctx, "lo", sizeof(int32_t) * n_occ * (nhb + 1), &lo)) != GW_OK) return s;
-    if ((s = ws(ctx, "rowoff", sizeof(int32_t) * n_occ * nhb, &rowoff)) != GW_OK) return s;
-    if ((s = ws(ctx, "binoff", sizeof(int32_t) * nhb, &binoff)) != GW_OK) return s;
-    if ((s = ws(ctx, "perm", sizeof(int32_t) * n_pairs, &perm)) != GW_OK) return s;
-    if ((s = ws(ctx, "fsort", sizeof(double) * n_pairs, &fsort)) != GW_OK) return s;
-    if ((s = ws(ctx, "stat", 64, &stat)) != GW_OK) return s;
-    if ((s = ws(ctx, "vmax", 64, &vmax)) != GW_OK) return s;
-    if ((s = ws(ctx, "sdev", 64, &sdev)) != GW_OK) return s;
-    if ((s = ws(ctx, "Kt", sizeof(zdbl) * L, &Kt)) != GW_OK) return s;
-    if ((s = ws(ctx, "tw", sizeof(zdbl) * L, &tw)) != GW_OK) return s;
-    if (hist_out) H = hist_out;
-    else if ((s = ws(ctx, "H", sizeof(int64_t) * nhb * n_upper, &H)) != GW_OK) return s;
-
-    if (!basis)
-        GW_HIP(ctx, gwk::launch_pairvec(st, n_orb, n_occ, n_prod, m->n_blk, m->X, m->blk_prod, m->blk_orb, m->orb_idx,
-                                        m->blk_val, m->vals, h.max_o, 0, n_occ, n_pairs, (double *)P));
-    const double *Psrc = basis ? (const double *)Pt : (const double *)P;
-    GW_HIP(ctx, gwk::launch_absmax(st, Psrc, (int64_t)rows * n_pairs, (uint64_t *)vmax));
-    GW_HIP(ctx, gwk::launch_fracbits(st, (const uint64_t *)vmax, n_pairs, g->frac_bits, (int32_t *)sdev));
-    GW_HIP(ctx, gwk::launch_pair_sort(st, n_orb, n_occ, m->eig, kbits, nhb, (int32_t *)lo, (int32_t *)rowoff,
-                                      (int32_t *)binoff, (int32_t *)perm, (double *)fsort, (int64_t *)stat));
-    GW_HIP(ctx, gwk::launch_gather(st, rows, n_pairs, Psrc, (const int32_t *)perm, (const int64_t *)stat, (double *)Ps));
-    // enough workgroups to fill 256 CUs a few times over
-    const int ntiles = (rows + 63) / 64;
-    const int ntp = ntiles * (ntiles + 1) / 2;
-    int splits = std::max(1, std::min(64, (2048 + ntp - 1) / ntp));
-    splits = std::min(splits, std::max(1, nhb - 1));
-    GW_HIP(ctx, gwk::launch_hist(st, rows, n_pairs, (const double *)Ps, (const double *)fsort, (const int32_t *)binoff,
-                                 (const int64_t *)stat, (const int32_t *)sdev, nhb, (int64_t *)H, splits));
-    const double dom = (g->omega_max - g->omega_min) / g->n_omega;
-    if (ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != dom || ctx->ks_eps != g->eps) {
-        const int j0 = (int)std::lround(g->omega_min / dom);
-        GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, j0, dom, g->eps, (zdbl *)Kt, (zdbl *)tw));
+    const bool kspec = ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != p.dom ||
+                       ctx->ks_eps != g->eps;
+    s = gwp::build_enqueue(ctx, p, st, chi0_out, kspec);
+    if (s != GW_OK) return s;
+    if (kspec) {
         ctx->ks_n = g->n_omega;
         ctx->ks_min = g->omega_min;
-        ctx->ks_d = dom;
+        ctx->ks_d = p.dom;
         ctx->ks_eps = g->eps;
     }
-    GW_HIP(ctx, gwk::launch_fftconv(st, rows, g->n_omega, nhb, (const int64_t *)H, (const int32_t *)sdev,
-                                    (const zdbl *)Kt, (const zdbl *)tw, (zdbl *)chi0_out));
     if (rep) {
         int64_t hs[2];
         int32_t sv = 0;
-        GW_HIP(ctx, hipMemcpyAsync(hs, stat, sizeof(hs), hipMemcpyDeviceToHost, st));
-        GW_HIP(ctx, hipMemcpyAsync(&sv, sdev, sizeof(sv), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipMemcpyAsync(hs, p.stat, sizeof(hs), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipMemcpyAsync(&sv, p.sdev, sizeof(sv), hipMemcpyDeviceToHost, st));
         GW_HIP(ctx, hipStreamSynchronize(st));
         std::memset(rep, 0, sizeof(*rep));
-        rep->n_hbins = nhb;
+        rep->n_hbins = p.nhb;
         rep->frac_bits_used = sv;
         rep->n_dropped_pairs = hs[1];
     }
@@ -447,78 +555,43 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     hipStream_t st = as_stream(stream);
     const bool mixed = prec != GW_FP64;
     const int64_t nn = (int64_t)n * n;
-    const int nblk = (n + 63) / 64;
-
-    // batch size from the budget (the caller's chi0/W are not counted)
-    const int nbmax = solve_batch_max(n, n_omega, mixed, ctx->budget);
-    SolveWs w;
-    gw_status s;
-    void *p;
-    if ((s = ws(ctx, "sA", (size_t)nbmax * nn * 16, &p)) != GW_OK) return s;
-    w.A = (zdbl *)p;
-    if ((s = ws(ctx, "sScr", (size_t)nbmax * (64 * (size_t)n * 16 + 4 * 257 + 256), &p)) != GW_OK) return s;
-    w.scratch = p;
-    const size_t esz = mixed ? 8 : 16;
-    if ((s = ws(ctx, "sLi", (size_t)nbmax * nblk * 64 * 64 * esz, &p)) != GW_OK) return s;
-    w.Li = p;
-    if ((s = ws(ctx, "sUi", (size_t)nbmax * nblk * 64 * 64 * esz, &p)) != GW_OK) return s;
-    w.Ui = p;
-    if ((s = ws(ctx, "sIpiv", (size_t)nbmax * n * 4, &p)) != GW_OK) return s;
-    w.ipiv = (int32_t *)p;
-    if ((s = ws(ctx, "sPerm", (size_t)nbmax * n * 4, &p)) != GW_OK) return s;
-    w.perm = (int32_t *)p;
-    if ((s = ws(ctx, "sInfo", (size_t)nbmax * 4, &p)) != GW_OK) return s;
-    w.info = (int32_t *)p;
-    if ((s = ws(ctx, "sAct", (size_t)nbmax * 4, &p)) != GW_OK) return s;
-    w.active = (int32_t *)p;
-    if ((s = ws(ctx, "sNorm", (size_t)nbmax * 16, &p)) != GW_OK) return s;
-    w.norms = (double *)p;
-    if (mixed) {
-        if ((s = ws(ctx, "sA32", (size_t)nbmax * nn * 8, &p)) != GW_OK) return s;
-        w.A32 = (zflt *)p;
-        if ((s = ws(ctx, "sB32", (size_t)nbmax * nn * 8, &p)) != GW_OK) return s;
-        w.B32 = (zflt *)p;
-        if ((s = ws(ctx, "sR", (size_t)nbmax * nn * 16, &p)) != GW_OK) return s;
-        w.R = (zdbl *)p;
-    }
-
+    gwp::SolvePlan p;
+    gw_status s = gwp::solve_plan(ctx, n, n_omega, mixed, "", &p);
+    if (s != GW_OK) return s;
     const zdbl *X0 = (const zdbl *)chi0;
     zdbl *W = (zdbl *)W_out;
-    // frequency batches: {0}, then [n/2, n) in chunks
-    std::vector<std::pair<int, int>> batches;
-    batches.push_back({0, 1});
-    for (int j = n_omega / 2; j < n_omega; j += nbmax) batches.push_back({j, std::min(nbmax, n_omega - j)});
-    if (n_omega == 2) batches = {{0, 2}};
     int n_solved = 0, n_fallback = 0, max_it = 0;
     double max_rel = 0.0;
-    for (auto &bt : batches) {
-        const int j0 = bt.first, nb = bt.second;
-        n_solved += nb;
-        if (!mixed) {
-            if ((s = solve_batch_fp64(ctx, st, n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, w)) != GW_OK) return s;
-        } else {
+    if (!mixed) {
+        s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0);
+        if (s != GW_OK) return s;
+        for (auto &bt : freq_batches(n_omega, p.nbmax)) n_solved += bt.second;
+    } else {
+        for (auto &bt : freq_batches(n_omega, p.nbmax)) {
+            const int j0 = bt.first, nb = bt.second;
+            n_solved += nb;
             std::vector<int> its;
             std::vector<double> rel;
-            if ((s = solve_batch_mixed(ctx, st, n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, tol, w, &its, &rel, 6)) !=
-                GW_OK)
-                return s;
+            s = solve_batch_mixed(ctx, st, n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, tol, p.w, &its, &rel, 6);
+            if (s != GW_OK) return s;
             for (int b = 0; b < nb; ++b) {
                 if (its[b] < 0) {
                     // not converged: FP64 fallback for this frequency
                     ++n_fallback;
-                    if ((s = solve_batch_fp64(ctx, st, n, v, v_is_diag, X0 + (j0 + b) * nn, W + (j0 + b) * nn, 1, w)) !=
-                        GW_OK)
-                        return s;
+                    gwp::SolvePlan p64;
+                    if ((s = gwp::solve_plan(ctx, n, 2, false, "fb", &p64)) != GW_OK) return s;
+                    s = gwp::solve_batch_fp64(ctx, st, n, v, v_is_diag, X0 + (j0 + b) * nn, W + (j0 + b) * nn, 1,
+                                              p64.w);
+                    if (s != GW_OK) return s;
                 } else {
                     max_it = std::max(max_it, its[b]);
                     max_rel = std::max(max_rel, rel[b]);
                 }
             }
         }
+        if (n_omega >= 4) GW_HIP(ctx, gwk::launch_conj_mirror(st, nn, n_omega, W));
     }
-    if (n_omega >= 4) GW_HIP(ctx, gwk::launch_conj_mirror(st, nn, n_omega, W));
     if (rep) {
-        std::vector<int32_t> info(1, 0);
         GW_HIP(ctx, hipStreamSynchronize(st));
         rep->n_solved = n_solved;
         rep->n_fallback = n_fallback;
@@ -576,4 +649,3 @@ void gwk_ctx_trim(gw_ctx *c) {
 }
 
 size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) { return solve_ws_bytes(n, n_omega, mixed, budget); }
-

@@ -1,0 +1,370 @@
+// Batched form: many molecules of different sizes on one mesh, recorded once
+// into a hipGraph and replayed.
+//
+// gw_batch_create validates and plans every molecule (the only host
+// synchronisation), sizes the shared workspaces (two planning passes, so
+// every recorded pointer is final), picks GEMM tile shapes per size class
+// from the autotuner table, then records: all chi0 builds on the caller's
+// stream, then the molecules' W solves spread over parallel stream branches
+// (fork/join through events), so solves of different molecules run
+// concurrently.  gw_batch_run replays the graph; for the mixed form it then
+// checks every frequency's last refinement step and re-solves in FP64 (outside
+// the graph) any frequency that did not reach the tolerance.
+#include "gw_plan.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace gwk {
+hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
+                        const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
+                        int batch);
+}
+
+using gwp::fail;
+
+struct gw_batch {
+    gw_ctx *ctx = nullptr;
+    int n_mol = 0;
+    std::vector<gw_molecule> mols;
+    std::vector<const double *> v;
+    std::vector<void *> chi0, W;
+    std::vector<int> n, tile;
+    gw_grid g{};
+    gw_precision prec = GW_FP64;
+    double tol = 1e-7;
+    int n_refine = 0;
+    std::vector<double *> norms;  // per molecule [n_omega][2]
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;  // private stream the graph is recorded on
+    std::vector<hipStream_t> branches;
+    std::vector<hipEvent_t> events;
+    uint64_t generation = 0;  // the context's batch generation this graph was recorded in
+};
+
+namespace {
+
+// ------------------------------------------------------------------ autotuner
+// Table: size class (n rounded up to a multiple of 256) and precision -> GEMM
+// tile (0: 64x64 K16, 1: 128x64 K8).  Measured on the trailing-update shape
+// (n x n x 256, complex) the first time a class is seen, kept in memory and in
+// a JSON file ($GW_TUNE_FILE, default $HOME/.cache/gw_tune.json).
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_path() {
+    if (const char *e = std::getenv("GW_TUNE_FILE")) return e;
+    const char *h = std::getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/gw_tune.json";
+}
+
+void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    std::ifstream f(tune_path());
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    // flat {"key": value, ...}
+    size_t p = 0;
+    while ((p = t.find('"', p)) != std::string::npos) {
+        const size_t q = t.find('"', p + 1);
+        if (q == std::string::npos) break;
+        const std::string key = t.substr(p + 1, q - p - 1);
+        const size_t c = t.find(':', q);
+        if (c == std::string::npos) break;
+        g_tune[key] = std::atoi(t.c_str() + c + 1);
+        p = t.find_first_of(",}", c);
+        if (p == std::string::npos) break;
+    }
+}
+
+void tune_save() {
+    const std::string path = tune_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        std::string cmd = "mkdir -p '" + dir + "'";
+        if (std::system(cmd.c_str()) != 0) return;
+    }
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{";
+    bool first = true;
+    for (auto &kv : g_tune) {
+        f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
+        first = false;
+    }
+    f << "}\n";
+}
+
+gw_status tune_tile(gw_ctx *ctx, int n, hipStream_t st, int *tile) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    const int cls = ((n + 255) / 256) * 256;
+    const std::string key = "zgemm_n" + std::to_string(cls);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+        *tile = it->second;
+        return GW_OK;
+    }
+    if (cls < 128) {
+        *tile = 0;
+        g_tune[key] = 0;
+        return GW_OK;
+    }
+    // operands: C (cls x cls), A (cls x 256), B (256 x cls), batch 4
+    const int K = 256, batch = 4;
+    const size_t elems = (size_t)batch * ((size_t)cls * cls + 2 * (size_t)cls * K);
+    void *buf;
+    gw_status s = gwp::ws(ctx, "tune", elems * 16, &buf);
+    if (s != GW_OK) return s;
+    gwk::zdbl *C = (gwk::zdbl *)buf, *A = C + (size_t)batch * cls * cls, *B = A + (size_t)batch * cls * K;
+    GW_HIP(ctx, hipMemsetAsync(buf, 0, elems * 16, st));
+    hipEvent_t e0, e1;
+    GW_HIP(ctx, hipEventCreate(&e0));
+    GW_HIP(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_t = 0;
+    for (int t = 0; t < 2; ++t) {
+        gwp::set_thread_gemm_tile(t);
+        float ms = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            GW_HIP(ctx, hipEventRecord(e0, st));
+            GW_HIP(ctx, gwk::launch_zgemm(st, cls, cls, K, -1.0, A, K, (int64_t)cls * K, B, cls, (int64_t)K * cls, 1.0,
+                                          C, cls, (int64_t)cls * cls, batch));
+            GW_HIP(ctx, hipEventRecord(e1, st));
+            GW_HIP(ctx, hipEventSynchronize(e1));
+            GW_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (ms < best) {
+            best = ms;
+            best_t = t;
+        }
+    }
+    gwp::set_thread_gemm_tile(-1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_tune[key] = best_t;
+    tune_save();
+    *tile = best_t;
+    return GW_OK;
+}
+
+void destroy_graph(gw_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+gw_status record(gw_batch *b) {
+    gw_ctx *ctx = b->ctx;
+    hipStream_t st = b->cap;
+    const int nbr = (int)b->branches.size();
+    const bool mixed = b->prec != GW_FP64;
+    // planning, pass 1 (grows the shared buffers) and pass 2 (final pointers)
+    std::vector<gwp::BuildPlan> bp(b->n_mol);
+    std::vector<gwp::SolvePlan> sp(b->n_mol);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < b->n_mol; ++i) {
+            gw_status s = gwp::build_plan(ctx, &b->mols[i], &b->g, nullptr, 0, st, "bb", nullptr, &bp[i]);
+            if (s != GW_OK) return s;
+            s = gwp::solve_plan(ctx, b->n[i], b->g.n_omega, mixed, "bs" + std::to_string(i % nbr), &sp[i]);
+            if (s != GW_OK) return s;
+            sp[i].final_norms = b->norms[i];
+        }
+    }
+    GW_HIP(ctx, hipStreamSynchronize(st));
+    GW_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    // from here on every failure still ends the capture below
+    gw_status s = GW_OK;
+    auto hip = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && s == GW_OK) s = fail(ctx, GW_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    for (int i = 0; i < b->n_mol && s == GW_OK; ++i) s = gwp::build_enqueue(ctx, bp[i], st, b->chi0[i], i == 0);
+    if (s == GW_OK) {
+        hip(hipEventRecord(b->events[0], st), "fork");
+        for (int r = 0; r < nbr; ++r) hip(hipStreamWaitEvent(b->branches[r], b->events[0], 0), "fork");
+        for (int i = 0; i < b->n_mol && s == GW_OK; ++i) {
+            gwp::set_thread_gemm_tile(b->tile[i]);
+            s = gwp::solve_enqueue_nosync(ctx, sp[i], b->branches[i % nbr], b->v[i], 0, (const gwp::zdbl *)b->chi0[i],
+                                          (gwp::zdbl *)b->W[i], mixed ? b->n_refine : 0);
+        }
+        gwp::set_thread_gemm_tile(-1);
+        for (int r = 0; r < nbr; ++r) {
+            hip(hipEventRecord(b->events[1 + r], b->branches[r]), "join");
+            hip(hipStreamWaitEvent(st, b->events[1 + r], 0), "join");
+        }
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s != GW_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    GW_HIP(ctx, e);
+    b->graph = graph;
+    GW_HIP(ctx, hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
+    return GW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, const double *const *v,
+                          const gw_grid *g, gw_precision prec, double tol, int32_t n_refine, void *stream,
+                          void *const *chi0_out, void *const *W_out, gw_batch **out) {
+    if (!ctx || !out) return GW_E_INVALID;
+    *out = nullptr;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    if (n_mol < 1 || !mols || !v || !g || !chi0_out || !W_out) return fail(ctx, GW_E_INVALID, "bad batch arguments");
+    if (prec != GW_FP64 && prec != GW_FP32_IR) return fail(ctx, GW_E_INVALID, "batch precision must be FP64 or FP32_IR");
+    if (prec != GW_FP64 && (n_refine < 1 || n_refine > 6 || !(tol > 0)))
+        return fail(ctx, GW_E_INVALID, "mixed batch needs 1..6 refinement steps and tol > 0");
+    for (int i = 0; i < n_mol; ++i)
+        if (!v[i] || !chi0_out[i] || !W_out[i]) return fail(ctx, GW_E_INVALID, "NULL buffer in batch");
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    gw_batch *b = new gw_batch();
+    b->ctx = ctx;
+    b->n_mol = n_mol;
+    b->mols.assign(mols, mols + n_mol);
+    b->v.assign(v, v + n_mol);
+    b->chi0.assign(chi0_out, chi0_out + n_mol);
+    b->W.assign(W_out, W_out + n_mol);
+    b->g = *g;
+    b->prec = prec;
+    b->tol = tol;
+    b->n_refine = n_refine;
+    int nbr = 4;
+    if (const char *e = std::getenv("GW_BATCH_STREAMS")) nbr = std::max(1, std::min(16, std::atoi(e)));
+    nbr = std::min(nbr, n_mol);
+    auto bail = [&](gw_status s) {
+        gw_batch_destroy(b);
+        return s;
+    };
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(ctx, GW_E_DEVICE, "cannot create batch stream"));
+    for (int r = 0; r < nbr; ++r) {
+        hipStream_t s2;
+        if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(ctx, GW_E_DEVICE, "cannot create batch stream"));
+        b->branches.push_back(s2);
+    }
+    for (int r = 0; r < nbr + 1; ++r) {
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(ctx, GW_E_DEVICE, "cannot create batch event"));
+        b->events.push_back(ev);
+    }
+    for (int i = 0; i < n_mol; ++i) {
+        b->n.push_back(mols[i].n_prod);
+        void *p;
+        gw_status s = gwp::ws(ctx, "bnorm" + std::to_string(i), (size_t)g->n_omega * 16, &p);
+        if (s != GW_OK) return bail(s);
+        b->norms.push_back((double *)p);
+        int tile = 0;
+        s = tune_tile(ctx, mols[i].n_prod, st, &tile);
+        if (s != GW_OK) return bail(s);
+        b->tile.push_back(tile);
+    }
+    // a new batch may grow the shared batch workspaces: older graphs are retired
+    b->generation = ++ctx->batch_generation;
+    // the caller's stream may hold work on these buffers: finish it first
+    GW_HIP(ctx, hipStreamSynchronize(st));
+    gw_status s = record(b);
+    if (s != GW_OK) return bail(s);
+    *out = b;
+    return GW_OK;
+}
+
+gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
+    if (!b) return GW_E_INVALID;
+    gw_ctx *ctx = b->ctx;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    if (b->generation != ctx->batch_generation)
+        return fail(ctx, GW_E_STATE, "batch was recorded before a newer gw_batch_create on this context; recreate it");
+    hipStream_t st = (hipStream_t)stream;
+    ctx->ks_n = 0;  // the graph rewrites the context's kernel-spectrum buffer
+    GW_HIP(ctx, hipGraphLaunch(b->exec, st));
+    const bool mixed = b->prec != GW_FP64;
+    if (!mixed && !reps) return GW_OK;
+    GW_HIP(ctx, hipStreamSynchronize(st));
+    const int N = b->g.n_omega;
+    for (int i = 0; i < b->n_mol; ++i) {
+        int fallback = 0, solved = 0;
+        double worst = 0;
+        if (mixed) {
+            std::vector<double> hn(2 * (size_t)N);
+            GW_HIP(ctx, hipMemcpy(hn.data(), b->norms[i], sizeof(double) * 2 * N, hipMemcpyDeviceToHost));
+            gwp::SolvePlan p64;
+            bool planned = false;
+            const int64_t nn = (int64_t)b->n[i] * b->n[i];
+            std::vector<int> js;
+            js.push_back(0);
+            for (int j = N / 2; j < N; ++j) js.push_back(j);
+            for (int j : js) {
+                ++solved;
+                const double r = std::sqrt(hn[2 * j]) / std::max(std::sqrt(hn[2 * j + 1]), 1e-300);
+                if (r <= b->tol) {
+                    worst = std::max(worst, r);
+                    continue;
+                }
+                if (!planned) {
+                    gw_status s = gwp::solve_plan(ctx, b->n[i], 2, false, "bfb", &p64);
+                    if (s != GW_OK) return s;
+                    planned = true;
+                }
+                gw_status s = gwp::solve_batch_fp64(ctx, st, b->n[i], b->v[i], 0,
+                                                    (const gwp::zdbl *)b->chi0[i] + j * nn,
+                                                    (gwp::zdbl *)b->W[i] + j * nn, 1, p64.w);
+                if (s != GW_OK) return s;
+                ++fallback;
+            }
+            if (fallback) {
+                GW_HIP(ctx, gwk::launch_conj_mirror(st, nn, N, (gwp::zdbl *)b->W[i]));
+                GW_HIP(ctx, hipStreamSynchronize(st));
+            }
+        } else {
+            solved = N / 2 + 1;
+        }
+        if (reps) {
+            gw_report &r = reps[i];
+            r = gw_report{};
+            r.n_solved = solved;
+            r.n_fallback = fallback;
+            r.max_iter = mixed ? b->n_refine : 0;
+            r.max_rel_update = worst;
+        }
+    }
+    return GW_OK;
+}
+
+gw_status gw_batch_destroy(gw_batch *b) {
+    if (!b) return GW_E_INVALID;
+    (void)hipSetDevice(b->ctx->device);
+    destroy_graph(b);
+    for (auto s : b->branches) (void)hipStreamDestroy(s);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (auto e : b->events) (void)hipEventDestroy(e);
+    delete b;
+    return GW_OK;
+}
+
+}  // extern "C"

@@ -25,6 +25,7 @@ struct gw_ctx {
     // set for the private contexts of serving slots: the only stream they use
     hipStream_t own_stream = nullptr;
     GwServe *serve = nullptr;
+    uint64_t batch_generation = 0;
 };
 
 void gwk_ctx_trim(gw_ctx *c);

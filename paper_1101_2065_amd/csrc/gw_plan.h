@@ -1,0 +1,86 @@
+// Private planning layer shared by the single-molecule ABI (gw_abi.cpp) and
+// the batched driver (gw_batch.cpp).  A plan validates the arguments (which
+// may read small index arrays back to the host) and allocates every buffer;
+// enqueueing a plan only launches kernels on a stream, with no host
+// synchronisation and no allocation, so it can be recorded into a hipGraph.
+#pragma once
+
+#include "../../include/gw.h"
+#include "gw_ctx.h"
+#include "gw_internal.h"
+
+#include <string>
+
+namespace gwp {
+
+using gwk::zdbl;
+using gwk::zflt;
+
+gw_status fail(gw_ctx *c, gw_status s, const std::string &msg);
+// Grow-only named device buffer of the context.
+gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out);
+
+#define GW_HIP(ctx, call)                                                                                     \
+    do {                                                                                                      \
+        hipError_t _e = (call);                                                                               \
+        if (_e != hipSuccess)                                                                                 \
+            return gwp::fail((ctx), _e == hipErrorOutOfMemory ? GW_E_OOM : GW_E_DEVICE,                       \
+                             std::string(#call) + ": " + hipGetErrorString(_e));                             \
+    } while (0)
+
+struct BuildPlan {
+    gw_molecule m{};
+    gw_grid g{};
+    const double *basis = nullptr;
+    int k = 0;
+    int n_orb = 0, n_occ = 0, n_prod = 0, n_virt = 0, rows = 0, nhb = 0, kbits = 0, max_o = 0;
+    int echunk = 0, splits = 1, j0 = 0;
+    int64_t n_pairs = 0, n_upper = 0;
+    double dom = 0;
+    double *P = nullptr, *Pt = nullptr, *bt = nullptr, *Ps = nullptr, *fsort = nullptr;
+    int32_t *lo = nullptr, *rowoff = nullptr, *binoff = nullptr, *perm = nullptr, *sdev = nullptr;
+    int64_t *stat = nullptr, *H = nullptr;
+    uint64_t *vmax = nullptr;
+    zdbl *Kt = nullptr, *tw = nullptr;
+};
+
+// Validate, size and allocate (buffer names get `prefix`).
+gw_status build_plan(gw_ctx *c, const gw_molecule *m, const gw_grid *g, const double *basis, int k, hipStream_t st,
+                     const std::string &prefix, int64_t *hist_out, BuildPlan *p);
+// Launch a1-a4 for a plan.  with_kspec: also compute the Cauchy-kernel
+// spectrum (once per mesh).
+gw_status build_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec);
+
+struct SolveWs {
+    zdbl *A = nullptr;
+    zflt *A32 = nullptr, *B32 = nullptr;
+    zdbl *R = nullptr;
+    void *scratch = nullptr;
+    void *Li = nullptr, *Ui = nullptr;
+    int32_t *ipiv = nullptr, *perm = nullptr, *info = nullptr, *active = nullptr;
+    double *norms = nullptr;
+};
+
+struct SolvePlan {
+    int n = 0, n_omega = 0, nbmax = 0;
+    bool mixed = false;
+    SolveWs w;
+    double *final_norms = nullptr;  // [n_omega][2]: |dW|^2, |W|^2 of the last refinement step
+};
+
+size_t per_freq_bytes(int n, bool mixed);
+int solve_batch_max(int n, int n_omega, bool mixed, size_t budget);
+gw_status solve_plan(gw_ctx *c, int n, int n_omega, bool mixed, const std::string &prefix, SolvePlan *p);
+// Enqueue all solves of one mesh: FP64, or FP32 with exactly fixed_ir FP64
+// refinement steps; the last step's norms go to p.final_norms.  No host
+// synchronisation.
+gw_status solve_enqueue_nosync(gw_ctx *c, SolvePlan &p, hipStream_t st, const double *v, int v_is_diag,
+                               const zdbl *chi0, zdbl *W, int fixed_ir);
+// One frequency (or a strided run of them) in FP64.
+gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
+                           zdbl *W, int nb, SolveWs &w);
+
+// GEMM tile policy for the launches of the calling host thread (autotuner).
+void set_thread_gemm_tile(int tile);
+
+}  // namespace gwp

@@ -241,7 +241,9 @@ __global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *
     if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
 }
 
-int g_gemm_tile = -1;  // < 0: choose by shape; 0: 64x64; 1: 128x64 (for measurements)
+// < 0: choose by shape; 0: 64x64 K16; 1: 128x64 K8.  Per host thread, so the
+// batched driver can record each molecule with its tuned tile.
+thread_local int g_gemm_tile = -1;
 
 template <typename T, bool AC, bool BC>
 hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *A, int64_t lda, int64_t sA,
@@ -319,4 +321,6 @@ hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const
 
 }  // namespace gwk
 
-extern "C" void gwk_set_gemm_tile(int t) { gwk::g_gemm_tile = t; }
+namespace gwp {
+void set_thread_gemm_tile(int tile) { gwk::g_gemm_tile = tile; }
+}  // namespace gwp

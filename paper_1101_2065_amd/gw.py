@@ -77,6 +77,11 @@ _SIGS = {
                                  ctypes.POINTER(ctypes.c_uint64)]),
     "gw_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P), ctypes.POINTER(gw_report)]),
     "gw_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "gw_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(gw_molecule), ctypes.POINTER(_P),
+                                       ctypes.POINTER(gw_grid), ctypes.c_int, ctypes.c_double, ctypes.c_int32, _P,
+                                       ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "gw_batch_run": (ctypes.c_int, [_P, _P, ctypes.POINTER(gw_report)]),
+    "gw_batch_destroy": (ctypes.c_int, [_P]),
 }
 
 
@@ -190,6 +195,43 @@ class Context:
 
     def release(self, ticket: int):
         self._check(lib.gw_release(self.h, ticket), "gw_release")
+
+    def batch_create(self, mols, vs, grid: "gw_grid", chi0_outs, W_outs, prec: int = GW_FP64,
+                     tol: float = 1e-7, n_refine: int = 2, stream=None) -> "Batch":
+        n = len(mols)
+        arr = (gw_molecule * n)(*mols)
+        pv = (_P * n)(*[_ptr(v) for v in vs])
+        pc = (_P * n)(*[_ptr(c) for c in chi0_outs])
+        pw = (_P * n)(*[_ptr(w) for w in W_outs])
+        h = _P()
+        st = lib.gw_batch_create(self.h, n, arr, pv, ctypes.byref(grid), prec, tol, n_refine,
+                                 _stream_handle(stream), pc, pw, ctypes.byref(h))
+        self._check(st, "gw_batch_create")
+        return Batch(self, h, n)
+
+
+class Batch:
+    """A recorded batch (hipGraph) of molecules; run() replays it."""
+
+    def __init__(self, ctx: "Context", h, n: int):
+        self.ctx, self.h, self.n = ctx, h, n
+
+    def run(self, stream=None, report: bool = True):
+        reps = (gw_report * self.n)() if report else None
+        st = lib.gw_batch_run(self.h, _stream_handle(stream), reps)
+        self.ctx._check(st, "gw_batch_run")
+        return list(reps) if report else None
+
+    def close(self):
+        if self.h:
+            lib.gw_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def query_sizes(n_orb: int, n_occ: int, n_prod: int, eig_host, grid: "gw_grid", k: int = 0) -> gw_sizes:

@@ -1,0 +1,111 @@
+"""Batched form: several molecules of different sizes recorded into one
+hipGraph; every replay (with unrelated eager work and synchronisation between
+replays) must give the eager single-molecule results, and the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+
+import gw_synth as gs
+import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_2065_amd.gw as gw
+
+    ctx = gw.Context(0)
+    yield gw, ctx, torch
+    ctx.close()
+
+
+def _mols():
+    return [
+        gs.make_config(0),
+        gs.chain_molecule(8, 7, orb_per_atom=4, occ_per_atom=2, prod_per_atom=10, prod_per_bond=8,
+                          bond_cutoff=None),
+        gs.chain_molecule(6, 21),
+        gs.chain_molecule(3, 33),
+    ]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+def test_batch_graph_replays_match_eager(gpu, prec):
+    gw, ctx, torch = gpu
+    grid = gs.config_grid(0)
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    mols = _mols()
+    dms = [gw.DeviceMolecule(m) for m in mols]
+    p = gw.GW_FP64 if prec == "fp64" else gw.GW_FP32_IR
+    # eager references, one molecule at a time
+    ref = []
+    for m, dm in zip(mols, dms):
+        c = torch.empty((grid.n_omega, m.n_prod, m.n_prod), dtype=torch.complex128, device="cuda")
+        w = torch.empty_like(c)
+        ctx.build_chi0(dm.struct, g, c)
+        ctx.solve_W(dm.v, m.n_prod, c, grid.n_omega, w)
+        ref.append(w.cpu().numpy())
+    chis = [torch.zeros((grid.n_omega, m.n_prod, m.n_prod), dtype=torch.complex128, device="cuda") for m in mols]
+    Ws = [torch.zeros_like(c) for c in chis]
+    stream = torch.cuda.current_stream()
+    b = ctx.batch_create([dm.struct for dm in dms], [dm.v for dm in dms], g, chis, Ws, prec=p, tol=1e-9,
+                         n_refine=3, stream=stream)
+    other = gs.chain_molecule(5, 44)
+    dmo = gw.DeviceMolecule(other)
+    for replay in range(3):
+        for w in Ws:
+            w.fill_(float("nan"))
+        reps = b.run(stream=stream)
+        torch.cuda.synchronize()
+        for i, (w, r) in enumerate(zip(Ws, ref)):
+            e = np.linalg.norm(w.cpu().numpy() - r) / np.linalg.norm(r)
+            _say(prec, "replay", replay, "molecule", i, "n", mols[i].n_prod, "rel vs eager", e,
+                 "fallback", reps[i].n_fallback)
+            assert e < (1e-12 if prec == "fp64" else 1e-8)
+        # unrelated eager work between replays
+        c = torch.empty((grid.n_omega, other.n_prod, other.n_prod), dtype=torch.complex128, device="cuda")
+        ctx.build_chi0(dmo.struct, g, c)
+        torch.cuda.synchronize()
+    b.close()
+    # the smallest molecule against the oracle
+    m = mols[0]
+    P = o.pair_vectors(m)
+    mm, fr = o.pair_bins(m.eig, m.n_occ, grid.domega)
+    nhb = o.hist_bins(m.eig, grid.n_omega, grid.domega)
+    s = o.frac_bits(P, m.n_pairs)
+    H = o.histogram(P, mm, fr, s, nhb)
+    js = [grid.n_omega // 2 + 3, 100]
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps, js=js),
+                         m.n_prod)
+    for i, j in enumerate(js):
+        Wr = o.screened_W(m.v, chi[i])
+        assert np.linalg.norm(Ws[0][j].cpu().numpy() - Wr) <= 1e-6 * np.linalg.norm(Wr)
+
+
+def test_newer_batch_retires_older(gpu):
+    gw, ctx, torch = gpu
+    grid = gs.config_grid(0)
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    m = gs.make_config(0)
+    dm = gw.DeviceMolecule(m)
+    c = torch.zeros((grid.n_omega, m.n_prod, m.n_prod), dtype=torch.complex128, device="cuda")
+    w = torch.zeros_like(c)
+    b1 = ctx.batch_create([dm.struct], [dm.v], g, [c], [w])
+    b2 = ctx.batch_create([dm.struct], [dm.v], g, [c], [w])
+    with pytest.raises(gw.GwError) as e:
+        b1.run()
+    assert e.value.status == gw.GW_E_STATE
+    b2.run()
+    torch.cuda.synchronize()
+    b1.close()
+    b2.close()
