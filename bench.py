@@ -6,9 +6,10 @@ One step = the whole hot path on one molecule: pair vertex, mesh bins, exact
 int64 histogram, FFT chi0 on all 1024 mesh points (gw_build_chi0), then
 W(omega) = (1 - v chi0)^{-1} v on all 1024 points (gw_solve_W: 513 factorised,
 the rest by the conjugate mirror).  Inputs are resident in HBM before the
-timed region.  Both precision forms are timed (FP64, and FP32 LU + FP64
-residual refinement); `value` is the faster form that meets the 1e-6 error
-target relative to the FP64 result.
+timed region.  The precision forms are timed in turn (FP64; FP32 LU + FP64
+residual refinement; the same with split-BF16 trailing updates); `value` is
+the fastest form that meets the 1e-6 error target relative to the FP64
+result.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -98,7 +99,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="fp64,fp32_ir")
+    ap.add_argument("--forms", default="fp64,fp32_ir,bf16x_ir")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -124,7 +125,7 @@ def main():
     W = torch.empty((N, n, n), dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream()
     forms = [f for f in args.forms.split(",") if f]
-    precs = {"fp64": gw.GW_FP64, "fp32_ir": gw.GW_FP32_IR}
+    precs = {"fp64": gw.GW_FP64, "fp32_ir": gw.GW_FP32_IR, "bf16x_ir": gw.GW_BF16X_IR}
     sample_js = [0, N // 2, N // 2 + 30, N // 2 + 100, N - 1, 200]
     W_ref = None
     results = {}

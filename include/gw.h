@@ -203,8 +203,8 @@ gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, cons
  * 4) parallel branches.  gw_batch_run replays that graph on `stream`.
  *   v[i]: DEVICE [n_i][n_i]; chi0_out[i], W_out[i]: DEVICE complex128
  *   [n_omega][n_i][n_i], caller-owned, fixed for the life of the batch.
- *   prec GW_FP64, or GW_FP32_IR with exactly n_refine (1..6) FP64 refinement
- *   steps in the graph; gw_batch_run then re-solves in FP64 every frequency
+ *   prec GW_FP64, or GW_FP32_IR / GW_BF16X_IR with exactly n_refine (1..6)
+ *   FP64 refinement steps in the graph; gw_batch_run then re-solves in FP64 every frequency
  *   whose last step left ||dW||_F > tol ||W||_F (counted in the report).
  *   reps: HOST [n_mol] or NULL (then gw_batch_run does not synchronise for
  *   FP64).  A later gw_batch_create on the same context retires earlier

@@ -550,11 +550,11 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     if (n_omega < 2 || (n_omega & 1)) return fail(ctx, GW_E_INVALID, "n_omega must be even and >= 2");
     if (prec != GW_FP64 && prec != GW_FP32_IR && prec != GW_BF16X_IR)
         return fail(ctx, GW_E_INVALID, "unknown precision");
-    if (prec == GW_BF16X_IR) return fail(ctx, GW_E_INVALID, "GW_BF16X_IR is not available in this build");
     if (prec != GW_FP64 && !(tol > 0.0)) return fail(ctx, GW_E_INVALID, "tol must be positive for mixed precision");
     hipStream_t st = as_stream(stream);
     const bool mixed = prec != GW_FP64;
     const int64_t nn = (int64_t)n * n;
+    gwp::Bf16xScope bf16x(prec == GW_BF16X_IR);
     gwp::SolvePlan p;
     gw_status s = gwp::solve_plan(ctx, n, n_omega, mixed, "", &p);
     if (s != GW_OK) return s;

@@ -199,6 +199,7 @@ gw_status record(gw_batch *b) {
     if (s == GW_OK) {
         hip(hipEventRecord(b->events[0], st), "fork");
         for (int r = 0; r < nbr; ++r) hip(hipStreamWaitEvent(b->branches[r], b->events[0], 0), "fork");
+        gwp::Bf16xScope bf16x(b->prec == GW_BF16X_IR);
         for (int i = 0; i < b->n_mol && s == GW_OK; ++i) {
             gwp::set_thread_gemm_tile(b->tile[i]);
             s = gwp::solve_enqueue_nosync(ctx, sp[i], b->branches[i % nbr], b->v[i], 0, (const gwp::zdbl *)b->chi0[i],
@@ -233,7 +234,8 @@ gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, c
     *out = nullptr;
     if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
     if (n_mol < 1 || !mols || !v || !g || !chi0_out || !W_out) return fail(ctx, GW_E_INVALID, "bad batch arguments");
-    if (prec != GW_FP64 && prec != GW_FP32_IR) return fail(ctx, GW_E_INVALID, "batch precision must be FP64 or FP32_IR");
+    if (prec != GW_FP64 && prec != GW_FP32_IR && prec != GW_BF16X_IR)
+        return fail(ctx, GW_E_INVALID, "unknown batch precision");
     if (prec != GW_FP64 && (n_refine < 1 || n_refine > 6 || !(tol > 0)))
         return fail(ctx, GW_E_INVALID, "mixed batch needs 1..6 refinement steps and tol > 0");
     for (int i = 0; i < n_mol; ++i)

@@ -82,5 +82,14 @@ gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, in
 
 // GEMM tile policy for the launches of the calling host thread (autotuner).
 void set_thread_gemm_tile(int tile);
+// Complex-float GEMMs of the calling host thread on split-BF16 MFMA (BF16x LU);
+// returns the previous setting.
+bool set_thread_cgemm_bf16x(bool on);
+// Scoped form: BF16x on for the lifetime of the guard when `on`.
+struct Bf16xScope {
+    bool prev;
+    explicit Bf16xScope(bool on) : prev(set_thread_cgemm_bf16x(on)) {}
+    ~Bf16xScope() { set_thread_cgemm_bf16x(prev); }
+};
 
 }  // namespace gwp

@@ -224,7 +224,7 @@ gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw
         ctx->err = "gw_submit: k_compress must be in [0, n_prod]";
         return GW_E_INVALID;
     }
-    if (prec != GW_FP64 && prec != GW_FP32_IR) {
+    if (prec != GW_FP64 && prec != GW_FP32_IR && prec != GW_BF16X_IR) {
         ctx->err = "gw_submit: precision not available for serving";
         return GW_E_INVALID;
     }

@@ -227,6 +227,159 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
             }
 }
 
+// ------------------------------------------------------------------ split-BF16 complex GEMM
+// C = alpha A B + beta C for complex float, on v_mfma_f32_16x16x32_bf16: every
+// float x is split into three bf16 terms x = h + m + l (round to nearest even
+// at each step, so each remainder is exact in float), and the six products
+// with h h, h m, m h, h l, m m, l h are accumulated in float.  The neglected
+// terms are below 2^-24 relative, so the result is as accurate as an FP32
+// product while running on the BF16 matrix rate.  Operand layout (measured on
+// gfx950): lane l holds A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16],
+// i = 0..7; result element r of lane l is D[4 (l / 16) + r][l % 16].
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline unsigned short bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+constexpr int XK = 32;  // complex k per stage
+
+__global__ __launch_bounds__(256, 1) void k_cgemm_bf16x(int M, int N, int K, float alpha, const float *__restrict__ A,
+                                                        int64_t lda, int64_t sA, const float *B, int64_t ldb,
+                                                        int64_t sB, float beta, float *C, int64_t ldc, int64_t sC) {
+    // planes [term 0..2][part re/im][row or col 0..63][k 0..31] of bf16
+    __shared__ unsigned short As[3][2][64][XK];
+    __shared__ unsigned short Bs[3][2][64][XK];
+    const int bz = blockIdx.z;
+    A += (int64_t)bz * sA * 2;
+    B += (int64_t)bz * sB * 2;
+    C += (int64_t)bz * sC * 2;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    f32x4 arr[2][2], aii[2][2], ari[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) arr[i][j] = aii[i][j] = ari[i][j] = f32x4{0, 0, 0, 0};
+    // staging: A thread (row = tid / 4, k = (tid % 4) * 8 .. +8); B thread (col = tid % 64, k = (tid / 64) * 8 .. +8)
+    const int a_row = tid >> 2, a_k = (tid & 3) * 8;
+    const int b_col = tid & 63, b_k = (tid >> 6) * 8;
+    float ar[8], ai[8], br[8], bi[8];
+    auto gload = [&](int k0) {
+        const int gr = m0 + a_row;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int gk = k0 + a_k + c;
+            if (gr < M && gk < K) {
+                const float *p = A + ((int64_t)gr * lda + gk) * 2;
+                ar[c] = p[0];
+                ai[c] = p[1];
+            } else {
+                ar[c] = 0.f;
+                ai[c] = 0.f;
+            }
+        }
+        const int gc = n0 + b_col;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int gk = k0 + b_k + c;
+            if (gc < N && gk < K) {
+                const float *p = B + ((int64_t)gk * ldb + gc) * 2;
+                br[c] = p[0];
+                bi[c] = p[1];
+            } else {
+                br[c] = 0.f;
+                bi[c] = 0.f;
+            }
+        }
+    };
+    auto split_store = [&](unsigned short (*P)[2][64][XK], int part, int rc, int k, const float *x) {
+        unsigned short h[8], mm[8], l[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            h[c] = bf16_rne(x[c]);
+            const float r1 = x[c] - bf16_to_f(h[c]);
+            mm[c] = bf16_rne(r1);
+            l[c] = bf16_rne(r1 - bf16_to_f(mm[c]));
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            P[0][part][rc][k + c] = h[c];
+            P[1][part][rc][k + c] = mm[c];
+            P[2][part][rc][k + c] = l[c];
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < K; k0 += XK) {
+        __syncthreads();
+        split_store(As, 0, a_row, a_k, ar);
+        split_store(As, 1, a_row, a_k, ai);
+        split_store(Bs, 0, b_col, b_k, br);
+        split_store(Bs, 1, b_col, b_k, bi);
+        __syncthreads();
+        if (k0 + XK < K) gload(k0 + XK);
+        // B fragments of all three terms for both column blocks
+        bf16x8 fb[3][2][2];  // [term][part][block j]
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int part = 0; part < 2; ++part)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    fb[t][part][j] = *reinterpret_cast<const bf16x8 *>(
+                        &Bs[t][part][wn * 32 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+        // A term t pairs with B terms q, t + q <= 2
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            bf16x8 fa[2][2];  // [part][block i]
+#pragma unroll
+            for (int part = 0; part < 2; ++part)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    fa[part][i] = *reinterpret_cast<const bf16x8 *>(
+                        &As[t][part][wm * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (t + q > 2) continue;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        arr[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[q][0][j], arr[i][j], 0, 0, 0);
+                        aii[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[q][1][j], aii[i][j], 0, 0, 0);
+                        ari[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][i], fb[q][1][j], ari[i][j], 0, 0, 0);
+                        ari[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][i], fb[q][0][j], ari[i][j], 0, 0, 0);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + e;
+                const int col = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (row < M && col < N) {
+                    float *pc = C + ((int64_t)row * ldc + col) * 2;
+                    float vr = alpha * (arr[i][j][e] - aii[i][j][e]);
+                    float vi = alpha * ari[i][j][e];
+                    if (beta != 0.f) {
+                        vr += beta * pc[0];
+                        vi += beta * pc[1];
+                    }
+                    pc[0] = vr;
+                    pc[1] = vi;
+                }
+            }
+}
+
 // A = 1 - diag(lam) chi0 (compressed metric), optional complex-float copy.
 __global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *__restrict__ chi0, int64_t s_chi,
                              zdbl *__restrict__ A, int64_t s_A, zflt *A32, int64_t s_A32) {
@@ -273,9 +426,20 @@ hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const
                                              sB, beta, (double *)C, ldc, sC, batch);
 }
 
+// Complex-float products of the calling thread run as split-BF16 MFMA when set
+// (the trailing updates of the BF16x LU).
+thread_local bool g_cgemm_bf16x = false;
+
 hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha, const zflt *A, int64_t lda, int64_t sA,
                         const zflt *B, int64_t ldb, int64_t sB, float beta, zflt *C, int64_t ldc, int64_t sC,
                         int batch) {
+    if (g_cgemm_bf16x && K >= 32) {
+        if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+        dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+        hipLaunchKernelGGL(k_cgemm_bf16x, grid, dim3(256), 0, st, M, N, K, alpha, (const float *)A, lda, sA,
+                           (const float *)B, ldb, sB, beta, (float *)C, ldc, sC);
+        return hipGetLastError();
+    }
     return launch_gemm_t<float, true, true>(st, M, N, K, alpha, (const float *)A, lda, sA, (const float *)B, ldb, sB,
                                             beta, (float *)C, ldc, sC, batch);
 }
@@ -323,4 +487,9 @@ hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const
 
 namespace gwp {
 void set_thread_gemm_tile(int tile) { gwk::g_gemm_tile = tile; }
+bool set_thread_cgemm_bf16x(bool on) {
+    const bool prev = gwk::g_cgemm_bf16x;
+    gwk::g_cgemm_bf16x = on;
+    return prev;
+}
 }  // namespace gwp

@@ -39,14 +39,14 @@ def _mols():
     ]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32_ir"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "bf16x_ir"])
 def test_batch_graph_replays_match_eager(gpu, prec):
     gw, ctx, torch = gpu
     grid = gs.config_grid(0)
     g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
     mols = _mols()
     dms = [gw.DeviceMolecule(m) for m in mols]
-    p = gw.GW_FP64 if prec == "fp64" else gw.GW_FP32_IR
+    p = {"fp64": gw.GW_FP64, "fp32_ir": gw.GW_FP32_IR, "bf16x_ir": gw.GW_BF16X_IR}[prec]
     # eager references, one molecule at a time
     ref = []
     for m, dm in zip(mols, dms):

@@ -94,7 +94,10 @@ def test_histogram_independent_of_launch_and_repeat(gpu):
     assert torch.equal(H1, H2)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32_ir", 1e-6)])
+_PREC = {"fp64": 0, "fp32_ir": 1, "bf16x_ir": 2}  # gw_precision values
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32_ir", 1e-6), ("bf16x_ir", 1e-6)])
 def test_W_matches_oracle_tiny(gpu, prec, tol):
     gw, ctx, torch = gpu
     mol, grid = gs.make_config(0), gs.config_grid(0)
@@ -104,11 +107,13 @@ def test_W_matches_oracle_tiny(gpu, prec, tol):
                              mol.n_prod)
     dm, chi, _, _ = _gpu_chi0(gw, ctx, torch, mol, grid, want_hist=False)
     W = torch.empty_like(chi)
-    p = gw.GW_FP64 if prec == "fp64" else gw.GW_FP32_IR
+    p = _PREC[prec]
     rep = ctx.solve_W(dm.v, mol.n_prod, chi, grid.n_omega, W, prec=p, tol=1e-8)
     torch.cuda.synchronize()
     Wg = W.cpu().numpy()
     assert rep.n_solved == grid.n_omega // 2 + 1
+    # the mixed forms must reach the tolerance themselves, not via the FP64 fallback
+    assert rep.n_fallback == 0
     worst = 0.0
     for j in range(grid.n_omega):
         Wr = o.screened_W(mol.v, chi_ref[j])
@@ -153,7 +158,7 @@ def test_single_product_closed_form(gpu):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32_ir", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32_ir", 1e-6), ("bf16x_ir", 1e-6)])
 def test_W_multi_tile_medium(gpu, prec, tol):
     """16-atom chain with the 1024-point mesh of the 40-atom workload: ~900
     products (14 LU panels, ragged last panel), W checked at sampled
@@ -166,8 +171,10 @@ def test_W_multi_tile_medium(gpu, prec, tol):
     dm, chi, Hg, rep = _gpu_chi0(gw, ctx, torch, mol, grid)
     assert np.array_equal(Hg.cpu().numpy(), H)
     W = torch.empty_like(chi)
-    p = gw.GW_FP64 if prec == "fp64" else gw.GW_FP32_IR
+    p = _PREC[prec]
     rep = ctx.solve_W(dm.v, mol.n_prod, chi, grid.n_omega, W, prec=p, tol=1e-8)
+    _say("report iters", rep.max_iter, "fallback", rep.n_fallback)
+    assert rep.n_fallback == 0
     N = grid.n_omega
     js = [N // 2, N // 2 + 20, N // 2 + 64, N // 2 + 150, N // 2 + 400, N - 1, 300, 0]
     chi_ref = o.unpack_upper(o.chi0_from_hist(H, s, N, grid.omega_min, grid.omega_max, grid.eps, js=js),
