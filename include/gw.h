@@ -166,7 +166,8 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g,
  *   prec: GW_FP64, or a mixed form refined with an FP64 residual
  *      r = v - (1 - v chi0) W until ||dW||_F <= tol ||W||_F (at most 6
  *      steps); a frequency that does not converge is re-solved in FP64.
- *   W_out: DEVICE complex128 [n_omega][n][n].
+ *   W_out: DEVICE complex128 [n_omega][n][n].  W_out == chi0 is allowed:
+ *      W then overwrites chi0 in place (half the HBM; chi0 is lost).
  *   rep: HOST or NULL; if non-NULL the call synchronises and reports.
  * n_omega must be even and at least 2.  The call synchronises the stream
  * once per refinement step for the mixed forms. */
@@ -206,6 +207,9 @@ gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, cons
  *   prec GW_FP64, or GW_FP32_IR / GW_BF16X_IR with exactly n_refine (1..6)
  *   FP64 refinement steps in the graph; gw_batch_run then re-solves in FP64 every frequency
  *   whose last step left ||dW||_F > tol ||W||_F (counted in the report).
+ *   W_out[i] == chi0_out[i] solves in place; the FP64 re-solve then has no
+ *   chi0 to start from, so such a frequency makes gw_batch_run return
+ *   GW_E_NOCONV (after filling every report).
  *   reps: HOST [n_mol] or NULL (then gw_batch_run does not synchronise for
  *   FP64).  A later gw_batch_create on the same context retires earlier
  *   batches (gw_batch_run on them returns GW_E_STATE).  Not thread-safe with
@@ -232,8 +236,32 @@ gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw
  * the device-resident result ([n_omega][n][n] complex128) and *rep filled. */
 gw_status gw_poll(gw_ctx *ctx, uint64_t ticket, void **W_dev, gw_report *rep);
 
-/* Frees the device result of a finished request. */
+/* Frees the device result of a finished (or failed) request, or cancels a
+ * request that is still waiting for admission; GW_E_STATE while it runs or
+ * for an unknown ticket.  The ticket is unknown afterwards. */
 gw_status gw_release(gw_ctx *ctx, uint64_t ticket);
+
+/* Kernel timing, for measurement against the rooflines.  While on, every
+ * launch of the library's main kernels made by calls on the calling host
+ * thread is bracketed by a pair of HIP events on its stream (launches recorded
+ * into a batch graph are not timed).  gw_profile_read waits for them and
+ * returns one entry per kernel class: launches, summed event time, and summed
+ * algorithmic work (flops for products: 8MNK complex, 4MNK real-by-complex;
+ * contributions for the histogram) and bytes (the operands read and written
+ * once).  Call all three from the thread that called gw_profile_begin; a new
+ * gw_profile_begin clears the sums.  The events cost a few microseconds per
+ * launch.
+ *   out: HOST [cap]; *n_out: number of classes (may exceed cap). */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double ms;
+    double flops;
+    double bytes;
+} gw_kernel_stat;
+gw_status gw_profile_begin(gw_ctx *ctx);
+gw_status gw_profile_read(gw_ctx *ctx, gw_kernel_stat *out, int32_t cap, int32_t *n_out);
+gw_status gw_profile_end(gw_ctx *ctx);
 
 #ifdef __cplusplus
 }

@@ -185,15 +185,18 @@ size_t per_freq_bytes(int n, bool mixed) {
 }
 
 int solve_batch_max(int n, int n_omega, bool mixed, size_t budget) {
+    // at most half the budget and 24 GiB of solve workspace: beyond a few
+    // dozen frequencies per batch the GEMMs are already wide enough
     const size_t pf = per_freq_bytes(n, mixed);
-    int nb = (int)std::max<size_t>(1, std::min<size_t>(budget / 2 / pf, 256));
+    const size_t cap = std::min<size_t>(budget / 2, (size_t)24 << 30);
+    int nb = (int)std::max<size_t>(1, std::min<size_t>(cap / pf, 256));
     return std::max(1, std::min(nb, n_omega / 2));
 }
 
 gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
                            zdbl *W, int nb, SolveWs &w) {
     const int64_t nn = (int64_t)n * n;
-    GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, nullptr, 0, nb));
+    if (chi0) GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, nullptr, 0, nb));
     GW_HIP(c, gwk::launch_fill_u32(st, (uint32_t *)w.info, nb, 0u));
     GW_HIP(c, gwk::getrf_batched<zdbl>(st, n, w.A, nn, w.ipiv, (zdbl *)w.Li, (zdbl *)w.Ui, (zdbl *)w.scratch, w.info, nb));
     GW_HIP(c, gwk::launch_perm(st, n, w.ipiv, w.perm, nb));
@@ -278,12 +281,17 @@ gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, i
     return GW_OK;
 }
 
-// frequency batches: {0}, then [n/2, n) in chunks of nbmax
+// frequency batches: {0}, then [n/2, n) in equal chunks of at most nbmax
 std::vector<std::pair<int, int>> freq_batches(int n_omega, int nbmax) {
     std::vector<std::pair<int, int>> b;
     if (n_omega == 2) return {{0, 2}};
     b.push_back({0, 1});
-    for (int j = n_omega / 2; j < n_omega; j += nbmax) b.push_back({j, std::min(nbmax, n_omega - j)});
+    const int cnt = n_omega / 2, nbat = (cnt + nbmax - 1) / nbmax;
+    for (int i = 0, j = n_omega / 2; i < nbat; ++i) {
+        const int sz = cnt / nbat + (i < cnt % nbat ? 1 : 0);
+        b.push_back({j, sz});
+        j += sz;
+    }
     return b;
 }
 
@@ -390,10 +398,11 @@ gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *c
     return GW_OK;
 }
 
-gw_status solve_plan(gw_ctx *ctx, int n, int n_omega, bool mixed, const std::string &pre, SolvePlan *p) {
+gw_status solve_plan(gw_ctx *ctx, int n, int n_omega, bool mixed, const std::string &pre, SolvePlan *p,
+                     size_t ws_budget) {
     const int64_t nn = (int64_t)n * n;
     const int nblk = (n + 63) / 64;
-    const int nbmax = solve_batch_max(n, n_omega, mixed, ctx->budget);
+    const int nbmax = solve_batch_max(n, n_omega, mixed, ws_budget ? ws_budget : ctx->budget);
     p->n = n;
     p->n_omega = n_omega;
     p->nbmax = nbmax;
@@ -483,6 +492,7 @@ gw_status gw_destroy(gw_ctx *ctx) {
     gwk_serve_stop(ctx);
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    gwk_prof_release(ctx);
     for (auto &kv : ctx->bufs)
         if (kv.second.ptr) (void)hipFree(kv.second.ptr);
     delete ctx;
@@ -576,12 +586,14 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
             if (s != GW_OK) return s;
             for (int b = 0; b < nb; ++b) {
                 if (its[b] < 0) {
-                    // not converged: FP64 fallback for this frequency
+                    // not converged: FP64 fallback for this frequency, from the FP64
+                    // A of the batch (chi0 may already be overwritten in place)
                     ++n_fallback;
                     gwp::SolvePlan p64;
                     if ((s = gwp::solve_plan(ctx, n, 2, false, "fb", &p64)) != GW_OK) return s;
-                    s = gwp::solve_batch_fp64(ctx, st, n, v, v_is_diag, X0 + (j0 + b) * nn, W + (j0 + b) * nn, 1,
-                                              p64.w);
+                    GW_HIP(ctx, hipMemcpyAsync(p64.w.A, p.w.A + (int64_t)b * nn, (size_t)nn * 16,
+                                               hipMemcpyDeviceToDevice, st));
+                    s = gwp::solve_batch_fp64(ctx, st, n, v, v_is_diag, nullptr, W + (j0 + b) * nn, 1, p64.w);
                     if (s != GW_OK) return s;
                 } else {
                     max_it = std::max(max_it, its[b]);

@@ -183,7 +183,8 @@ gw_status record(gw_batch *b) {
         for (int i = 0; i < b->n_mol; ++i) {
             gw_status s = gwp::build_plan(ctx, &b->mols[i], &b->g, nullptr, 0, st, "bb", nullptr, &bp[i]);
             if (s != GW_OK) return s;
-            s = gwp::solve_plan(ctx, b->n[i], b->g.n_omega, mixed, "bs" + std::to_string(i % nbr), &sp[i]);
+            s = gwp::solve_plan(ctx, b->n[i], b->g.n_omega, mixed, "bs" + std::to_string(i % nbr), &sp[i],
+                                ctx->budget / nbr);
             if (s != GW_OK) return s;
             sp[i].final_norms = b->norms[i];
         }
@@ -309,9 +310,11 @@ gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
     if (!mixed && !reps) return GW_OK;
     GW_HIP(ctx, hipStreamSynchronize(st));
     const int N = b->g.n_omega;
+    gw_status result = GW_OK;
     for (int i = 0; i < b->n_mol; ++i) {
         int fallback = 0, solved = 0;
         double worst = 0;
+        const bool in_place = b->W[i] == b->chi0[i];
         if (mixed) {
             std::vector<double> hn(2 * (size_t)N);
             GW_HIP(ctx, hipMemcpy(hn.data(), b->norms[i], sizeof(double) * 2 * N, hipMemcpyDeviceToHost));
@@ -326,6 +329,15 @@ gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
                 const double r = std::sqrt(hn[2 * j]) / std::max(std::sqrt(hn[2 * j + 1]), 1e-300);
                 if (r <= b->tol) {
                     worst = std::max(worst, r);
+                    continue;
+                }
+                if (in_place) {
+                    // chi0 was overwritten: no FP64 re-solve possible
+                    worst = std::max(worst, r);
+                    if (result == GW_OK)
+                        result = fail(ctx, GW_E_NOCONV,
+                                      "batched in-place solve: molecule " + std::to_string(i) + " frequency " +
+                                          std::to_string(j) + " did not reach the tolerance");
                     continue;
                 }
                 if (!planned) {
@@ -355,7 +367,7 @@ gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
             r.max_rel_update = worst;
         }
     }
-    return GW_OK;
+    return result;
 }
 
 gw_status gw_batch_destroy(gw_batch *b) {

@@ -12,6 +12,9 @@ struct DevBuf {
 };
 
 struct GwServe;  // serving state (gw_serve.cpp)
+namespace gwk {
+struct ProfSink;  // kernel timing (gw_prof.cpp)
+}
 
 struct gw_ctx {
     int device = 0;
@@ -26,8 +29,10 @@ struct gw_ctx {
     hipStream_t own_stream = nullptr;
     GwServe *serve = nullptr;
     uint64_t batch_generation = 0;
+    gwk::ProfSink *prof = nullptr;
 };
 
 void gwk_ctx_trim(gw_ctx *c);
 void gwk_serve_stop(gw_ctx *c);
+void gwk_prof_release(gw_ctx *c);
 size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget);

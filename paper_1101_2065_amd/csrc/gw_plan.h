@@ -70,7 +70,9 @@ struct SolvePlan {
 
 size_t per_freq_bytes(int n, bool mixed);
 int solve_batch_max(int n, int n_omega, bool mixed, size_t budget);
-gw_status solve_plan(gw_ctx *c, int n, int n_omega, bool mixed, const std::string &prefix, SolvePlan *p);
+// ws_budget: bytes the solve workspace may take (0: the context budget).
+gw_status solve_plan(gw_ctx *c, int n, int n_omega, bool mixed, const std::string &prefix, SolvePlan *p,
+                     size_t ws_budget = 0);
 // Enqueue all solves of one mesh: FP64, or FP32 with exactly fixed_ir FP64
 // refinement steps; the last step's norms go to p.final_norms.  No host
 // synchronisation.

@@ -8,7 +8,8 @@
 // slots' streams, so work of different molecules overlaps on the device.
 // After a request finishes, its transient workspace is freed and only the
 // results stay resident (chi0 and W, plus the compression basis) until
-// gw_release.  Requests are admitted in arrival order.
+// gw_release.  Requests are admitted in arrival order; gw_release on a request
+// still in the queue cancels it.
 #include "../../include/gw.h"
 #include "gw_ctx.h"
 
@@ -298,9 +299,13 @@ gw_status gw_release(gw_ctx *ctx, uint64_t ticket) {
             return GW_E_STATE;
         }
         ServeReq &r = *it->second;
-        if (r.state == Q_QUEUED || r.state == Q_RUNNING) {
-            ctx->err = "gw_release: request still pending";
+        if (r.state == Q_RUNNING) {
+            ctx->err = "gw_release: request is running";
             return GW_E_STATE;
+        }
+        if (r.state == Q_QUEUED) {
+            // not admitted yet: cancel
+            sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), ticket));
         }
         if (r.state == Q_DONE) sv->in_use -= r.bytes_result;
         free_results(r);

@@ -2,6 +2,7 @@
 // spectral function as an FFT convolution with a precomputed kernel spectrum
 // (Section 5.A eq. chi_by_spectra; Section 8.A does its convolutions by FFT).
 #include "gw_internal.h"
+#include "gw_prof.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -226,6 +227,7 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
     const int nch = (n + 15) / 16;
     dim3 grid((unsigned)((int64_t)n * nch));
     const int L = 2 * n_omega;
+    ProfScope ps(st, "fftconv", 0.0, 8.0 * nhb * (double)n_upper + 16.0 * n_omega * (double)n * n);
 #define GW_FFT_CASE(LL)                                                                                    \
     case LL:                                                                                               \
         hipLaunchKernelGGL(k_fftconv<LL>, grid, dim3(256), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \

@@ -8,6 +8,7 @@
 //   spectral function Section 5.A eq. chi_by_spectra (odd extension a(-s) = -a(s))
 //   mesh              Section 5 and 5.B
 #include "gw_internal.h"
+#include "gw_prof.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -392,6 +393,7 @@ hipError_t launch_hist(hipStream_t st, int n, int64_t n_pairs_cap, const double 
     const int ntiles = (n + HT - 1) / HT;
     const int ntp = ntiles * (ntiles + 1) / 2;
     if (splits < 1) splits = 1;
+    ProfScope ps(st, "hist", (double)n_pairs_cap * n_upper, 8.0 * (double)n_pairs_cap * n + 8.0 * nhb * n_upper);
     hipLaunchKernelGGL(k_hist, dim3(ntp, splits), dim3(256), 0, st, n, n_pairs_cap, Ps, fsort, binoff, stat, s_dev,
                        nhb, (unsigned long long *)H, n_upper, ntiles, splits);
     return hipGetLastError();

@@ -10,6 +10,7 @@
 // wave, K steps of 8).  K is staged through a double-buffered LDS tile, the
 // next step prefetched into registers.
 #include "gw_internal.h"
+#include "gw_prof.h"
 
 #include <hip/hip_runtime.h>
 
@@ -405,6 +406,21 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     int tile = g_gemm_tile;
     if (tile < 0) tile = (AC && BC && M >= 128 && K >= 64) ? 1 : 0;
+    ProfSink *prof = g_prof;
+    const char *cls = nullptr;
+    double flops = 0, bytes = 0;
+    if (prof) {
+        const bool dbl = sizeof(T) == 8;
+        if (AC && BC) cls = dbl ? (tile == 1 ? "zgemm_128x64" : "zgemm_64x64") : (tile == 1 ? "cgemm_128x64" : "cgemm_64x64");
+        else if (BC) cls = add_eye ? "formA" : "dzgemm";
+        else if (AC) cls = "zdgemm";
+        else cls = "dgemm";
+        const double ea = sizeof(T) * (AC ? 2 : 1), eb = sizeof(T) * (BC ? 2 : 1), ec = sizeof(T) * ((AC || BC) ? 2 : 1);
+        flops = (AC && BC ? 8.0 : (AC || BC) ? 4.0 : 2.0) * M * N * (double)K * batch;
+        bytes = (double)M * K * ea * (sA ? batch : 1) + (double)K * N * eb * (sB ? batch : 1) +
+                (double)M * N * ec * batch * (beta != T(0) ? 2 : 1);
+    }
+    ProfScope ps(st, cls ? cls : "", flops, bytes);
     if (tile == 1) {
         dim3 grid((N + 63) / 64, (M + 127) / 128, batch);
         hipLaunchKernelGGL((k_gemm<T, AC, BC, 4, 2, 8>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb,
@@ -436,6 +452,8 @@ hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha, const 
     if (g_cgemm_bf16x && K >= 32) {
         if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
         dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+        ProfScope ps(st, "cgemm_bf16x", 8.0 * M * N * (double)K * batch,
+                     8.0 * ((double)M * K + (double)K * N + (beta != 0.f ? 2.0 : 1.0) * M * N) * batch);
         hipLaunchKernelGGL(k_cgemm_bf16x, grid, dim3(256), 0, st, M, N, K, alpha, (const float *)A, lda, sA,
                            (const float *)B, ldb, sB, beta, (float *)C, ldc, sC);
         return hipGetLastError();

@@ -13,6 +13,7 @@
 // A22 -= L21 U12 run on the MFMA GEMM.  The solve uses the stored inverses the
 // same way, so every O(N^3) flop of factor and solve is an MFMA product.
 #include "gw_internal.h"
+#include "gw_prof.h"
 
 #include <hip/hip_runtime.h>
 
@@ -702,6 +703,7 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
         for (int kb = KB; kb < KB + WO; kb += NB) {
             const int w = min(NB, n - kb);
             const int m = n - kb;
+            ProfScope ps(st, "lu_panel", 0.0, 2.0 * m * w * sizeof(Cx<T>) * (double)batch);
             if (m <= 512)
                 hipLaunchKernelGGL((k_getf2r<T, 1>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
                                    Uinv, nblk, swp, info);
@@ -722,6 +724,7 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
                                    scratch, swp, info);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (n - w > 0) {
+                ProfScope pl(st, "laswp", 0.0, 2.0 * w * (n - w) * sizeof(Cx<T>) * (double)batch);
                 hipLaunchKernelGGL(k_laswp<T>, dim3((n - w + 31) / 32, batch), dim3(256), 0, st, n, kb, w, A, sA, swp);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
             }
@@ -871,6 +874,7 @@ hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *pe
 hipError_t launch_init_rhs_perm(hipStream_t st, int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
                                 int64_t sB, int batch) {
     dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
+    ProfScope ps(st, "init_rhs", 0.0, 16.0 * (double)n * n * batch);
     hipLaunchKernelGGL(k_init_rhs, grid, dim3(256), 0, st, n, v, v_is_diag, perm, B, sB);
     return hipGetLastError();
 }
@@ -882,6 +886,7 @@ hipError_t launch_init_rhs(hipStream_t st, int n, const double *v, int v_is_diag
 hipError_t launch_conj_mirror(hipStream_t st, int64_t nn, int n_omega, zdbl *W) {
     if (n_omega < 4) return hipSuccess;
     dim3 grid((unsigned)((nn + 255) / 256), n_omega / 2 - 1);
+    ProfScope ps(st, "conj_mirror", 0.0, 2.0 * 16.0 * (double)nn * (n_omega / 2 - 1));
     hipLaunchKernelGGL(k_conj_mirror, grid, dim3(256), 0, st, nn, n_omega, W);
     return hipGetLastError();
 }

@@ -59,6 +59,13 @@ class gw_sizes(ctypes.Structure):
     ]
 
 
+class gw_kernel_stat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+        ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+    ]
+
+
 _P = ctypes.c_void_p
 _SIGS = {
     "gw_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_P)]),
@@ -82,6 +89,10 @@ _SIGS = {
                                        ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "gw_batch_run": (ctypes.c_int, [_P, _P, ctypes.POINTER(gw_report)]),
     "gw_batch_destroy": (ctypes.c_int, [_P]),
+    "gw_profile_begin": (ctypes.c_int, [_P]),
+    "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(gw_kernel_stat), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "gw_profile_end": (ctypes.c_int, [_P]),
 }
 
 
@@ -195,6 +206,21 @@ class Context:
 
     def release(self, ticket: int):
         self._check(lib.gw_release(self.h, ticket), "gw_release")
+
+    def profile_begin(self):
+        self._check(lib.gw_profile_begin(self.h), "gw_profile_begin")
+
+    def profile_read(self):
+        """Per kernel class: dict(name, launches, ms, flops, bytes)."""
+        cap = 64
+        arr = (gw_kernel_stat * cap)()
+        n = ctypes.c_int32()
+        self._check(lib.gw_profile_read(self.h, arr, cap, ctypes.byref(n)), "gw_profile_read")
+        return [{"name": a.name.decode(), "launches": a.launches, "ms": a.ms, "flops": a.flops, "bytes": a.bytes}
+                for a in arr[: min(n.value, cap)]]
+
+    def profile_end(self):
+        self._check(lib.gw_profile_end(self.h), "gw_profile_end")
 
     def batch_create(self, mols, vs, grid: "gw_grid", chi0_outs, W_outs, prec: int = GW_FP64,
                      tol: float = 1e-7, n_refine: int = 2, stream=None) -> "Batch":

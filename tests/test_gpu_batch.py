@@ -92,6 +92,48 @@ def test_batch_graph_replays_match_eager(gpu, prec):
         assert np.linalg.norm(Ws[0][j].cpu().numpy() - Wr) <= 1e-6 * np.linalg.norm(Wr)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x_ir"])
+def test_batch_in_place(gpu, prec):
+    """W_out[i] == chi0_out[i]: every replay rebuilds chi0 and overwrites it
+    with W; results equal the eager out-of-place solve."""
+    gw, ctx, torch = gpu
+    grid = gs.config_grid(0)
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    mols = _mols()[1:]
+    dms = [gw.DeviceMolecule(m) for m in mols]
+    p = {"fp64": gw.GW_FP64, "bf16x_ir": gw.GW_BF16X_IR}[prec]
+    ref = []
+    for m, dm in zip(mols, dms):
+        c = torch.empty((grid.n_omega, m.n_prod, m.n_prod), dtype=torch.complex128, device="cuda")
+        w = torch.empty_like(c)
+        ctx.build_chi0(dm.struct, g, c)
+        ctx.solve_W(dm.v, m.n_prod, c, grid.n_omega, w)
+        ref.append(w.cpu().numpy())
+    bufs = [torch.zeros((grid.n_omega, m.n_prod, m.n_prod), dtype=torch.complex128, device="cuda") for m in mols]
+    stream = torch.cuda.current_stream()
+    b = ctx.batch_create([dm.struct for dm in dms], [dm.v for dm in dms], g, bufs, bufs, prec=p, tol=1e-6,
+                         n_refine=3, stream=stream)
+    for replay in range(2):
+        for w in bufs:
+            w.fill_(float("nan"))
+        b.run(stream=stream)
+        torch.cuda.synchronize()
+        for i, (w, r) in enumerate(zip(bufs, ref)):
+            e = np.linalg.norm(w.cpu().numpy() - r) / np.linalg.norm(r)
+            _say(prec, "in place replay", replay, "molecule", i, "rel vs eager", e)
+            assert e < (1e-12 if prec == "fp64" else 1e-6)
+    b.close()
+    if prec != "fp64":
+        # a tolerance that three refinement steps cannot reach: with chi0
+        # overwritten there is no FP64 re-solve, so the run reports it
+        b = ctx.batch_create([dm.struct for dm in dms], [dm.v for dm in dms], g, bufs, bufs, prec=p, tol=1e-15,
+                             n_refine=1, stream=stream)
+        with pytest.raises(gw.GwError) as e:
+            b.run(stream=stream)
+        assert e.value.status == gw.GW_E_NOCONV
+        b.close()
+
+
 def test_newer_batch_retires_older(gpu):
     gw, ctx, torch = gpu
     grid = gs.config_grid(0)

@@ -122,6 +122,25 @@ def test_W_matches_oracle_tiny(gpu, prec, tol):
     assert worst < tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_ir", "bf16x_ir"])
+def test_W_in_place_equals_out_of_place(gpu, prec):
+    """W_out == chi0: the in-place solve gives bit-for-bit the out-of-place W
+    (same kernels on the same inputs), for a ragged multi-panel size."""
+    gw, ctx, torch = gpu
+    mol = gs.chain_molecule(3, 5)
+    grid = gs.config_grid(0)
+    _say("in place", prec, "n_prod", mol.n_prod)
+    dm, chi, _, _ = _gpu_chi0(gw, ctx, torch, mol, grid, want_hist=False)
+    W = torch.empty_like(chi)
+    p = _PREC[prec]
+    r1 = ctx.solve_W(dm.v, mol.n_prod, chi, grid.n_omega, W, prec=p, tol=1e-8)
+    buf = chi.clone()
+    r2 = ctx.solve_W(dm.v, mol.n_prod, buf, grid.n_omega, buf, prec=p, tol=1e-8)
+    torch.cuda.synchronize()
+    assert r1.n_fallback == r2.n_fallback == 0
+    assert torch.equal(buf, W)
+
+
 def test_W_is_v_without_vertex(gpu):
     """V = 0: chi0 = 0 and W = v exactly (identity LU, no rounding)."""
     gw, ctx, torch = gpu
@@ -186,3 +205,22 @@ def test_W_multi_tile_medium(gpu, prec, tol):
         e = _rel(W[j].cpu().numpy(), Wr)
         _say("j", j, "rel", e)
         assert e < tol
+
+
+def test_kernel_timing_counts_the_work(gpu):
+    """gw_profile_*: the form-A product of every solved frequency is timed and
+    its algorithmic flops are exactly 4 n^3 per frequency."""
+    gw, ctx, torch = gpu
+    mol = gs.chain_molecule(3, 5)
+    grid = gs.config_grid(0)
+    dm, chi, _, _ = _gpu_chi0(gw, ctx, torch, mol, grid, want_hist=False)
+    W = torch.empty_like(chi)
+    ctx.profile_begin()
+    rep = ctx.solve_W(dm.v, mol.n_prod, chi, grid.n_omega, W)
+    st = {s["name"]: s for s in ctx.profile_read()}
+    ctx.profile_end()
+    _say({k: (v["launches"], round(v["ms"], 3)) for k, v in st.items()})
+    n = mol.n_prod
+    assert st["formA"]["flops"] == 4.0 * n ** 3 * rep.n_solved
+    assert all(v["ms"] > 0 and v["launches"] > 0 for v in st.values())
+    assert any(k.startswith("zgemm") for k in st) and "lu_panel" in st

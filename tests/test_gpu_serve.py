@@ -131,3 +131,34 @@ def test_serving_error_paths(gpu):
         ctx.submit(dm.struct, dm.v, g, k_compress=dm.n_prod + 1)
     assert e.value.status == gw.GW_E_INVALID
     ctx.close()
+
+
+def test_release_cancels_a_queued_request(gpu):
+    """A request that cannot be admitted waits in the queue; gw_release
+    cancels it, its ticket becomes unknown, and the queue keeps moving."""
+    gw, torch = gpu
+    grid = gs.config_grid(0)
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    m = gs.chain_molecule(3, 5)  # 152 products
+    # One request keeps 32 * 152^2 * 256 B = 189 MB of results until released
+    # and needs about 300 MB at its peak, so under a 384 MiB budget a second
+    # request cannot be admitted while the first one's results are held.
+    ctx = gw.Context(0, budget_bytes=384 << 20)
+    dm = gw.DeviceMolecule(m)
+    t1 = ctx.submit(dm.struct, dm.v, g)
+    ptr1, _ = _wait(ctx, t1)
+    t2 = ctx.submit(dm.struct, dm.v, g)
+    time.sleep(0.2)
+    assert ctx.poll(t2) is None  # still waiting for admission
+    ctx.release(t2)
+    with pytest.raises(gw.GwError) as e:
+        ctx.poll(t2)
+    assert e.value.status == gw.GW_E_STATE
+    first = _fetch(gw, torch, ptr1, grid.n_omega, m.n_prod)
+    ctx.release(t1)
+    t3 = ctx.submit(dm.struct, dm.v, g)
+    ptr3, _ = _wait(ctx, t3)
+    again = _fetch(gw, torch, ptr3, grid.n_omega, m.n_prod)
+    assert np.array_equal(first, again)
+    ctx.release(t3)
+    ctx.close()
