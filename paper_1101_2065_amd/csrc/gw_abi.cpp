@@ -622,7 +622,7 @@ gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, 
     hipStream_t st = as_stream(stream);
     void *work;
     gw_status s;
-    if ((s = ws(ctx, "cWork", sizeof(double) * (3 * (size_t)k * n + k + 16), &work)) != GW_OK) return s;
+    if ((s = ws(ctx, "cWork", sizeof(double) * gwk::compress_work_doubles(n, k), &work)) != GW_OK) return s;
     hipError_t e = gwk::compress_basis(st, n, k, v, Q_out, S_out, (double *)work, 4);
     if (e == hipErrorUnknown) return fail(ctx, GW_E_NOCONV, "subspace iteration lost a direction (v not finite?)");
     GW_HIP(ctx, e);

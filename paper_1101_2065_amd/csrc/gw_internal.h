@@ -104,7 +104,8 @@ hipError_t launch_residual(hipStream_t st, int n, const double *v, int v_is_diag
                            zdbl *R, int64_t sR, int batch);
 
 // Orthonormal basis Q [n][k] of the dominant k-dimensional eigenspace of v and
-// S = Q^T v Q [k][k] (shifted subspace iteration); work: 3 k n + k + 16 doubles.
+// S = Q^T v Q [k][k] (shifted subspace iteration); work: compress_work_doubles.
+size_t compress_work_doubles(int n, int k);
 hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double *Q_out, double *S_out,
                           double *work, int iters);
 

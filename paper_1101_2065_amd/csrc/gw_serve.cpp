@@ -12,6 +12,7 @@
 // still in the queue cancels it.
 #include "../../include/gw.h"
 #include "gw_ctx.h"
+#include "gw_internal.h"
 
 #include <hip/hip_runtime.h>
 
@@ -74,7 +75,7 @@ size_t est_transient(const gw_molecule &m, int k, int n_omega, gw_precision prec
         b += 8 * n_prod * std::min(n_occ, chunk_rows) * n_virt;  // pair-vector chunk
         b += 8 * kk * n_pairs;                                   // projected pair vectors
         b += 8 * (size_t)k * n_prod;                             // basis transpose
-        b += 8 * (3 * (size_t)k * n_prod + k + 16);              // basis iteration
+        b += 8 * gwk::compress_work_doubles((int)n_prod, k);     // basis iteration
     } else {
         b += 8 * n_prod * n_pairs;
     }
