@@ -437,14 +437,16 @@ def run_c4(args, gw, gs, torch):
                 break
             time.sleep(0.001)
         t_window = time.perf_counter() - t_start
-        # end of the arrival window: cancel what is still queued, finish what runs
-        for t in list(pending):
-            try:
-                ctx.release(t)
-                pending.pop(t)
-                cancelled += 1
-            except gw.GwError:
-                pass
+        # end of the arrival window: when overloaded, cancel what is still
+        # queued; in every case finish what was admitted
+        if label == "overloaded":
+            for t in list(pending):
+                try:
+                    ctx.release(t)
+                    pending.pop(t)
+                    cancelled += 1
+                except gw.GwError:
+                    pass
         while pending:
             for t in list(pending):
                 r = ctx.poll(t)
@@ -484,7 +486,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mols", type=int, default=64, help="c3: number of molecules")
     ap.add_argument("--rate", type=float, default=20.0, help="c4: offered requests/s")
-    ap.add_argument("--low-rate", type=float, default=1.0, help="c4: the below-capacity run")
+    ap.add_argument("--low-rate", type=float, default=0.3, help="c4: the below-capacity run")
     ap.add_argument("--duration", type=float, default=60.0, help="c4: arrival window (s)")
     ap.add_argument("--pool", type=int, default=32, help="c4: distinct molecules drawn by the arrivals")
     args = ap.parse_args()

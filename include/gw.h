@@ -228,7 +228,9 @@ gw_status gw_batch_destroy(gw_batch *b);
  *   k_compress: 0 for the full basis, else the rank of the top-k compression
  *   (W_dev then holds X [n_omega][k][k] complex128 followed by Q [n][k]
  *   doubles, W = Q X Q^T).
- *   v: DEVICE [n_prod][n_prod] Coulomb metric of the molecule. */
+ *   v: DEVICE [n_prod][n_prod] Coulomb metric of the molecule.
+ * GW_SERVE_SLOTS (default 2) sets the number of concurrent slots;
+ * GW_SERVE_TRACE=1 prints each request's phase times to stderr. */
 gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
                     int32_t k_compress, gw_precision prec, double tol, uint64_t *ticket);
 

@@ -49,20 +49,25 @@ gw_status fail(gw_ctx *c, gw_status s, const std::string &msg) {
     return s;
 }
 
-// Grow-only named device buffers.  Reallocation waits for the device first.
+// Grow-only named device buffers.  Reallocation waits for the device first,
+// except in a serving slot's context: that context only ever uses its own
+// stream, so its buffers are stream-ordered allocations on it (no device-wide
+// synchronisation, memory recycled by the device's pool).
 gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out) {
     DevBuf &b = c->bufs[name];
     if (bytes == 0) bytes = 256;
     if (b.bytes < bytes) {
         if (b.ptr) {
-            // a serving slot's context only ever uses its own stream
-            if (c->own_stream) GW_HIP(c, hipStreamSynchronize(c->own_stream));
-            else GW_HIP(c, hipDeviceSynchronize());
-            GW_HIP(c, hipFree(b.ptr));
+            if (c->own_stream) {
+                GW_HIP(c, hipFreeAsync(b.ptr, c->own_stream));
+            } else {
+                GW_HIP(c, hipDeviceSynchronize());
+                GW_HIP(c, hipFree(b.ptr));
+            }
             b.ptr = nullptr;
             b.bytes = 0;
         }
-        hipError_t e = hipMalloc(&b.ptr, bytes);
+        hipError_t e = c->own_stream ? gwk_malloc_async(&b.ptr, bytes, c->own_stream) : hipMalloc(&b.ptr, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             b.ptr = nullptr;
@@ -494,7 +499,11 @@ gw_status gw_destroy(gw_ctx *ctx) {
     (void)hipDeviceSynchronize();
     gwk_prof_release(ctx);
     for (auto &kv : ctx->bufs)
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        if (kv.second.ptr) {
+            if (ctx->own_stream) (void)hipFreeAsync(kv.second.ptr, ctx->own_stream);
+            else (void)hipFree(kv.second.ptr);
+        }
+    if (ctx->own_stream) (void)hipStreamSynchronize(ctx->own_stream);
     delete ctx;
     return GW_OK;
 }
@@ -652,12 +661,38 @@ gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, cons
 // Free every workspace buffer of a context (serving slots do this after each
 // request so that admission can count transient memory exactly).
 void gwk_ctx_trim(gw_ctx *c) {
-    if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
-    else (void)hipDeviceSynchronize();
-    for (auto &kv : c->bufs)
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    if (c->own_stream) {
+        for (auto &kv : c->bufs)
+            if (kv.second.ptr) (void)hipFreeAsync(kv.second.ptr, c->own_stream);
+    } else {
+        (void)hipDeviceSynchronize();
+        for (auto &kv : c->bufs)
+            if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    }
     c->bufs.clear();
     c->ks_n = 0;
+}
+
+// Stream-ordered allocation from the device's pool.  The pool keeps freed
+// memory for reuse; when it cannot satisfy a request from that cache (sizes
+// differ) and the device is out of memory, the cache is handed back to the
+// device and the allocation tried once more.
+hipError_t gwk_malloc_async(void **p, size_t bytes, hipStream_t st) {
+    hipError_t e = hipMallocAsync(p, bytes, st);
+    if (e != hipErrorOutOfMemory) return e;
+    (void)hipGetLastError();
+    int dev = 0;
+    hipMemPool_t pool = nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess || !pool) return e;
+    (void)hipStreamSynchronize(st);
+    (void)hipMemPoolTrimTo(pool, 0);
+    return hipMallocAsync(p, bytes, st);
+}
+
+size_t gwk_ctx_bytes(const gw_ctx *c) {
+    size_t b = 0;
+    for (auto &kv : c->bufs) b += kv.second.bytes;
+    return b;
 }
 
 size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) { return solve_ws_bytes(n, n_omega, mixed, budget); }

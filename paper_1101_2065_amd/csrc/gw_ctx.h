@@ -33,6 +33,8 @@ struct gw_ctx {
 };
 
 void gwk_ctx_trim(gw_ctx *c);
+size_t gwk_ctx_bytes(const gw_ctx *c);
+hipError_t gwk_malloc_async(void **p, size_t bytes, hipStream_t st);
 void gwk_serve_stop(gw_ctx *c);
 void gwk_prof_release(gw_ctx *c);
 size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget);

@@ -3,11 +3,15 @@
 // gw_submit queues a request and returns a ticket at once.  A fixed number of
 // slots (GW_SERVE_SLOTS, default 2) each own a host thread, a HIP stream and a
 // private context.  A free slot admits the request at the head of the queue
-// as soon as its estimated HBM footprint (transient workspace + results) fits
-// under the context's budget; admitted requests run concurrently on their
-// slots' streams, so work of different molecules overlaps on the device.
-// After a request finishes, its transient workspace is freed and only the
-// results stay resident (chi0 and W, plus the compression basis) until
+// as soon as its estimated HBM footprint (workspace + results) fits under the
+// context's budget, next to the results still held and the workspace the
+// other slots keep; admitted requests run concurrently on their slots'
+// streams, so work of different molecules overlaps on the device.  All
+// serving memory is stream-ordered (hipMallocAsync / hipFreeAsync on the
+// slot's stream, recycled by the device pool), so no allocation or release
+// synchronises the device.  A slot keeps its workspace for the next request
+// and only gives it back when the head of the queue would not fit otherwise;
+// the results (chi0 and W, plus the compression basis) stay resident until
 // gw_release.  Requests are admitted in arrival order; gw_release on a request
 // still in the queue cancels it.
 #include "../../include/gw.h"
@@ -17,6 +21,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <condition_variable>
 #include <cstdlib>
 #include <deque>
@@ -39,9 +45,10 @@ struct ServeReq {
     int k = 0, kk = 0;
     gw_precision prec = GW_FP64;
     double tol = 1e-7;
-    size_t bytes_result = 0, bytes_peak = 0;
+    size_t bytes_result = 0, bytes_ws = 0, bytes_peak = 0;
     ReqState state = Q_QUEUED;
     void *chi = nullptr, *res = nullptr, *Q = nullptr, *S = nullptr;
+    hipStream_t stream = nullptr;  // the slot stream its buffers were allocated on
     gw_report rep{};
     gw_status status = GW_OK;
     std::string err;
@@ -54,7 +61,9 @@ struct GwServe {
     std::condition_variable cv;
     std::deque<uint64_t> queue;
     std::map<uint64_t, std::unique_ptr<ServeReq>> reqs;
-    size_t budget = 0, in_use = 0;
+    size_t budget = 0;
+    size_t results = 0;        // result buffers of running and finished, unreleased requests
+    std::vector<size_t> held;  // workspace each slot keeps between requests
     size_t slot_ws_budget = 0;
     std::vector<std::thread> workers;
     bool stop = false;
@@ -87,7 +96,39 @@ size_t est_transient(const gw_molecule &m, int k, int n_omega, gw_precision prec
     return b + (64ull << 20);
 }
 
+// GW_SERVE_TRACE=1: one line per request on stderr with its phase times.
+bool trace_on() {
+    static const bool on = [] {
+        const char *e = std::getenv("GW_SERVE_TRACE");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
+    const bool tr = trace_on();
+    double t[6] = {now_ms(), 0, 0, 0, 0, 0};
+    auto mark = [&](int i) {
+        if (!tr) return;
+        (void)hipStreamSynchronize(st);
+        t[i] = now_ms();
+    };
+    struct Report {
+        bool on;
+        double *t;
+        ServeReq &r;
+        ~Report() {
+            if (on)
+                std::fprintf(stderr, "gw serve: ticket %llu n_prod %d k %d basis %.1f alloc %.1f chi0 %.1f solve %.1f "
+                                     "total %.1f ms\n",
+                             (unsigned long long)r.ticket, r.mol.n_prod, r.k, t[1] - t[0], t[2] - t[1], t[3] - t[2],
+                             t[4] - t[3], now_ms() - t[0]);
+        }
+    } report{tr, t, r};
     auto hip_ok = [&](hipError_t e, const char *what) {
         if (e == hipSuccess) return true;
         r.status = e == hipErrorOutOfMemory ? GW_E_OOM : GW_E_DEVICE;
@@ -97,8 +138,8 @@ void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
     const size_t nn = (size_t)r.kk * r.kk;
     const size_t n = r.mol.n_prod;
     if (r.k) {
-        if (!hip_ok(hipMalloc(&r.Q, 8 * n * r.k), "basis")) return;
-        if (!hip_ok(hipMalloc(&r.S, 8 * (size_t)r.k * r.k), "metric")) return;
+        if (!hip_ok(gwk_malloc_async((void **)&r.Q, 8 * n * r.k, st), "basis")) return;
+        if (!hip_ok(gwk_malloc_async((void **)&r.S, 8 * (size_t)r.k * r.k, st), "metric")) return;
         gw_status s = gw_compress_basis(child, r.v, (int)n, r.k, st, (double *)r.Q, (double *)r.S);
         if (s != GW_OK) {
             r.status = s;
@@ -106,11 +147,14 @@ void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
             return;
         }
     }
-    if (!hip_ok(hipMalloc(&r.chi, 16 * nn * r.grid.n_omega), "chi0")) return;
+    mark(1);
+    if (!hip_ok(gwk_malloc_async((void **)&r.chi, 16 * nn * r.grid.n_omega, st), "chi0")) return;
     const size_t res_bytes = 16 * nn * r.grid.n_omega + (r.k ? 8 * n * r.k : 0);
-    if (!hip_ok(hipMalloc(&r.res, res_bytes), "W")) return;
+    if (!hip_ok(gwk_malloc_async((void **)&r.res, res_bytes, st), "W")) return;
+    mark(2);
     gw_report rb{}, rs{};
     gw_status s = gw_build_chi0(child, &r.mol, &r.grid, (const double *)r.Q, r.k, st, nullptr, r.chi, &rb);
+    mark(3);
     if (s == GW_OK)
         s = gw_solve_W(child, r.k ? (const double *)r.S : r.v, 0, r.kk, r.chi, r.grid.n_omega, r.prec, r.tol, st,
                        r.res, &rs);
@@ -124,21 +168,36 @@ void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
         if (!hip_ok(hipMemcpyAsync(tail, r.Q, 8 * n * r.k, hipMemcpyDeviceToDevice, st), "copy basis")) return;
     }
     if (!hip_ok(hipStreamSynchronize(st), "stream")) return;
+    mark(4);
     r.rep = rs;
     r.rep.n_hbins = rb.n_hbins;
     r.rep.frac_bits_used = rb.frac_bits_used;
     r.rep.n_dropped_pairs = rb.n_dropped_pairs;
 }
 
+// Stream-ordered free on the stream that produced the buffers (no device-wide
+// synchronisation; the memory goes back to the device's pool).
 void free_results(ServeReq &r) {
     for (void **p : {&r.chi, &r.res, &r.Q, &r.S})
         if (*p) {
-            (void)hipFree(*p);
+            (void)hipFreeAsync(*p, r.stream);
             *p = nullptr;
         }
 }
 
-void worker(GwServe *sv) {
+// Can slot i admit h?  Results in use, every other slot's kept workspace and
+// this slot's workspace grown to h's estimate must fit the budget.
+bool fits(const GwServe *sv, int i, const ServeReq *h) {
+    size_t others = 0;
+    for (size_t j = 0; j < sv->held.size(); ++j)
+        if ((int)j != i) others += sv->held[j];
+    return sv->results + h->bytes_result + others + std::max(sv->held[i], h->bytes_ws) <= sv->budget;
+}
+
+// One serving slot.  The slot keeps its workspace between requests (no
+// allocation churn); it gives it back only when the request at the head of
+// the queue would not fit otherwise.
+void worker(GwServe *sv, int slot) {
     (void)hipSetDevice(sv->device);
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
@@ -150,31 +209,52 @@ void worker(GwServe *sv) {
     child->own_stream = st;
     for (;;) {
         ServeReq *r = nullptr;
+        bool trim = false;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv.wait(lk, [&] {
-                if (sv->stop) return true;
-                if (sv->queue.empty()) return false;
-                ServeReq *h = sv->reqs[sv->queue.front()].get();
-                return sv->in_use + h->bytes_peak <= sv->budget;
-            });
+            for (;;) {
+                if (sv->stop) break;
+                if (!sv->queue.empty()) {
+                    ServeReq *h = sv->reqs[sv->queue.front()].get();
+                    if (fits(sv, slot, h)) {
+                        r = h;
+                        sv->queue.pop_front();
+                        sv->results += r->bytes_result;
+                        sv->held[slot] = std::max(sv->held[slot], r->bytes_ws);
+                        r->state = Q_RUNNING;
+                        break;
+                    }
+                    if (sv->held[slot] > 0) {
+                        trim = true;
+                        break;
+                    }
+                }
+                sv->cv.wait(lk);
+            }
             if (sv->stop) break;
-            r = sv->reqs[sv->queue.front()].get();
-            sv->queue.pop_front();
-            sv->in_use += r->bytes_peak;
-            r->state = Q_RUNNING;
         }
+        if (trim) {
+            gwk_ctx_trim(child);
+            (void)hipStreamSynchronize(st);
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->held[slot] = 0;
+            }
+            sv->cv.notify_all();
+            continue;
+        }
+        r->stream = st;
         run_request(child, st, *r);
-        gwk_ctx_trim(child);
+        const size_t kept = gwk_ctx_bytes(child);
         {
             std::lock_guard<std::mutex> lk(sv->mu);
+            sv->held[slot] = kept;
             if (r->status != GW_OK) {
                 free_results(*r);
                 r->state = Q_FAILED;
-                sv->in_use -= r->bytes_peak;
+                sv->results -= r->bytes_result;
             } else {
                 r->state = Q_DONE;
-                sv->in_use -= r->bytes_peak - r->bytes_result;
             }
         }
         sv->cv.notify_all();
@@ -187,11 +267,18 @@ GwServe *serve_of(gw_ctx *ctx) {
     if (ctx->serve) return ctx->serve;
     GwServe *sv = new GwServe();
     sv->device = ctx->device;
+    // keep memory freed by finished requests in the device pool for the next ones
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
     sv->budget = ctx->budget;
     int slots = 2;
     if (const char *e = std::getenv("GW_SERVE_SLOTS")) slots = std::max(1, std::min(8, std::atoi(e)));
     sv->slot_ws_budget = std::min<size_t>(32ull << 30, ctx->budget / (4 * slots));
-    for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv);
+    sv->held.assign(slots, 0);
+    for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker, sv, i);
     ctx->serve = sv;
     return sv;
 }
@@ -207,7 +294,14 @@ void gwk_serve_stop(gw_ctx *ctx) {
     }
     sv->cv.notify_all();
     for (auto &t : sv->workers) t.join();
-    for (auto &kv : sv->reqs) free_results(*kv.second);
+    (void)hipSetDevice(sv->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : sv->reqs)
+        for (void **p : {&kv.second->chi, &kv.second->res, &kv.second->Q, &kv.second->S})
+            if (*p) {
+                (void)hipFree(*p);
+                *p = nullptr;
+            }
     delete sv;
     ctx->serve = nullptr;
 }
@@ -245,7 +339,8 @@ gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw
     r->tol = tol;
     const size_t nn = (size_t)r->kk * r->kk;
     r->bytes_result = 32 * nn * g->n_omega + (k_compress ? 16ull * m->n_prod * k_compress + 8ull * nn : 0);
-    r->bytes_peak = r->bytes_result + est_transient(*m, k_compress, g->n_omega, prec, sv->slot_ws_budget);
+    r->bytes_ws = est_transient(*m, k_compress, g->n_omega, prec, sv->slot_ws_budget);
+    r->bytes_peak = r->bytes_result + r->bytes_ws;
     if (r->bytes_peak > sv->budget) {
         ctx->err = "gw_submit: request needs " + std::to_string(r->bytes_peak) + " bytes, more than the budget";
         return GW_E_OOM;
@@ -308,7 +403,7 @@ gw_status gw_release(gw_ctx *ctx, uint64_t ticket) {
             // not admitted yet: cancel
             sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), ticket));
         }
-        if (r.state == Q_DONE) sv->in_use -= r.bytes_result;
+        if (r.state == Q_DONE) sv->results -= r.bytes_result;
         free_results(r);
         sv->reqs.erase(it);
     }
