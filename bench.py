@@ -331,21 +331,25 @@ def run_c3(args, gw, gs, torch):
     mols = gs.batch_molecules(args.mols)
     dev = torch.device("cuda:0")
     g = gw.make_grid(N, grid.omega_min, grid.omega_max, grid.eps)
-    free, total = torch.cuda.mem_get_info()
     ws_budget = 64 << 30
-    out_cap = int(free - ws_budget - (16 << 30))
     ctx = gw.Context(0, budget_bytes=ws_budget)
     stream = torch.cuda.current_stream()
-    # groups of consecutive molecules whose in-place outputs fit together
-    groups, cur, used = [], [], 0
-    for i, m in enumerate(mols):
-        b = N * m.n_prod ** 2 * 16
-        if cur and used + b > out_cap:
-            groups.append(cur)
-            cur, used = [], 0
-        cur.append(i)
-        used += b
-    groups.append(cur)
+
+    def next_group(start):
+        # consecutive molecules whose in-place outputs fit in what is free now,
+        # leaving room for the context's (grow-only) workspaces
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info()
+        cap = free - (64 << 30)
+        grp, used = [], 0
+        for i in range(start, len(mols)):
+            b = N * mols[i].n_prod ** 2 * 16
+            if grp and used + b > cap:
+                break
+            grp.append(i)
+            used += b
+        return grp
+
     forms = [f for f in args.forms.split(",") if f]
     res = {}
     for form in forms:
@@ -353,7 +357,11 @@ def run_c3(args, gw, gs, torch):
         solves = 0
         flops = 0.0
         worst_fb = 0
-        for gi, grp in enumerate(groups):
+        start, gi, n_groups = 0, 0, 0
+        while start < len(mols):
+            grp = next_group(start)
+            start = grp[-1] + 1
+            n_groups += 1
             dms = [gw.DeviceMolecule(mols[i], device=dev) for i in grp]
             bufs = [torch.empty((N, mols[i].n_prod, mols[i].n_prod), dtype=torch.complex128, device=dev)
                     for i in grp]
@@ -378,10 +386,10 @@ def run_c3(args, gw, gs, torch):
                 form, gi, len(grp), min(mols[i].n_prod for i in grp), max(mols[i].n_prod for i in grp), tc, tr))
             b.close()
             del bufs, dms
-            torch.cuda.empty_cache()
+            gi += 1
         res[form] = {"t_replay_s": t_run, "t_create_s": t_create, "W_per_s": len(mols) * N / t_run,
                      "solves_per_s": solves / t_run, "W_per_s_incl_create": len(mols) * N / (t_run + t_create),
-                     "solve_TFLOPs": flops / t_run / 1e12, "fp64_fallbacks": worst_fb, "groups": len(groups)}
+                     "solve_TFLOPs": flops / t_run / 1e12, "fp64_fallbacks": worst_fb, "groups": n_groups}
     best = max(res, key=lambda f: res[f]["W_per_s"])
     r = res[best]
     out = base_record(args, "W(omega)/s, %d chain molecules batched in recorded hipGraphs, 512 points" % len(mols),
