@@ -272,14 +272,25 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
 
     for (int j0 = 0; j0 < w; j0 += BW) {
         const int bw = min(BW, w - j0);
-        // (1) U rows of the block: x_i = a_i - sum_{k<i} L_ik x_k, i < j0
+        // (1) U rows of the block: x_i = a_i - sum_{k<i} L_ik x_k, i < j0.  The
+        // unit-lower j0 x j0 corner of the panel and the block's rows < j0 are
+        // staged in LDS first (Ts is free until the inverses at the end), so
+        // the sequential substitution waits on LDS, not on memory.
+        if (j0 > 0) {
+            for (int idx = tid; idx < j0 * (j0 + BW); idx += GF_NT) {
+                const int i = idx / (j0 + BW), k = idx % (j0 + BW);
+                if (k < j0) Ts[i][k] = P[(int64_t)i * n + k];
+                else if (k - j0 < bw) Ux[i][k - j0] = P[(int64_t)i * n + k];
+            }
+            __syncthreads();
+        }
         if (j0 > 0 && wave < bw) {
-            const int c = j0 + wave;
+            const int c = wave;
             Cx<T> xl = zero;  // lane k keeps x_k
             for (int i = 0; i < j0; ++i) {
                 T pr = 0, pi = 0;
                 if (lane < i) {
-                    const Cx<T> l = P[(int64_t)i * n + lane];
+                    const Cx<T> l = Ts[i][lane];
                     pr = l.re * xl.re - l.im * xl.im;
                     pi = l.re * xl.im + l.im * xl.re;
                 }
@@ -287,12 +298,12 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
                     pr += __shfl_xor(pr, off);
                     pi += __shfl_xor(pi, off);
                 }
-                const Cx<T> a = P[(int64_t)i * n + c];
+                const Cx<T> a = Ux[i][c];
                 const Cx<T> x{a.re - pr, a.im - pi};
                 if (lane == i) xl = x;
                 if (lane == 0) {
-                    Ux[i][wave] = x;
-                    P[(int64_t)i * n + c] = x;
+                    Ux[i][c] = x;
+                    P[(int64_t)i * n + j0 + c] = x;
                 }
             }
         }
