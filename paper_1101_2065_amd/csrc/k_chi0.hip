@@ -213,6 +213,296 @@ __global__ __launch_bounds__(256) void k_fftconv(int n, int n_omega, int nhb, co
     }
 }
 
+
+// ------------------------------------------------------------------ wave FFT convolution
+// One wave per (mu, nu) sequence, E = L / 64 complex values per lane kept in
+// registers; a radix-R Stockham pass works on butterflies j = lane + 64 t
+// (t < E / R), element r of butterfly t in register slot t R + r holding
+// position j + (L / R) r.  Between passes the wave exchanges through its own
+// LDS region (real and imaginary parts in turn, positions padded by one
+// double per 16 against bank conflicts); no workgroup barrier is involved.
+// The last pass leaves position q = lane + 64 sigma in the lane that also
+// owns q in the first pass, so forward output, kernel multiply and inverse
+// input stay in registers.
+__device__ inline int fpad(int pos) { return pos + (pos >> 4); }
+
+template <bool INV>
+__device__ inline void dft16(zdbl *v) {
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, h = 0.70710678118654752440;
+    zdbl a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        a[n2][0] = v[n2];
+        a[n2][1] = v[n2 + 4];
+        a[n2][2] = v[n2 + 8];
+        a[n2][3] = v[n2 + 12];
+        dft4<INV>(a[n2]);
+    }
+    // twiddles W16^(n2 k1), forward exp(-2 pi i m / 16)
+    const double wr[10] = {1, c1, h, s1, 0, -s1, -h, -c1, -1, -c1};
+    const double wi[10] = {0, -s1, -h, -c1, -1, -c1, -h, -s1, 0, s1};
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) {
+            const int m = n2 * k1;
+            const zdbl w{wr[m], INV ? -wi[m] : wi[m]};
+            a[n2][k1] = zmul(a[n2][k1], w);
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        zdbl b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<INV>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
+
+template <int R, bool INV>
+__device__ inline void dftR(zdbl *v) {
+    if constexpr (R == 16) dft16<INV>(v);
+    else if constexpr (R == 8) dft8<INV>(v);
+    else if constexpr (R == 4) dft4<INV>(v);
+    else dft2<INV>(v);
+}
+
+// Register slot of a butterfly element.  PERM: the data still sit in the
+// last-pass layout of the forward transform (radix RL) while this pass reads
+// them in the first-pass layout (radix R): canonical slot t R + r is position
+// lane + 64 sg with sg = t + (E / R) r, which the forward transform left in
+// slot (sg % (E / RL)) RL + sg / (E / RL).
+template <int L, int R, int RL, bool PERM>
+__device__ constexpr int wslot(int t, int r) {
+    constexpr int E = L / 64;
+    if constexpr (!PERM) return t * R + r;
+    const int sg = t + (E / R) * r;
+    return (sg % (E / RL)) * RL + sg / (E / RL);
+}
+
+// Twiddle and butterfly of one pass (radix R, NS points already transformed).
+template <int L, int R, int NS, bool INV, bool PERM = false, int RL = R>
+__device__ inline void wpass(zdbl *x, const zdbl *__restrict__ tw, int lane) {
+    constexpr int E = L / 64, NBF = E / R;
+#pragma unroll
+    for (int t = 0; t < NBF; ++t) {
+        const int j = lane + 64 * t;
+        zdbl v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = x[wslot<L, R, RL, PERM>(t, r)];
+        if constexpr (NS > 1) {
+            // W^(jm r) for r < R from the table entries of r = 1, 2, 4, 8
+            // (at most two further roundings per factor)
+            const int jm = j & (NS - 1);
+            constexpr int st = L / (NS * R);
+            zdbl w[R];
+            w[1] = tw[jm * st];
+            if constexpr (R > 2) w[2] = tw[2 * jm * st];
+            if constexpr (R > 4) w[4] = tw[4 * jm * st];
+            if constexpr (R > 8) w[8] = tw[8 * jm * st];
+            if constexpr (R > 2) w[3] = zmul(w[2], w[1]);
+            if constexpr (R > 4) {
+                w[5] = zmul(w[4], w[1]);
+                w[6] = zmul(w[4], w[2]);
+                w[7] = zmul(w[4], w[3]);
+            }
+            if constexpr (R > 8) {
+#pragma unroll
+                for (int r = 9; r < 16; ++r) w[r] = zmul(w[8], w[r - 8]);
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                if (INV) w[r].im = -w[r].im;
+                v[r] = zmul(v[r], w[r]);
+            }
+        }
+        dftR<R, INV>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[wslot<L, R, RL, PERM>(t, r)] = v[r];
+        __builtin_amdgcn_sched_barrier(0);  // one butterfly's registers at a time
+    }
+}
+
+// Outputs of a (R, NS) pass go to y = (j / NS) NS R + j % NS + r NS; the next
+// pass (radix R2) reads position j2 + (L / R2) r2 into slot t2 R2 + r2.  All
+// writes of a part precede its reads, so the reads may land in the same
+// registers.
+template <int L, int R, int NS, int R2, bool PERM = false, int RL = R>
+__device__ inline void wexchange(zdbl *x, double *lds, int lane) {
+    constexpr int E = L / 64, NBF = E / R, NBF2 = E / R2;
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+        for (int t = 0; t < NBF; ++t) {
+            const int j = lane + 64 * t;
+            const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const zdbl &v = x[wslot<L, R, RL, PERM>(t, r)];
+                lds[fpad(base + r * NS)] = part ? v.im : v.re;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t2 = 0; t2 < NBF2; ++t2)
+#pragma unroll
+            for (int r2 = 0; r2 < R2; ++r2) {
+                const double d = lds[fpad(lane + 64 * t2 + (L / R2) * r2)];
+                if (part) x[t2 * R2 + r2].im = d;
+                else x[t2 * R2 + r2].re = d;
+            }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Whole FFT of length L in registers + the wave's LDS region; output in the
+// layout of the last pass.  PERM: the input is in the last-pass layout (of a
+// previous transform), else in the first-pass layout.
+template <int L, bool INV, bool PERM>
+__device__ inline void wfft(zdbl *x, double *lds, const zdbl *__restrict__ tw, int lane) {
+    if constexpr (L == 2048) {
+        wpass<L, 16, 1, INV, PERM, 8>(x, tw, lane);
+        wexchange<L, 16, 1, 16, PERM, 8>(x, lds, lane);
+        wpass<L, 16, 16, INV>(x, tw, lane);
+        wexchange<L, 16, 16, 8>(x, lds, lane);
+        wpass<L, 8, 256, INV>(x, tw, lane);
+    } else if constexpr (L == 1024) {
+        wpass<L, 16, 1, INV, PERM, 8>(x, tw, lane);
+        wexchange<L, 16, 1, 8, PERM, 8>(x, lds, lane);
+        wpass<L, 8, 16, INV>(x, tw, lane);
+        wexchange<L, 8, 16, 8>(x, lds, lane);
+        wpass<L, 8, 128, INV>(x, tw, lane);
+    } else if constexpr (L == 512) {
+        wpass<L, 8, 1, INV, PERM, 8>(x, tw, lane);
+        wexchange<L, 8, 1, 8, PERM, 8>(x, lds, lane);
+        wpass<L, 8, 8, INV>(x, tw, lane);
+        wexchange<L, 8, 8, 8>(x, lds, lane);
+        wpass<L, 8, 64, INV>(x, tw, lane);
+    } else {
+        static_assert(L == 256, "wave FFT length");
+        wpass<L, 4, 1, INV, PERM, 4>(x, tw, lane);
+        wexchange<L, 4, 1, 4, PERM, 4>(x, lds, lane);
+        wpass<L, 4, 4, INV>(x, tw, lane);
+        wexchange<L, 4, 4, 4>(x, lds, lane);
+        wpass<L, 4, 16, INV>(x, tw, lane);
+        wexchange<L, 4, 16, 4>(x, lds, lane);
+        wpass<L, 4, 64, INV>(x, tw, lane);
+    }
+}
+
+template <int L>
+struct WPlan {
+    static constexpr int R1 = (L == 2048 || L == 1024) ? 16 : (L == 512 ? 8 : 4);  // first pass radix
+    static constexpr int RL = (L == 256) ? 4 : 8;                                  // last pass radix
+};
+
+// chi0 from the histogram, one sequence per wave.  Workgroup = 8 waves = row
+// mu and the 8 consecutive nu >= mu of one 8-column group: the outputs are
+// staged through LDS so that every 8 lanes write 128 contiguous bytes of a
+// chi0 row.  Each sequence: forward FFT of the odd extension (purely
+// imaginary spectrum i alpha), times i Kt, inverse FFT, scale 1/L.
+template <int L>
+__global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, const int64_t *__restrict__ H,
+                                                   int64_t n_upper, const int32_t *__restrict__ s_dev,
+                                                   const zdbl *__restrict__ Kt, const zdbl *__restrict__ tw,
+                                                   zdbl *__restrict__ chi0) {
+    constexpr int E = L / 64, REG = L + L / 16;  // doubles per wave region
+    constexpr int R1 = WPlan<L>::R1, RL = WPlan<L>::RL;
+    __shared__ double lds[8 * REG];
+    const int nch = (n + 7) / 8;
+    const int mu = blockIdx.x / nch;
+    const int nu0 = (blockIdx.x % nch) * 8;
+    if (nu0 + 7 < mu) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int s = *s_dev;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t trow = (int64_t)mu * n - ((int64_t)mu * (mu - 1)) / 2 - mu;
+    // histogram rows of the 8 sequences, scaled to doubles: Hs[m][w], m < nhb
+    double *Hs = lds;
+    for (int idx = tid; idx < nhb * 8; idx += 512) {
+        const int m = idx >> 3, ww = idx & 7;
+        const int nu = nu0 + ww;
+        double v = 0.0;
+        if (m >= 1 && nu >= mu && nu < n) v = ldexp((double)H[(int64_t)m * n_upper + trow + nu], -s);
+        Hs[m * 9 + ww] = v;
+    }
+    __syncthreads();
+    // odd extension a(q) = h(q), a(L - q) = -h(q), in the first pass layout
+    zdbl x[E];
+#pragma unroll
+    for (int t = 0; t < E / R1; ++t)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int q = lane + 64 * t + (L / R1) * r;
+            double a = 0.0;
+            if (q < nhb) a = Hs[q * 9 + w];
+            else if (q > L - nhb) a = -Hs[(L - q) * 9 + w];
+            x[t * R1 + r] = zdbl{a, 0.0};
+        }
+    __syncthreads();
+    double *my = lds + w * REG;
+    wfft<L, false, false>(x, my, tw, lane);
+    // times i Kt at position q = lane + 64 sg, in place in the last-pass layout
+#pragma unroll
+    for (int sg = 0; sg < E; ++sg) {
+        const int sf = (sg % (E / RL)) * RL + sg / (E / RL);
+        const zdbl K = Kt[lane + 64 * sg];
+        const double al = x[sf].im;
+        x[sf] = zdbl{-al * K.im, al * K.re};
+        if ((sg & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // keep few loads in flight (registers)
+    }
+    wfft<L, true, true>(x, my, tw, lane);
+    // stage q < n_omega (last-pass layout) as complex pairs in the wave region
+    const double inv_l = 1.0 / (double)L;
+#pragma unroll
+    for (int sg = 0; sg < E / 2; ++sg) {
+        const int sf = (sg % (E / RL)) * RL + sg / (E / RL);
+        const int q = lane + 64 * sg;
+        my[2 * q] = x[sf].re * inv_l;
+        my[2 * q + 1] = x[sf].im * inv_l;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 8 * n_omega; idx += 512) {
+        const int ww = idx & 7, j = idx >> 3;
+        const int nu = nu0 + ww;
+        if (nu >= mu && nu < n) {
+            const double *src = lds + ww * REG + 2 * j;
+            const zdbl v{src[0], src[1]};
+            chi0[j * nn + (int64_t)mu * n + nu] = v;
+        }
+    }
+}
+
+// chi0 is symmetric: fill the strict lower triangle of every frequency from
+// the upper one, 32 x 32 tiles through LDS (both sides coalesced rows).
+// Workgroup = one upper tile (bi <= bj) for 8 consecutive frequencies.
+__global__ __launch_bounds__(256) void k_symmetrize(int n, int n_omega, int nt, zdbl *__restrict__ chi0) {
+    __shared__ zdbl t[32][33];
+    int tile = blockIdx.x, bi = 0;
+    while (tile >= nt - bi) {  // upper tiles enumerated row by row
+        tile -= nt - bi;
+        ++bi;
+    }
+    const int bj = bi + tile;
+    const int64_t nn = (int64_t)n * n;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int j_end = min(n_omega, (int)(blockIdx.y + 1) * 8);
+    for (int j = blockIdx.y * 8; j < j_end; ++j) {
+        zdbl *c = chi0 + j * nn;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = bi * 32 + ty + 8 * q, col = bj * 32 + tx;
+            if (r < n && col < n) t[ty + 8 * q][tx] = c[(int64_t)r * n + col];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = bj * 32 + ty + 8 * q, col = bi * 32 + tx;  // lower element (r, col) = upper (col, r)
+            if (r < n && col < n && r > col) c[(int64_t)r * n + col] = t[tx][ty + 8 * q];
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, double eps, zdbl *Kt, zdbl *tw) {
@@ -224,10 +514,36 @@ hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, doub
 hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H, const int32_t *s_dev,
                           const zdbl *Kt, const zdbl *tw, zdbl *chi0) {
     const int64_t n_upper = (int64_t)n * (n + 1) / 2;
+    const int L = 2 * n_omega;
+    if (L >= 256 && L <= 2048) {
+        // wave kernel on the upper triangle, then the lower one by symmetry
+        {
+            ProfScope ps(st, "fftconv", 0.0, 8.0 * nhb * (double)n_upper + 16.0 * n_omega * (double)n_upper);
+            dim3 gw((unsigned)((int64_t)n * ((n + 7) / 8)));
+#define GW_FFTW_CASE(LL)                                                                                     \
+    case LL:                                                                                                 \
+        hipLaunchKernelGGL(k_fftconv_w<LL>, gw, dim3(512), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
+                           chi0);                                                                            \
+        break;
+            switch (L) {
+                GW_FFTW_CASE(256)
+                GW_FFTW_CASE(512)
+                GW_FFTW_CASE(1024)
+                GW_FFTW_CASE(2048)
+            }
+#undef GW_FFTW_CASE
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        const int nt = (n + 31) / 32;
+        ProfScope pm(st, "symmetrize", 0.0, 16.0 * 2.0 * n_omega * ((double)n * (n - 1) / 2));
+        hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)((n_omega + 7) / 8)),
+                           dim3(256), 0, st, n, n_omega, nt, chi0);
+        return hipGetLastError();
+    }
+    ProfScope ps(st, "fftconv", 0.0, 8.0 * nhb * (double)n_upper + 16.0 * n_omega * (double)n * n);
     const int nch = (n + 15) / 16;
     dim3 grid((unsigned)((int64_t)n * nch));
-    const int L = 2 * n_omega;
-    ProfScope ps(st, "fftconv", 0.0, 8.0 * nhb * (double)n_upper + 16.0 * n_omega * (double)n * n);
 #define GW_FFT_CASE(LL)                                                                                    \
     case LL:                                                                                               \
         hipLaunchKernelGGL(k_fftconv<LL>, grid, dim3(256), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
@@ -237,10 +553,6 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
         GW_FFT_CASE(32)
         GW_FFT_CASE(64)
         GW_FFT_CASE(128)
-        GW_FFT_CASE(256)
-        GW_FFT_CASE(512)
-        GW_FFT_CASE(1024)
-        GW_FFT_CASE(2048)
         GW_FFT_CASE(4096)
         default:
             return hipErrorInvalidValue;
