@@ -164,7 +164,8 @@ def kernel_roofline(stats):
         achieved = d["bytes"] / sec / 1e9
         rec = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
                "bytes_per_launch": d["bytes"] / d["launches"]}
-    rec.update({"traffic": None, "kernel": d["name"], "launches": d["launches"],
+    rec.update({"traffic": stored_traffic() if d["name"] == "zgemm_128x64" else None,
+                "kernel": d["name"], "launches": d["launches"],
                 "avg_launch_us": d["ms"] * 1e3 / d["launches"]})
     rec["all_kernels"] = {s["name"]: {"launches": s["launches"], "ms": round(s["ms"], 3),
                                       "TFLOP/s": round(s["flops"] / (s["ms"] / 1e3) / 1e12, 2) if s["flops"] else None,
@@ -484,6 +485,98 @@ def run_c4(args, gw, gs, torch):
     return rec
 
 
+# ---------------------------------------------------------------------- profiles
+# Kernel whose HBM traffic the roofline reports, and the source it is built from.
+TRAFFIC_KERNEL = "k_gemm<double, true, true, 4, 2, 8>"
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    with open(os.path.join(HERE, "paper_1101_2065_amd", "csrc", "k_gemm.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel source changed since it was measured."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def _csv_rows(path):
+    import csv
+
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_profiles(stats_csv, fetch_csv, write_csv, out_json):
+    """Per-kernel HBM traffic from two counter runs (FETCH_SIZE, WRITE_SIZE,
+    KiB per dispatch), scaled by the same counters on a plain device copy of
+    COPY_BYTES bytes."""
+    def per_kernel(path, counter):
+        acc = {}
+        for r in _csv_rows(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            k = r["Kernel_Name"]
+            a = acc.setdefault(k, [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+        return {k: v[0] / v[1] for k, v in acc.items()}
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in fetch if "MulFunctor" in k]
+    copy_k = copy[0] if copy else None
+    f_scale = (COPY_BYTES / 1024.0) / fetch[copy_k] if copy_k else 1.0
+    w_scale = (COPY_BYTES / 1024.0) / write[copy_k] if copy_k and write.get(copy_k) else 1.0
+    rows = []
+    for k in sorted(fetch, key=lambda k: -fetch[k]):
+        rows.append({"kernel": k, "fetch_KiB": fetch[k], "write_KiB": write.get(k),
+                     "bytes": (fetch[k] * f_scale + (write.get(k) or 0.0) * w_scale) * 1024.0})
+    dom = [r for r in rows if TRAFFIC_KERNEL in r["kernel"]]
+    out = {"kernel": TRAFFIC_KERNEL, "kernel_source_sha256_16": kernel_source_hash(),
+           "copy_kernel": copy_k, "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_launch": dom[0]["bytes"] if dom else None, "kernels": rows[:20]}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    md = [
+        "# HBM traffic per dispatch: FP64 step (chi0 build + W solve), 40-atom chain truncated to N_prod=2000, "
+        "1024 frequencies", "",
+        "Commands (repository root, one MI355X; one counter per run):", "", "```",
+        "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv -- python3 bench.py "
+        "--forms fp64 --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run --output-format csv -- python3 bench.py "
+        "--forms fp64 --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "python bench.py --summarize-counters gpurun_out/prof_n2000/run_kernel_stats.csv "
+        "gpurun_out/pmc_fetch/run_counter_collection.csv gpurun_out/pmc_write/run_counter_collection.csv",
+        "```", "",
+        "Calibration: a plain elementwise pass over %d bytes (`%s`) reads FETCH_SIZE %.0f KiB and writes WRITE_SIZE "
+        "%.0f KiB per dispatch; factors %.4f (fetch) and %.4f (write) convert the counters to bytes."
+        % (COPY_BYTES, (copy_k or "none")[:60], fetch.get(copy_k, 0.0), write.get(copy_k, 0.0), f_scale, w_scale),
+        "", "| kernel | dispatches avg FETCH_SIZE KiB | avg WRITE_SIZE KiB | HBM bytes per dispatch |", "|---|---:|---:|---:|"]
+    for r in rows[:14]:
+        md.append("| `%s` | %.0f | %s | %.3e |" % (r["kernel"][:90], r["fetch_KiB"],
+                                                  "%.0f" % r["write_KiB"] if r["write_KiB"] is not None else "-",
+                                                  r["bytes"]))
+    with open(os.path.join(os.path.dirname(out_json), "hbm_traffic_chain40_n2000.md"), "w") as f:
+        f.write("\n".join(md) + "\n")
+    print(json.dumps({"copy_kernel": copy_k, "fetch_scale": f_scale, "write_scale": w_scale,
+                      "dominant_bytes_per_launch": out["bytes_per_launch"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -497,7 +590,14 @@ def main():
     ap.add_argument("--low-rate", type=float, default=0.3, help="c4: the below-capacity run")
     ap.add_argument("--duration", type=float, default=60.0, help="c4: arrival window (s)")
     ap.add_argument("--pool", type=int, default=32, help="c4: distinct molecules drawn by the arrivals")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain 1 GiB device copies (reference for the HBM counters)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/hbm_traffic.json from rocprofv3 outputs and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_profiles(*args.summarize_counters, TRAFFIC_FILE)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is "
               "documented, not built); run with --gpus 1", file=sys.stderr)
@@ -526,6 +626,13 @@ def main():
         out = run_c3(args, gw, gs, torch)
     else:
         out = run_c4(args, gw, gs, torch)
+    if args.copy_calibration:
+        a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # one kernel: reads and writes COPY_BYTES
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d bytes" % COPY_BYTES)
     print(json.dumps(out), flush=True)
 
 
