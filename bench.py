@@ -45,12 +45,14 @@ def log(*a):
 
 
 def solve_flops(n, n_solved, n_ir=0, mixed=False):
-    """Algorithmic flops of the W solve (per solved frequency: A = 1 - v chi0
-    4N^3, LU 8/3 N^3, two triangular solves with N right-hand sides 8N^3; a
-    refinement step adds an FP64 residual 8N^3 and a low-precision solve 8N^3)."""
+    """Algorithmic flops of the W solve per solved frequency.  FP64: A = 1 -
+    v chi0 4N^3, LU 8/3 N^3, forward substitution with N right-hand sides 4N^3,
+    back substitution of the lower triangle of the symmetric W 8/3 N^3.  Mixed:
+    low-precision LU and full solves (8N^3), and per refinement step an FP64
+    residual 8N^3 and a low-precision solve 8N^3."""
     n3 = float(n) ** 3
     if not mixed:
-        return {"fp64": n_solved * (4 + 8.0 / 3 + 8) * n3, "fp32": 0.0}
+        return {"fp64": n_solved * (4 + 8.0 / 3 + 4 + 8.0 / 3) * n3, "fp32": 0.0}
     return {"fp64": n_solved * (4 + 8 * n_ir) * n3, "fp32": n_solved * (8.0 / 3 + 8 * (1 + n_ir)) * n3}
 
 
@@ -493,11 +495,13 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_hash():
+    """Hash of the sources that define the dominant kernel and its launches."""
     import hashlib
 
     h = hashlib.sha256()
-    with open(os.path.join(HERE, "paper_1101_2065_amd", "csrc", "k_gemm.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("k_gemm.hip", "k_lu.hip", "gw_abi.cpp"):
+        with open(os.path.join(HERE, "paper_1101_2065_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -206,7 +206,10 @@ gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, in
     GW_HIP(c, gwk::getrf_batched<zdbl>(st, n, w.A, nn, w.ipiv, (zdbl *)w.Li, (zdbl *)w.Ui, (zdbl *)w.scratch, w.info, nb));
     GW_HIP(c, gwk::launch_perm(st, n, w.ipiv, w.perm, nb));
     GW_HIP(c, gwk::launch_init_rhs_perm(st, n, v, v_is_diag, w.perm, W, nn, nb));
-    GW_HIP(c, gwk::getrs_batched<zdbl>(st, n, n, w.A, nn, w.ipiv, (const zdbl *)w.Li, (const zdbl *)w.Ui, W, nn, nb));
+    // W = (1 - v chi0)^{-1} v is symmetric for symmetric v and chi0: only its
+    // lower triangle is solved for, then mirrored
+    GW_HIP(c, gwk::getrs_batched<zdbl>(st, n, n, w.A, nn, w.ipiv, (const zdbl *)w.Li, (const zdbl *)w.Ui, W, nn, nb,
+                                       true));
     return GW_OK;
 }
 

@@ -80,10 +80,12 @@ template <typename Z>
 hipError_t getrf_batched(hipStream_t st, int n, Z *A, int64_t sA, int32_t *ipiv,
                          Z *Linv, Z *Uinv, Z *scratch, int32_t *info, int batch);
 // Solve A X = B with the factors above, B [batch][n][nrhs] in place.
+// sym_lower (nrhs == n, X known to be symmetric): the back substitution only
+// produces the lower triangle, which is then mirrored into the upper one.
 template <typename Z>
 hipError_t getrs_batched(hipStream_t st, int n, int nrhs, const Z *LU, int64_t sA,
                          const int32_t *ipiv, const Z *Linv, const Z *Uinv,
-                         Z *B, int64_t sB, int batch);
+                         Z *B, int64_t sB, int batch, bool sym_lower = false);
 
 // B[b] = v (as complex), v dense or diagonal.
 hipError_t launch_init_rhs(hipStream_t st, int n, const double *v, int v_is_diag,

@@ -778,9 +778,34 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
     return hipSuccess;
 }
 
+// X[b][i][j] = X[b][j][i] for j > i (32 x 32 tiles through LDS).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror_lower(int n, int nt, Cx<T> *X, int64_t sX) {
+    __shared__ Cx<T> t[32][33];
+    int tile = blockIdx.x, bi = 0;
+    while (tile >= nt - bi) {  // upper tiles (bi <= bj) row by row
+        tile -= nt - bi;
+        ++bi;
+    }
+    const int bj = bi + tile;
+    Cx<T> *x = X + (int64_t)blockIdx.y * sX;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = bj * 32 + ty + 8 * q, c = bi * 32 + tx;  // lower tile (bj, bi)
+        if (r < n && c < n) t[ty + 8 * q][tx] = x[(int64_t)r * n + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = bi * 32 + ty + 8 * q, c = bj * 32 + tx;  // upper (r, c) = lower (c, r)
+        if (r < n && c < n && c > r) x[(int64_t)r * n + c] = t[tx][ty + 8 * q];
+    }
+}
+
 template <typename T>
 hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t sA, const Cx<T> *Linv,
-                      const Cx<T> *Uinv, Cx<T> *B, int64_t sB, int batch) {
+                      const Cx<T> *Uinv, Cx<T> *B, int64_t sB, int batch, bool sym_lower) {
     const int nblk = (n + NB - 1) / NB;
     const int64_t sI = (int64_t)nblk * NB * NB;
     hipError_t e;
@@ -807,27 +832,36 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
             if (e != hipSuccess) return e;
         }
     }
-    // backward: U X = Y
+    // backward: U X = Y.  With sym_lower, rows [r0, r1) are only needed in
+    // columns [0, r1): every product below is cut to those columns.
     for (int KB = ((n - 1) / NBO) * NBO; KB >= 0; KB -= NBO) {
         const int WO = min(NBO, n - KB);
         for (int kb = KB + ((WO - 1) / NB) * NB; kb >= KB; kb -= NB) {
             const int w = min(NB, n - kb);
             Cx<T> *Bk = B + (int64_t)kb * nrhs;
-            e = gemm_t<T>(st, w, nrhs, w, T(1), Uinv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk,
+            const int cols = sym_lower ? kb + w : nrhs;
+            e = gemm_t<T>(st, w, cols, w, T(1), Uinv + (int64_t)(kb / NB) * NB * NB, NB, sI, Bk, nrhs, sB, T(0), Bk,
                           nrhs, sB, batch);
             if (e != hipSuccess) return e;
             const int r2 = kb - KB;
             if (r2 > 0) {
-                e = gemm_t<T>(st, r2, nrhs, w, T(-1), LU + (int64_t)KB * n + kb, n, sA, Bk, nrhs, sB, T(1),
-                              B + (int64_t)KB * nrhs, nrhs, sB, batch);
+                e = gemm_t<T>(st, r2, sym_lower ? kb : nrhs, w, T(-1), LU + (int64_t)KB * n + kb, n, sA, Bk, nrhs, sB,
+                              T(1), B + (int64_t)KB * nrhs, nrhs, sB, batch);
                 if (e != hipSuccess) return e;
             }
         }
         if (KB > 0) {
-            e = gemm_t<T>(st, KB, nrhs, WO, T(-1), LU + KB, n, sA, B + (int64_t)KB * nrhs, nrhs, sB, T(1), B, nrhs, sB,
-                          batch);
+            e = gemm_t<T>(st, KB, sym_lower ? KB : nrhs, WO, T(-1), LU + KB, n, sA, B + (int64_t)KB * nrhs, nrhs, sB,
+                          T(1), B, nrhs, sB, batch);
             if (e != hipSuccess) return e;
         }
+    }
+    if (sym_lower && n > 1) {
+        const int nt = (n + 31) / 32;
+        ProfScope ps(st, "mirror_lower", 0.0, 2.0 * sizeof(Cx<T>) * (double)n * (n - 1) / 2 * batch);
+        hipLaunchKernelGGL(k_mirror_lower<T>, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)batch), dim3(256), 0, st,
+                           n, nt, B, sB);
+        return hipGetLastError();
     }
     return hipSuccess;
 }
@@ -849,17 +883,17 @@ hipError_t getrf_batched<zflt>(hipStream_t st, int n, zflt *A, int64_t sA, int32
 }
 template <>
 hipError_t getrs_batched<zdbl>(hipStream_t st, int n, int nrhs, const zdbl *LU, int64_t sA, const int32_t *ipiv,
-                               const zdbl *Linv, const zdbl *Uinv, zdbl *B, int64_t sB, int batch) {
+                               const zdbl *Linv, const zdbl *Uinv, zdbl *B, int64_t sB, int batch, bool sym_lower) {
     (void)ipiv;  // rows of B are already in pivot order (see launch_perm / launch_init_rhs)
     return getrs_impl<double>(st, n, nrhs, (const Cx<double> *)LU, sA, (const Cx<double> *)Linv,
-                              (const Cx<double> *)Uinv, (Cx<double> *)B, sB, batch);
+                              (const Cx<double> *)Uinv, (Cx<double> *)B, sB, batch, sym_lower && nrhs == n);
 }
 template <>
 hipError_t getrs_batched<zflt>(hipStream_t st, int n, int nrhs, const zflt *LU, int64_t sA, const int32_t *ipiv,
-                               const zflt *Linv, const zflt *Uinv, zflt *B, int64_t sB, int batch) {
+                               const zflt *Linv, const zflt *Uinv, zflt *B, int64_t sB, int batch, bool sym_lower) {
     (void)ipiv;
     return getrs_impl<float>(st, n, nrhs, (const Cx<float> *)LU, sA, (const Cx<float> *)Linv,
-                             (const Cx<float> *)Uinv, (Cx<float> *)B, sB, batch);
+                             (const Cx<float> *)Uinv, (Cx<float> *)B, sB, batch, sym_lower && nrhs == n);
 }
 
 hipError_t launch_perm(hipStream_t st, int n, const int32_t *ipiv, int32_t *perm, int batch) {
