@@ -171,6 +171,14 @@ gw_status check_molecule(gw_ctx *c, const gw_molecule *m, hipStream_t st, HostMo
 
 hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
+// The context's second solve stream and its fork/join events (created once).
+gw_status aux_stream(gw_ctx *c) {
+    if (!c->aux) GW_HIP(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    if (!c->fork_ev) GW_HIP(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    if (!c->join_ev) GW_HIP(c, hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    return GW_OK;
+}
+
 
 
 
@@ -501,6 +509,9 @@ gw_status gw_destroy(gw_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     gwk_prof_release(ctx);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     for (auto &kv : ctx->bufs)
         if (kv.second.ptr) {
             if (ctx->own_stream) (void)hipFreeAsync(kv.second.ptr, ctx->own_stream);
@@ -585,9 +596,35 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     int n_solved = 0, n_fallback = 0, max_it = 0;
     double max_rel = 0.0;
     if (!mixed) {
-        s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0);
-        if (s != GW_OK) return s;
-        for (auto &bt : freq_batches(n_omega, p.nbmax)) n_solved += bt.second;
+        int nstreams = 2;
+        if (const char *e = std::getenv("GW_SOLVE_STREAMS")) nstreams = std::max(1, std::min(2, std::atoi(e)));
+        if (ctx->own_stream || n_omega < 8) nstreams = 1;
+        if (nstreams == 1) {
+            s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0);
+            if (s != GW_OK) return s;
+            for (auto &bt : freq_batches(n_omega, p.nbmax)) n_solved += bt.second;
+        } else {
+            // frequency batches alternate between the caller's stream and a
+            // second one, so that one batch's latency-bound panels overlap the
+            // other's matrix-core products; each stream has its own workspace
+            gwp::SolvePlan p2[2];
+            if ((s = gwp::solve_plan(ctx, n, n_omega, false, "", &p2[0], ctx->budget / 2)) != GW_OK) return s;
+            if ((s = gwp::solve_plan(ctx, n, n_omega, false, "t1", &p2[1], ctx->budget / 2)) != GW_OK) return s;
+            if ((s = aux_stream(ctx)) != GW_OK) return s;
+            hipStream_t ss[2] = {ctx->aux, st};
+            GW_HIP(ctx, hipEventRecord(ctx->fork_ev, st));
+            GW_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+            const auto bts = freq_batches(n_omega, std::max(1, std::min(p2[0].nbmax, (n_omega / 2 + 1) / 2)));
+            for (size_t i = 0; i < bts.size(); ++i) {
+                const int j0 = bts[i].first, nb = bts[i].second, q = (int)(i % 2);
+                s = gwp::solve_batch_fp64(ctx, ss[q], n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, p2[q].w);
+                if (s != GW_OK) return s;
+                n_solved += nb;
+            }
+            GW_HIP(ctx, hipEventRecord(ctx->join_ev, ctx->aux));
+            GW_HIP(ctx, hipStreamWaitEvent(st, ctx->join_ev, 0));
+            if (n_omega >= 4) GW_HIP(ctx, gwk::launch_conj_mirror(st, nn, n_omega, W));
+        }
     } else {
         for (auto &bt : freq_batches(n_omega, p.nbmax)) {
             const int j0 = bt.first, nb = bt.second;

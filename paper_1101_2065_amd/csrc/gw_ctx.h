@@ -30,6 +30,10 @@ struct gw_ctx {
     GwServe *serve = nullptr;
     uint64_t batch_generation = 0;
     gwk::ProfSink *prof = nullptr;
+    // second stream of the FP64 solve (frequency batches on two streams) and
+    // the events that fork it from and join it to the caller's stream
+    hipStream_t aux = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 void gwk_ctx_trim(gw_ctx *c);
