@@ -14,7 +14,9 @@ What the method computes, in the paper's notation (energies in Hartree):
   than the broadening) and Section 5.B (eps = 1.5 domega by default).
 * Screening, Section 2 eq. Coulombscreening / Section 3 eq.
   tensorform-scr-inter: W = (1 - v chi0)^{-1} v, frequency by frequency.
-* Compression, Section 7.B eqs. subspace_chi0 and chi_RPA.
+* Compression, Section 7.B eqs. subspace_chi0 and chi_RPA; the paper's own
+  subspace, Section 7.A eqs. subsetof_vef, projector0, subspace and
+  global-basis-orthogonality.
 
 Readings where the paper is silent (each also listed in the design notes):
 
@@ -55,6 +57,10 @@ __all__ = [
     "compress_basis",
     "screened_W_compressed",
     "project_pairs",
+    "pair_subset",
+    "pair_basis",
+    "pair_projector",
+    "screened_W_pair_basis",
 ]
 
 
@@ -338,3 +344,49 @@ def screened_W_compressed(v: np.ndarray, chi0: np.ndarray, k: int) -> np.ndarray
     A = np.eye(k, dtype=np.complex128) - lam[:, None] * chat
     Xk = np.linalg.solve(A, np.diag(lam).astype(np.complex128))
     return U @ Xk @ U.T
+
+
+# ----------------------------------------------------------------------------
+# the paper's compression subspace (Section 7.A), and W in it (Section 7.B)
+
+
+def pair_subset(eig: np.ndarray, n_occ: int, e_threshold: float) -> np.ndarray:
+    """Indices p = E*N_virt + (F - N_occ) of the electron-hole pairs with
+    F - E < e_threshold (Section 7.A eq. subsetof_vef), ascending."""
+    e_occ = eig[:n_occ]
+    e_vir = eig[n_occ:]
+    delta = (e_vir[None, :] - e_occ[:, None]).ravel()
+    return np.nonzero(delta < e_threshold)[0]
+
+
+def pair_basis(X: np.ndarray, v: np.ndarray, k: int):
+    """Section 7.A: Gram matrix of the generators in the Coulomb metric,
+    g^{mn} = X_mu^m v^{mu nu} X_nu^n (eq. projector0), its eigenpairs
+    g xi = lambda xi, and Z^lambda = X xi^lambda / sqrt(lambda) for the k
+    largest lambda (eq. subspace).  The Z are orthonormal in the Coulomb
+    metric, Z^T v Z = 1 (eq. global-basis-orthogonality).  Returns Z [n][k]
+    and the kept eigenvalues, descending."""
+    g = X.T @ v @ X
+    lam, xi = np.linalg.eigh(g)
+    order = np.argsort(lam)[::-1][:k]
+    lam, xi = lam[order], xi[:, order]
+    Z = X @ xi / np.sqrt(lam)[None, :]
+    return Z, lam
+
+
+def pair_projector(Z: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Section 7.A: the projector onto the subspace, P^mu_nu = v^{mu mu'}
+    P_{mu' nu} with P_{mu nu} = Z_mu Z_nu (the generators with g inverted on
+    the kept space), so P^2 = P."""
+    return v @ Z @ Z.T
+
+
+def screened_W_pair_basis(v: np.ndarray, chi0: np.ndarray, Z: np.ndarray) -> np.ndarray:
+    """Section 7.B: chi0_mn = Z_m^mu chi0_{mu nu} Z_n^nu with Z^mu = v Z
+    (eq. subspace_chi0), chi_RPA = (1 - chi0_mn)^{-1} chi0_mn, and
+    W = v + Z^mu chi_RPA Z^nu (eq. chi_RPA)."""
+    U = v @ Z
+    c = U.T @ chi0 @ U
+    k = c.shape[0]
+    rpa = np.linalg.solve(np.eye(k, dtype=np.complex128) - c, c)
+    return v.astype(np.complex128) + U @ rpa @ U.T

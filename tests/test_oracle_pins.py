@@ -388,3 +388,66 @@ def test_projected_histogram_is_projected_chi0():
     for i in range(len(js)):
         ref = U.T @ chi[i] @ U
         assert np.abs(chit[i] - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+def _chi_of_pairs(P, mol, sel, omega, eps):
+    """Retarded chi0 of the listed electron-hole pairs at one frequency
+    directly from Section 7.A's double sum (no mesh)."""
+    e_occ, e_vir = mol.eig[:mol.n_occ], mol.eig[mol.n_occ:]
+    delta = (e_vir[None, :] - e_occ[:, None]).ravel()[sel]
+    g = 1.0 / (omega - delta + 1j * eps) - 1.0 / (omega + delta + 1j * eps)
+    return 2.0 * (P[:, sel] * g[None, :]) @ P[:, sel].T
+
+
+def test_pair_subset_threshold():
+    """Section 7.A eq. subsetof_vef: exactly the pairs with F - E below the
+    threshold, for hand-placed levels."""
+    eig = np.array([-0.5, -0.3, 0.1, 0.4, 0.9])
+    sel = o.pair_subset(eig, 2, 0.75)
+    # pairs (E, F): (-0.5, 0.1)=0.6 (-0.5,0.4)=0.9 (-0.5,0.9)=1.4 (-0.3,0.1)=0.4 (-0.3,0.4)=0.7 (-0.3,0.9)=1.2
+    assert list(sel) == [0, 3, 4]
+
+
+def test_pair_basis_orthonormal_and_projector():
+    """Section 7.A: Z is orthonormal in the Coulomb metric
+    (eq. global-basis-orthogonality), spans the generators' visible part, and
+    P = v Z Z^T is a projector (P^2 = P) that reproduces v X."""
+    mol = gs.chain_molecule(3, 5)
+    P = o.pair_vectors(mol)
+    sel = o.pair_subset(mol.eig, mol.n_occ, 1.0)
+    X = P[:, sel]
+    lam_all = np.linalg.eigvalsh(X.T @ mol.v @ X)[::-1]
+    k = int(np.sum(lam_all > 1e-10 * lam_all[0]))
+    Z, lam = o.pair_basis(X, mol.v, k)
+    assert np.allclose(lam, lam_all[:k], rtol=1e-10, atol=0)
+    G = Z.T @ mol.v @ Z
+    assert np.abs(G - np.eye(k)).max() < 1e-9
+    Pr = o.pair_projector(Z, mol.v)
+    assert np.abs(Pr @ Pr - Pr).max() < 1e-9 * np.abs(Pr).max()
+    # every generator's Coulomb image lies in the subspace: P (v X) = v X
+    VX = mol.v @ X
+    assert np.abs(Pr @ VX - VX).max() < 1e-9 * np.abs(VX).max()
+
+
+def test_pair_basis_W_exact_when_chi0_in_subspace():
+    """Section 7.B eq. chi_RPA: when chi0 is built from the generating pairs
+    only, it acts inside the subspace and W = v + Z^mu chi_RPA Z^nu equals the
+    full (1 - v chi0)^{-1} v; keeping fewer eigenvectors loses accuracy."""
+    mol = gs.make_config(0)
+    P = o.pair_vectors(mol)
+    for thr in (10.0, 1.2):
+        sel = o.pair_subset(mol.eig, mol.n_occ, thr)
+        assert 0 < len(sel) <= mol.n_pairs
+        X = P[:, sel]
+        lam_all = np.linalg.eigvalsh(X.T @ mol.v @ X)[::-1]
+        k = int(np.sum(lam_all > 1e-10 * lam_all[0]))
+        Z, _ = o.pair_basis(X, mol.v, k)
+        for w in (0.3, 1.1, -0.7):
+            chi = _chi_of_pairs(P, mol, sel, w, 0.05)
+            Wf = o.screened_W(mol.v, chi)
+            Wp = o.screened_W_pair_basis(mol.v, chi, Z)
+            assert np.linalg.norm(Wp - Wf) < 1e-9 * np.linalg.norm(Wf)
+        Z2, _ = o.pair_basis(X, mol.v, max(1, k - 3))
+        chi = _chi_of_pairs(P, mol, sel, 0.3, 0.05)
+        Wf = o.screened_W(mol.v, chi)
+        assert np.linalg.norm(o.screened_W_pair_basis(mol.v, chi, Z2) - Wf) > 1e-4 * np.linalg.norm(Wf)
