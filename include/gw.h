@@ -192,11 +192,37 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
 gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream,
                             double *Q_out, double *S_out);
 
-/* Decompress one frequency: W = Q X Q^T (Section 8.B, decompression on the fly).
- *   U: DEVICE [n][k] (the basis Q); X: DEVICE complex128 [k][k];
- *   W_out: DEVICE complex128 [n][n]. */
+/* Decompress one frequency: W = R + U X U^T (Section 8.B, decompression on
+ * the fly).  For the top-k subspace pass U = Q and R = NULL; for the paper's
+ * pair subspace pass U and R from gw_pair_basis.
+ *   U: DEVICE [n][k]; X: DEVICE complex128 [k][k]; R: DEVICE [n][n] real or
+ *   NULL; W_out: DEVICE complex128 [n][n]. */
 gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X,
-                        void *stream, void *W_out);
+                        const double *R, void *stream, void *W_out);
+
+/* The paper's own compression subspace (Section 7.A): the pair vectors
+ * V^{EF} of the electron-hole pairs with F - E < e_threshold (eq.
+ * subsetof_vef) generate it; of their Gram matrix in the Coulomb metric,
+ * g = X^T v X (eq. projector0), the k-dimensional dominant eigenspace is kept
+ * (eq. subspace: the paper keeps the eigenvalues above a threshold; k is that
+ * count).  Outputs, all DEVICE, caller-owned:
+ *   Z_out [n][k]: basis orthonormal in the Coulomb metric, Z^T v Z = 1
+ *     (eq. global-basis-orthogonality); any such basis of the subspace gives
+ *     the same W;
+ *   U_out [n][k]: U = v Z (the contravariant Z^mu);
+ *   R_out [n][n] or NULL: R = v - U U^T.
+ *   n_rank_out: HOST or NULL, the number of generating pairs (N_rank).
+ * With them, Section 7.B eq. chi_RPA is
+ *   chi_hat = U^T chi0 U                   (gw_build_chi0 with basis = U)
+ *   X = (1 - chi_hat)^{-1}                 (gw_solve_W with a diagonal metric of ones)
+ *   W = v + U (X - 1) U^T = R + U X U^T    (gw_decompress with R)
+ * since chi_RPA = (1 - chi_hat)^{-1} chi_hat = X - 1.
+ * GW_E_INVALID if fewer than k pairs are below the threshold (or more than
+ * 65536); GW_E_NOCONV if the k-th eigenvalue of g is below 1e-10 of the
+ * kept trace (k exceeds the rank of the generators).  Synchronous. */
+gw_status gw_pair_basis(gw_ctx *ctx, const gw_molecule *m, const double *v, double e_threshold,
+                        int32_t k, void *stream, double *Z_out, double *U_out, double *R_out,
+                        int64_t *n_rank_out);
 
 /* Batched form: n_mol molecules of different sizes on one mesh (all
  * frequencies of all molecules).  gw_batch_create validates every molecule,

@@ -678,7 +678,64 @@ gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, 
     return GW_OK;
 }
 
-gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X, void *stream, void *W_out) {
+gw_status gw_pair_basis(gw_ctx *ctx, const gw_molecule *m, const double *v, double e_threshold, int32_t k,
+                        void *stream, double *Z_out, double *U_out, double *R_out, int64_t *n_rank_out) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    if (!v || !Z_out || !U_out || k < 1) return fail(ctx, GW_E_INVALID, "bad pair-basis arguments");
+    if (!(e_threshold > 0.0) || !std::isfinite(e_threshold))
+        return fail(ctx, GW_E_INVALID, "e_threshold must be positive and finite");
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    HostMol h;
+    gw_status s = check_molecule(ctx, m, st, &h);
+    if (s != GW_OK) return s;
+    const int n = m->n_prod, n_occ = m->n_occ, n_virt = m->n_orb - m->n_occ;
+    if (k > n) return fail(ctx, GW_E_INVALID, "k must not exceed n_prod");
+    // pairs with F - E < e_threshold: for each occupied E a prefix of the
+    // empty states (eigenvalues ascend), and the prefix grows with E
+    std::vector<int32_t> src;
+    std::vector<int64_t> off(n_occ + 1, 0);
+    for (int e = 0; e < n_occ; ++e) {
+        int c = 0;
+        while (c < n_virt && h.eig[n_occ + c] - h.eig[e] < e_threshold) ++c;
+        off[e + 1] = off[e] + c;
+        for (int f = 0; f < c; ++f) src.push_back((int32_t)((int64_t)e * n_virt + f));
+    }
+    const int64_t nr = off[n_occ];
+    if (n_rank_out) *n_rank_out = nr;
+    if (nr < k) return fail(ctx, GW_E_INVALID, "fewer pairs below the threshold (" + std::to_string(nr) + ") than k");
+    if (nr > 65536) return fail(ctx, GW_E_INVALID, "more than 65536 pairs below the threshold");
+    // pair vectors of the occupied states that have selected pairs, in chunks
+    int e_first = 0;
+    while (off[e_first + 1] == 0) ++e_first;
+    const int64_t cap = std::max<int64_t>(1, ((int64_t)1 << 31) / (8 * (int64_t)n * n_virt));
+    const int echunk = (int)std::min<int64_t>(n_occ - e_first, cap);
+    void *Pc, *Xg, *srcd, *work;
+    if ((s = ws(ctx, "pbP", sizeof(double) * (size_t)n * echunk * n_virt, &Pc)) != GW_OK) return s;
+    if ((s = ws(ctx, "pbX", sizeof(double) * (size_t)n * nr, &Xg)) != GW_OK) return s;
+    if ((s = ws(ctx, "pbSrc", sizeof(int32_t) * (size_t)nr, &srcd)) != GW_OK) return s;
+    if ((s = ws(ctx, "pbWork", sizeof(double) * gwk::pair_basis_work_doubles(n, (int)nr, k), &work)) != GW_OK)
+        return s;
+    GW_HIP(ctx, hipMemcpyAsync(srcd, src.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, st));
+    for (int e0 = e_first; e0 < n_occ; e0 += echunk) {
+        const int ec = std::min(echunk, n_occ - e0);
+        const int64_t cw = (int64_t)ec * n_virt;
+        GW_HIP(ctx, gwk::launch_pairvec(st, m->n_orb, n_occ, n, m->n_blk, m->X, m->blk_prod, m->blk_orb, m->orb_idx,
+                                        m->blk_val, m->vals, h.max_o, e0, ec, cw, (double *)Pc));
+        GW_HIP(ctx, gwk::launch_gather_cols(st, n, (int)(off[e0 + ec] - off[e0]), cw, (const double *)Pc,
+                                            (const int32_t *)srcd, (int64_t)e0 * n_virt, (int)off[e0],
+                                            (double *)Xg, nr));
+    }
+    hipError_t e = gwk::pair_basis(st, n, (int)nr, k, v, (const double *)Xg, Z_out, U_out, R_out, (double *)work, 4);
+    if (e == hipErrorUnknown)
+        return fail(ctx, GW_E_NOCONV, "k exceeds the rank of the generating pair vectors (or v is not finite)");
+    GW_HIP(ctx, e);
+    return GW_OK;
+}
+
+gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, const void *X, const double *R,
+                        void *stream, void *W_out) {
     if (!ctx) return GW_E_INVALID;
     if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
     if (!U || !X || !W_out || n < 1 || k < 1 || k > n) return fail(ctx, GW_E_INVALID, "bad decompress arguments");
@@ -691,7 +748,8 @@ gw_status gw_decompress(gw_ctx *ctx, const double *U, int32_t n, int32_t k, cons
     GW_HIP(ctx, gwk::launch_transpose_d(st, n, k, U, (double *)Ut));
     // T = U X ([n][k]), W = T U^T ([n][n]) (Section 8.B decompression)
     GW_HIP(ctx, gwk::launch_dzgemm(st, n, k, k, 1.0, U, k, 0, (const zdbl *)X, k, 0, 0.0, (zdbl *)T, k, 0, 1));
-    GW_HIP(ctx, gwk::launch_zdgemm(st, n, n, k, 1.0, (const zdbl *)T, k, 0, (const double *)Ut, n, 0, 0.0,
+    if (R) GW_HIP(ctx, gwk::launch_init_rhs(st, n, R, 0, (zdbl *)W_out, 0, 1));
+    GW_HIP(ctx, gwk::launch_zdgemm(st, n, n, k, 1.0, (const zdbl *)T, k, 0, (const double *)Ut, n, 0, R ? 1.0 : 0.0,
                                    (zdbl *)W_out, n, 0, 1));
     return GW_OK;
 }

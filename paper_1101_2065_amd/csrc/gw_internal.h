@@ -108,6 +108,15 @@ hipError_t launch_residual(hipStream_t st, int n, const double *v, int v_is_diag
 // Orthonormal basis Q [n][k] of the dominant k-dimensional eigenspace of v and
 // S = Q^T v Q [k][k] (shifted subspace iteration); work: compress_work_doubles.
 size_t compress_work_doubles(int n, int k);
+// Section 7.A subspace: Z [n][k] orthonormal in the Coulomb metric spanning
+// the dominant k-dimensional part of the generators X [n][nr], U = v Z and
+// (R non-null) R = v - U U^T; work: pair_basis_work_doubles.
+size_t pair_basis_work_doubles(int n, int nr, int k);
+hipError_t pair_basis(hipStream_t st, int n, int nr, int k, const double *v, const double *X, double *Z, double *U,
+                      double *R, double *work, int iters);
+// X[mu][j0 + j] = P[mu][src[j0 + j] - base] for j < ncols.
+hipError_t launch_gather_cols(hipStream_t st, int rows, int ncols, int64_t ldp, const double *P, const int32_t *src,
+                              int64_t base, int j0, double *X, int64_t ldx);
 hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double *Q_out, double *S_out,
                           double *work, int iters);
 

@@ -63,14 +63,15 @@ __global__ __launch_bounds__(1024) void k_trace(const double *v, int n, double *
 // Cholesky of the w x w diagonal block at (p, p) of G (row-major, ld k) in
 // LDS, after adding shift_rel * (*tr) to its diagonal.  Writes L back into
 // the lower triangle of the block, L^{-1} to Li and L^{-T} to LiT (64 x 64,
-// zero outside w x w).  A pivot that is not positive sets *bad (the rows were
-// linearly dependent, or not finite) and is replaced by 1.
+// zero outside w x w).  A pivot not above floor_rel * (*tr) (and positive)
+// sets *bad (the rows were linearly dependent, or not finite) and is replaced
+// by 1.
 __global__ __launch_bounds__(256) void k_potf2(int k, int p, int w, double *G, const double *tr, double shift_rel,
-                                               double *Li, double *LiT, int *bad) {
+                                               double floor_rel, double *Li, double *LiT, int *bad) {
     __shared__ double a[64][65];
     __shared__ double inv[64][65];
     const int t = threadIdx.x;
-    const double shift = shift_rel * *tr;
+    const double shift = shift_rel * *tr, floor_piv = floor_rel * *tr;
     for (int e = t; e < 64 * 64; e += 256) {
         const int i = e >> 6, j = e & 63;
         double x = 0.0;
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void k_potf2(int k, int p, int w, double *G, c
     __syncthreads();
     for (int c = 0; c < w; ++c) {
         const double d = a[c][c];
-        const bool ok = d > 0.0;
+        const bool ok = d > floor_piv && d > 0.0;
         const double piv = ok ? sqrt(d) : 1.0;
         __syncthreads();
         if (t == 0) {
@@ -150,12 +151,13 @@ struct CholWs {
 // diagonal block in LDS, then L21 = G21 L11^{-T} and G22 -= L21 L21^T on the
 // matrix cores.  The L21 product runs in place: each 64-row band of the
 // output reads its own w input columns completely before writing.
-hipError_t potrf(hipStream_t st, int k, double shift_rel, const CholWs &c) {
+hipError_t potrf(hipStream_t st, int k, double shift_rel, const CholWs &c, double floor_rel = 0.0) {
     hipError_t e;
     for (int p = 0; p < k; p += 64) {
         const int w = std::min(64, k - p), rest = k - p - w;
         double *li = c.Li + (int64_t)(p / 64) * 4096, *lit = c.LiT + (int64_t)(p / 64) * 4096;
-        hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), 0, st, k, p, w, c.G, c.tr, shift_rel, li, lit, c.bad);
+        hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), 0, st, k, p, w, c.G, c.tr, shift_rel, floor_rel, li, lit,
+                           c.bad);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (rest > 0) {
             double *G21 = c.G + (int64_t)(p + w) * k + p;
@@ -267,6 +269,91 @@ hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double 
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return e;
+    return hb ? hipErrorUnknown : hipSuccess;
+}
+
+namespace {
+
+// X[mu][j0 + j] = P[mu][src[j0 + j] - base] for j < ncols (selected pair columns)
+__global__ void k_gather_cols(int ncols, int64_t ldp, const double *__restrict__ P, const int32_t *__restrict__ src,
+                              int64_t base, int j0, double *__restrict__ X, int64_t ldx) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (j >= ncols) return;
+    X[(int64_t)mu * ldx + j0 + j] = P[(int64_t)mu * ldp + (src[j0 + j] - base)];
+}
+
+}  // namespace
+
+hipError_t launch_gather_cols(hipStream_t st, int rows, int ncols, int64_t ldp, const double *P, const int32_t *src,
+                              int64_t base, int j0, double *X, int64_t ldx) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((ncols + 255) / 256), (unsigned)rows), dim3(256), 0, st, ncols,
+                       ldp, P, src, base, j0, X, ldx);
+    return hipGetLastError();
+}
+
+size_t pair_basis_work_doubles(int n, int nr, int k) {
+    const size_t nblk = (size_t)(k + 63) / 64;
+    return 2 * (size_t)n * nr + (size_t)nr * nr + (size_t)nr * k + (size_t)k * k + compress_work_doubles(nr, k) +
+           3 * (size_t)n * k + 2 * nblk * 4096 + (size_t)64 * std::max(n, k) + 64;
+}
+
+// Section 7.A subspace from its generators X [n][nr] (pair vectors below the
+// energy threshold): g = X^T v X (eq. projector0); Qg [nr][k] an orthonormal
+// basis of the dominant k-dimensional eigenspace of g (shifted subspace
+// iteration, as for v) and Sg = Qg^T g Qg; with Sg = L L^T,
+// Z = X Qg L^{-T} is orthonormal in the Coulomb metric (Z^T v Z = 1,
+// eq. global-basis-orthogonality) and spans the same space as the paper's
+// X xi / sqrt(lambda) (eq. subspace).  Also U = v Z and, if R is not null,
+// R = v - U U^T.  Returns hipErrorUnknown if the iteration lost a direction
+// or the k-th eigenvalue of g is below 1e-10 of the trace of Sg (k exceeds
+// the rank of the generators).
+hipError_t pair_basis(hipStream_t st, int n, int nr, int k, const double *v, const double *X, double *Z, double *U,
+                      double *R, double *work, int iters) {
+    hipError_t e;
+    const int64_t nblk = (k + 63) / 64;
+    double *Xt = work;                         // [nr][n]
+    double *T1 = Xt + (int64_t)nr * n;         // [n][nr], later reused
+    double *g = T1 + (int64_t)n * nr;          // [nr][nr]
+    double *Qg = g + (int64_t)nr * nr;         // [nr][k]
+    double *Sg = Qg + (int64_t)nr * k;         // [k][k]
+    double *cw = Sg + (int64_t)k * k;          // compress_basis work
+    double *Y = cw + compress_work_doubles(nr, k);  // [n][k]
+    double *Yt = Y + (int64_t)n * k;           // [k][n]
+    double *Ut = Yt + (int64_t)k * n;          // [k][n]
+    CholWs c;
+    c.G = Sg;
+    c.Li = Ut + (int64_t)k * n;
+    c.LiT = c.Li + nblk * 4096;
+    c.T = c.LiT + nblk * 4096;                 // 64 x max(n, k)
+    c.tr = c.T + (int64_t)64 * std::max(n, k);
+    c.bad = (int *)(c.tr + 2);
+    // g = X^T (v X)
+    if ((e = launch_dgemm(st, n, nr, n, 1.0, v, n, 0, X, nr, 0, 0.0, T1, nr, 0, 1)) != hipSuccess) return e;
+    if ((e = transpose_ld(st, n, nr, X, nr, Xt, n)) != hipSuccess) return e;
+    if ((e = launch_dgemm(st, nr, nr, n, 1.0, Xt, n, 0, T1, nr, 0, 0.0, g, nr, 0, 1)) != hipSuccess) return e;
+    if ((e = compress_basis(st, nr, k, g, Qg, Sg, cw, iters)) != hipSuccess) return e;
+    // Y = X Qg; Sg = L L^T (pivots must exceed 1e-10 tr Sg); Z^T = L^{-1} Y^T
+    if ((e = launch_dgemm(st, n, k, nr, 1.0, X, nr, 0, Qg, k, 0, 0.0, Y, k, 0, 1)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_zero_i, dim3(1), dim3(1), 0, st, c.bad);
+    hipLaunchKernelGGL(k_trace, dim3(1), dim3(1024), 0, st, Sg, k, c.tr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = potrf(st, k, 0.0, c, 1e-10)) != hipSuccess) return e;
+    if ((e = transpose_ld(st, n, k, Y, k, Yt, n)) != hipSuccess) return e;
+    if ((e = trsm_lower(st, k, n, c, Yt)) != hipSuccess) return e;
+    if ((e = transpose_ld(st, k, n, Yt, n, Z, k)) != hipSuccess) return e;
+    // U = v Z; R = v - U U^T
+    if ((e = launch_dgemm(st, n, k, n, 1.0, v, n, 0, Z, k, 0, 0.0, U, k, 0, 1)) != hipSuccess) return e;
+    if (R) {
+        if ((e = transpose_ld(st, n, k, U, k, Ut, n)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)std::min<int64_t>(((int64_t)n * n + 255) / 256, 8192)), dim3(256),
+                           0, st, v, R, (int64_t)n * n);
+        if ((e = launch_dgemm(st, n, n, k, -1.0, U, k, 0, Ut, n, 0, 1.0, R, n, 0, 1)) != hipSuccess) return e;
+    }
+    int hb = 0;
+    if ((e = hipMemcpyAsync(&hb, c.bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     return hb ? hipErrorUnknown : hipSuccess;
 }
 

@@ -78,7 +78,9 @@ _SIGS = {
     "gw_solve_W": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
-    "gw_decompress": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "gw_decompress": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
+    "gw_pair_basis": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.c_double, ctypes.c_int32, _P, _P,
+                                     _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "gw_submit": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid),
                                  ctypes.c_int32, ctypes.c_int, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_uint64)]),
@@ -182,9 +184,18 @@ class Context:
         st = lib.gw_compress_basis(self.h, _ptr(v), n, k, _stream_handle(stream), _ptr(Q_out), _ptr(S_out))
         self._check(st, "gw_compress_basis")
 
-    def decompress(self, U, n: int, k: int, X, W_out, stream=None):
-        st = lib.gw_decompress(self.h, _ptr(U), n, k, _ptr(X), _stream_handle(stream), _ptr(W_out))
+    def decompress(self, U, n: int, k: int, X, W_out, R=None, stream=None):
+        st = lib.gw_decompress(self.h, _ptr(U), n, k, _ptr(X), _ptr(R), _stream_handle(stream), _ptr(W_out))
         self._check(st, "gw_decompress")
+
+    def pair_basis(self, mol: "gw_molecule", v, e_threshold: float, k: int, Z_out, U_out, R_out=None,
+                   stream=None) -> int:
+        """Returns N_rank, the number of generating pairs."""
+        nr = ctypes.c_int64()
+        st = lib.gw_pair_basis(self.h, ctypes.byref(mol), _ptr(v), e_threshold, k, _stream_handle(stream),
+                               _ptr(Z_out), _ptr(U_out), _ptr(R_out), ctypes.byref(nr))
+        self._check(st, "gw_pair_basis")
+        return nr.value
 
     def submit(self, mol: "gw_molecule", v, grid: "gw_grid", k_compress: int = 0, prec: int = GW_FP64,
                tol: float = 1e-7) -> int:

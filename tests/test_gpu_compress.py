@@ -104,3 +104,87 @@ def test_compressed_W_cluster(gpu):
         e = _rel(Ws[i], ref)
         _say("j", j, "rel", e)
         assert e < 1e-7
+
+
+def _oracle_chi(mol, grid, js):
+    P = o.pair_vectors(mol)
+    d = grid.domega
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+    nhb = o.hist_bins(mol.eig, grid.n_omega, d)
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, nhb)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps, js=js),
+                         mol.n_prod)
+    return P, chi
+
+
+def _pair_rank(P, mol, thr):
+    sel = o.pair_subset(mol.eig, mol.n_occ, thr)
+    X = P[:, sel]
+    lam = np.linalg.eigvalsh(X.T @ mol.v @ X)[::-1]
+    return X, int(np.sum(lam > 1e-10 * lam[0])), len(sel)
+
+
+@pytest.mark.parametrize("case", ["tiny_all_pairs", "chain3_threshold"])
+def test_pair_basis_W(gpu, case):
+    """Section 7.A/7.B with the paper's own subspace: GPU Z is orthonormal in
+    the Coulomb metric, and W = R + U (1 - chi_hat)^{-1} U^T through
+    gw_build_chi0 / gw_solve_W / gw_decompress equals the oracle's
+    v + Z^mu chi_RPA Z^nu (and, when every pair generates the subspace, the
+    full W)."""
+    gw, ctx, torch = gpu
+    if case == "tiny_all_pairs":
+        mol, thr = gs.make_config(0), 10.0
+    else:
+        mol, thr = gs.chain_molecule(3, 5), 1.2
+    grid = gs.config_grid(0)
+    js = [grid.n_omega // 2 + 5, grid.n_omega // 2 + 40, 60]
+    P, chi = _oracle_chi(mol, grid, js)
+    X, k, nr = _pair_rank(P, mol, thr)
+    _say(case, "n_prod", mol.n_prod, "pairs", nr, "rank", k)
+    n = mol.n_prod
+    dm = gw.DeviceMolecule(mol)
+    Z = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    U = torch.empty_like(Z)
+    R = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    assert ctx.pair_basis(dm.struct, dm.v, thr, k, Z, U, R) == nr
+    torch.cuda.synchronize()
+    Zh = Z.cpu().numpy()
+    assert np.abs(Zh.T @ mol.v @ Zh - np.eye(k)).max() < 1e-9
+    assert np.abs(U.cpu().numpy() - mol.v @ Zh).max() < 1e-10 * np.abs(mol.v).max()
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    chat = torch.empty((grid.n_omega, k, k), dtype=torch.complex128, device="cuda")
+    ctx.build_chi0(dm.struct, g, chat, basis=U, k=k)
+    ones = torch.ones(k, dtype=torch.float64, device="cuda")
+    Xk = torch.empty_like(chat)
+    ctx.solve_W(ones, k, chat, grid.n_omega, Xk, v_is_diag=True)
+    Zo, _ = o.pair_basis(X, mol.v, k)
+    for i, j in enumerate(js):
+        Wj = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+        ctx.decompress(U, n, k, Xk[j], Wj, R=R)
+        Wg = Wj.cpu().numpy()
+        Wr = o.screened_W_pair_basis(mol.v, chi[i], Zo)
+        e = _rel(Wg, Wr)
+        _say(case, "j", j, "rel vs oracle pair-basis W", e)
+        assert e < 1e-9
+        if case == "tiny_all_pairs":
+            assert _rel(Wg, o.screened_W(mol.v, chi[i])) < 1e-9
+
+
+def test_pair_basis_errors(gpu):
+    gw, ctx, torch = gpu
+    mol = gs.make_config(0)
+    P = o.pair_vectors(mol)
+    X, k, nr = _pair_rank(P, mol, 10.0)
+    dm = gw.DeviceMolecule(mol)
+    n = mol.n_prod
+    Z = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    U = torch.empty_like(Z)
+    # more than the number of pairs below the threshold
+    with pytest.raises(gw.GwError) as e:
+        ctx.pair_basis(dm.struct, dm.v, 0.25, 50, Z, U)
+    assert e.value.status == gw.GW_E_INVALID
+    # more than the rank of the generators
+    with pytest.raises(gw.GwError) as e:
+        ctx.pair_basis(dm.struct, dm.v, 10.0, k + 5, Z, U)
+    assert e.value.status == gw.GW_E_NOCONV
