@@ -14,6 +14,7 @@ What the method computes, in the paper's notation (energies in Hartree):
   than the broadening) and Section 5.B (eps = 1.5 domega by default).
 * Screening, Section 2 eq. Coulombscreening / Section 3 eq.
   tensorform-scr-inter: W = (1 - v chi0)^{-1} v, frequency by frequency.
+* Two spectral windows, Section 5.B eq. win2-for-response.
 * Compression, Section 7.B eqs. subspace_chi0 and chi_RPA; the paper's own
   subspace, Section 7.A eqs. subsetof_vef, projector0, subspace and
   global-basis-orthogonality.
@@ -61,6 +62,8 @@ __all__ = [
     "pair_basis",
     "pair_projector",
     "screened_W_pair_basis",
+    "two_window_split",
+    "chi0_two_window",
 ]
 
 
@@ -390,3 +393,48 @@ def screened_W_pair_basis(v: np.ndarray, chi0: np.ndarray, Z: np.ndarray) -> np.
     k = c.shape[0]
     rpa = np.linalg.solve(np.eye(k, dtype=np.complex128) - c, c)
     return v.astype(np.complex128) + U @ rpa @ U.T
+
+
+# ----------------------------------------------------------------------------
+# two spectral windows (Section 5.B eq. win2-for-response)
+
+
+def two_window_split(domega_small: float, omega_max_small: float, domega_large: float) -> float:
+    """Energy lambda_s that separates the pairs of the two windows: the
+    largest edge of the large mesh's bins with lambda_s <= lambda - domega_small
+    (lambda = omega_max_small, the half-width of the small window), so that a
+    pair below it deposits its split weight inside the small mesh and a pair at
+    or above it starts a large-mesh bin."""
+    m = math.floor((omega_max_small - domega_small) / domega_large)
+    return m * domega_large
+
+
+def chi0_two_window(P: np.ndarray, eig: np.ndarray, n_occ: int, s: int,
+                    small: tuple, large: tuple, js: Optional[Sequence[int]] = None) -> np.ndarray:
+    """chi0 on the small window's mesh (Section 5.B eq. win2-for-response):
+    the Cauchy transform with eps_small of the spectral function of the pairs
+    with Delta < lambda_s (histogrammed on the small mesh), plus the Cauchy
+    transform with eps_large of the spectral function of the pairs with
+    Delta >= lambda_s (histogrammed on the large mesh) evaluated at the small
+    mesh's frequencies.  small/large: (n_omega, omega_min, omega_max, eps).
+    Every pair is counted once: the split is by pair, at a bin edge of the
+    large mesh.  Returns packed upper [len(js)][n(n+1)/2]."""
+    ns, a_s, b_s, e_s = small
+    nl, a_l, b_l, e_l = large
+    ds = grid_spacing(ns, a_s, b_s)
+    dl = grid_spacing(nl, a_l, b_l)
+    lam_s = two_window_split(ds, b_s, dl)
+    delta = (eig[n_occ:][None, :] - eig[:n_occ][:, None]).ravel()
+    low = delta < lam_s
+    # small window, fine mesh
+    m_s, f_s = pair_bins(eig, n_occ, ds)
+    nhb_s = hist_bins(eig, ns, ds)
+    H_s = histogram(P[:, low], m_s[low], f_s[low], s, nhb_s)
+    chi = chi0_from_hist(H_s, s, ns, a_s, b_s, e_s, js=js)
+    # the rest, coarse mesh, evaluated at the fine mesh's frequencies
+    m_l, f_l = pair_bins(eig, n_occ, dl)
+    nhb_l = hist_bins(eig, nl, dl)
+    H_l = histogram(P[:, ~low], m_l[~low], f_l[~low], s, nhb_l)
+    om = grid_omegas(ns, a_s, b_s)
+    om = om if js is None else om[np.asarray(list(js), dtype=np.int64)]
+    return chi + chi0_from_hist(H_l, s, nl, a_l, b_l, e_l, omegas=om)

@@ -451,3 +451,43 @@ def test_pair_basis_W_exact_when_chi0_in_subspace():
         chi = _chi_of_pairs(P, mol, sel, 0.3, 0.05)
         Wf = o.screened_W(mol.v, chi)
         assert np.linalg.norm(o.screened_W_pair_basis(mol.v, chi, Z2) - Wf) > 1e-4 * np.linalg.norm(Wf)
+
+
+def test_two_window_same_mesh_is_single_window():
+    """Section 5.B eq. win2-for-response: the two windows partition the pairs,
+    so with the same mesh and broadening in both windows the result is the
+    single-window chi0; the split sits on a bin edge below lambda."""
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    lam = o.two_window_split(grid.domega, grid.omega_max, grid.domega)
+    assert lam == grid.omega_max - grid.domega
+    g = (grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    js = [grid.n_omega // 2 + 3, 150, 60, 250]
+    two = o.chi0_two_window(P, mol.eig, mol.n_occ, s, g, g, js=js)
+    one = o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps, js=js)
+    assert np.abs(two - one).max() < 1e-12 * np.abs(one).max()
+
+
+def test_two_window_partition_and_sum_rule():
+    """Every pair lands in exactly one window: the small-window histogram
+    (fine mesh) and the large-window one (coarse mesh) carry the integer sum
+    rule 2 sum_p V_mu V_nu together, and the split agrees with the bins."""
+    mol = gs.chain_molecule(3, 5)
+    P = o.pair_vectors(mol)
+    ds, dl = 2.0 ** -6, 2.0 ** -3
+    lam = o.two_window_split(ds, 0.5, dl)
+    assert lam == 0.375 and lam <= 0.5 - ds
+    delta = (mol.eig[mol.n_occ:][None, :] - mol.eig[:mol.n_occ][:, None]).ravel()
+    low = delta < lam
+    assert 0 < low.sum() < mol.n_pairs
+    s = o.frac_bits(P, mol.n_pairs)
+    ms, fs = o.pair_bins(mol.eig, mol.n_occ, ds)
+    ml, fl = o.pair_bins(mol.eig, mol.n_occ, dl)
+    assert ms[low].max() + 1 < 0.5 / ds  # small-window pairs stay inside the small mesh
+    assert np.all(ml[~low] >= lam / dl)  # large-window pairs start at or above the split bin
+    Hs = o.histogram(P[:, low], ms[low], fs[low], s, o.hist_bins(mol.eig, 64, ds))
+    Hl = o.histogram(P[:, ~low], ml[~low], fl[~low], s, o.hist_bins(mol.eig, 64, dl))
+    iu, ju = np.triu_indices(mol.n_prod)
+    t = np.rint(np.ldexp(P[iu] * P[ju], s)).astype(np.int64)
+    assert np.array_equal(Hs.sum(axis=0) + Hl.sum(axis=0), 2 * t.sum(axis=1))
