@@ -155,6 +155,31 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g,
                         const double *basis, int32_t k, void *stream,
                         int64_t *hist_out, void *chi0_out, gw_report *rep);
 
+/* Two spectral windows (Section 5.B eq. win2-for-response): chi0 on a coarse
+ * mesh over a wide window and on a fine mesh over a narrow low-energy window,
+ * each with its own broadening.  The pairs are split at
+ *   lambda_s = floor((omega_max_small - domega_small) / domega_large) * domega_large,
+ * a bin edge of the large mesh: a pair with Delta_p < lambda_s enters the
+ * small window's spectral function (histogrammed on the fine mesh, Cauchy
+ * transform with g_small->eps); every other pair enters through the large
+ * mesh's histogram, Cauchy-transformed with g_large->eps and evaluated at the
+ * fine mesh's frequencies, so that no pair is counted twice.
+ *   g_small, g_large: meshes as for gw_build_chi0, with
+ *          domega_small <= domega_large and omega_max_small <= omega_max_large.
+ *          Both windows use one fixed-point exponent s, chosen from every
+ *          pair with g_large->frac_bits as the request (g_small->frac_bits
+ *          is not read).
+ *   basis, k: as for gw_build_chi0.
+ *   chi_small_out: DEVICE complex128 [g_small->n_omega][k][k], both triangles.
+ *   chi_large_out: DEVICE complex128 [g_large->n_omega][k][k]: the ordinary
+ *          one-window chi0 of the large mesh (every pair), both triangles.
+ *   rep: HOST or NULL; as for gw_build_chi0, for the large mesh.
+ * The outputs must not alias.  Errors: GW_E_INVALID for a bad mesh or a pair
+ * of meshes that breaks the rules above, GW_E_OOM, GW_E_DEVICE. */
+gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_small,
+                           const gw_grid *g_large, const double *basis, int32_t k, void *stream,
+                           void *chi_small_out, void *chi_large_out, gw_report *rep);
+
 /* Step 4: W(omega_j) = (1 - v chi0(omega_j))^{-1} v for every mesh point
  * (Section 2 eq. Coulombscreening).  Only j = 0 and j >= n_omega/2 are
  * factorised; W(omega_{n-j}) = conj W(omega_j) fills the rest (retarded

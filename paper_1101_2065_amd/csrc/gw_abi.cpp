@@ -107,11 +107,14 @@ gw_status check_grid(gw_ctx *c, const gw_grid *g, int *kbits) {
     return GW_OK;
 }
 
-int hist_bins_host(const double *eig, int n_orb, int n_omega, int kbits) {
-    const double dmax = eig[n_orb - 1] - eig[0];
+int hist_bins_range(double dmax, int n_omega, int kbits) {
     const double x = std::ldexp(dmax, kbits);
     const long mmax = (long)std::floor(x);
     return (int)std::min<long>(n_omega / 2, mmax + 2);
+}
+
+int hist_bins_host(const double *eig, int n_orb, int n_omega, int kbits) {
+    return hist_bins_range(eig[n_orb - 1] - eig[0], n_omega, kbits);
 }
 
 struct HostMol {
@@ -336,7 +339,8 @@ gw_status build_plan(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const 
     p->n_prod = m->n_prod;
     p->n_virt = m->n_orb - m->n_occ;
     p->n_pairs = (int64_t)p->n_occ * p->n_virt;
-    p->nhb = hist_bins_host(h.eig.data(), p->n_orb, g->n_omega, kbits);
+    p->dmax = h.eig[p->n_orb - 1] - h.eig[0];
+    p->nhb = hist_bins_range(p->dmax, g->n_omega, kbits);
     p->rows = basis ? k : p->n_prod;
     p->n_upper = (int64_t)p->rows * (p->rows + 1) / 2;
     p->max_o = h.max_o;
@@ -567,6 +571,114 @@ gw_status gw_build_chi0(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, con
         GW_HIP(ctx, hipStreamSynchronize(st));
         std::memset(rep, 0, sizeof(*rep));
         rep->n_hbins = p.nhb;
+        rep->frac_bits_used = sv;
+        rep->n_dropped_pairs = hs[1];
+    }
+    return GW_OK;
+}
+
+gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_small, const gw_grid *g_large,
+                           const double *basis, int32_t k, void *stream, void *chi_small_out, void *chi_large_out,
+                           gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    if (!chi_small_out || !chi_large_out) return fail(ctx, GW_E_INVALID, "chi_small_out and chi_large_out must be set");
+    if (chi_small_out == chi_large_out) return fail(ctx, GW_E_INVALID, "the two outputs must not alias");
+    int kbits_s = 0;
+    gw_status s = check_grid(ctx, g_small, &kbits_s);
+    if (s != GW_OK) return s;
+    gwp::BuildPlan pl;
+    s = gwp::build_plan(ctx, m, g_large, basis, k, st, "", nullptr, &pl);
+    if (s != GW_OK) return s;
+    const double ds = (g_small->omega_max - g_small->omega_min) / g_small->n_omega;
+    const double dl = pl.dom;
+    if (ds > dl) return fail(ctx, GW_E_INVALID, "the small window's spacing must not exceed the large one's");
+    if (g_small->omega_max > g_large->omega_max)
+        return fail(ctx, GW_E_INVALID, "the small window must lie inside the large one");
+    // split energy lambda_s = m_lam * dl: the largest large-mesh bin edge with
+    // lambda_s + ds <= omega_max of the small window (powers of two: exact)
+    const int m_lam = std::max(0, (int)std::floor((g_small->omega_max - ds) / dl));
+    const int ratio = (int)std::lround(dl / ds);
+    const int m_cut = m_lam * ratio;  // the same edge on the small mesh
+    const int n_s = g_small->n_omega;
+    const int nhb_s = hist_bins_range(pl.dmax, n_s, kbits_s);
+    const int nh_s = std::min(m_cut, nhb_s - 1) + 1;  // rows of the small histogram that can be non-zero
+    const int64_t nu = pl.n_upper;
+    const int rows = pl.rows;
+    const int L_s = 2 * n_s;
+    const int M = pl.nhb - m_lam;  // large-mesh rows that enter the small window's frequencies
+    void *q;
+    int32_t *lo_s, *rowoff_s, *binoff_s, *perm_s;
+    double *fsort_s;
+    int64_t *stat_s, *H_s, *Hb = nullptr;
+    zdbl *Kt_s, *tw_s, *K = nullptr;
+#define GW_WS(name, bytes, dst)                                   \
+    do {                                                          \
+        if ((s = ws(ctx, name, (bytes), &q)) != GW_OK) return s;  \
+        dst = (decltype(dst))q;                                   \
+    } while (0)
+    GW_WS("2w_lo", sizeof(int32_t) * pl.n_occ * (nhb_s + 1), lo_s);
+    GW_WS("2w_rowoff", sizeof(int32_t) * pl.n_occ * nhb_s, rowoff_s);
+    GW_WS("2w_binoff", sizeof(int32_t) * nhb_s, binoff_s);
+    GW_WS("2w_perm", sizeof(int32_t) * pl.n_pairs, perm_s);
+    GW_WS("2w_fsort", sizeof(double) * pl.n_pairs, fsort_s);
+    GW_WS("2w_stat", 64, stat_s);
+    GW_WS("2w_H", sizeof(int64_t) * nh_s * nu, H_s);
+    GW_WS("2w_Kt", sizeof(zdbl) * L_s, Kt_s);
+    GW_WS("2w_tw", sizeof(zdbl) * L_s, tw_s);
+    if (M > 0) {
+        GW_WS("2w_K", sizeof(zdbl) * n_s * M, K);
+        if (m_lam > 0) GW_WS("2w_Hb", sizeof(int64_t) * (m_lam + 1) * nu, Hb);
+    }
+#undef GW_WS
+    // large window: the ordinary build over every pair
+    const bool kspec = ctx->ks_n != g_large->n_omega || ctx->ks_min != g_large->omega_min || ctx->ks_d != pl.dom ||
+                       ctx->ks_eps != g_large->eps;
+    s = gwp::build_enqueue(ctx, pl, st, chi_large_out, kspec);
+    if (s != GW_OK) return s;
+    if (kspec) {
+        ctx->ks_n = g_large->n_omega;
+        ctx->ks_min = g_large->omega_min;
+        ctx->ks_d = pl.dom;
+        ctx->ks_eps = g_large->eps;
+    }
+    // large-mesh histogram of the pairs with Delta >= lambda_s: rows above
+    // m_lam are those of the whole histogram; row m_lam loses the upper split
+    // weight of the pairs in bin m_lam - 1
+    const int64_t *H_lo = nullptr;
+    if (M > 0 && m_lam > 0) {
+        GW_HIP(ctx, gwk::launch_hist(st, rows, pl.n_pairs, pl.Ps, pl.fsort, pl.binoff, pl.stat, pl.sdev, pl.nhb, Hb,
+                                     pl.splits, 0, m_lam));
+        int64_t *row = Hb + (int64_t)m_lam * nu;
+        GW_HIP(ctx, gwk::launch_sub_i64(st, pl.H + (int64_t)m_lam * nu, row, nu));
+        H_lo = row;
+    }
+    // small window: the pairs with Delta < lambda_s on the fine mesh, same s
+    const double *Psrc = pl.basis ? pl.Pt : pl.P;
+    GW_HIP(ctx, gwk::launch_pair_sort(st, pl.n_orb, pl.n_occ, pl.m.eig, kbits_s, nhb_s, lo_s, rowoff_s, binoff_s,
+                                      perm_s, fsort_s, stat_s));
+    GW_HIP(ctx, gwk::launch_gather(st, rows, pl.n_pairs, Psrc, perm_s, stat_s, pl.Ps));
+    GW_HIP(ctx, gwk::launch_hist(st, rows, pl.n_pairs, pl.Ps, fsort_s, binoff_s, stat_s, pl.sdev, nhb_s, H_s,
+                                 std::min(pl.splits, std::max(1, nhb_s - 1)), 0, m_cut));
+    GW_HIP(ctx, gwk::launch_kspec(st, n_s, (int)std::lround(g_small->omega_min / ds), ds, g_small->eps, Kt_s, tw_s));
+    GW_HIP(ctx, gwk::launch_fftconv(st, rows, n_s, nh_s, H_s, pl.sdev, Kt_s, tw_s, (zdbl *)chi_small_out, false));
+    // the rest, broadened with the large window's eps, at the small mesh's frequencies
+    if (M > 0) {
+        GW_HIP(ctx, gwk::launch_cauchy_table(st, n_s, g_small->omega_min, ds, pl.nhb, m_lam, dl, g_large->eps, K));
+        GW_HIP(ctx, gwk::launch_cauchy_add(st, rows, n_s, pl.nhb, m_lam, pl.H, H_lo, pl.sdev, K,
+                                           (zdbl *)chi_small_out));
+    }
+    GW_HIP(ctx, gwk::launch_symmetrize(st, rows, n_s, (zdbl *)chi_small_out));
+    if (rep) {
+        int64_t hs[2];
+        int32_t sv = 0;
+        GW_HIP(ctx, hipMemcpyAsync(hs, pl.stat, sizeof(hs), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipMemcpyAsync(&sv, pl.sdev, sizeof(sv), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_hbins = pl.nhb;
         rep->frac_bits_used = sv;
         rep->n_dropped_pairs = hs[1];
     }

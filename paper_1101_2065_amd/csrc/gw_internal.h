@@ -43,9 +43,12 @@ hipError_t launch_fracbits(hipStream_t st, const uint64_t *vmax_bits, int64_t n_
 hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t value);
 
 // Exact int64 histogram H[nhb][n_upper] (Section 5.A eq. chi_by_spectra).
+// With a bin range, only pairs whose lower bin lies in [bin_lo, bin_hi) are
+// counted and only rows [bin_lo, bin_hi] of H are written (cleared first);
+// bin_hi < 0 means nhb - 1, i.e. every kept pair.
 hipError_t launch_hist(hipStream_t st, int n, int64_t n_pairs_cap, const double *Ps,
                        const double *fsort, const int32_t *binoff, const int64_t *stat,
-                       const int32_t *s_dev, int nhb, int64_t *H, int splits);
+                       const int32_t *s_dev, int nhb, int64_t *H, int splits, int bin_lo = 0, int bin_hi = -1);
 
 // Kernel spectrum Kt[q] = DFT of k(r) = 1/((r + j0) domega + i eps) (wrapped) and
 // the twiddle table tw[q] = exp(-2 pi i q / L).
@@ -53,8 +56,13 @@ hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, doub
                         zdbl *Kt, zdbl *tw);
 
 // chi0[j][mu][nu] from H by FFT convolution (Section 5.A, 8.A).
+// symmetrize = false: the wave-kernel sizes (256 <= 2 n_omega <= 2048) leave
+// the strict lower triangle unwritten (launch_symmetrize fills it later).
 hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H,
-                          const int32_t *s_dev, const zdbl *Kt, const zdbl *tw, zdbl *chi0);
+                          const int32_t *s_dev, const zdbl *Kt, const zdbl *tw, zdbl *chi0,
+                          bool symmetrize = true);
+// chi0[j][nu][mu] = chi0[j][mu][nu] for mu < nu, all j < n_omega.
+hipError_t launch_symmetrize(hipStream_t st, int n, int n_omega, zdbl *chi0);
 
 // ---------------------------------------------------------------- dense algebra
 // Batched complex GEMM, C = alpha*A*B + beta*C, row-major, element strides,
@@ -114,6 +122,16 @@ size_t compress_work_doubles(int n, int k);
 size_t pair_basis_work_doubles(int n, int nr, int k);
 hipError_t pair_basis(hipStream_t st, int n, int nr, int k, const double *v, const double *X, double *Z, double *U,
                       double *R, double *work, int iters);
+// b = a - b over n int64 entries.
+hipError_t launch_sub_i64(hipStream_t st, const int64_t *a, int64_t *b, int64_t n);
+// chi[j][mu][nu] += sum_{m in [m_lo, nhb)} 2^-s H[m][mu<=nu] K[j][m - m_lo] for
+// j < n_om on the upper triangle only (K: [n_om][nhb - m_lo] complex).  Row
+// m_lo comes from H_lo ([n_upper]) instead of H when H_lo is non-null.
+hipError_t launch_cauchy_add(hipStream_t st, int n, int n_om, int nhb, int m_lo, const int64_t *H,
+                             const int64_t *H_lo, const int32_t *s_dev, const zdbl *K, zdbl *chi);
+// K[j][m - m_lo] = 1/(w_j - m d + i eps) - 1/(w_j + m d + i eps), w_j = w0 + j dw.
+hipError_t launch_cauchy_table(hipStream_t st, int n_om, double w0, double dw, int nhb, int m_lo, double d,
+                               double eps, zdbl *K);
 // X[mu][j0 + j] = P[mu][src[j0 + j] - base] for j < ncols.
 hipError_t launch_gather_cols(hipStream_t st, int rows, int ncols, int64_t ldp, const double *P, const int32_t *src,
                               int64_t base, int j0, double *X, int64_t ldx);

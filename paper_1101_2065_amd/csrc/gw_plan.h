@@ -37,6 +37,7 @@ struct BuildPlan {
     int echunk = 0, splits = 1, j0 = 0;
     int64_t n_pairs = 0, n_upper = 0;
     double dom = 0;
+    double dmax = 0;  // largest pair energy eig[n_orb-1] - eig[0]
     double *P = nullptr, *Pt = nullptr, *bt = nullptr, *Ps = nullptr, *fsort = nullptr;
     int32_t *lo = nullptr, *rowoff = nullptr, *binoff = nullptr, *perm = nullptr, *sdev = nullptr;
     int64_t *stat = nullptr, *H = nullptr;

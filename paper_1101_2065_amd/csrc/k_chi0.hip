@@ -511,8 +511,16 @@ hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, doub
     return hipGetLastError();
 }
 
+hipError_t launch_symmetrize(hipStream_t st, int n, int n_omega, zdbl *chi0) {
+    const int nt = (n + 31) / 32;
+    ProfScope pm(st, "symmetrize", 0.0, 16.0 * 2.0 * n_omega * ((double)n * (n - 1) / 2));
+    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)((n_omega + 7) / 8)), dim3(256), 0,
+                       st, n, n_omega, nt, chi0);
+    return hipGetLastError();
+}
+
 hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H, const int32_t *s_dev,
-                          const zdbl *Kt, const zdbl *tw, zdbl *chi0) {
+                          const zdbl *Kt, const zdbl *tw, zdbl *chi0, bool symmetrize) {
     const int64_t n_upper = (int64_t)n * (n + 1) / 2;
     const int L = 2 * n_omega;
     if (L >= 256 && L <= 2048) {
@@ -535,11 +543,7 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        const int nt = (n + 31) / 32;
-        ProfScope pm(st, "symmetrize", 0.0, 16.0 * 2.0 * n_omega * ((double)n * (n - 1) / 2));
-        hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)((n_omega + 7) / 8)),
-                           dim3(256), 0, st, n, n_omega, nt, chi0);
-        return hipGetLastError();
+        return symmetrize ? launch_symmetrize(st, n, n_omega, chi0) : hipSuccess;
     }
     ProfScope ps(st, "fftconv", 0.0, 8.0 * nhb * (double)n_upper + 16.0 * n_omega * (double)n * n);
     const int nch = (n + 15) / 16;
@@ -558,6 +562,96 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
             return hipErrorInvalidValue;
     }
 #undef GW_FFT_CASE
+    return hipGetLastError();
+}
+
+namespace {
+
+// K[j][m - m_lo] = 1/(w_j - m d + i eps) - 1/(w_j + m d + i eps), w_j = w0 + j dw
+__global__ void k_cauchy_table(int n_om, double w0, double dw, int nhb, int m_lo, double d, double eps, zdbl *K) {
+    const int M = nhb - m_lo;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_om * M) return;
+    const int j = idx / M, m = m_lo + idx % M;
+    const double w = w0 + j * dw, sm = m * d;
+    const double a = w - sm, b = w + sm, e2 = eps * eps;
+    const double da = a * a + e2, db = b * b + e2;
+    // 1/(a + i eps) = (a - i eps) / (a^2 + eps^2)
+    K[idx] = zdbl{a / da - b / db, -eps / da + eps / db};
+}
+
+// chi[j][mu][nu] += sum_m 2^-s H[m][mu<=nu] K[j][m - m_lo] on the upper
+// triangle, one packed (mu <= nu) per thread.  Row m_lo is read from H_lo when
+// that is given.  K is uniform over the workgroup (scalar loads); each thread
+// keeps CJ frequencies in registers and walks its histogram column once per
+// chunk of frequencies.
+constexpr int CJ = 16;
+__global__ __launch_bounds__(256) void k_cauchy_add(int n, int n_om, int nhb, int m_lo, const int64_t *__restrict__ H,
+                                                    const int64_t *__restrict__ H_lo, const int32_t *__restrict__ s_dev,
+                                                    const zdbl *__restrict__ K, zdbl *__restrict__ chi) {
+    const int64_t n_upper = (int64_t)n * (n + 1) / 2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_upper) return;
+    // row mu of the packed upper triangle: r(mu) = mu n - mu (mu - 1) / 2 <= t < r(mu + 1)
+    auto rstart = [&](int64_t r) { return r * n - (r * (r - 1)) / 2; };
+    const double b2 = 2.0 * n + 1.0;
+    int64_t mu = (int64_t)((b2 - sqrt(b2 * b2 - 8.0 * (double)t)) * 0.5);
+    if (mu < 0) mu = 0;
+    if (mu > n - 1) mu = n - 1;
+    while (mu > 0 && rstart(mu) > t) --mu;
+    while (mu < n - 1 && rstart(mu + 1) <= t) ++mu;
+    const int64_t nu = mu + (t - rstart(mu));
+    const int s = *s_dev;
+    const int M = nhb - m_lo;
+    const int64_t nn = (int64_t)n * n;
+    for (int j0 = 0; j0 < n_om; j0 += CJ) {
+        const int nj = min(CJ, n_om - j0);
+        double ar[CJ], ai[CJ];
+#pragma unroll
+        for (int q = 0; q < CJ; ++q) ar[q] = ai[q] = 0.0;
+        for (int mm = 0; mm < M; ++mm) {
+            const int64_t hv = (mm == 0 && H_lo) ? H_lo[t] : H[(int64_t)(m_lo + mm) * n_upper + t];
+            const double h = ldexp((double)hv, -s);
+            const zdbl *Kc = K + (int64_t)j0 * M + mm;
+#pragma unroll
+            for (int q = 0; q < CJ; ++q)
+                if (q < nj) {
+                    const zdbl k = Kc[(int64_t)q * M];
+                    ar[q] += h * k.re;
+                    ai[q] += h * k.im;
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < CJ; ++q)
+            if (q < nj) {
+                zdbl *c = chi + (int64_t)(j0 + q) * nn + mu * n + nu;
+                zdbl v = *c;
+                v.re += ar[q];
+                v.im += ai[q];
+                *c = v;
+            }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cauchy_table(hipStream_t st, int n_om, double w0, double dw, int nhb, int m_lo, double d,
+                               double eps, zdbl *K) {
+    const int64_t total = (int64_t)n_om * (nhb - m_lo);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cauchy_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n_om, w0, dw, nhb,
+                       m_lo, d, eps, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_cauchy_add(hipStream_t st, int n, int n_om, int nhb, int m_lo, const int64_t *H,
+                             const int64_t *H_lo, const int32_t *s_dev, const zdbl *K, zdbl *chi) {
+    const int64_t n_upper = (int64_t)n * (n + 1) / 2;
+    if (nhb - m_lo <= 0 || n_om <= 0 || n_upper == 0) return hipSuccess;
+    ProfScope ps(st, "cauchy_add", 8.0 * (nhb - m_lo) * (double)n_om * n_upper,
+                 8.0 * (nhb - m_lo) * (double)n_upper + 32.0 * n_om * (double)n_upper);
+    hipLaunchKernelGGL(k_cauchy_add, dim3((unsigned)((n_upper + 255) / 256)), dim3(256), 0, st, n, n_om, nhb, m_lo, H,
+                       H_lo, s_dev, K, chi);
     return hipGetLastError();
 }
 

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_hist(int n, int64_t ldp, const double *
                                               const int64_t *__restrict__ stat,
                                               const int32_t *__restrict__ s_dev, int nhb,
                                               unsigned long long *__restrict__ H, int64_t n_upper,
-                                              int ntiles, int splits) {
+                                              int ntiles, int splits, int bin_lo, int bin_hi) {
 #pragma clang fp contract(off)
     __shared__ double Pm[HC][HT];
     __shared__ double Pn[HC][HT];
@@ -236,8 +236,9 @@ __global__ __launch_bounds__(256) void k_hist(int n, int64_t ldp, const double *
         }
         return a;
     };
-    const int mb = (q == 0) ? 0 : first_bin((n_kept * q) / splits);
-    const int me = (q == splits - 1) ? nhb - 1 : first_bin((n_kept * (q + 1)) / splits);
+    // only pairs whose lower bin lies in [bin_lo, bin_hi)
+    const int mb = max(bin_lo, (q == 0) ? 0 : first_bin((n_kept * q) / splits));
+    const int me = min(bin_hi, (q == splits - 1) ? nhb - 1 : first_bin((n_kept * (q + 1)) / splits));
     if (mb >= me) return;
 
     uint64_t A[4][4], B[4][4], Bp[4][4];
@@ -386,16 +387,35 @@ hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t valu
 
 hipError_t launch_hist(hipStream_t st, int n, int64_t n_pairs_cap, const double *Ps, const double *fsort,
                        const int32_t *binoff, const int64_t *stat, const int32_t *s_dev, int nhb, int64_t *H,
-                       int splits) {
+                       int splits, int bin_lo, int bin_hi) {
     const int64_t n_upper = (int64_t)n * (n + 1) / 2;
-    hipError_t e = launch_fill_u64(st, (uint64_t *)H, (int64_t)nhb * n_upper, 0);
+    if (bin_hi < 0 || bin_hi > nhb - 1) bin_hi = nhb - 1;
+    if (bin_lo < 0 || bin_lo > bin_hi) return hipErrorInvalidValue;
+    // only rows [bin_lo, bin_hi] can receive weight; only they are cleared
+    hipError_t e = launch_fill_u64(st, (uint64_t *)H + (int64_t)bin_lo * n_upper,
+                                   (int64_t)(bin_hi - bin_lo + 1) * n_upper, 0);
     if (e != hipSuccess) return e;
     const int ntiles = (n + HT - 1) / HT;
     const int ntp = ntiles * (ntiles + 1) / 2;
     if (splits < 1) splits = 1;
-    ProfScope ps(st, "hist", (double)n_pairs_cap * n_upper, 8.0 * (double)n_pairs_cap * n + 8.0 * nhb * n_upper);
+    ProfScope ps(st, "hist", (double)n_pairs_cap * n_upper,
+                 8.0 * (double)n_pairs_cap * n + 8.0 * (bin_hi - bin_lo + 1) * n_upper);
     hipLaunchKernelGGL(k_hist, dim3(ntp, splits), dim3(256), 0, st, n, n_pairs_cap, Ps, fsort, binoff, stat, s_dev,
-                       nhb, (unsigned long long *)H, n_upper, ntiles, splits);
+                       nhb, (unsigned long long *)H, n_upper, ntiles, splits, bin_lo, bin_hi);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_sub_i64(const int64_t *__restrict__ a, int64_t *__restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = a[i] - b[i];
+}
+}  // namespace
+
+// b = a - b (exact integer histogram difference)
+hipError_t launch_sub_i64(hipStream_t st, const int64_t *a, int64_t *b, int64_t n) {
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 8192);
+    hipLaunchKernelGGL(k_sub_i64, dim3((unsigned)blocks), dim3(256), 0, st, a, b, n);
     return hipGetLastError();
 }
 

@@ -75,6 +75,9 @@ _SIGS = {
                                       ctypes.POINTER(gw_grid), ctypes.c_int32, ctypes.POINTER(gw_sizes)]),
     "gw_build_chi0": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid), _P,
                                      ctypes.c_int32, _P, _P, _P, ctypes.POINTER(gw_report)]),
+    "gw_build_chi0_2w": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid),
+                                        ctypes.POINTER(gw_grid), _P, ctypes.c_int32, _P, _P, _P,
+                                        ctypes.POINTER(gw_report)]),
     "gw_solve_W": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
@@ -169,6 +172,15 @@ class Context:
                                _stream_handle(stream), _ptr(hist_out), _ptr(chi0_out),
                                ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_build_chi0")
+        return rep
+
+    def build_chi0_2w(self, mol: "gw_molecule", g_small: "gw_grid", g_large: "gw_grid", chi_small_out,
+                      chi_large_out, basis=None, k: int = 0, stream=None, report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_build_chi0_2w(self.h, ctypes.byref(mol), ctypes.byref(g_small), ctypes.byref(g_large),
+                                  _ptr(basis), k, _stream_handle(stream), _ptr(chi_small_out), _ptr(chi_large_out),
+                                  ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_build_chi0_2w")
         return rep
 
     def solve_W(self, v, n: int, chi0, n_omega: int, W_out, prec: int = GW_FP64, tol: float = 1e-7,
