@@ -16,6 +16,8 @@ Other workloads (one JSON line each, same keys):
   c1    the 40-atom chain with all of its products
   c2    120-atom cluster, v compressed to its top-1500 subspace, 2048 points
   c2pair  the same cluster in the paper's own pair subspace (k = 256)
+  n2000_2w  the 2000-product molecule with two spectral windows (256 fine
+        points over |omega| < 0.5 Ha, 256 coarse ones over |omega| < 4 Ha)
   c3    64 chain molecules (8..80 atoms, 512 points) as recorded hipGraph
         batches, W written over chi0 in place
   c4    serving: Poisson arrivals at 20/s for 60 s (overloaded), then a
@@ -387,6 +389,64 @@ def run_c2pair(args, gw, gs, torch):
     return out
 
 
+# ---------------------------------------------------------------------- two windows
+def run_two_window(args, gw, gs, torch):
+    """The 2000-product molecule with two spectral windows (Section 5.B): a
+    fine 256-point mesh over |omega| < 0.5 Ha and a coarse 256-point mesh over
+    |omega| < 4 Ha, eps = 1.5 domega in each.  One step = gw_build_chi0_2w
+    (both meshes) + W on both meshes (in place, 2 x 129 factorised points)."""
+    log("generating molecule")
+    mol = gs.truncate_products(gs.make_config(1), N_PROD)
+    small, large = gs.two_window_grids()
+    n = mol.n_prod
+    dev = torch.device("cuda:0")
+    dm = gw.DeviceMolecule(mol, device=dev)
+    gsm = gw.make_grid(small.n_omega, small.omega_min, small.omega_max, small.eps)
+    glg = gw.make_grid(large.n_omega, large.omega_min, large.omega_max, large.eps)
+    ctx = gw.Context(0)
+    cs = torch.empty((small.n_omega, n, n), dtype=torch.complex128, device=dev)
+    cl = torch.empty((large.n_omega, n, n), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+    ts = []
+    roof = None
+    for it in range(args.warmup + args.steps):
+        timed = it >= args.warmup
+        if timed and roof is None:
+            ctx.profile_begin()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        ctx.build_chi0_2w(dm.struct, gsm, glg, cs, cl, stream=stream, report=False)
+        ev[1].record(stream)
+        ctx.solve_W(dm.v, n, cs, small.n_omega, cs, stream=stream, report=False)
+        ev[2].record(stream)
+        ctx.solve_W(dm.v, n, cl, large.n_omega, cl, stream=stream, report=False)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        parts = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(3)]
+        log("two-window step %d: chi0 both meshes %.3fs W fine %.3fs W coarse %.3fs wall %.3fs" % (it, *parts,
+                                                                                                    wall))
+        if timed:
+            ts.append((wall, *parts))
+            if roof is None:
+                roof = kernel_roofline(ctx.profile_read())
+                ctx.profile_end()
+    a = np.median(np.array(ts), axis=0)
+    n_pts = small.n_omega + large.n_omega
+    out = base_record(args, "W(omega)/s, 2000 products, two spectral windows (256 fine + 256 coarse points)",
+                      n_pts / a[0], "W(omega)/s", a[0], "f64",
+                      {"workload": "chain40_nprod2000_two_windows_256x0.5Ha_256x4Ha", "n_prod": n,
+                       "n_omega_small": small.n_omega, "omega_max_small_Ha": small.omega_max,
+                       "n_omega_large": large.n_omega, "omega_max_large_Ha": large.omega_max,
+                       "parallelism": "none (1 GPU)"})
+    out["phases_s"] = {"chi0_both_meshes": a[1], "W_fine": a[2], "W_coarse": a[3]}
+    out["roofline"] = roof
+    ctx.close()
+    return out
+
+
 # ---------------------------------------------------------------------- batched
 def run_c3(args, gw, gs, torch):
     grid = gs.config_grid(3)
@@ -647,7 +707,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n2000", choices=["n2000", "c1", "c2", "c2pair", "c3", "c4"])
+    ap.add_argument("--workload", default="n2000", choices=["n2000", "n2000_2w", "c1", "c2", "c2pair", "c3", "c4"])
     ap.add_argument("--forms", default=None, help="comma list of fp64, fp32_ir, bf16x_ir")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mols", type=int, default=64, help="c3: number of molecules")
@@ -668,7 +728,8 @@ def main():
               "documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.forms is None:
-        args.forms = {"n2000": "fp64,fp32_ir,bf16x_ir", "c1": "fp64,bf16x_ir", "c2": "fp64,bf16x_ir",
+        args.forms = {"n2000": "fp64,fp32_ir,bf16x_ir", "n2000_2w": "fp64", "c1": "fp64,bf16x_ir",
+                      "c2": "fp64,bf16x_ir",
                       "c2pair": "fp64", "c3": "fp64", "c4": "fp64"}[args.workload]
 
     import torch
@@ -681,6 +742,8 @@ def main():
         log("generating molecule")
         mol = gs.truncate_products(gs.make_config(1), N_PROD)
         out = run_single(args, gw, gs, torch, mol, gs.config_grid(1), "chain40_nprod2000_nomega1024")
+    elif args.workload == "n2000_2w":
+        out = run_two_window(args, gw, gs, torch)
     elif args.workload == "c1":
         log("generating molecule")
         mol = gs.make_config(1)

@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -39,6 +39,7 @@ __all__ = [
     "batch_molecules",
     "serving_stream",
     "truncate_products",
+    "two_window_grids",
 ]
 
 
@@ -306,6 +307,19 @@ def config_grid(i: int) -> Grid:
     if i == 4:
         return Grid(1024, -8.0, 8.0, 0.02)
     raise ValueError(i)
+
+
+def two_window_grids() -> Tuple[Grid, Grid]:
+    """The two-window meshes of the 2000-product workload (Hartree): a fine
+    256-point mesh over |omega| < 0.5 (spacing 2^-8, about 0.11 eV) and a
+    coarse 256-point mesh over |omega| < 4 (spacing 2^-5, about 0.85 eV), each
+    broadened by 1.5 times its own spacing (the paper's automatic choice).
+    Returns (small, large)."""
+    small = Grid(256, -0.5, 0.5, 0.0)
+    large = Grid(256, -4.0, 4.0, 0.0)
+    small.eps = 1.5 * small.domega
+    large.eps = 1.5 * large.domega
+    return small, large
 
 
 def make_config(i: int, seed: Optional[int] = None) -> Molecule:

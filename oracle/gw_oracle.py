@@ -410,7 +410,8 @@ def two_window_split(domega_small: float, omega_max_small: float, domega_large: 
 
 
 def chi0_two_window(P: np.ndarray, eig: np.ndarray, n_occ: int, s: int,
-                    small: tuple, large: tuple, js: Optional[Sequence[int]] = None) -> np.ndarray:
+                    small: tuple, large: tuple, js: Optional[Sequence[int]] = None,
+                    entries: Optional[tuple] = None) -> np.ndarray:
     """chi0 on the small window's mesh (Section 5.B eq. win2-for-response):
     the Cauchy transform with eps_small of the spectral function of the pairs
     with Delta < lambda_s (histogrammed on the small mesh), plus the Cauchy
@@ -418,7 +419,8 @@ def chi0_two_window(P: np.ndarray, eig: np.ndarray, n_occ: int, s: int,
     Delta >= lambda_s (histogrammed on the large mesh) evaluated at the small
     mesh's frequencies.  small/large: (n_omega, omega_min, omega_max, eps).
     Every pair is counted once: the split is by pair, at a bin edge of the
-    large mesh.  Returns packed upper [len(js)][n(n+1)/2]."""
+    large mesh.  Returns packed upper [len(js)][n(n+1)/2], or with
+    entries = (mu, nu) (mu <= nu) those entries only, [len(js)][len(mu)]."""
     ns, a_s, b_s, e_s = small
     nl, a_l, b_l, e_l = large
     ds = grid_spacing(ns, a_s, b_s)
@@ -429,12 +431,17 @@ def chi0_two_window(P: np.ndarray, eig: np.ndarray, n_occ: int, s: int,
     # small window, fine mesh
     m_s, f_s = pair_bins(eig, n_occ, ds)
     nhb_s = hist_bins(eig, ns, ds)
-    H_s = histogram(P[:, low], m_s[low], f_s[low], s, nhb_s)
+    def hist(sel, m, f, nhb):
+        if entries is None:
+            return histogram(P[:, sel], m[sel], f[sel], s, nhb)
+        return histogram_c(P[:, sel], m[sel], f[sel], s, nhb, entries[0], entries[1])[0]
+
+    H_s = hist(low, m_s, f_s, nhb_s)
     chi = chi0_from_hist(H_s, s, ns, a_s, b_s, e_s, js=js)
     # the rest, coarse mesh, evaluated at the fine mesh's frequencies
     m_l, f_l = pair_bins(eig, n_occ, dl)
     nhb_l = hist_bins(eig, nl, dl)
-    H_l = histogram(P[:, ~low], m_l[~low], f_l[~low], s, nhb_l)
+    H_l = hist(~low, m_l, f_l, nhb_l)
     om = grid_omegas(ns, a_s, b_s)
     om = om if js is None else om[np.asarray(list(js), dtype=np.int64)]
     return chi + chi0_from_hist(H_l, s, nl, a_l, b_l, e_l, omegas=om)

@@ -491,3 +491,20 @@ def test_two_window_partition_and_sum_rule():
     iu, ju = np.triu_indices(mol.n_prod)
     t = np.rint(np.ldexp(P[iu] * P[ju], s)).astype(np.int64)
     assert np.array_equal(Hs.sum(axis=0) + Hl.sum(axis=0), 2 * t.sum(axis=1))
+
+
+def test_two_window_sampled_entries_equal_full():
+    """The sampled-entry form of the two-window chi0 (the C histogram on
+    chosen entries) returns exactly the full form's values at those entries."""
+    mol = gs.chain_molecule(3, 5)
+    P = o.pair_vectors(mol)
+    s = o.frac_bits(P, mol.n_pairs)
+    small, large = gs.two_window_grids()
+    sm = (small.n_omega, small.omega_min, small.omega_max, small.eps)
+    lg = (large.n_omega, large.omega_min, large.omega_max, large.eps)
+    js = [small.n_omega // 2 + 5, 40]
+    full = o.chi0_two_window(P, mol.eig, mol.n_occ, s, sm, lg, js=js)
+    iu, ju = np.triu_indices(mol.n_prod)
+    pick = np.array([0, 7, len(iu) // 2, len(iu) - 1])
+    part = o.chi0_two_window(P, mol.eig, mol.n_occ, s, sm, lg, js=js, entries=(iu[pick], ju[pick]))
+    assert np.array_equal(part, full[:, pick])
