@@ -15,6 +15,11 @@ What the method computes, in the paper's notation (energies in Hartree):
 * Screening, Section 2 eq. Coulombscreening / Section 3 eq.
   tensorform-scr-inter: W = (1 - v chi0)^{-1} v, frequency by frequency.
 * Two spectral windows, Section 5.B eq. win2-for-response.
+* The paper's own route to a0: the electronic density matrix rho_ab(s) of
+  Section 5 split into its empty (rho^+) and occupied (rho^-) parts on the
+  mesh, and a0 as their convolution contracted with the vertex (Section 5.A
+  eq. chi_by_spectra), which Section 8.A eq. sf-of-response-time evaluates
+  time by time.
 * Compression, Section 7.B eqs. subspace_chi0 and chi_RPA; the paper's own
   subspace, Section 7.A eqs. subsetof_vef, projector0, subspace and
   global-basis-orthogonality.
@@ -64,6 +69,12 @@ __all__ = [
     "screened_W_pair_basis",
     "two_window_split",
     "chi0_two_window",
+    "level_bins",
+    "spectral_densities",
+    "level_hist_bins",
+    "a0_by_convolution",
+    "a0_by_pairs",
+    "chi0_from_spectrum",
 ]
 
 
@@ -445,3 +456,140 @@ def chi0_two_window(P: np.ndarray, eig: np.ndarray, n_occ: int, s: int,
     om = grid_omegas(ns, a_s, b_s)
     om = om if js is None else om[np.asarray(list(js), dtype=np.int64)]
     return chi + chi0_from_hist(H_l, s, nl, a_l, b_l, e_l, omegas=om)
+
+
+# ----------------------------------------------------------------------------
+# the paper's own route to a0 (Section 5 density matrix; Section 5.A
+# eq. chi_by_spectra; Section 8.A eq. sf-of-response-time)
+
+
+def level_bins(e: np.ndarray, domega: float):
+    """One-particle poles on the mesh: x = |e| / domega (exact for a power of
+    two), k = floor(x), phi = x - k; the pole's weight is split linearly,
+    1 - phi into bin k and phi into bin k + 1 (the same deposition rule as for
+    the pair poles)."""
+    kb = grid_shift_bits(domega)
+    x = np.ldexp(np.abs(np.asarray(e, dtype=np.float64)), kb)
+    k = np.floor(x)
+    return k.astype(np.int64), x - k
+
+
+def spectral_densities(mol, domega: float):
+    """rho^+_ab[k] = sum over empty F of X_a^F X_b^F w_F[k] (poles at E_F >= 0)
+    and rhobar^-_ab[k] = rho^-_ab(-s) = sum over occupied E of X_a^E X_b^E
+    wbar_E[k] (poles at -E_E > 0), where w is the two-bin split of the pole
+    (level_bins).  Section 5: rho_ab(s) = sum_E X_a^E X_b^E delta(s - E),
+    positive and negative parts as in eq. spectral_1.
+    Returns (rho_p [K+][n_orb][n_orb], rho_m [K-][n_orb][n_orb])."""
+    X, eig, n_occ = mol.X, mol.eig, mol.n_occ
+    if not (eig[n_occ - 1] < 0.0 <= eig[n_occ]):
+        raise ValueError("energies must be measured from the Fermi level")
+    k_p, f_p = level_bins(eig[n_occ:], domega)
+    k_m, f_m = level_bins(eig[:n_occ], domega)
+    n = mol.n_orb
+    rho_p = np.zeros((int(k_p.max()) + 2, n, n))
+    rho_m = np.zeros((int(k_m.max()) + 2, n, n))
+    for F in range(n_occ, mol.n_orb):
+        xx = np.outer(X[:, F], X[:, F])
+        i = F - n_occ
+        rho_p[k_p[i]] += (1.0 - f_p[i]) * xx
+        rho_p[k_p[i] + 1] += f_p[i] * xx
+    for E in range(n_occ):
+        xx = np.outer(X[:, E], X[:, E])
+        rho_m[k_m[E]] += (1.0 - f_m[E]) * xx
+        rho_m[k_m[E] + 1] += f_m[E] * xx
+    return rho_p, rho_m
+
+
+def level_hist_bins(eig: np.ndarray, n_occ: int, n_omega: int, domega: float) -> int:
+    """Bins of a0 on this route: the convolution of rho^+ (bins up to
+    k_max^+ + 1) with rhobar^- (up to k_max^- + 1) reaches k_max^+ + k_max^- + 2,
+    so k_max^+ + k_max^- + 3 bins, at most n_omega/2."""
+    k_p, _ = level_bins(eig[-1:], domega)
+    k_m, _ = level_bins(eig[:1], domega)
+    return int(min(n_omega // 2, int(k_p[0]) + int(k_m[0]) + 3))
+
+
+def _dense_vertex(mol) -> np.ndarray:
+    """V[mu][a][b] with the block matrices placed at their orbital sets."""
+    V = np.zeros((mol.n_prod, mol.n_orb, mol.n_orb))
+    for b in range(mol.n_blk):
+        p0, nprod, orbs, mats = mol.block_of(b)
+        for i, M in enumerate(mats):
+            V[p0 + i][np.ix_(orbs, orbs)] = M
+    return V
+
+
+def a0_by_convolution(mol, rho_p: np.ndarray, rho_m: np.ndarray, nhb: int) -> np.ndarray:
+    """a_{mu nu}[m] = 2 sum_{k1 + k2 = m} V_mu^{ab} rho^+_{bc}[k1] V_nu^{cd}
+    rhobar^-_{da}[k2], m < nhb: eq. chi_by_spectra on the mesh (the s1, s2
+    integrals become sums over bins, the delta function the condition
+    k1 + k2 = m), with the spin factor 2 of the pair route.  Bins m >= nhb
+    are dropped.  Packed upper triangle [nhb][n(n+1)/2]."""
+    V = _dense_vertex(mol)
+    n = mol.n_prod
+    iu, ju = np.triu_indices(n)
+    out = np.zeros((nhb, len(iu)))
+    Z = {}
+    for k2 in range(rho_m.shape[0]):
+        if np.any(rho_m[k2]):
+            Z[k2] = (V @ rho_m[k2]).reshape(n, -1)  # (V_nu rhobar^-)[c][a]
+    for k1 in range(rho_p.shape[0]):
+        if not np.any(rho_p[k1]):
+            continue
+        Y = V @ rho_p[k1]  # (V_mu rho^+)[a][c]
+        Yt = np.transpose(Y, (0, 2, 1)).reshape(n, -1)  # [mu][(c, a)]
+        for k2, Zk in Z.items():
+            m = k1 + k2
+            if m >= nhb:
+                continue
+            A = Yt @ Zk.T  # sum_{a,c} (V_mu rho^+)[a][c] (V_nu rhobar^-)[c][a]
+            out[m] += 2.0 * A[iu, ju]
+    return out
+
+
+def a0_by_pairs(P: np.ndarray, eig: np.ndarray, n_occ: int, domega: float, nhb: int,
+                entries: Optional[tuple] = None) -> np.ndarray:
+    """The same discrete a0 from the pair vectors (Section 7.A closed form):
+    each pair (E, F) carries 2 V_mu^p V_nu^p with the convolution of the two
+    one-particle splits as its weight, (1-phi_F)(1-phi_E) at k_F + k_E,
+    (1-phi_F) phi_E + phi_F (1-phi_E) one bin up and phi_F phi_E two bins up.
+    Packed upper [nhb][n(n+1)/2], or [nhb][len(mu)] for entries = (mu, nu)."""
+    k_p, f_p = level_bins(eig[n_occ:], domega)
+    k_m, f_m = level_bins(eig[:n_occ], domega)
+    base = (k_m[:, None] + k_p[None, :]).ravel()
+    fm = np.repeat(f_m, len(k_p))
+    fp = np.tile(f_p, len(k_m))
+    w = [(1.0 - fp) * (1.0 - fm), (1.0 - fp) * fm + fp * (1.0 - fm), fp * fm]
+    if entries is None:
+        mu, nu = np.triu_indices(P.shape[0])
+    else:
+        mu, nu = entries
+    out = np.zeros((nhb, len(mu)))
+    for d in range(3):
+        bins = base + d
+        for m in np.unique(bins):
+            if m >= nhb:
+                continue
+            sel = bins == m
+            Pw = P[:, sel] * w[d][sel][None, :]
+            out[m] += 2.0 * np.einsum("ip,ip->i", Pw[mu], P[nu][:, sel])
+    return out
+
+
+def chi0_from_spectrum(a: np.ndarray, n_omega: int, omega_min: float, omega_max: float, eps: float,
+                       js: Optional[Sequence[int]] = None, omegas: Optional[np.ndarray] = None) -> np.ndarray:
+    """chi0[j, entry] = sum_{m>=1} a[m, entry] (1/(omega_j - m domega + i eps)
+    - 1/(omega_j + m domega + i eps)) for a spectral array a in floating
+    point (the Cauchy transform of Section 5.A with a(-s) = -a(s))."""
+    d = grid_spacing(n_omega, omega_min, omega_max)
+    if omegas is None:
+        om = grid_omegas(n_omega, omega_min, omega_max)
+        if js is not None:
+            om = om[np.asarray(list(js), dtype=np.int64)]
+    else:
+        om = np.asarray(omegas, dtype=np.float64)
+    mvals = np.arange(1, a.shape[0], dtype=np.float64) * d
+    w = om[:, None]
+    K = 1.0 / (w - mvals[None, :] + 1j * eps) - 1.0 / (w + mvals[None, :] + 1j * eps)
+    return K @ a[1:]

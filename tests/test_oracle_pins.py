@@ -5,6 +5,7 @@ checks a printed number, a closed form, a conservation law, a brute-force
 contraction, a symmetry or a limit that a plausible mistake (wrong sign, lost
 factor 2, swapped bins, transposed operand, off-by-one grid) would break.
 """
+import dataclasses
 import math
 import os
 
@@ -508,3 +509,95 @@ def test_two_window_sampled_entries_equal_full():
     pick = np.array([0, 7, len(iu) // 2, len(iu) - 1])
     part = o.chi0_two_window(P, mol.eig, mol.n_occ, s, sm, lg, js=js, entries=(iu[pick], ju[pick]))
     assert np.array_equal(part, full[:, pick])
+
+
+# ---------------------------------------------------------------- the paper's own a0 route
+
+
+def _time_route(mol, domega, n_omega=256):
+    rho_p, rho_m = o.spectral_densities(mol, domega)
+    nhb = o.level_hist_bins(mol.eig, mol.n_occ, n_omega, domega)
+    return rho_p, rho_m, nhb, o.a0_by_convolution(mol, rho_p, rho_m, nhb)
+
+
+def test_spectral_densities_completeness():
+    """Section 5 density matrix on the mesh: summed over bins, rho^+ is the
+    projector onto the empty states and rhobar^- the one onto the occupied
+    states (X orthogonal), so together they give the identity; each pole
+    keeps its position (first moment)."""
+    mol = gs.make_config(0)
+    d = gs.config_grid(0).domega
+    rho_p, rho_m = o.spectral_densities(mol, d)
+    Xv, Xo = mol.X[:, mol.n_occ:], mol.X[:, :mol.n_occ]
+    assert np.abs(rho_p.sum(0) - Xv @ Xv.T).max() < 1e-14
+    assert np.abs(rho_m.sum(0) - Xo @ Xo.T).max() < 1e-14
+    assert np.abs(rho_p.sum(0) + rho_m.sum(0) - np.eye(mol.n_orb)).max() < 1e-13
+    kk = np.arange(rho_p.shape[0])[:, None, None] * d
+    assert np.abs((kk * rho_p).sum(0) - (Xv * mol.eig[mol.n_occ:]) @ Xv.T).max() < 1e-14
+    kk = np.arange(rho_m.shape[0])[:, None, None] * d
+    assert np.abs((kk * rho_m).sum(0) + (Xo * mol.eig[:mol.n_occ]) @ Xo.T).max() < 1e-14
+
+
+@pytest.mark.parametrize("which", ["tiny", "chain3"])
+def test_time_route_equals_pair_form(which):
+    """The convolution of the two densities contracted with the vertex equals
+    the pair form: each pair (E, F) with weight 2 V_mu^p V_nu^p spread by the
+    convolution of its two one-particle splits.  The pair vectors come from an
+    independent contraction (pair_vectors), so a misplaced index or density
+    in the convolution breaks this."""
+    mol = gs.make_config(0) if which == "tiny" else gs.chain_molecule(3, 5)
+    d = 2.0 ** -5
+    _, _, nhb, a = _time_route(mol, d)
+    P = o.pair_vectors(mol)
+    b = o.a0_by_pairs(P, mol.eig, mol.n_occ, d, nhb)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+def test_time_route_sum_rule_and_first_moment():
+    """Zeroth moment: the integer-free sum rule 2 sum_p V_mu V_nu; first
+    moment: 2 sum_p Delta_p V_mu V_nu (linear splits keep each pole's
+    position, and the convolution adds the two positions)."""
+    mol = gs.chain_molecule(3, 5)
+    d = 2.0 ** -5
+    _, _, nhb, a = _time_route(mol, d)
+    P = o.pair_vectors(mol)
+    iu, ju = np.triu_indices(mol.n_prod)
+    pp = P[iu] * P[ju]
+    delta = (mol.eig[mol.n_occ:][None, :] - mol.eig[:mol.n_occ][:, None]).ravel()
+    s0 = 2.0 * pp.sum(1)
+    s1 = 2.0 * (pp * delta[None, :]).sum(1)
+    assert np.abs(a.sum(0) - s0).max() <= 1e-13 * np.abs(s0).max()
+    m1 = (np.arange(nhb)[:, None] * d * a).sum(0)
+    assert np.abs(m1 - s1).max() <= 1e-13 * np.abs(s1).max()
+
+
+def test_time_route_on_mesh_equals_pair_histogram():
+    """With every level on a mesh point no pole is split, and the two routes
+    (convolution of densities, int64 pair histogram) put the same weight in
+    the same bins, up to the histogram's 2^-s quantisation."""
+    d = 2.0 ** -5
+    mol = gs.make_config(0)
+    eig = np.round(mol.eig / d) * d
+    assert np.all(np.diff(eig) >= 0) and eig[mol.n_occ - 1] < 0 <= eig[mol.n_occ]
+    mol = dataclasses.replace(mol, eig=eig)
+    _, _, nhb, a = _time_route(mol, d)
+    P = o.pair_vectors(mol)
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+    assert not fr.any()
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, o.hist_bins(mol.eig, 256, d))
+    h = np.ldexp(H.astype(np.float64), -s)
+    k = min(len(h), nhb)
+    assert np.abs(a[:k] - h[:k]).max() <= 2.0 * mol.n_pairs * 2.0 ** -s
+    assert not a[k:].any() and not h[k:].any()
+
+
+def test_chi0_from_spectrum_is_the_histogram_transform():
+    mol = gs.make_config(0)
+    grid = gs.config_grid(0)
+    P, m, fr, nhb, s, H = _pipeline(mol, grid)
+    js = [grid.n_omega // 2 + 3, 7, 200]
+    a = o.chi0_from_hist(H, s, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps, js=js)
+    b = o.chi0_from_spectrum(np.ldexp(H.astype(np.float64), -s), grid.n_omega, grid.omega_min, grid.omega_max,
+                             grid.eps, js=js)
+    assert np.array_equal(a, b)
