@@ -180,6 +180,36 @@ gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_s
                            const gw_grid *g_large, const double *basis, int32_t k, void *stream,
                            void *chi_small_out, void *chi_large_out, gw_report *rep);
 
+/* The paper's own route to a0 (Section 5 density matrix; Section 5.A eq.
+ * chi_by_spectra; Section 8.A eq. sf-of-response-time): the electronic
+ * densities rho+_ab (empty states, poles at E >= 0) and rhobar-_ab(s) =
+ * rho-_ab(-s) (occupied states, poles at -E > 0) on the mesh, each pole split
+ * linearly between two bins; their discrete Fourier transforms to L time
+ * points (L the smallest power of two holding the linear convolution); the
+ * local product a_mu_nu(t) = 2 V_mu^ab rho+_bc(t) V_nu^cd rhobar-_da(t) time
+ * by time over the vertex blocks (O(N^2) per time); the transform back to the
+ * mesh; chi0 by the same FFT Cauchy transform as gw_build_chi0.  The result
+ * is floating point: a pair (E, F) lands on up to three bins (the
+ * convolution of its two one-particle splits), not the two of the exact pair
+ * histogram.
+ *   m: as for gw_build_chi0; additionally eig[n_occ-1] < 0 <= eig[n_occ]
+ *      (energies from the Fermi level) and every orbital set of at most 32
+ *      orbitals.
+ *   g: as for gw_build_chi0 (frac_bits is not read).
+ *   a_out: DEVICE double [n_hbins][n_prod(n_prod+1)/2] or NULL: a0 on the
+ *      mesh, bin m integrated, packed upper triangle as hist_out.  n_hbins =
+ *      min(n_omega/2, K+ + K- - 1), K+- = floor(max |E|/domega) + 2 over the
+ *      empty (occupied) levels; weight beyond the last bin is dropped.
+ *   chi0_out: DEVICE complex128 [n_omega][n_prod][n_prod], both triangles.
+ *   rep: HOST or NULL: n_hbins, and in n_dropped_pairs the pairs whose
+ *      weight reaches beyond the last bin; frac_bits_used = 0.
+ * Workspace: the transformed densities take 16 (L/2+1) n_orb^2 bytes each;
+ * the time points are processed in chunks of at most 4 GiB of products.
+ * Synchronises the stream once (level tables).  Errors: GW_E_INVALID,
+ * GW_E_OOM, GW_E_DEVICE. */
+gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream,
+                             double *a_out, void *chi0_out, gw_report *rep);
+
 /* Step 4: W(omega_j) = (1 - v chi0(omega_j))^{-1} v for every mesh point
  * (Section 2 eq. Coulombscreening).  Only j = 0 and j >= n_omega/2 are
  * factorised; W(omega_{n-j}) = conj W(omega_j) fills the rest (retarded

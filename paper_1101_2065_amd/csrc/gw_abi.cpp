@@ -24,9 +24,6 @@ hipError_t launch_dzgemm(hipStream_t st, int M, int N, int K, double alpha, cons
 hipError_t launch_zdgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
                          const double *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
                          int batch);
-hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
-                        const double *B, int64_t ldb, int64_t sB, double beta, double *C, int64_t ldc, int64_t sC,
-                        int batch);
 hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *src, double *dst);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
 hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
@@ -681,6 +678,137 @@ gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_s
         rep->n_hbins = pl.nhb;
         rep->frac_bits_used = sv;
         rep->n_dropped_pairs = hs[1];
+    }
+    return GW_OK;
+}
+
+gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream, double *a_out,
+                             void *chi0_out, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    if (!chi0_out) return fail(ctx, GW_E_INVALID, "chi0_out is NULL");
+    int kbits = 0;
+    gw_status s = check_grid(ctx, g, &kbits);
+    if (s != GW_OK) return s;
+    HostMol h;
+    s = check_molecule(ctx, m, st, &h);
+    if (s != GW_OK) return s;
+    const int n_orb = m->n_orb, n_occ = m->n_occ, n = m->n_prod, nblk = m->n_blk;
+    if (!(h.eig[n_occ - 1] < 0.0 && h.eig[n_occ] >= 0.0))
+        return fail(ctx, GW_E_INVALID, "energies must be measured from the Fermi level: eig[n_occ-1] < 0 <= eig[n_occ]");
+    if (h.max_o > TIME_MAX_ORB)
+        return fail(ctx, GW_E_INVALID, "the time-domain route takes orbital sets of at most " +
+                                           std::to_string(TIME_MAX_ORB) + " orbitals");
+    // one-particle poles on the mesh, listed bin by bin: empty states by
+    // rising energy, occupied ones by rising -E
+    std::vector<int32_t> lev(n_orb), kb(n_orb);
+    std::vector<double> ph(n_orb);
+    for (int i = 0; i < n_orb; ++i) {
+        const int st_i = i < n_orb - n_occ ? n_occ + i : n_occ - 1 - (i - (n_orb - n_occ));
+        const double x = std::ldexp(std::fabs(h.eig[st_i]), kbits);
+        const double k = std::floor(x);
+        if (!(k < 1e8)) return fail(ctx, GW_E_INVALID, "a level lies too far from the Fermi level for this mesh");
+        lev[i] = st_i;
+        kb[i] = (int32_t)k;
+        ph[i] = x - k;
+    }
+    const int nv = n_orb - n_occ;
+    const int Kp = kb[nv - 1] + 2, Km = kb[n_orb - 1] + 2;
+    std::vector<int32_t> start(Kp + 1 + Km + 1, 0);
+    for (int k = 0, i = 0; k <= Kp; ++k) {
+        while (i < nv && kb[i] < k) ++i;
+        start[k] = i;
+    }
+    for (int k = 0, i = 0; k <= Km; ++k) {
+        while (i < n_occ && kb[nv + i] < k) ++i;
+        start[Kp + 1 + k] = i;
+    }
+    const int nhb = std::min(g->n_omega / 2, Kp + Km - 1);
+    int L = 2;
+    while (L < Kp + Km - 1) L *= 2;
+    if (L > (1 << 16)) return fail(ctx, GW_E_INVALID, "the levels span too many mesh points for the time route");
+    const int Q = L / 2 + 1;
+    // pairs whose convolved weight reaches a bin beyond the mesh
+    int64_t dropped = 0;
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < n_occ; ++j) {
+            const int top = kb[i] + kb[nv + j] + (ph[i] > 0.0) + (ph[nv + j] > 0.0);
+            if (top >= nhb) ++dropped;
+        }
+    // block pairs B1 <= B2 and the contraction's flop count
+    std::vector<int32_t> pbs;
+    double cflops = 0.0;
+    for (int b1 = 0; b1 < nblk; ++b1)
+        for (int b2 = b1; b2 < nblk; ++b2) pbs.push_back(b1);
+    const int npb = (int)pbs.size();
+    pbs.resize(2 * (size_t)npb);
+    for (int b1 = 0, i = 0; b1 < nblk; ++b1)
+        for (int b2 = b1; b2 < nblk; ++b2, ++i) {
+            pbs[npb + i] = b2;
+            const double n1 = h.blk_orb[b1 + 1] - h.blk_orb[b1], n2 = h.blk_orb[b2 + 1] - h.blk_orb[b2];
+            const double pm = h.blk_prod[b1 + 1] - h.blk_prod[b1], pn = h.blk_prod[b2 + 1] - h.blk_prod[b2];
+            const double pmn = b1 == b2 ? pm * (pm + 1) / 2 : pm * pn;
+            cflops += pn * (4.0 * n1 * n2 * n2 + 8.0 * n1 * n1 * n2) + 4.0 * pmn * n1 * n1;
+        }
+    const int64_t nn = (int64_t)n_orb * n_orb;
+    const int64_t n_upper = (int64_t)n * (n + 1) / 2;
+    // time points per chunk: the transformed product of a chunk takes at most 4 GiB
+    const int qc = (int)std::max<int64_t>(1, std::min<int64_t>(Q, (int64_t)(4ll << 30) / (16 * n_upper)));
+    void *q;
+    int32_t *d_lev, *d_start, *d_pb;
+    double *d_ph, *rho, *F, *G, *Rp, *Rm, *Ahat, *a = a_out;
+    zdbl *Kt, *tw;
+#define GW_WS(name, bytes, dst)                                   \
+    do {                                                          \
+        if ((s = ws(ctx, name, (bytes), &q)) != GW_OK) return s;  \
+        dst = (decltype(dst))q;                                   \
+    } while (0)
+    GW_WS("t_lev", sizeof(int32_t) * n_orb, d_lev);
+    GW_WS("t_ph", sizeof(double) * n_orb, d_ph);
+    GW_WS("t_start", sizeof(int32_t) * start.size(), d_start);
+    GW_WS("t_pairs", sizeof(int32_t) * pbs.size(), d_pb);
+    GW_WS("t_rho", sizeof(double) * std::max(Kp, Km) * nn, rho);
+    GW_WS("t_F", sizeof(double) * 2 * Q * std::max(Kp, Km), F);
+    GW_WS("t_G", sizeof(double) * nhb * 2 * Q, G);
+    GW_WS("t_Rp", sizeof(double) * 2 * Q * nn, Rp);
+    GW_WS("t_Rm", sizeof(double) * 2 * Q * nn, Rm);
+    GW_WS("t_Ahat", sizeof(double) * 2 * (int64_t)qc * n_upper, Ahat);
+    if (!a) GW_WS("t_a", sizeof(double) * nhb * n_upper, a);
+    GW_WS("t_Kt", sizeof(zdbl) * 2 * g->n_omega, Kt);
+    GW_WS("t_tw", sizeof(zdbl) * 2 * g->n_omega, tw);
+#undef GW_WS
+    GW_HIP(ctx, hipMemcpyAsync(d_lev, lev.data(), sizeof(int32_t) * n_orb, hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipMemcpyAsync(d_ph, ph.data(), sizeof(double) * n_orb, hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipMemcpyAsync(d_start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipMemcpyAsync(d_pb, pbs.data(), sizeof(int32_t) * pbs.size(), hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipStreamSynchronize(st));  // the host vectors above are released on return
+    // densities on the mesh and their transforms: Rp = F+ rho+, Rm = F- rhobar-
+    GW_HIP(ctx, gwk::launch_rho_bins(st, n_orb, Kp, m->X, d_lev, d_ph, d_start, rho));
+    GW_HIP(ctx, gwk::launch_dft_matrices(st, L, Q, Kp, F, 0, nullptr));
+    GW_HIP(ctx, gwk::launch_dgemm(st, 2 * Q, (int)nn, Kp, 1.0, F, Kp, 0, rho, nn, 0, 0.0, Rp, nn, 0, 1));
+    GW_HIP(ctx, gwk::launch_rho_bins(st, n_orb, Km, m->X, d_lev + nv, d_ph + nv, d_start + Kp + 1, rho));
+    GW_HIP(ctx, gwk::launch_dft_matrices(st, L, Q, Km, F, nhb, G));
+    GW_HIP(ctx, gwk::launch_dgemm(st, 2 * Q, (int)nn, Km, 1.0, F, Km, 0, rho, nn, 0, 0.0, Rm, nn, 0, 1));
+    // time by time (in chunks): the local product, then its share of the
+    // transform back, a = sum over chunks of G[:, chunk] Ahat[chunk]
+    for (int q0 = 0; q0 < Q; q0 += qc) {
+        const int nq = std::min(qc, Q - q0);
+        GW_HIP(ctx, gwk::launch_time_contract(st, n_orb, n, npb, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
+                                              m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Ahat, cflops * nq));
+        GW_HIP(ctx, gwk::launch_dgemm(st, nhb, (int)n_upper, 2 * nq, 1.0, G + 2 * q0, 2 * Q, 0, Ahat, n_upper, 0,
+                                      q0 == 0 ? 0.0 : 1.0, a, n_upper, 0, 1));
+    }
+    const double dom = (g->omega_max - g->omega_min) / g->n_omega;
+    GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, (int)std::lround(g->omega_min / dom), dom, g->eps, Kt, tw));
+    GW_HIP(ctx, gwk::launch_fftconv(st, n, g->n_omega, nhb, (const double *)a, Kt, tw, (zdbl *)chi0_out));
+    if (rep) {
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_hbins = nhb;
+        rep->frac_bits_used = 0;
+        rep->n_dropped_pairs = dropped;
     }
     return GW_OK;
 }

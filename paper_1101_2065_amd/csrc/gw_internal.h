@@ -61,6 +61,9 @@ hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, doub
 hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H,
                           const int32_t *s_dev, const zdbl *Kt, const zdbl *tw, zdbl *chi0,
                           bool symmetrize = true);
+// The same from a spectral array A[nhb][n_upper] already in floating point.
+hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const double *A,
+                          const zdbl *Kt, const zdbl *tw, zdbl *chi0, bool symmetrize = true);
 // chi0[j][nu][mu] = chi0[j][mu][nu] for mu < nu, all j < n_omega.
 hipError_t launch_symmetrize(hipStream_t st, int n, int n_omega, zdbl *chi0);
 
@@ -137,5 +140,26 @@ hipError_t launch_gather_cols(hipStream_t st, int rows, int ncols, int64_t ldp, 
                               int64_t base, int j0, double *X, int64_t ldx);
 hipError_t compress_basis(hipStream_t st, int n, int k, const double *v, double *Q_out, double *S_out,
                           double *work, int iters);
+
+// C[b] = alpha A[b] B[b] + beta C[b], real FP64, row-major (MFMA).
+hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const double *A, int64_t lda, int64_t sA,
+                        const double *B, int64_t ldb, int64_t sB, double beta, double *C, int64_t ldc, int64_t sC,
+                        int batch);
+
+// ---------------------------------------------------------------- time-domain a0 route
+// Largest orbital set of a vertex block on this route (LDS staging).
+#define TIME_MAX_ORB 32
+// rho[k][a][b] for k < K from levels listed bin by bin (two-bin split).
+hipError_t launch_rho_bins(hipStream_t st, int n_orb, int K, const double *X, const int32_t *lev, const double *ph,
+                           const int32_t *start, double *rho);
+// F [2Q][K] forward cosine/sine rows (F may be null) and G [M][2Q] inverse
+// rows for a real sequence (G may be null), length L, Q = L/2 + 1.
+hipError_t launch_dft_matrices(hipStream_t st, int L, int Q, int K, double *F, int M, double *G);
+// Ahat[2 qq (+1)][t] for time points q0 .. q0 + nq - 1 over the listed block
+// pairs (pb1[i] <= pb2[i]); Rp, Rm: [2Q][n_orb^2] transformed densities.
+hipError_t launch_time_contract(hipStream_t st, int n_orb, int n_prod, int n_pairs_blk, int q0, int nq,
+                                const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
+                                const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
+                                const double *Rp, const double *Rm, double *Ahat, double flops);
 
 }  // namespace gwk

@@ -150,8 +150,13 @@ __device__ inline void fft(zdbl *buf, const zdbl *__restrict__ tw) {
 // nu >= mu.  Two real odd sequences a, b are packed as z = a + i b; since the
 // DFT of a real odd sequence is i*alpha with alpha real, Z = i alpha - beta:
 // alpha = Im Z, beta = -Re Z.  Then chi = IFFT(i alpha Kt) / L for each.
-template <int L>
-__global__ __launch_bounds__(256) void k_fftconv(int n, int n_omega, int nhb, const int64_t *__restrict__ H,
+// Spectral bin value as a double: the exact histogram scaled by 2^-s, or a
+// spectral array already in floating point.
+__device__ inline double hval(const int64_t *H, int64_t i, int s) { return ldexp((double)H[i], -s); }
+__device__ inline double hval(const double *H, int64_t i, int) { return H[i]; }
+
+template <typename HT, int L>
+__global__ __launch_bounds__(256) void k_fftconv(int n, int n_omega, int nhb, const HT *__restrict__ H,
                                                  int64_t n_upper, const int32_t *__restrict__ s_dev,
                                                  const zdbl *__restrict__ Kt, const zdbl *__restrict__ tw,
                                                  zdbl *__restrict__ chi0) {
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(256) void k_fftconv(int n, int n_omega, int nhb, co
     const int nu0 = (blockIdx.x % nch) * 16;
     if (nu0 + 15 < mu) return;
     const int nua = max(nu0, mu), nue = min(nu0 + 16, n);
-    const int s = *s_dev;
+    const int s = s_dev ? *s_dev : 0;
     const double inv_l = 1.0 / (double)L;
     const int64_t nn = (int64_t)n * n;
     const int64_t trow = (int64_t)mu * n - ((int64_t)mu * (mu - 1)) / 2 - mu;
@@ -173,8 +178,8 @@ __global__ __launch_bounds__(256) void k_fftconv(int n, int n_omega, int nhb, co
         for (int q = threadIdx.x; q < L; q += 256) buf[q] = zdbl{0.0, 0.0};
         __syncthreads();
         for (int m = 1 + threadIdx.x; m < nhb; m += 256) {
-            const double ha = ldexp((double)H[(int64_t)m * n_upper + ta], -s);
-            const double hb = hasb ? ldexp((double)H[(int64_t)m * n_upper + tb], -s) : 0.0;
+            const double ha = hval(H, (int64_t)m * n_upper + ta, s);
+            const double hb = hasb ? hval(H, (int64_t)m * n_upper + tb, s) : 0.0;
             buf[m] = zdbl{ha, hb};
             buf[L - m] = zdbl{-ha, -hb};
         }
@@ -400,8 +405,8 @@ struct WPlan {
 // staged through LDS so that every 8 lanes write 128 contiguous bytes of a
 // chi0 row.  Each sequence: forward FFT of the odd extension (purely
 // imaginary spectrum i alpha), times i Kt, inverse FFT, scale 1/L.
-template <int L>
-__global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, const int64_t *__restrict__ H,
+template <typename HT, int L>
+__global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, const HT *__restrict__ H,
                                                    int64_t n_upper, const int32_t *__restrict__ s_dev,
                                                    const zdbl *__restrict__ Kt, const zdbl *__restrict__ tw,
                                                    zdbl *__restrict__ chi0) {
@@ -413,7 +418,7 @@ __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, 
     const int nu0 = (blockIdx.x % nch) * 8;
     if (nu0 + 7 < mu) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int s = *s_dev;
+    const int s = s_dev ? *s_dev : 0;
     const int64_t nn = (int64_t)n * n;
     const int64_t trow = (int64_t)mu * n - ((int64_t)mu * (mu - 1)) / 2 - mu;
     // histogram rows of the 8 sequences, scaled to doubles: Hs[m][w], m < nhb
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, 
         const int m = idx >> 3, ww = idx & 7;
         const int nu = nu0 + ww;
         double v = 0.0;
-        if (m >= 1 && nu >= mu && nu < n) v = ldexp((double)H[(int64_t)m * n_upper + trow + nu], -s);
+        if (m >= 1 && nu >= mu && nu < n) v = hval(H, (int64_t)m * n_upper + trow + nu, s);
         Hs[m * 9 + ww] = v;
     }
     __syncthreads();
@@ -519,8 +524,10 @@ hipError_t launch_symmetrize(hipStream_t st, int n, int n_omega, zdbl *chi0) {
     return hipGetLastError();
 }
 
-hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H, const int32_t *s_dev,
-                          const zdbl *Kt, const zdbl *tw, zdbl *chi0, bool symmetrize) {
+namespace {
+template <typename HT>
+hipError_t fftconv_impl(hipStream_t st, int n, int n_omega, int nhb, const HT *H, const int32_t *s_dev,
+                        const zdbl *Kt, const zdbl *tw, zdbl *chi0, bool symmetrize) {
     const int64_t n_upper = (int64_t)n * (n + 1) / 2;
     const int L = 2 * n_omega;
     if (L >= 256 && L <= 2048) {
@@ -530,7 +537,7 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
             dim3 gw((unsigned)((int64_t)n * ((n + 7) / 8)));
 #define GW_FFTW_CASE(LL)                                                                                     \
     case LL:                                                                                                 \
-        hipLaunchKernelGGL(k_fftconv_w<LL>, gw, dim3(512), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
+        hipLaunchKernelGGL((k_fftconv_w<HT, LL>), gw, dim3(512), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
                            chi0);                                                                            \
         break;
             switch (L) {
@@ -550,7 +557,7 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
     dim3 grid((unsigned)((int64_t)n * nch));
 #define GW_FFT_CASE(LL)                                                                                    \
     case LL:                                                                                               \
-        hipLaunchKernelGGL(k_fftconv<LL>, grid, dim3(256), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
+        hipLaunchKernelGGL((k_fftconv<HT, LL>), grid, dim3(256), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
                            chi0);                                                                          \
         break;
     switch (L) {
@@ -563,6 +570,17 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int
     }
 #undef GW_FFT_CASE
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const int64_t *H, const int32_t *s_dev,
+                          const zdbl *Kt, const zdbl *tw, zdbl *chi0, bool symmetrize) {
+    return fftconv_impl(st, n, n_omega, nhb, H, s_dev, Kt, tw, chi0, symmetrize);
+}
+
+hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const double *A, const zdbl *Kt,
+                          const zdbl *tw, zdbl *chi0, bool symmetrize) {
+    return fftconv_impl(st, n, n_omega, nhb, A, (const int32_t *)nullptr, Kt, tw, chi0, symmetrize);
 }
 
 namespace {

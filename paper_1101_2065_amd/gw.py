@@ -78,6 +78,8 @@ _SIGS = {
     "gw_build_chi0_2w": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid),
                                         ctypes.POINTER(gw_grid), _P, ctypes.c_int32, _P, _P, _P,
                                         ctypes.POINTER(gw_report)]),
+    "gw_build_chi0_time": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid), _P, _P, _P,
+                                          ctypes.POINTER(gw_report)]),
     "gw_solve_W": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
@@ -181,6 +183,14 @@ class Context:
                                   _ptr(basis), k, _stream_handle(stream), _ptr(chi_small_out), _ptr(chi_large_out),
                                   ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_build_chi0_2w")
+        return rep
+
+    def build_chi0_time(self, mol: "gw_molecule", grid: "gw_grid", chi0_out, a_out=None, stream=None,
+                        report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_build_chi0_time(self.h, ctypes.byref(mol), ctypes.byref(grid), _stream_handle(stream),
+                                    _ptr(a_out), _ptr(chi0_out), ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_build_chi0_time")
         return rep
 
     def solve_W(self, v, n: int, chi0, n_omega: int, W_out, prec: int = GW_FP64, tol: float = 1e-7,

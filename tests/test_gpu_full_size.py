@@ -153,3 +153,31 @@ def test_full_size_two_windows(setup):
     e = np.linalg.norm(Wc - mol.v @ (c0 @ Wc) - mol.v[:, cols]) / np.linalg.norm(mol.v[:, cols])
     _say("two windows: residual of W on the fine mesh", e)
     assert e < 1e-10
+
+
+def test_full_size_time_route(setup):
+    """The paper's own a0 route at the full size on the 1024-point mesh: a0
+    and chi0 at the sampled entries against the pair form of the oracle
+    (pinned equal to its convolution form)."""
+    gw, ctx, torch, mol, dm, P, s, (mu, nu) = setup
+    grid = gs.config_grid(1)
+    N, n = grid.n_omega, mol.n_prod
+    nhb = o.level_hist_bins(mol.eig, mol.n_occ, N, grid.domega)
+    a = torch.empty((nhb, n * (n + 1) // 2), dtype=torch.float64, device="cuda")
+    chi = torch.empty((N, n, n), dtype=torch.complex128, device="cuda")
+    rep = ctx.build_chi0_time(dm.struct, _g(gw, grid), chi, a_out=a)
+    torch.cuda.synchronize()
+    assert rep.n_hbins == nhb and rep.n_dropped_pairs == 0
+    ref = o.a0_by_pairs(P, mol.eig, mol.n_occ, grid.domega, nhb, entries=(mu, nu))
+    t = mu * n - mu * (mu - 1) // 2 + (nu - mu)
+    got = a[:, torch.as_tensor(t, device="cuda")].cpu().numpy()
+    e = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("time route a0: max rel over %d sampled entries" % len(mu), e)
+    assert e < 1e-12
+    del a
+    js = [0, 100, N // 2, N // 2 + 40, N // 2 + 300, N - 1]
+    cref = o.chi0_from_spectrum(ref, N, grid.omega_min, grid.omega_max, grid.eps, js=js)
+    cg = _entries(torch, chi[js], mu, nu)
+    e = np.abs(cg - cref).max() / np.abs(cref).max()
+    _say("time route chi0: max rel", e)
+    assert e < 1e-12
