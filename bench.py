@@ -18,6 +18,7 @@ Other workloads (one JSON line each, same keys):
   c2pair  the same cluster in the paper's own pair subspace (k = 256)
   n2000_2w  the 2000-product molecule with two spectral windows (256 fine
         points over |omega| < 0.5 Ha, 256 coarse ones over |omega| < 4 Ha)
+  n2000_time  the 2000-product molecule, a0 by the paper's time-domain route
   c3    64 chain molecules (8..80 atoms, 512 points) as recorded hipGraph
         batches, W written over chi0 in place
   c4    serving: Poisson arrivals at 20/s for 60 s (overloaded), then a
@@ -447,6 +448,64 @@ def run_two_window(args, gw, gs, torch):
     return out
 
 
+# ---------------------------------------------------------------------- the paper's a0 route
+def run_time_route(args, gw, gs, torch):
+    """The 2000-product molecule on the 1024-point mesh with a0 built by the
+    paper's own route (Section 8.A: densities to time, local product per
+    time, back).  One step = gw_build_chi0_time + W on all points (FP64).
+    The pair-route chi0 build is timed beside it for comparison."""
+    log("generating molecule")
+    mol = gs.truncate_products(gs.make_config(1), N_PROD)
+    grid = gs.config_grid(1)
+    n, N = mol.n_prod, grid.n_omega
+    dev = torch.device("cuda:0")
+    dm = gw.DeviceMolecule(mol, device=dev)
+    g = gw.make_grid(N, grid.omega_min, grid.omega_max, grid.eps)
+    ctx = gw.Context(0)
+    chi = torch.empty((N, n, n), dtype=torch.complex128, device=dev)
+    W = torch.empty_like(chi)
+    stream = torch.cuda.current_stream()
+    ts, roof = [], None
+    for it in range(args.warmup + args.steps):
+        timed = it >= args.warmup
+        if timed and roof is None:
+            ctx.profile_begin()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        ctx.build_chi0_time(dm.struct, g, chi, stream=stream, report=False)
+        ev[1].record(stream)
+        ctx.solve_W(dm.v, n, chi, N, W, stream=stream, report=False)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        parts = [ev[0].elapsed_time(ev[1]) / 1e3, ev[1].elapsed_time(ev[2]) / 1e3]
+        if timed and roof is None:
+            roof = kernel_roofline(ctx.profile_read())
+            ctx.profile_end()
+        # the pair-route build of the same chi0, outside the step, for comparison
+        ev[3].record(stream)
+        ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
+        e5 = torch.cuda.Event(enable_timing=True)
+        e5.record(stream)
+        torch.cuda.synchronize()
+        t_pair = ev[3].elapsed_time(e5) / 1e3
+        log("time-route step %d: chi0 (time route) %.3fs solve %.3fs wall %.3fs | chi0 (pair route) %.3fs" % (
+            it, parts[0], parts[1], wall, t_pair))
+        if timed:
+            ts.append((wall, parts[0], parts[1], t_pair))
+    a = np.median(np.array(ts), axis=0)
+    out = base_record(args, "W(omega)/s, 2000 products, 1024 points, a0 by the paper's time-domain route",
+                      N / a[0], "W(omega)/s", a[0], "f64",
+                      {"workload": "chain40_nprod2000_nomega1024_time_route", "n_prod": n, "n_omega": N,
+                       "n_orb": mol.n_orb, "parallelism": "none (1 GPU)"})
+    out["phases_s"] = {"chi0_time_route": a[1], "solve": a[2], "chi0_pair_route": a[3]}
+    out["roofline"] = roof
+    ctx.close()
+    return out
+
+
 # ---------------------------------------------------------------------- batched
 def run_c3(args, gw, gs, torch):
     grid = gs.config_grid(3)
@@ -707,7 +766,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n2000", choices=["n2000", "n2000_2w", "c1", "c2", "c2pair", "c3", "c4"])
+    ap.add_argument("--workload", default="n2000", choices=["n2000", "n2000_2w", "n2000_time", "c1", "c2", "c2pair", "c3",
+                                                                  "c4"])
     ap.add_argument("--forms", default=None, help="comma list of fp64, fp32_ir, bf16x_ir")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mols", type=int, default=64, help="c3: number of molecules")
@@ -728,7 +788,8 @@ def main():
               "documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.forms is None:
-        args.forms = {"n2000": "fp64,fp32_ir,bf16x_ir", "n2000_2w": "fp64", "c1": "fp64,bf16x_ir",
+        args.forms = {"n2000": "fp64,fp32_ir,bf16x_ir", "n2000_2w": "fp64", "n2000_time": "fp64",
+                      "c1": "fp64,bf16x_ir",
                       "c2": "fp64,bf16x_ir",
                       "c2pair": "fp64", "c3": "fp64", "c4": "fp64"}[args.workload]
 
@@ -744,6 +805,8 @@ def main():
         out = run_single(args, gw, gs, torch, mol, gs.config_grid(1), "chain40_nprod2000_nomega1024")
     elif args.workload == "n2000_2w":
         out = run_two_window(args, gw, gs, torch)
+    elif args.workload == "n2000_time":
+        out = run_time_route(args, gw, gs, torch)
     elif args.workload == "c1":
         log("generating molecule")
         mol = gs.make_config(1)
