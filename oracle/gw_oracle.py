@@ -20,6 +20,12 @@ What the method computes, in the paper's notation (energies in Hartree):
   mesh, and a0 as their convolution contracted with the vertex (Section 5.A
   eq. chi_by_spectra), which Section 8.A eq. sf-of-response-time evaluates
   time by time.
+* Downstream of W: the spectral function gamma of the dynamical part
+  W - v, the spectral functions sigma+- of the GW self-energy as convolutions
+  of rho+- with gamma contracted with the vertex (Section 5.A eq. spectral_3,
+  evaluated time by time in Section 8.B), the self-energy as their Cauchy
+  transform (eq. Cauchy1), and the instantaneous exchange part (Section 4
+  eq. instantaneous).
 * Compression, Section 7.B eqs. subspace_chi0 and chi_RPA; the paper's own
   subspace, Section 7.A eqs. subsetof_vef, projector0, subspace and
   global-basis-orthogonality.
@@ -75,6 +81,11 @@ __all__ = [
     "a0_by_convolution",
     "a0_by_pairs",
     "chi0_from_spectrum",
+    "w_spectral",
+    "self_energy_spectra",
+    "self_energy_spectra_by_levels",
+    "self_energy_from_spectra",
+    "exchange_self_energy",
 ]
 
 
@@ -593,3 +604,107 @@ def chi0_from_spectrum(a: np.ndarray, n_omega: int, omega_min: float, omega_max:
     w = om[:, None]
     K = 1.0 / (w - mvals[None, :] + 1j * eps) - 1.0 / (w + mvals[None, :] + 1j * eps)
     return K @ a[1:]
+
+
+# ----------------------------------------------------------------------------
+# the GW self-energy from W (Section 5.A eqs. spectral_3 and Cauchy1; Section
+# 8.B; Section 4 eq. instantaneous)
+
+
+def w_spectral(W: np.ndarray, n_omega: int, omega_min: float, omega_max: float) -> np.ndarray:
+    """Spectral weight of the dynamical interaction W - v on the mesh bins
+    s = k domega, k = 0 .. n_omega/2 - 1:
+        gamma[k] = -(domega / pi) Im W(omega = k domega),
+    (v is real, so Im(W - v) = Im W; the factor domega turns the density into
+    the weight of the bin, as for the histograms).  gamma(-s) = -gamma(s), so
+    gamma[0] = 0.  W: [n_omega][n][n] on the whole mesh.  Returns
+    [n_omega/2][n][n]."""
+    d = grid_spacing(n_omega, omega_min, omega_max)
+    j0 = int(round(-omega_min / d))
+    g = -(d / math.pi) * np.imag(W[j0:j0 + n_omega // 2])
+    g = np.array(g, dtype=np.float64)
+    g[0] = 0.0
+    return g
+
+
+def self_energy_spectra(mol, rho_p: np.ndarray, rho_m: np.ndarray, gamma: np.ndarray, n_sbins: int):
+    """sigma+^{ab}[m] = sum_{k1 + k2 = m} V_mu^{aa'} rho+_{a'b'}[k1] V_nu^{b'b} gamma^{mu nu}[k2]
+    and, at s = -m domega,
+    sigma-^{ab}[m] = sum_{k1 + k2 = m} V_mu^{aa'} rhobar-_{a'b'}[k1] V_nu^{b'b} gamma^{mu nu}[k2]:
+    eq. spectral_3 on the mesh (sigma-'s explicit minus sign meets
+    gamma(-s) = -gamma(s)).  m < n_sbins; weight beyond is dropped.
+    Returns (sigma_p, sigma_m), each [n_sbins][n_orb][n_orb]."""
+    V = _dense_vertex(mol)
+    no = mol.n_orb
+    out = []
+    for rho in (rho_p, rho_m):
+        sig = np.zeros((n_sbins, no, no))
+        G = {}
+        for k2 in range(gamma.shape[0]):
+            if np.any(gamma[k2]):
+                G[k2] = np.einsum("mn,ncd->mcd", gamma[k2], V)  # sum_nu gamma^{mu nu} V_nu
+        for k1 in range(rho.shape[0]):
+            if not np.any(rho[k1]):
+                continue
+            A = V @ rho[k1]  # (V_mu rho)[a][b']
+            for k2, Gk in G.items():
+                m = k1 + k2
+                if m >= n_sbins:
+                    continue
+                sig[m] += np.einsum("mab,mbc->ac", A, Gk)
+        out.append(sig)
+    return out[0], out[1]
+
+
+def self_energy_spectra_by_levels(mol, gamma: np.ndarray, domega: float, n_sbins: int):
+    """The same spectra from the levels: with u^E_{mu a} = sum_{a'} V_mu^{aa'} X_{a'}^E,
+    sigma+[m] = sum over empty F of sum_k w_F[m - k] (u^F)^T gamma[k] u^F and
+    sigma-[m] likewise over the occupied E at -E (w: the two-bin split of the
+    level).  An independent contraction order, for checking."""
+    V = _dense_vertex(mol)
+    U = np.einsum("mab,bE->Ema", V, mol.X)  # [state][mu][a]
+    kk, ph = level_bins(mol.eig, domega)
+    no = mol.n_orb
+    sp = np.zeros((n_sbins, no, no))
+    sm = np.zeros((n_sbins, no, no))
+    for E in range(mol.n_orb):
+        tgt = sp if E >= mol.n_occ else sm
+        for k in range(gamma.shape[0]):
+            if not np.any(gamma[k]):
+                continue
+            blk = U[E].T @ gamma[k] @ U[E]
+            for dm, w in ((0, 1.0 - ph[E]), (1, ph[E])):
+                m = kk[E] + k + dm
+                if m < n_sbins and w != 0.0:
+                    tgt[m] += w * blk
+    return sp, sm
+
+
+def self_energy_from_spectra(sp: np.ndarray, sm: np.ndarray, n_omega: int, omega_min: float, omega_max: float,
+                             eps: float, js: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Sigma(omega_j + i eps) = sum_m sigma+[m] / (omega_j - m domega + i eps)
+                              + sum_m sigma-[m] / (omega_j + m domega + i eps)
+    (eq. Cauchy1 on the mesh, the sigma+ weights at s = m domega and the
+    sigma- weights at s = -m domega).  Returns [len(js)][n][n]."""
+    d = grid_spacing(n_omega, omega_min, omega_max)
+    om = grid_omegas(n_omega, omega_min, omega_max)
+    if js is not None:
+        om = om[np.asarray(list(js), dtype=np.int64)]
+    mv = np.arange(sp.shape[0], dtype=np.float64) * d
+    w = om[:, None]
+    Kp = 1.0 / (w - mv[None, :] + 1j * eps)
+    Km = 1.0 / (w + mv[None, :] + 1j * eps)
+    n = sp.shape[1]
+    return (Kp @ sp.reshape(sp.shape[0], -1) + Km @ sm.reshape(sm.shape[0], -1)).reshape(len(om), n, n)
+
+
+def exchange_self_energy(mol) -> np.ndarray:
+    """Sigma_x^{ab} = -V_mu^{aa'} (sum over occupied E of X_{a'}^E X_{b'}^E) V_nu^{b'b} v^{mu nu}
+    (Section 4 eq. instantaneous; the minus sign of exchange, i G(0-) v with
+    G(0-) = i times the density matrix, is written out here)."""
+    V = _dense_vertex(mol)
+    Xo = mol.X[:, :mol.n_occ]
+    D = Xo @ Xo.T
+    A = V @ D  # (V_mu D)[a][b']
+    G = np.einsum("mn,ncd->mcd", mol.v, V)
+    return -np.einsum("mab,mbc->ac", A, G)

@@ -601,3 +601,119 @@ def test_chi0_from_spectrum_is_the_histogram_transform():
     b = o.chi0_from_spectrum(np.ldexp(H.astype(np.float64), -s), grid.n_omega, grid.omega_min, grid.omega_max,
                              grid.eps, js=js)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- the self-energy downstream of W
+
+
+def _w_on_mesh(mol, n_omega=64, wmax=4.0):
+    g = gs.Grid(n_omega, -wmax, wmax, 0.0)
+    g.eps = 1.5 * g.domega
+    d = g.domega
+    P = o.pair_vectors(mol)
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, o.hist_bins(mol.eig, n_omega, d))
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, n_omega, g.omega_min, g.omega_max, g.eps), mol.n_prod)
+    W = np.array([o.screened_W(mol.v, c) for c in chi])
+    return g, W
+
+
+def test_w_spectral_is_positive_and_odd():
+    """-Im W(omega > 0) is positive semidefinite (Im chi0 <= 0 and v >= 0 give
+    Im W <= 0), W(-omega) = W(omega)* makes it odd, and bin 0 is empty."""
+    mol = gs.make_config(0)
+    g, W = _w_on_mesh(mol)
+    gam = o.w_spectral(W, g.n_omega, g.omega_min, g.omega_max)
+    assert gam.shape == (g.n_omega // 2, mol.n_prod, mol.n_prod)
+    assert not gam[0].any()
+    scale = np.abs(gam).max()
+    for k in range(1, len(gam)):
+        assert np.linalg.eigvalsh(gam[k]).min() >= -1e-12 * scale
+    j0 = g.n_omega // 2
+    for k in (1, 5, 17):
+        assert np.array_equal(-(g.domega / math.pi) * np.imag(W[j0 - k]), -gam[k])
+
+
+@pytest.mark.parametrize("which", ["tiny", "chain3"])
+def test_self_energy_convolution_equals_levels(which):
+    """eq. spectral_3 on the mesh, summed as a convolution of the densities
+    with gamma, equals the sum over levels of (u^E)^T gamma u^E with
+    u^E = V X^E (an independent contraction order)."""
+    mol = gs.make_config(0) if which == "tiny" else gs.chain_molecule(3, 5)
+    g, W = _w_on_mesh(mol)
+    gam = o.w_spectral(W, g.n_omega, g.omega_min, g.omega_max)
+    rho_p, rho_m = o.spectral_densities(mol, g.domega)
+    sp, sm = o.self_energy_spectra(mol, rho_p, rho_m, gam, g.n_omega // 2)
+    lp, lm = o.self_energy_spectra_by_levels(mol, gam, g.domega, g.n_omega // 2)
+    assert np.abs(sp - lp).max() <= 1e-13 * np.abs(lp).max()
+    assert np.abs(sm - lm).max() <= 1e-13 * np.abs(lm).max()
+
+
+def test_self_energy_zeroth_moment_factorises():
+    """The sum over bins of a convolution is the product of the sums: with no
+    weight dropped, sum_m sigma+[m] = V_mu D+ V_nu Gamma^{mu nu}, D+ the
+    projector on the empty states and Gamma = sum_k gamma[k] (and likewise
+    for sigma- with the occupied projector)."""
+    mol = gs.make_config(0)
+    g, W = _w_on_mesh(mol, n_omega=256)
+    gam = o.w_spectral(W, g.n_omega, g.omega_min, g.omega_max)
+    gam[g.n_omega // 4:] = 0.0  # keep every convolution inside the bins
+    rho_p, rho_m = o.spectral_densities(mol, g.domega)
+    sp, sm = o.self_energy_spectra(mol, rho_p, rho_m, gam, g.n_omega // 2)
+    V = np.zeros((mol.n_prod, mol.n_orb, mol.n_orb))
+    for b in range(mol.n_blk):
+        p0, _, orbs, mats = mol.block_of(b)
+        for i, M in enumerate(mats):
+            V[p0 + i][np.ix_(orbs, orbs)] = M
+    Gam = gam.sum(0)
+    for sig, X in ((sp, mol.X[:, mol.n_occ:]), (sm, mol.X[:, :mol.n_occ])):
+        D = X @ X.T
+        ref = sum(Gam[i, j] * V[i] @ D @ V[j] for i in range(mol.n_prod) for j in range(mol.n_prod))
+        assert np.abs(sig.sum(0) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_self_energy_cauchy_single_pole_and_sign():
+    """eq. Cauchy1 on the mesh: one unit weight of sigma+ at m0 gives
+    1/(omega - m0 domega + i eps), one of sigma- at m0 gives
+    1/(omega + m0 domega + i eps); from W of a molecule, Sigma is complex
+    symmetric with Im Sigma negative semidefinite at every mesh point."""
+    n_omega, wmax, eps = 64, 4.0, 0.1
+    d = 2 * wmax / n_omega
+    om = -wmax + d * np.arange(n_omega)
+    sp = np.zeros((32, 2, 2))
+    sm = np.zeros((32, 2, 2))
+    sp[5, 0, 1] = sp[5, 1, 0] = 1.0
+    sm[9, 1, 1] = 1.0
+    S = o.self_energy_from_spectra(sp, sm, n_omega, -wmax, wmax, eps)
+    assert np.abs(S[:, 0, 1] - 1.0 / (om - 5 * d + 1j * eps)).max() < 1e-15
+    assert np.abs(S[:, 1, 1] - 1.0 / (om + 9 * d + 1j * eps)).max() < 1e-15
+    assert not S[:, 0, 0].any()
+    mol = gs.make_config(0)
+    g, W = _w_on_mesh(mol)
+    gam = o.w_spectral(W, g.n_omega, g.omega_min, g.omega_max)
+    rho_p, rho_m = o.spectral_densities(mol, g.domega)
+    sp, sm = o.self_energy_spectra(mol, rho_p, rho_m, gam, g.n_omega // 2)
+    S = o.self_energy_from_spectra(sp, sm, g.n_omega, g.omega_min, g.omega_max, g.eps)
+    assert np.abs(S - np.transpose(S, (0, 2, 1))).max() <= 1e-13 * np.abs(S).max()
+    for x in S:
+        assert np.linalg.eigvalsh(x.imag).max() <= 1e-13 * np.abs(S).max()
+
+
+def test_exchange_self_energy_by_levels():
+    """Section 4 eq. instantaneous: -sum over occupied E of (u^E)^T v u^E,
+    u^E = V X^E; symmetric and negative semidefinite (v >= 0)."""
+    mol = gs.chain_molecule(3, 5)
+    Sx = o.exchange_self_energy(mol)
+    V = np.zeros((mol.n_prod, mol.n_orb, mol.n_orb))
+    for b in range(mol.n_blk):
+        p0, _, orbs, mats = mol.block_of(b)
+        for i, M in enumerate(mats):
+            V[p0 + i][np.ix_(orbs, orbs)] = M
+    ref = np.zeros_like(Sx)
+    for E in range(mol.n_occ):
+        u = V @ mol.X[:, E]  # [mu][a]
+        ref -= u.T @ mol.v @ u
+    assert np.abs(Sx - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(Sx - Sx.T).max() <= 1e-12 * np.abs(Sx).max()
+    assert np.linalg.eigvalsh(Sx).max() <= 1e-10 * np.abs(Sx).max()
