@@ -185,7 +185,7 @@ gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_s
  * densities rho+_ab (empty states, poles at E >= 0) and rhobar-_ab(s) =
  * rho-_ab(-s) (occupied states, poles at -E > 0) on the mesh, each pole split
  * linearly between two bins; their discrete Fourier transforms to L time
- * points (L the smallest power of two holding the linear convolution); the
+ * points (L = K+ + K- - 1, the length of the linear convolution); the
  * local product a_mu_nu(t) = 2 V_mu^ab rho+_bc(t) V_nu^cd rhobar-_da(t) time
  * by time over the vertex blocks (O(N^2) per time); the transform back to the
  * mesh; chi0 by the same FFT Cauchy transform as gw_build_chi0.  The result
@@ -209,6 +209,39 @@ gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_s
  * GW_E_OOM, GW_E_DEVICE. */
 gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream,
                              double *a_out, void *chi0_out, gw_report *rep);
+
+/* The GW self-energy downstream of W (Section 5.A eqs. spectral_3 and
+ * Cauchy1, time by time as in Section 8.B; exchange by Section 4 eq.
+ * instantaneous), on the mesh of g:
+ *   gamma[k] = -(domega/pi) Im W(k domega), k = 1 .. n_omega/2 - 1 (the
+ *     spectral weight of W - v per bin; gamma[0] = 0 since gamma is odd);
+ *   sigma+^{ab}[m] = sum_{k1+k2=m} V_mu^{aa'} rho+_{a'b'}[k1] V_nu^{b'b} gamma^{mu nu}[k2],
+ *   sigma-^{ab}[m] the same with rhobar- (weights at s = -m domega),
+ *     m < n_omega/2 (weight beyond is dropped), rho+- as for
+ *     gw_build_chi0_time;
+ *   Sigma(omega_j + i eps) = sum_m sigma+[m] / (omega_j - m domega + i eps)
+ *                          + sigma-[m] / (omega_j + m domega + i eps);
+ *   Sigma_x^{ab} = -V_mu^{aa'} (sum_{E occ} X_a'^E X_b'^E) V_nu^{b'b} v^{mu nu}.
+ * The convolutions go through L = max(K+, K-) + n_omega/2 - 1 time points
+ * (L/2 + 1 formed), the products over pairs of vertex blocks.
+ *   m: as for gw_build_chi0_time (energies from the Fermi level, orbital
+ *      sets of at most 32 orbitals).
+ *   v: DEVICE [n_prod][n_prod] (only read for Sigma_x_out; may be NULL
+ *      without it).
+ *   g: the mesh W was computed on (n_omega even).
+ *   W: DEVICE complex128 [n_omega][n_prod][n_prod] (gw_solve_W's output).
+ *   sigma_out: DEVICE double [2][n_omega/2][n_orb][n_orb] or NULL: sigma+
+ *      then sigma-.
+ *   Sigma_out: DEVICE complex128 [n_omega][n_orb][n_orb]: the correlation
+ *      part Sigma(omega_j + i eps) (complex symmetric).
+ *   Sigma_x_out: DEVICE double [n_orb][n_orb] or NULL.
+ *   rep: HOST or NULL: n_hbins = n_omega/2.
+ * The accumulation over block pairs uses floating-point atomics, so the last
+ * bits may differ between runs.  Synchronises the stream once (level
+ * tables).  Errors: GW_E_INVALID, GW_E_OOM, GW_E_DEVICE. */
+gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
+                         const void *W, void *stream, double *sigma_out, void *Sigma_out,
+                         double *Sigma_x_out, gw_report *rep);
 
 /* Step 4: W(omega_j) = (1 - v chi0(omega_j))^{-1} v for every mesh point
  * (Section 2 eq. Coulombscreening).  Only j = 0 and j >= n_omega/2 are

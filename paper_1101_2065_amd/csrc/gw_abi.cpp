@@ -682,6 +682,69 @@ gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_s
     return GW_OK;
 }
 
+namespace {
+
+// One-particle poles on the mesh, listed bin by bin: the empty states by rising
+// energy (bins of E), then the occupied ones by rising -E (bins of -E); each
+// level's weight is split between its bin k and k + 1.  Kp, Km: bins of the two
+// densities, at most kcap (levels whose weight lies wholly beyond are left out).
+struct LevelTables {
+    std::vector<int32_t> lev, kb, start;  // start: [Kp + 1] then [Km + 1]
+    std::vector<double> ph;
+    int nv = 0, Kp = 0, Km = 0;
+};
+
+gw_status level_tables(gw_ctx *ctx, const HostMol &h, int n_orb, int n_occ, int kbits, int kcap, LevelTables *t) {
+    if (!(h.eig[n_occ - 1] < 0.0 && h.eig[n_occ] >= 0.0))
+        return fail(ctx, GW_E_INVALID, "energies must be measured from the Fermi level: eig[n_occ-1] < 0 <= eig[n_occ]");
+    const int nv = n_orb - n_occ;
+    t->lev.resize(n_orb);
+    t->kb.resize(n_orb);
+    t->ph.resize(n_orb);
+    for (int i = 0; i < n_orb; ++i) {
+        const int st_i = i < nv ? n_occ + i : n_occ - 1 - (i - nv);
+        const double x = std::ldexp(std::fabs(h.eig[st_i]), kbits);
+        const double k = std::floor(x);
+        if (!(k < 1e8)) return fail(ctx, GW_E_INVALID, "a level lies too far from the Fermi level for this mesh");
+        t->lev[i] = st_i;
+        t->kb[i] = (int32_t)k;
+        t->ph[i] = x - k;
+    }
+    t->nv = nv;
+    t->Kp = std::min(kcap, t->kb[nv - 1] + 2);
+    t->Km = std::min(kcap, t->kb[n_orb - 1] + 2);
+    t->start.assign(t->Kp + 1 + t->Km + 1, 0);
+    for (int k = 0, i = 0; k <= t->Kp; ++k) {
+        while (i < nv && t->kb[i] < k) ++i;
+        t->start[k] = i;
+    }
+    for (int k = 0, i = 0; k <= t->Km; ++k) {
+        while (i < n_occ && t->kb[nv + i] < k) ++i;
+        t->start[t->Kp + 1 + k] = i;
+    }
+    return GW_OK;
+}
+
+// Vertex block pairs B1 <= B2 (pb1 then pb2 in one array) and the largest
+// (products x |O|^2) of a block.
+int block_pairs(const HostMol &h, int nblk, std::vector<int32_t> *pbs, int *max_vblock) {
+    pbs->clear();
+    for (int b1 = 0; b1 < nblk; ++b1)
+        for (int b2 = b1; b2 < nblk; ++b2) pbs->push_back(b1);
+    const int npb = (int)pbs->size();
+    pbs->resize(2 * (size_t)npb);
+    for (int b1 = 0, i = 0; b1 < nblk; ++b1)
+        for (int b2 = b1; b2 < nblk; ++b2, ++i) (*pbs)[npb + i] = b2;
+    *max_vblock = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const int no = h.blk_orb[b + 1] - h.blk_orb[b];
+        *max_vblock = std::max(*max_vblock, (h.blk_prod[b + 1] - h.blk_prod[b]) * no * no);
+    }
+    return npb;
+}
+
+}  // namespace
+
 gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream, double *a_out,
                              void *chi0_out, gw_report *rep) {
     if (!ctx) return GW_E_INVALID;
@@ -696,38 +759,19 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
     s = check_molecule(ctx, m, st, &h);
     if (s != GW_OK) return s;
     const int n_orb = m->n_orb, n_occ = m->n_occ, n = m->n_prod, nblk = m->n_blk;
-    if (!(h.eig[n_occ - 1] < 0.0 && h.eig[n_occ] >= 0.0))
-        return fail(ctx, GW_E_INVALID, "energies must be measured from the Fermi level: eig[n_occ-1] < 0 <= eig[n_occ]");
     if (h.max_o > TIME_MAX_ORB)
         return fail(ctx, GW_E_INVALID, "the time-domain route takes orbital sets of at most " +
                                            std::to_string(TIME_MAX_ORB) + " orbitals");
-    // one-particle poles on the mesh, listed bin by bin: empty states by
-    // rising energy, occupied ones by rising -E
-    std::vector<int32_t> lev(n_orb), kb(n_orb);
-    std::vector<double> ph(n_orb);
-    for (int i = 0; i < n_orb; ++i) {
-        const int st_i = i < n_orb - n_occ ? n_occ + i : n_occ - 1 - (i - (n_orb - n_occ));
-        const double x = std::ldexp(std::fabs(h.eig[st_i]), kbits);
-        const double k = std::floor(x);
-        if (!(k < 1e8)) return fail(ctx, GW_E_INVALID, "a level lies too far from the Fermi level for this mesh");
-        lev[i] = st_i;
-        kb[i] = (int32_t)k;
-        ph[i] = x - k;
-    }
-    const int nv = n_orb - n_occ;
-    const int Kp = kb[nv - 1] + 2, Km = kb[n_orb - 1] + 2;
-    std::vector<int32_t> start(Kp + 1 + Km + 1, 0);
-    for (int k = 0, i = 0; k <= Kp; ++k) {
-        while (i < nv && kb[i] < k) ++i;
-        start[k] = i;
-    }
-    for (int k = 0, i = 0; k <= Km; ++k) {
-        while (i < n_occ && kb[nv + i] < k) ++i;
-        start[Kp + 1 + k] = i;
-    }
+    LevelTables lt;
+    s = level_tables(ctx, h, n_orb, n_occ, kbits, 1 << 30, &lt);
+    if (s != GW_OK) return s;
+    const std::vector<int32_t> &lev = lt.lev, &kb = lt.kb, &start = lt.start;
+    const std::vector<double> &ph = lt.ph;
+    const int nv = lt.nv, Kp = lt.Kp, Km = lt.Km;
     const int nhb = std::min(g->n_omega / 2, Kp + Km - 1);
-    int L = 2;
-    while (L < Kp + Km - 1) L *= 2;
+    // L = the length of the linear convolution: the cyclic one of that length
+    // has no wrap-around (the transforms are explicit, any L will do)
+    const int L = std::max(2, Kp + Km - 1);
     if (L > (1 << 16)) return fail(ctx, GW_E_INVALID, "the levels span too many mesh points for the time route");
     const int Q = L / 2 + 1;
     // pairs whose convolved weight reaches a bin beyond the mesh
@@ -740,13 +784,10 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
     // block pairs B1 <= B2 and the contraction's flop count
     std::vector<int32_t> pbs;
     double cflops = 0.0;
+    int max_vblock = 0;
+    const int npb = block_pairs(h, nblk, &pbs, &max_vblock);
     for (int b1 = 0; b1 < nblk; ++b1)
-        for (int b2 = b1; b2 < nblk; ++b2) pbs.push_back(b1);
-    const int npb = (int)pbs.size();
-    pbs.resize(2 * (size_t)npb);
-    for (int b1 = 0, i = 0; b1 < nblk; ++b1)
-        for (int b2 = b1; b2 < nblk; ++b2, ++i) {
-            pbs[npb + i] = b2;
+        for (int b2 = b1; b2 < nblk; ++b2) {
             const double n1 = h.blk_orb[b1 + 1] - h.blk_orb[b1], n2 = h.blk_orb[b2 + 1] - h.blk_orb[b2];
             const double pm = h.blk_prod[b1 + 1] - h.blk_prod[b1], pn = h.blk_prod[b2 + 1] - h.blk_prod[b2];
             const double pmn = b1 == b2 ? pm * (pm + 1) / 2 : pm * pn;
@@ -796,7 +837,8 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
     for (int q0 = 0; q0 < Q; q0 += qc) {
         const int nq = std::min(qc, Q - q0);
         GW_HIP(ctx, gwk::launch_time_contract(st, n_orb, n, npb, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
-                                              m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Ahat, cflops * nq));
+                                              m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Ahat, max_vblock,
+                                              cflops * nq));
         GW_HIP(ctx, gwk::launch_dgemm(st, nhb, (int)n_upper, 2 * nq, 1.0, G + 2 * q0, 2 * Q, 0, Ahat, n_upper, 0,
                                       q0 == 0 ? 0.0 : 1.0, a, n_upper, 0, 1));
     }
@@ -809,6 +851,136 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
         rep->n_hbins = nhb;
         rep->frac_bits_used = 0;
         rep->n_dropped_pairs = dropped;
+    }
+    return GW_OK;
+}
+
+gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, const void *W,
+                         void *stream, double *sigma_out, void *Sigma_out, double *Sigma_x_out, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    if (!W || !Sigma_out) return fail(ctx, GW_E_INVALID, "W and Sigma_out must be set");
+    if (Sigma_x_out && !v) return fail(ctx, GW_E_INVALID, "the exchange part needs v");
+    int kbits = 0;
+    gw_status s = check_grid(ctx, g, &kbits);
+    if (s != GW_OK) return s;
+    HostMol h;
+    s = check_molecule(ctx, m, st, &h);
+    if (s != GW_OK) return s;
+    const int n_orb = m->n_orb, n_occ = m->n_occ, n = m->n_prod, nblk = m->n_blk;
+    if (h.max_o > TIME_MAX_ORB)
+        return fail(ctx, GW_E_INVALID, "the self-energy takes orbital sets of at most " +
+                                           std::to_string(TIME_MAX_ORB) + " orbitals");
+    const int N = g->n_omega, n_sb = N / 2;
+    const double d = (g->omega_max - g->omega_min) / N;
+    LevelTables lt;
+    s = level_tables(ctx, h, n_orb, n_occ, kbits, n_sb, &lt);
+    if (s != GW_OK) return s;
+    const int nv = lt.nv, Kp = lt.Kp, Km = lt.Km;
+    // the convolutions of rho+- (Kp, Km bins) with gamma (n_sb bins): the
+    // cyclic transform of length L has no wrap-around
+    const int L = std::max(Kp, Km) + n_sb - 1;
+    const int Q = L / 2 + 1;
+    std::vector<int32_t> pbs;
+    int max_vblock = 0;
+    const int npb = block_pairs(h, nblk, &pbs, &max_vblock);
+    double cflops = 0.0;
+    for (int b1 = 0; b1 < nblk; ++b1)
+        for (int b2 = b1; b2 < nblk; ++b2) {
+            const double n1 = h.blk_orb[b1 + 1] - h.blk_orb[b1], n2 = h.blk_orb[b2 + 1] - h.blk_orb[b2];
+            const double pm = h.blk_prod[b1 + 1] - h.blk_prod[b1], pn = h.blk_prod[b2 + 1] - h.blk_prod[b2];
+            cflops += pm * (4.0 * pn * n2 * n2 + 16.0 * n1 * n2 * n2 + 8.0 * n1 * n1 * n2);
+        }
+    const int64_t nn = (int64_t)n_orb * n_orb;
+    const int64_t n_upper = (int64_t)n * (n + 1) / 2;
+    // time points per chunk: transformed gamma and the two products within 4 GiB
+    const int qc = (int)std::max<int64_t>(1, std::min<int64_t>(Q, (int64_t)(4ll << 30) / (16 * n_upper + 32 * nn)));
+    void *q;
+    int32_t *d_lev, *d_start, *d_pb;
+    double *d_ph, *rho, *F, *Gi, *Rp, *Rm, *gam, *Gh, *S, *sig = sigma_out, *Xt = nullptr;
+    zdbl *Kpm;
+    const int kf = std::max(std::max(Kp, Km), n_sb);
+#define GW_WS(name, bytes, dst)                                   \
+    do {                                                          \
+        if ((s = ws(ctx, name, (bytes), &q)) != GW_OK) return s;  \
+        dst = (decltype(dst))q;                                   \
+    } while (0)
+    GW_WS("s_lev", sizeof(int32_t) * n_orb, d_lev);
+    GW_WS("s_ph", sizeof(double) * n_orb, d_ph);
+    GW_WS("s_start", sizeof(int32_t) * lt.start.size(), d_start);
+    GW_WS("s_pairs", sizeof(int32_t) * pbs.size(), d_pb);
+    GW_WS("s_rho", sizeof(double) * std::max(std::max(Kp, Km), 1) * nn, rho);
+    GW_WS("s_F", sizeof(double) * 2 * Q * kf, F);
+    GW_WS("s_Ginv", sizeof(double) * n_sb * 2 * Q, Gi);
+    GW_WS("s_Rp", sizeof(double) * 2 * Q * nn, Rp);
+    GW_WS("s_Rm", sizeof(double) * 2 * Q * nn, Rm);
+    GW_WS("s_gam", sizeof(double) * n_sb * n_upper, gam);
+    GW_WS("s_Gh", sizeof(double) * 2 * (int64_t)qc * n_upper, Gh);
+    GW_WS("s_S", sizeof(double) * 4 * (int64_t)qc * nn, S);
+    if (!sig) GW_WS("s_sigma", sizeof(double) * 2 * n_sb * nn, sig);
+    GW_WS("s_Kpm", sizeof(zdbl) * 2 * (int64_t)N * n_sb, Kpm);
+    if (Sigma_x_out) GW_WS("s_Xt", sizeof(double) * nn, Xt);
+#undef GW_WS
+    GW_HIP(ctx, hipMemcpyAsync(d_lev, lt.lev.data(), sizeof(int32_t) * n_orb, hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipMemcpyAsync(d_ph, lt.ph.data(), sizeof(double) * n_orb, hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipMemcpyAsync(d_start, lt.start.data(), sizeof(int32_t) * lt.start.size(), hipMemcpyHostToDevice,
+                               st));
+    GW_HIP(ctx, hipMemcpyAsync(d_pb, pbs.data(), sizeof(int32_t) * pbs.size(), hipMemcpyHostToDevice, st));
+    GW_HIP(ctx, hipStreamSynchronize(st));  // the host tables above are released on return
+    double *Sp = S, *Sm = S + 2 * (int64_t)qc * nn;
+    double *sig_p = sig, *sig_m = sig + (int64_t)n_sb * nn;
+    // the densities and gamma in time
+    GW_HIP(ctx, gwk::launch_rho_bins(st, n_orb, Kp, m->X, d_lev, d_ph, d_start, rho));
+    GW_HIP(ctx, gwk::launch_dft_matrices(st, L, Q, Kp, F, 0, nullptr));
+    GW_HIP(ctx, gwk::launch_dgemm(st, 2 * Q, (int)nn, Kp, 1.0, F, Kp, 0, rho, nn, 0, 0.0, Rp, nn, 0, 1));
+    GW_HIP(ctx, gwk::launch_rho_bins(st, n_orb, Km, m->X, d_lev + nv, d_ph + nv, d_start + Kp + 1, rho));
+    GW_HIP(ctx, gwk::launch_dft_matrices(st, L, Q, Km, F, n_sb, Gi));
+    GW_HIP(ctx, gwk::launch_dgemm(st, 2 * Q, (int)nn, Km, 1.0, F, Km, 0, rho, nn, 0, 0.0, Rm, nn, 0, 1));
+    GW_HIP(ctx, gwk::launch_w_spectral(st, n, n_sb, (int)std::lround(-g->omega_min / d), d, (const zdbl *)W, gam));
+    GW_HIP(ctx, gwk::launch_dft_matrices(st, L, Q, n_sb, F, 0, nullptr));
+    for (int q0 = 0; q0 < Q; q0 += qc) {
+        const int nq = std::min(qc, Q - q0);
+        GW_HIP(ctx, gwk::launch_dgemm(st, 2 * nq, (int)n_upper, n_sb, 1.0, F + (int64_t)2 * q0 * n_sb, n_sb, 0, gam,
+                                      n_upper, 0, 0.0, Gh, n_upper, 0, 1));
+        GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)S, 4 * (int64_t)nq * nn, 0));
+        Sm = S + 2 * (int64_t)nq * nn;
+        GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, npb, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
+                                               m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Gh, Sp, Sm,
+                                               cflops * nq));
+        const double beta = q0 == 0 ? 0.0 : 1.0;
+        GW_HIP(ctx, gwk::launch_dgemm(st, n_sb, (int)nn, 2 * nq, 1.0, Gi + 2 * q0, 2 * Q, 0, Sp, nn, 0, beta, sig_p,
+                                      nn, 0, 1));
+        GW_HIP(ctx, gwk::launch_dgemm(st, n_sb, (int)nn, 2 * nq, 1.0, Gi + 2 * q0, 2 * Q, 0, Sm, nn, 0, beta, sig_m,
+                                      nn, 0, 1));
+    }
+    // Sigma(omega_j + i eps) = Kp sigma+ + Km sigma-
+    zdbl *Kp_ = Kpm, *Km_ = Kpm + (int64_t)N * n_sb;
+    GW_HIP(ctx, gwk::launch_cauchy_pm(st, N, n_sb, g->omega_min, d, g->eps, Kp_, Km_));
+    GW_HIP(ctx, gwk::launch_zdgemm(st, N, (int)nn, n_sb, 1.0, Kp_, n_sb, 0, sig_p, nn, 0, 0.0, (zdbl *)Sigma_out, nn,
+                                   0, 1));
+    GW_HIP(ctx, gwk::launch_zdgemm(st, N, (int)nn, n_sb, 1.0, Km_, n_sb, 0, sig_m, nn, 0, 1.0, (zdbl *)Sigma_out, nn,
+                                   0, 1));
+    if (Sigma_x_out) {
+        // exchange: the same contraction once, with the occupied density
+        // matrix D = X_occ X_occ^T for rho and v for gamma (both real)
+        GW_HIP(ctx, gwk::launch_transpose_d(st, n_orb, n_orb, m->X, Xt));
+        GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)Rp, 2 * nn, 0));
+        GW_HIP(ctx, gwk::launch_dgemm(st, n_orb, n_orb, n_occ, 1.0, m->X, n_orb, 0, Xt, n_orb, 0, 0.0, Rp, n_orb, 0,
+                                      1));
+        GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)Gh, 2 * n_upper, 0));
+        GW_HIP(ctx, gwk::launch_pack_upper(st, n, v, Gh));
+        GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)S, 2 * nn, 0));
+        GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, npb, 0, 1, m->blk_prod, m->blk_orb, m->orb_idx,
+                                               m->blk_val, m->vals, d_pb, d_pb + npb, Rp, nullptr, Gh, S, nullptr,
+                                               cflops / 4));
+        GW_HIP(ctx, gwk::launch_scale_copy(st, nn, -1.0, S, Sigma_x_out));
+    }
+    if (rep) {
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_hbins = n_sb;
     }
     return GW_OK;
 }

@@ -156,10 +156,29 @@ hipError_t launch_rho_bins(hipStream_t st, int n_orb, int K, const double *X, co
 // rows for a real sequence (G may be null), length L, Q = L/2 + 1.
 hipError_t launch_dft_matrices(hipStream_t st, int L, int Q, int K, double *F, int M, double *G);
 // Ahat[2 qq (+1)][t] for time points q0 .. q0 + nq - 1 over the listed block
-// pairs (pb1[i] <= pb2[i]); Rp, Rm: [2Q][n_orb^2] transformed densities.
+// pairs (pb1[i] <= pb2[i]); Rp, Rm: [2Q][n_orb^2] transformed densities;
+// max_vblock: the largest (products x |O|^2) of a block (LDS staging).
 hipError_t launch_time_contract(hipStream_t st, int n_orb, int n_prod, int n_pairs_blk, int q0, int nq,
                                 const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
                                 const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
-                                const double *Rp, const double *Rm, double *Ahat, double flops);
+                                const double *Rp, const double *Rm, double *Ahat, int max_vblock, double flops);
+
+// ---------------------------------------------------------------- self-energy from W
+// gam[k][t] = -(domega/pi) Im W[j0 + k][mu][nu], packed upper t, k < n_sb; gam[0] = 0.
+hipError_t launch_w_spectral(hipStream_t st, int n, int n_sb, int j0, double domega, const zdbl *W, double *gam);
+// dst[t] = src[mu][nu], packed upper t.
+hipError_t launch_pack_upper(hipStream_t st, int n, const double *src, double *dst);
+// Kp[j][m] = 1/(w_j - m d + i eps), Km[j][m] = 1/(w_j + m d + i eps), w_j = w0 + j d.
+hipError_t launch_cauchy_pm(hipStream_t st, int n_om, int M, double w0, double d, double eps, zdbl *Kp, zdbl *Km);
+hipError_t launch_scale_copy(hipStream_t st, int64_t n, double alpha, const double *src, double *dst);
+// S+-[2 qq (+1)][a][b] += sum over the listed block pairs of
+// sum_{mu nu} gammahat^{mu nu} (V_mu rho+-(t) V_nu)^{ab} (and the transpose for
+// B1 < B2), time points q0 .. q0 + nq - 1.  Rm == nullptr: one density only.
+// S+- must be cleared by the caller.
+hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, int n_pairs_blk, int q0, int nq,
+                                 const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
+                                 const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
+                                 const double *Rp, const double *Rm, const double *Gh, double *Sp, double *Sm,
+                                 double flops);
 
 }  // namespace gwk

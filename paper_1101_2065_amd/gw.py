@@ -80,6 +80,8 @@ _SIGS = {
                                         ctypes.POINTER(gw_report)]),
     "gw_build_chi0_time": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid), _P, _P, _P,
                                           ctypes.POINTER(gw_report)]),
+    "gw_self_energy": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P, _P, _P,
+                                      _P, ctypes.POINTER(gw_report)]),
     "gw_solve_W": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
@@ -191,6 +193,15 @@ class Context:
         st = lib.gw_build_chi0_time(self.h, ctypes.byref(mol), ctypes.byref(grid), _stream_handle(stream),
                                     _ptr(a_out), _ptr(chi0_out), ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_build_chi0_time")
+        return rep
+
+    def self_energy(self, mol: "gw_molecule", grid: "gw_grid", W, Sigma_out, v=None, sigma_out=None,
+                    Sigma_x_out=None, stream=None, report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_self_energy(self.h, ctypes.byref(mol), _ptr(v), ctypes.byref(grid), _ptr(W),
+                                _stream_handle(stream), _ptr(sigma_out), _ptr(Sigma_out), _ptr(Sigma_x_out),
+                                ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_self_energy")
         return rep
 
     def solve_W(self, v, n: int, chi0, n_omega: int, W_out, prec: int = GW_FP64, tol: float = 1e-7,

@@ -1,0 +1,154 @@
+"""The GW self-energy downstream of W on the GPU (Section 5.A eqs. spectral_3
+and Cauchy1, time by time as in Section 8.B; Section 4 eq. instantaneous)
+against the oracle, end to end: chi0 and W from the library, then sigma+-,
+Sigma on the mesh and the exchange part, compared with the oracle's chain
+(its own chi0, W by LAPACK, the convolution of eq. spectral_3 summed
+directly).
+
+Bar: 1e-11 relative Frobenius for sigma+- and Sigma (W agrees to ~1e-13
+and the spectral weights are differences of it), 1e-12 for the exchange
+part; Sigma complex symmetric and Im Sigma negative semidefinite."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import gw_synth as gs
+import oracle as o
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_2065_amd.gw as gw
+
+    ctx = gw.Context(0)
+    yield gw, ctx, torch
+    ctx.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _mesh(n, wmax):
+    g = gs.Grid(n, -wmax, wmax, 0.0)
+    g.eps = 1.5 * g.domega
+    return g
+
+
+def _g(gw, g):
+    return gw.make_grid(g.n_omega, g.omega_min, g.omega_max, g.eps, g.frac_bits)
+
+
+def _oracle(mol, g, levels=False):
+    d = g.domega
+    P = o.pair_vectors(mol)
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, o.hist_bins(mol.eig, g.n_omega, d))
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, g.n_omega, g.omega_min, g.omega_max, g.eps), mol.n_prod)
+    W = np.array([o.screened_W(mol.v, c) for c in chi])
+    gam = o.w_spectral(W, g.n_omega, g.omega_min, g.omega_max)
+    if levels:  # pinned equal to the convolution form on the CPU
+        sp, sm = o.self_energy_spectra_by_levels(mol, gam, d, g.n_omega // 2)
+    else:
+        rho_p, rho_m = o.spectral_densities(mol, d)
+        sp, sm = o.self_energy_spectra(mol, rho_p, rho_m, gam, g.n_omega // 2)
+    S = o.self_energy_from_spectra(sp, sm, g.n_omega, g.omega_min, g.omega_max, g.eps)
+    return sp, sm, S, o.exchange_self_energy(mol)
+
+
+def _gpu(gw, ctx, torch, mol, g):
+    dm = gw.DeviceMolecule(mol)
+    n, no, N = mol.n_prod, mol.n_orb, g.n_omega
+    chi = torch.empty((N, n, n), dtype=torch.complex128, device="cuda")
+    W = torch.empty_like(chi)
+    ctx.build_chi0(dm.struct, _g(gw, g), chi)
+    ctx.solve_W(dm.v, n, chi, N, W)
+    sig = torch.full((2, N // 2, no, no), float("nan"), dtype=torch.float64, device="cuda")
+    S = torch.full((N, no, no), float("nan"), dtype=torch.complex128, device="cuda")
+    Sx = torch.full((no, no), float("nan"), dtype=torch.float64, device="cuda")
+    rep = ctx.self_energy(dm.struct, _g(gw, g), W, S, v=dm.v, sigma_out=sig, Sigma_x_out=Sx)
+    torch.cuda.synchronize()
+    assert rep.n_hbins == N // 2
+    return sig.cpu().numpy(), S.cpu().numpy(), Sx.cpu().numpy()
+
+
+_CASES = {
+    # 64 products, 16 orbitals in sets of 4 and 8
+    "tiny": (lambda: gs.make_config(0), (64, 4.0), False),
+    # 136 products (two 64-tiles and a ragged tail), 32 orbitals
+    "chain8_ragged": (lambda: gs.chain_molecule(8, 7, orb_per_atom=4, occ_per_atom=2, prod_per_atom=10,
+                                                prod_per_bond=8, bond_cutoff=None), (64, 4.0), True),
+    # the workload's atoms: 13 orbitals per atom, 26 per bonded pair
+    "chain3_workload_atoms": (lambda: gs.chain_molecule(3, 5), (128, 4.0), True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(_CASES))
+def test_self_energy_matches_oracle(gpu, case):
+    gw, ctx, torch = gpu
+    mk, (N, wmax), levels = _CASES[case]
+    mol = mk()
+    g = _mesh(N, wmax)
+    _say("self-energy", case, "n_prod", mol.n_prod, "n_orb", mol.n_orb, "n_omega", N)
+    sig, S, Sx = _gpu(gw, ctx, torch, mol, g)
+    sp, sm, Sref, Sxref = _oracle(mol, g, levels)
+    e = (_rel(sig[0], sp), _rel(sig[1], sm), _rel(S, Sref), _rel(Sx, Sxref))
+    _say("sigma+ %.2e sigma- %.2e Sigma %.2e Sigma_x %.2e" % e)
+    assert e[0] < 1e-11 and e[1] < 1e-11 and e[2] < 1e-11
+    assert e[3] < 1e-12
+    scale = np.abs(S).max()
+    assert np.abs(S - np.transpose(S, (0, 2, 1))).max() <= 1e-13 * scale
+    for j in (0, N // 4, N // 2, N // 2 + 3, N - 1):
+        assert np.linalg.eigvalsh(0.5 * (S[j].imag + S[j].imag.T)).max() <= 1e-12 * scale
+
+
+def test_self_energy_without_optional_outputs(gpu):
+    """sigma_out and Sigma_x_out are optional; Sigma is the same without them."""
+    gw, ctx, torch = gpu
+    mol = gs.make_config(0)
+    g = _mesh(64, 4.0)
+    _, S1, _ = _gpu(gw, ctx, torch, mol, g)
+    dm = gw.DeviceMolecule(mol)
+    n, no, N = mol.n_prod, mol.n_orb, g.n_omega
+    chi = torch.empty((N, n, n), dtype=torch.complex128, device="cuda")
+    W = torch.empty_like(chi)
+    ctx.build_chi0(dm.struct, _g(gw, g), chi)
+    ctx.solve_W(dm.v, n, chi, N, W)
+    S2 = torch.empty((N, no, no), dtype=torch.complex128, device="cuda")
+    ctx.self_energy(dm.struct, _g(gw, g), W, S2)
+    torch.cuda.synchronize()
+    assert _rel(S2.cpu().numpy(), S1) < 1e-14
+
+
+def test_self_energy_errors(gpu):
+    gw, ctx, torch = gpu
+    mol = gs.make_config(0)
+    g = _mesh(64, 4.0)
+    dm = gw.DeviceMolecule(mol)
+    n, no, N = mol.n_prod, mol.n_orb, g.n_omega
+    W = torch.zeros((N, n, n), dtype=torch.complex128, device="cuda")
+    S = torch.empty((N, no, no), dtype=torch.complex128, device="cuda")
+    Sx = torch.empty((no, no), dtype=torch.float64, device="cuda")
+    with pytest.raises(gw.GwError) as e:  # exchange without v
+        ctx.self_energy(dm.struct, _g(gw, g), W, S, Sigma_x_out=Sx)
+    assert e.value.status == gw.GW_E_INVALID
+    with pytest.raises(gw.GwError) as e:  # no W
+        ctx.self_energy(dm.struct, _g(gw, g), None, S)
+    assert e.value.status == gw.GW_E_INVALID
+    shifted = dataclasses.replace(mol, eig=mol.eig + 2.0)
+    with pytest.raises(gw.GwError) as e:  # energies not from the Fermi level
+        ctx.self_energy(gw.DeviceMolecule(shifted).struct, _g(gw, g), W, S)
+    assert e.value.status == gw.GW_E_INVALID
