@@ -57,8 +57,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
     constexpr int EB = BK * BN / 256, TPRB = BN / EB;  // (B)
     static_assert(EA >= 1 && EB >= 1 && TPRA >= 1 && TPRB >= 1, "tile too small");
     typedef typename Mfma<T>::v4 v4;
-    __shared__ T Ar[2][BK][BM];
-    __shared__ T Ai[2][AC ? BK : 1][AC ? BM : 1];
+    // the 64x64 tile pads the transposed A rows (its stores would otherwise
+    // hit one bank group) and gives each thread B columns TPRB apart
+    constexpr int PA = (BK == 16) ? 1 : 0;
+    constexpr int SB = (BK == 16) ? TPRB : 1;
+    __shared__ T Ar[2][BK][BM + PA];
+    __shared__ T Ai[2][AC ? BK : 1][AC ? BM + PA : 1];
     __shared__ T Br[2][BK][BN];
     __shared__ T Bi[2][BC ? BK : 1][BC ? BN : 1];
 
@@ -81,7 +85,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
         }
 
     const int a_row = tid / TPRA, a_k = (tid % TPRA) * EA;
-    const int b_row = tid / TPRB, b_col = (tid % TPRB) * EB;
+    const int b_row = tid / TPRB, b_col = (SB == 1) ? (tid % TPRB) * EB : tid % TPRB;
     T ra_r[EA], ra_i[EA], rb_r[EB], rb_i[EB];
     // interior tiles take an unpredicated path
     const bool rows_in = m0 + BM <= M;
@@ -116,14 +120,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
             const T *p = B + ((int64_t)gk * ldb + n0 + b_col) * eb;
 #pragma unroll
             for (int c = 0; c < EB; ++c) {
-                rb_r[c] = p[c * eb];
-                if constexpr (BC) rb_i[c] = p[c * eb + 1];
+                rb_r[c] = p[c * SB * eb];
+                if constexpr (BC) rb_i[c] = p[c * SB * eb + 1];
                 else rb_i[c] = T(0);
             }
         } else {
 #pragma unroll
             for (int c = 0; c < EB; ++c) {
-                const int gc = n0 + b_col + c;
+                const int gc = n0 + b_col + c * SB;
                 if (gk < K && gc < N) {
                     const T *p = B + ((int64_t)gk * ldb + gc) * eb;
                     rb_r[c] = p[0];
@@ -144,8 +148,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, c
         }
 #pragma unroll
         for (int c = 0; c < EB; ++c) {
-            Br[b][b_row][b_col + c] = rb_r[c];
-            if constexpr (BC) Bi[b][b_row][b_col + c] = rb_i[c];
+            Br[b][b_row][b_col + c * SB] = rb_r[c];
+            if constexpr (BC) Bi[b][b_row][b_col + c * SB] = rb_i[c];
         }
     };
     // LDS double buffer: compute on one buffer while the next K step is
