@@ -725,16 +725,28 @@ gw_status level_tables(gw_ctx *ctx, const HostMol &h, int n_orb, int n_occ, int 
     return GW_OK;
 }
 
-// Vertex block pairs B1 <= B2 (pb1 then pb2 in one array) and the largest
+// Vertex block pairs B1 <= B2 (pb1 then pb2 in one array), grouped by tile
+// class 2 (|O1| > 16) + (|O2| > 16) with class c at class_off[c] ..
+// class_off[c+1] - 1 (class_off may be null), and the largest
 // (products x |O|^2) of a block.
-int block_pairs(const HostMol &h, int nblk, std::vector<int32_t> *pbs, int *max_vblock) {
-    pbs->clear();
+int block_pairs(const HostMol &h, int nblk, std::vector<int32_t> *pbs, int *max_vblock, int *class_off = nullptr) {
+    std::vector<int32_t> b1s[4], b2s[4];
     for (int b1 = 0; b1 < nblk; ++b1)
-        for (int b2 = b1; b2 < nblk; ++b2) pbs->push_back(b1);
-    const int npb = (int)pbs->size();
-    pbs->resize(2 * (size_t)npb);
-    for (int b1 = 0, i = 0; b1 < nblk; ++b1)
-        for (int b2 = b1; b2 < nblk; ++b2, ++i) (*pbs)[npb + i] = b2;
+        for (int b2 = b1; b2 < nblk; ++b2) {
+            const int c = 2 * (h.blk_orb[b1 + 1] - h.blk_orb[b1] > 16) + (h.blk_orb[b2 + 1] - h.blk_orb[b2] > 16);
+            b1s[c].push_back(b1);
+            b2s[c].push_back(b2);
+        }
+    pbs->clear();
+    int off[5] = {0, 0, 0, 0, 0};
+    for (int c = 0; c < 4; ++c) {
+        pbs->insert(pbs->end(), b1s[c].begin(), b1s[c].end());
+        off[c + 1] = off[c] + (int)b1s[c].size();
+    }
+    for (int c = 0; c < 4; ++c) pbs->insert(pbs->end(), b2s[c].begin(), b2s[c].end());
+    const int npb = off[4];
+    if (class_off)
+        for (int c = 0; c < 5; ++c) class_off[c] = off[c];
     *max_vblock = 0;
     for (int b = 0; b < nblk; ++b) {
         const int no = h.blk_orb[b + 1] - h.blk_orb[b];
@@ -785,7 +797,8 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
     std::vector<int32_t> pbs;
     double cflops = 0.0;
     int max_vblock = 0;
-    const int npb = block_pairs(h, nblk, &pbs, &max_vblock);
+    int class_off[5];
+    const int npb = block_pairs(h, nblk, &pbs, &max_vblock, class_off);
     for (int b1 = 0; b1 < nblk; ++b1)
         for (int b2 = b1; b2 < nblk; ++b2) {
             const double n1 = h.blk_orb[b1 + 1] - h.blk_orb[b1], n2 = h.blk_orb[b2 + 1] - h.blk_orb[b2];
@@ -836,9 +849,8 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
     // transform back, a = sum over chunks of G[:, chunk] Ahat[chunk]
     for (int q0 = 0; q0 < Q; q0 += qc) {
         const int nq = std::min(qc, Q - q0);
-        GW_HIP(ctx, gwk::launch_time_contract(st, n_orb, n, npb, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
-                                              m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Ahat, max_vblock,
-                                              cflops * nq));
+        GW_HIP(ctx, gwk::launch_time_contract(st, n_orb, n, class_off, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
+                                              m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Ahat, cflops * nq));
         GW_HIP(ctx, gwk::launch_dgemm(st, nhb, (int)n_upper, 2 * nq, 1.0, G + 2 * q0, 2 * Q, 0, Ahat, n_upper, 0,
                                       q0 == 0 ? 0.0 : 1.0, a, n_upper, 0, 1));
     }

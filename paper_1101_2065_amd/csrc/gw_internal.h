@@ -156,12 +156,13 @@ hipError_t launch_rho_bins(hipStream_t st, int n_orb, int K, const double *X, co
 // rows for a real sequence (G may be null), length L, Q = L/2 + 1.
 hipError_t launch_dft_matrices(hipStream_t st, int L, int Q, int K, double *F, int M, double *G);
 // Ahat[2 qq (+1)][t] for time points q0 .. q0 + nq - 1 over the listed block
-// pairs (pb1[i] <= pb2[i]); Rp, Rm: [2Q][n_orb^2] transformed densities;
-// max_vblock: the largest (products x |O|^2) of a block (LDS staging).
-hipError_t launch_time_contract(hipStream_t st, int n_orb, int n_prod, int n_pairs_blk, int q0, int nq,
+// pairs (pb1[i] <= pb2[i]); Rp, Rm: [2Q][n_orb^2] transformed densities.
+// The pairs are grouped by tile class c = 2 (|O1| > 16) + (|O2| > 16):
+// class c holds the pairs class_off[c] .. class_off[c+1] - 1 (host array).
+hipError_t launch_time_contract(hipStream_t st, int n_orb, int n_prod, const int *class_off, int q0, int nq,
                                 const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
                                 const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
-                                const double *Rp, const double *Rm, double *Ahat, int max_vblock, double flops);
+                                const double *Rp, const double *Rm, double *Ahat, double flops);
 
 // ---------------------------------------------------------------- self-energy from W
 // gam[k][t] = -(domega/pi) Im W[j0 + k][mu][nu], packed upper t, k < n_sb; gam[0] = 0.
