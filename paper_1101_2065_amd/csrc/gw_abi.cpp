@@ -896,8 +896,8 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
     const int L = std::max(Kp, Km) + n_sb - 1;
     const int Q = L / 2 + 1;
     std::vector<int32_t> pbs;
-    int max_vblock = 0;
-    const int npb = block_pairs(h, nblk, &pbs, &max_vblock);
+    int max_vblock = 0, class_off[5];
+    const int npb = block_pairs(h, nblk, &pbs, &max_vblock, class_off);
     double cflops = 0.0;
     for (int b1 = 0; b1 < nblk; ++b1)
         for (int b2 = b1; b2 < nblk; ++b2) {
@@ -958,7 +958,7 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
                                       n_upper, 0, 0.0, Gh, n_upper, 0, 1));
         GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)S, 4 * (int64_t)nq * nn, 0));
         Sm = S + 2 * (int64_t)nq * nn;
-        GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, npb, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
+        GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, class_off, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
                                                m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Gh, Sp, Sm,
                                                cflops * nq));
         const double beta = q0 == 0 ? 0.0 : 1.0;
@@ -984,7 +984,7 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
         GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)Gh, 2 * n_upper, 0));
         GW_HIP(ctx, gwk::launch_pack_upper(st, n, v, Gh));
         GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)S, 2 * nn, 0));
-        GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, npb, 0, 1, m->blk_prod, m->blk_orb, m->orb_idx,
+        GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, class_off, 0, 1, m->blk_prod, m->blk_orb, m->orb_idx,
                                                m->blk_val, m->vals, d_pb, d_pb + npb, Rp, nullptr, Gh, S, nullptr,
                                                cflops / 4));
         GW_HIP(ctx, gwk::launch_scale_copy(st, nn, -1.0, S, Sigma_x_out));

@@ -175,8 +175,9 @@ hipError_t launch_scale_copy(hipStream_t st, int64_t n, double alpha, const doub
 // S+-[2 qq (+1)][a][b] += sum over the listed block pairs of
 // sum_{mu nu} gammahat^{mu nu} (V_mu rho+-(t) V_nu)^{ab} (and the transpose for
 // B1 < B2), time points q0 .. q0 + nq - 1.  Rm == nullptr: one density only.
-// S+- must be cleared by the caller.
-hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, int n_pairs_blk, int q0, int nq,
+// S+- must be cleared by the caller.  Block pairs grouped by tile class as
+// for launch_time_contract.
+hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, const int *class_off, int q0, int nq,
                                  const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
                                  const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
                                  const double *Rp, const double *Rm, const double *Gh, double *Sp, double *Sm,

@@ -4,7 +4,8 @@
 // electronic densities rho+ and rhobar- are transformed to time; per time
 // and per pair of vertex blocks the product
 //   sigma^{ab}(t) += sum_{mu in B1, nu in B2} gamma^{mu nu}(t) (V_mu rho(t) V_nu)^{ab}
-// is accumulated, and the sum is transformed back to the mesh.
+// is accumulated (small products on the matrix cores), and the sum is
+// transformed back to the mesh.
 #include "gw_internal.h"
 #include "gw_prof.h"
 
@@ -52,40 +53,170 @@ __global__ void k_scale_copy(int64_t n, double alpha, const double *__restrict__
 
 constexpr int SO = TIME_MAX_ORB;
 constexpr int SP = SO + 1;
-constexpr int SC_NT = 512;
 
-// One workgroup per (block pair B1 <= B2, time point q0 + blockIdx.y).  For
-// every product mu of B1: G = sum_{nu in B2} gammahat^{mu nu} V_nu (|O2| x |O2|),
-// U+- = rho+-_{O1 O2} G, C+- += V_mu U+-.  C+- is then added (atomically:
-// several block pairs share orbitals) to S+-[qq][O1][O2] and, for B1 < B2,
-// its transpose to S+-[qq][O2][O1] (the ordered pair (B2, B1)).  TWO = false:
-// one density only (Rm, Sm unused).  Rp, Rm: [2Q][n_orb^2] (Re, Im planes per
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ inline v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// One wave's share of a (block pair, time point): for its products mu of B1
+// (mu = p1 + wave, step 4)
+//   G = sum_{nu in B2} gammahat^{mu nu} V_nu  (|O2| x |O2|, on the vector units,
+//       computed directly in the B-operand layout),
+//   U+- = rho+- G  (matrix cores), C+- += V_mu U+-  (matrix cores; U's result
+//       layout is the B-operand layout of this product, and C accumulates in
+//       the MFMA registers over mu).
+// f64 16x16x4 layouts (gfx950): A operand lane l = A[l % 16][l / 16], B operand
+// lane l = B[l / 16][l % 16], result element e of lane l = D[l / 16 + 4 e][l % 16].
+// TWO = false: one density only.  The wave's C+- are then added to S+-
+// (atomically; the transpose too for B1 < B2).
+template <int T1, int T2, bool TWO>
+__device__ void sigma_wave(int n1, int n2, int p1, int e1, int p2, int e2, bool same, int n_prod, int n_orb,
+                           int lane, int wave, const double *__restrict__ v1, const double *__restrict__ v2,
+                           const double *__restrict__ ghr, const double *__restrict__ ghi, const double *ppr,
+                           const double *ppi, const double *pmr, const double *pmi, const int *o1, const int *o2,
+                           double *spr, double *spi, double *smr, double *smi) {
+    const int lr = lane & 15, lk = lane >> 4;
+    const int nsq1 = n1 * n1, nsq2 = n2 * n2;
+    v4d cpr[T1][T2], cpi[T1][T2], cmr[T1][T2], cmi[T1][T2];
+#pragma unroll
+    for (int at = 0; at < T1; ++at)
+#pragma unroll
+        for (int dt = 0; dt < T2; ++dt) cpr[at][dt] = cpi[at][dt] = cmr[at][dt] = cmi[at][dt] = v4d{0, 0, 0, 0};
+    for (int mu = p1 + wave; mu < e1; mu += 4) {
+        // G[c][d] at c = 4 s + lk, d = dt*16 + lr: the B operand of every k step
+        double gr[4 * T2][T2], gi[4 * T2][T2];
+#pragma unroll
+        for (int s = 0; s < 4 * T2; ++s)
+#pragma unroll
+            for (int dt = 0; dt < T2; ++dt) gr[s][dt] = gi[s][dt] = 0.0;
+        for (int nu = p2; nu < e2; ++nu) {
+            const int a = min(mu, nu), b = max(mu, nu);
+            const int64_t t = (int64_t)a * n_prod - ((int64_t)a * (a - 1)) / 2 + (b - a);
+            const double wr = ghr[t], wi = ghi[t];
+            const double *vnu = v2 + (int64_t)(nu - p2) * nsq2;
+#pragma unroll
+            for (int s = 0; s < 4 * T2; ++s)
+#pragma unroll
+                for (int dt = 0; dt < T2; ++dt) {
+                    const int c = 4 * s + lk, d = dt * 16 + lr;
+                    const double v = (c < n2 && d < n2) ? vnu[c * n2 + d] : 0.0;
+                    gr[s][dt] += wr * v;
+                    gi[s][dt] += wi * v;
+                }
+        }
+        // vertex entries of mu, the A operand of C += V_mu U: V[a][i] at
+        // a = at*16 + lr, i = 4 k + lk
+        double va[T1][4 * T1];
+        const double *vmu = v1 + (int64_t)(mu - p1) * nsq1;
+#pragma unroll
+        for (int at = 0; at < T1; ++at)
+#pragma unroll
+            for (int k = 0; k < 4 * T1; ++k) {
+                const int a = at * 16 + lr, ii = 4 * k + lk;
+                va[at][k] = (a < n1 && ii < n1) ? vmu[a * n1 + ii] : 0.0;
+            }
+#pragma unroll
+        for (int den = 0; den < (TWO ? 2 : 1); ++den) {
+            const double *qr = den ? pmr : ppr, *qi = den ? pmi : ppi;
+            // U[i][d] = sum_c rho[i][c] G[c][d]
+            v4d ur[T1][T2], ui[T1][T2];
+#pragma unroll
+            for (int it = 0; it < T1; ++it)
+#pragma unroll
+                for (int dt = 0; dt < T2; ++dt) ur[it][dt] = ui[it][dt] = v4d{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4 * T2; ++s) {
+                const int c = 4 * s + lk;
+#pragma unroll
+                for (int it = 0; it < T1; ++it) {
+                    const double ar = qr[(it * 16 + lr) * SP + c], ai = qi[(it * 16 + lr) * SP + c];
+#pragma unroll
+                    for (int dt = 0; dt < T2; ++dt) {
+                        ur[it][dt] = mfma4(ar, gr[s][dt], ur[it][dt]);
+                        ur[it][dt] = mfma4(-ai, gi[s][dt], ur[it][dt]);
+                        ui[it][dt] = mfma4(ar, gi[s][dt], ui[it][dt]);
+                        ui[it][dt] = mfma4(ai, gr[s][dt], ui[it][dt]);
+                    }
+                }
+            }
+            // C[a][d] += sum_i V[a][i] U[i][d]; k steps over i: tile it, element e
+#pragma unroll
+            for (int it = 0; it < T1; ++it)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int at = 0; at < T1; ++at)
+#pragma unroll
+                        for (int dt = 0; dt < T2; ++dt) {
+                            const double a = va[at][4 * it + e];
+                            if (den == 0) {
+                                cpr[at][dt] = mfma4(a, ur[it][dt][e], cpr[at][dt]);
+                                cpi[at][dt] = mfma4(a, ui[it][dt][e], cpi[at][dt]);
+                            } else {
+                                cmr[at][dt] = mfma4(a, ur[it][dt][e], cmr[at][dt]);
+                                cmi[at][dt] = mfma4(a, ui[it][dt][e], cmi[at][dt]);
+                            }
+                        }
+        }
+    }
+    // add this wave's C+- (element e of a lane: a = at*16 + lk + 4e, b = dt*16 + lr)
+    const int64_t no = n_orb;
+#pragma unroll
+    for (int at = 0; at < T1; ++at)
+#pragma unroll
+        for (int dt = 0; dt < T2; ++dt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int a = at * 16 + lk + 4 * e, b = dt * 16 + lr;
+                if (a < n1 && b < n2) {
+                    const int64_t ab = (int64_t)o1[a] * no + o2[b], ba = (int64_t)o2[b] * no + o1[a];
+                    atomicAdd(spr + ab, cpr[at][dt][e]);
+                    atomicAdd(spi + ab, cpi[at][dt][e]);
+                    if (TWO) {
+                        atomicAdd(smr + ab, cmr[at][dt][e]);
+                        atomicAdd(smi + ab, cmi[at][dt][e]);
+                    }
+                    if (!same) {
+                        atomicAdd(spr + ba, cpr[at][dt][e]);
+                        atomicAdd(spi + ba, cpi[at][dt][e]);
+                        if (TWO) {
+                            atomicAdd(smr + ba, cmr[at][dt][e]);
+                            atomicAdd(smi + ba, cmi[at][dt][e]);
+                        }
+                    }
+                }
+            }
+}
+
+// One workgroup (4 waves) per (time point q0 + blockIdx.x, block pair
+// B1 <= B2 of blockIdx.y); rho+- restricted to O1 x O2 are gathered into LDS
+// (zero padded to whole 16-tiles).  Rp, Rm: [2Q][n_orb^2] (Re, Im planes per
 // time point); Gh: [2 nq][n_upper]; S+-: [2 nq][n_orb^2].
-template <bool TWO>
-__global__ __launch_bounds__(SC_NT) void k_sigma_contract(
+template <int T1, int T2, bool TWO>
+__global__ __launch_bounds__(256) void k_sigma_contract(
     int n_orb, int n_prod, int q0, const int32_t *__restrict__ blk_prod, const int32_t *__restrict__ blk_orb,
     const int32_t *__restrict__ orb_idx, const int64_t *__restrict__ blk_val, const double *__restrict__ vals,
     const int32_t *__restrict__ pb1, const int32_t *__restrict__ pb2, const double *__restrict__ Rp,
     const double *__restrict__ Rm, const double *__restrict__ Gh, double *__restrict__ Sp, double *__restrict__ Sm) {
     __shared__ int o1[SO], o2[SO];
-    __shared__ double ppr[SO * SP], ppi[SO * SP], pmr[SO * SP], pmi[SO * SP];  // rho+- [a'][c], a' in O1, c in O2
-    __shared__ double gr[SO * SP], gi[SO * SP];                                // G [c][d], O2 x O2
-    __shared__ double upr[SO * SP], upi[SO * SP], umr[SO * SP], umi[SO * SP];  // U+- [a'][d]
-    __shared__ double vm[SO * SP];                                             // V_mu [a][a']
-    const int B1 = pb1[blockIdx.x], B2 = pb2[blockIdx.x];
-    const int qq = blockIdx.y, q = q0 + qq;
-    const int tid = threadIdx.x;
+    __shared__ double ppr[SO * SP], ppi[SO * SP], pmr[TWO ? SO * SP : 1], pmi[TWO ? SO * SP : 1];
+    const int B1 = pb1[blockIdx.y], B2 = pb2[blockIdx.y];
+    const int qq = blockIdx.x, q = q0 + qq;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ob1 = blk_orb[B1], ob2 = blk_orb[B2];
     const int n1 = blk_orb[B1 + 1] - ob1, n2 = blk_orb[B2 + 1] - ob2;
     if (tid < n1) o1[tid] = orb_idx[ob1 + tid];
     if (tid < n2) o2[tid] = orb_idx[ob2 + tid];
+    for (int idx = tid; idx < SO * SP; idx += 256) {
+        ppr[idx] = ppi[idx] = 0.0;
+        if (TWO) pmr[idx] = pmi[idx] = 0.0;
+    }
     __syncthreads();
     const int64_t nn = (int64_t)n_orb * n_orb;
     const int64_t n_upper = (int64_t)n_prod * (n_prod + 1) / 2;
     {
         const double *ar = Rp + (int64_t)(2 * q) * nn, *ai = ar + nn;
         const double *br = TWO ? Rm + (int64_t)(2 * q) * nn : nullptr, *bi = TWO ? br + nn : nullptr;
-        for (int idx = tid; idx < n1 * n2; idx += SC_NT) {
+        for (int idx = tid; idx < n1 * n2; idx += 256) {
             const int i = idx / n2, j = idx % n2;
             const int64_t ac = (int64_t)o1[i] * n_orb + o2[j];
             ppr[i * SP + j] = ar[ac];
@@ -96,104 +227,13 @@ __global__ __launch_bounds__(SC_NT) void k_sigma_contract(
             }
         }
     }
-    const int p1 = blk_prod[B1], e1 = blk_prod[B1 + 1];
-    const int p2 = blk_prod[B2], e2 = blk_prod[B2 + 1];
-    const int nsq1 = n1 * n1, nsq2 = n2 * n2, n12 = n1 * n2;
-    const double *v1 = vals + blk_val[B1];
-    const double *v2 = vals + blk_val[B2];
+    __syncthreads();
     const double *ghr = Gh + (int64_t)(2 * qq) * n_upper, *ghi = ghr + n_upper;
-    // this thread's elements (a, b) of C: e = tid + SC_NT r, r < 2 (n1 n2 <= 1024)
-    double cpr[2] = {0.0, 0.0}, cpi[2] = {0.0, 0.0}, cmr[2] = {0.0, 0.0}, cmi[2] = {0.0, 0.0};
-    for (int mu = p1; mu < e1; ++mu) {
-        __syncthreads();
-        const double *vmu = v1 + (int64_t)(mu - p1) * nsq1;
-        for (int idx = tid; idx < nsq1; idx += SC_NT) vm[(idx / n1) * SP + idx % n1] = vmu[idx];
-        // G = sum_nu gammahat^{mu nu} V_nu
-        for (int idx = tid; idx < nsq2; idx += SC_NT) {
-            double sr = 0.0, si = 0.0;
-            for (int nu = p2; nu < e2; ++nu) {
-                const int a = min(mu, nu), b = max(mu, nu);
-                const int64_t t = (int64_t)a * n_prod - ((int64_t)a * (a - 1)) / 2 + (b - a);
-                const double v = v2[(int64_t)(nu - p2) * nsq2 + idx];
-                sr += ghr[t] * v;
-                si += ghi[t] * v;
-            }
-            gr[(idx / n2) * SP + idx % n2] = sr;
-            gi[(idx / n2) * SP + idx % n2] = si;
-        }
-        __syncthreads();
-        // U+- = rho+- G
-        for (int idx = tid; idx < n12; idx += SC_NT) {
-            const int i = idx / n2, d = idx % n2;
-            double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-            for (int c = 0; c < n2; ++c) {
-                const double xr = gr[c * SP + d], xi = gi[c * SP + d];
-                const double pr = ppr[i * SP + c], pi = ppi[i * SP + c];
-                ar += pr * xr - pi * xi;
-                ai += pr * xi + pi * xr;
-                if (TWO) {
-                    const double mr = pmr[i * SP + c], mi = pmi[i * SP + c];
-                    br += mr * xr - mi * xi;
-                    bi += mr * xi + mi * xr;
-                }
-            }
-            upr[i * SP + d] = ar;
-            upi[i * SP + d] = ai;
-            if (TWO) {
-                umr[i * SP + d] = br;
-                umi[i * SP + d] = bi;
-            }
-        }
-        __syncthreads();
-        // C+- += V_mu U+-
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int e = tid + SC_NT * r;
-            if (e < n12) {
-                const int a = e / n2, b = e % n2;
-                double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-                for (int k = 0; k < n1; ++k) {
-                    const double v = vm[a * SP + k];
-                    ar += v * upr[k * SP + b];
-                    ai += v * upi[k * SP + b];
-                    if (TWO) {
-                        br += v * umr[k * SP + b];
-                        bi += v * umi[k * SP + b];
-                    }
-                }
-                cpr[r] += ar;
-                cpi[r] += ai;
-                if (TWO) {
-                    cmr[r] += br;
-                    cmi[r] += bi;
-                }
-            }
-        }
-    }
     double *spr = Sp + (int64_t)(2 * qq) * nn, *spi = spr + nn;
     double *smr = TWO ? Sm + (int64_t)(2 * qq) * nn : nullptr, *smi = TWO ? smr + nn : nullptr;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int e = tid + SC_NT * r;
-        if (e < n12) {
-            const int a = o1[e / n2], b = o2[e % n2];
-            const int64_t ab = (int64_t)a * n_orb + b, ba = (int64_t)b * n_orb + a;
-            atomicAdd(spr + ab, cpr[r]);
-            atomicAdd(spi + ab, cpi[r]);
-            if (TWO) {
-                atomicAdd(smr + ab, cmr[r]);
-                atomicAdd(smi + ab, cmi[r]);
-            }
-            if (B1 != B2) {
-                atomicAdd(spr + ba, cpr[r]);
-                atomicAdd(spi + ba, cpi[r]);
-                if (TWO) {
-                    atomicAdd(smr + ba, cmr[r]);
-                    atomicAdd(smi + ba, cmi[r]);
-                }
-            }
-        }
-    }
+    sigma_wave<T1, T2, TWO>(n1, n2, blk_prod[B1], blk_prod[B1 + 1], blk_prod[B2], blk_prod[B2 + 1], B1 == B2, n_prod,
+                            n_orb, lane, wave, vals + blk_val[B1], vals + blk_val[B2], ghr, ghi, ppr, ppi, pmr, pmi,
+                            o1, o2, spr, spi, smr, smi);
 }
 
 }  // namespace
@@ -225,21 +265,32 @@ hipError_t launch_scale_copy(hipStream_t st, int64_t n, double alpha, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, int n_pairs_blk, int q0, int nq,
+hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, const int *class_off, int q0, int nq,
                                  const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
                                  const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
                                  const double *Rp, const double *Rm, const double *Gh, double *Sp, double *Sm,
                                  double flops) {
-    if (n_pairs_blk <= 0 || nq <= 0) return hipSuccess;
+    if (class_off[4] <= 0 || nq <= 0) return hipSuccess;
     const double nn = (double)n_orb * n_orb;
     ProfScope ps(st, "sigma_contract", flops, 16.0 * nq * nn * (Rm ? 2 : 1));
-    dim3 grid((unsigned)n_pairs_blk, (unsigned)nq);
-    if (Rm)
-        hipLaunchKernelGGL(k_sigma_contract<true>, grid, dim3(SC_NT), 0, st, n_orb, n_prod, q0, blk_prod, blk_orb,
-                           orb_idx, blk_val, vals, pb1, pb2, Rp, Rm, Gh, Sp, Sm);
-    else
-        hipLaunchKernelGGL(k_sigma_contract<false>, grid, dim3(SC_NT), 0, st, n_orb, n_prod, q0, blk_prod, blk_orb,
-                           orb_idx, blk_val, vals, pb1, pb2, Rp, (const double *)nullptr, Gh, Sp, (double *)nullptr);
+    // one launch per tile class (|O1|, |O2| up to 16 or 32)
+#define GW_SC(T1, T2, c)                                                                                        \
+    if (class_off[c + 1] > class_off[c]) {                                                                     \
+        dim3 grid((unsigned)nq, (unsigned)(class_off[c + 1] - class_off[c]));                                  \
+        if (Rm)                                                                                                \
+            hipLaunchKernelGGL((k_sigma_contract<T1, T2, true>), grid, dim3(256), 0, st, n_orb, n_prod, q0,      \
+                               blk_prod, blk_orb, orb_idx, blk_val, vals, pb1 + class_off[c], pb2 + class_off[c], \
+                               Rp, Rm, Gh, Sp, Sm);                                                            \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_sigma_contract<T1, T2, false>), grid, dim3(256), 0, st, n_orb, n_prod, q0,     \
+                               blk_prod, blk_orb, orb_idx, blk_val, vals, pb1 + class_off[c], pb2 + class_off[c], \
+                               Rp, (const double *)nullptr, Gh, Sp, (double *)nullptr);                        \
+    }
+    GW_SC(1, 1, 0)
+    GW_SC(1, 2, 1)
+    GW_SC(2, 1, 2)
+    GW_SC(2, 2, 3)
+#undef GW_SC
     return hipGetLastError();
 }
 
