@@ -960,7 +960,7 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
         Sm = S + 2 * (int64_t)nq * nn;
         GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, class_off, q0, nq, m->blk_prod, m->blk_orb, m->orb_idx,
                                                m->blk_val, m->vals, d_pb, d_pb + npb, Rp, Rm, Gh, Sp, Sm,
-                                               cflops * nq));
+                                               max_vblock, cflops * nq));
         const double beta = q0 == 0 ? 0.0 : 1.0;
         GW_HIP(ctx, gwk::launch_dgemm(st, n_sb, (int)nn, 2 * nq, 1.0, Gi + 2 * q0, 2 * Q, 0, Sp, nn, 0, beta, sig_p,
                                       nn, 0, 1));
@@ -986,7 +986,7 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
         GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)S, 2 * nn, 0));
         GW_HIP(ctx, gwk::launch_sigma_contract(st, n_orb, n, class_off, 0, 1, m->blk_prod, m->blk_orb, m->orb_idx,
                                                m->blk_val, m->vals, d_pb, d_pb + npb, Rp, nullptr, Gh, S, nullptr,
-                                               cflops / 4));
+                                               max_vblock, cflops / 4));
         GW_HIP(ctx, gwk::launch_scale_copy(st, nn, -1.0, S, Sigma_x_out));
     }
     if (rep) {

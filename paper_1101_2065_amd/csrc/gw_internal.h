@@ -181,6 +181,6 @@ hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, const in
                                  const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
                                  const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
                                  const double *Rp, const double *Rm, const double *Gh, double *Sp, double *Sm,
-                                 double flops);
+                                 int max_vblock, double flops);
 
 }  // namespace gwk

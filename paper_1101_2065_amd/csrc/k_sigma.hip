@@ -70,7 +70,7 @@ __device__ inline v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn
 // (atomically; the transpose too for B1 < B2).
 template <int T1, int T2, bool TWO>
 __device__ void sigma_wave(int n1, int n2, int p1, int e1, int p2, int e2, bool same, int n_prod, int n_orb,
-                           int lane, int wave, const double *__restrict__ v1, const double *__restrict__ v2,
+                           int lane, int wave, const double *__restrict__ v1, const double *v2,
                            const double *__restrict__ ghr, const double *__restrict__ ghi, const double *ppr,
                            const double *ppi, const double *pmr, const double *pmi, const int *o1, const int *o2,
                            double *spr, double *spi, double *smr, double *smi) {
@@ -92,7 +92,7 @@ __device__ void sigma_wave(int n1, int n2, int p1, int e1, int p2, int e2, bool 
             const int a = min(mu, nu), b = max(mu, nu);
             const int64_t t = (int64_t)a * n_prod - ((int64_t)a * (a - 1)) / 2 + (b - a);
             const double wr = ghr[t], wi = ghi[t];
-            const double *vnu = v2 + (int64_t)(nu - p2) * nsq2;
+            const double *vnu = v2 + (int64_t)(nu - p2) * nsq2;  // LDS copy when staged
 #pragma unroll
             for (int s = 0; s < 4 * T2; ++s)
 #pragma unroll
@@ -193,12 +193,14 @@ __device__ void sigma_wave(int n1, int n2, int p1, int e1, int p2, int e2, bool 
 // time point); Gh: [2 nq][n_upper]; S+-: [2 nq][n_orb^2].
 template <int T1, int T2, bool TWO>
 __global__ __launch_bounds__(256) void k_sigma_contract(
-    int n_orb, int n_prod, int q0, const int32_t *__restrict__ blk_prod, const int32_t *__restrict__ blk_orb,
-    const int32_t *__restrict__ orb_idx, const int64_t *__restrict__ blk_val, const double *__restrict__ vals,
-    const int32_t *__restrict__ pb1, const int32_t *__restrict__ pb2, const double *__restrict__ Rp,
-    const double *__restrict__ Rm, const double *__restrict__ Gh, double *__restrict__ Sp, double *__restrict__ Sm) {
+    int n_orb, int n_prod, int q0, int v_cap, const int32_t *__restrict__ blk_prod,
+    const int32_t *__restrict__ blk_orb, const int32_t *__restrict__ orb_idx, const int64_t *__restrict__ blk_val,
+    const double *__restrict__ vals, const int32_t *__restrict__ pb1, const int32_t *__restrict__ pb2,
+    const double *__restrict__ Rp, const double *__restrict__ Rm, const double *__restrict__ Gh,
+    double *__restrict__ Sp, double *__restrict__ Sm) {
     __shared__ int o1[SO], o2[SO];
     __shared__ double ppr[SO * SP], ppi[SO * SP], pmr[TWO ? SO * SP : 1], pmi[TWO ? SO * SP : 1];
+    extern __shared__ double vstage[];  // V of B2, when it fits in v_cap doubles
     const int B1 = pb1[blockIdx.y], B2 = pb2[blockIdx.y];
     const int qq = blockIdx.x, q = q0 + qq;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -227,12 +229,18 @@ __global__ __launch_bounds__(256) void k_sigma_contract(
             }
         }
     }
+    const double *v2 = vals + blk_val[B2];
+    const int nv2 = (blk_prod[B2 + 1] - blk_prod[B2]) * n2 * n2;
+    if (nv2 <= v_cap) {
+        for (int idx = tid; idx < nv2; idx += 256) vstage[idx] = v2[idx];
+        v2 = vstage;
+    }
     __syncthreads();
     const double *ghr = Gh + (int64_t)(2 * qq) * n_upper, *ghi = ghr + n_upper;
     double *spr = Sp + (int64_t)(2 * qq) * nn, *spi = spr + nn;
     double *smr = TWO ? Sm + (int64_t)(2 * qq) * nn : nullptr, *smi = TWO ? smr + nn : nullptr;
     sigma_wave<T1, T2, TWO>(n1, n2, blk_prod[B1], blk_prod[B1 + 1], blk_prod[B2], blk_prod[B2 + 1], B1 == B2, n_prod,
-                            n_orb, lane, wave, vals + blk_val[B1], vals + blk_val[B2], ghr, ghi, ppr, ppi, pmr, pmi,
+                            n_orb, lane, wave, vals + blk_val[B1], v2, ghr, ghi, ppr, ppi, pmr, pmi,
                             o1, o2, spr, spi, smr, smi);
 }
 
@@ -269,22 +277,31 @@ hipError_t launch_sigma_contract(hipStream_t st, int n_orb, int n_prod, const in
                                  const int32_t *blk_prod, const int32_t *blk_orb, const int32_t *orb_idx,
                                  const int64_t *blk_val, const double *vals, const int32_t *pb1, const int32_t *pb2,
                                  const double *Rp, const double *Rm, const double *Gh, double *Sp, double *Sm,
-                                 double flops) {
+                                 int max_vblock, double flops) {
     if (class_off[4] <= 0 || nq <= 0) return hipSuccess;
+    // the vertex block of B2 is staged in LDS when it fits next to the
+    // densities (96 KB); larger blocks are read from memory
+    const int v_cap = std::min(max_vblock, 96 * 1024 / 8);
+    const size_t lds = sizeof(double) * (size_t)v_cap;
     const double nn = (double)n_orb * n_orb;
     ProfScope ps(st, "sigma_contract", flops, 16.0 * nq * nn * (Rm ? 2 : 1));
     // one launch per tile class (|O1|, |O2| up to 16 or 32)
 #define GW_SC(T1, T2, c)                                                                                        \
     if (class_off[c + 1] > class_off[c]) {                                                                     \
         dim3 grid((unsigned)nq, (unsigned)(class_off[c + 1] - class_off[c]));                                  \
+        hipError_t ea = Rm ? hipFuncSetAttribute((const void *)k_sigma_contract<T1, T2, true>,                  \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)           \
+                           : hipFuncSetAttribute((const void *)k_sigma_contract<T1, T2, false>,                 \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);          \
+        if (ea != hipSuccess) return ea;                                                                       \
         if (Rm)                                                                                                \
-            hipLaunchKernelGGL((k_sigma_contract<T1, T2, true>), grid, dim3(256), 0, st, n_orb, n_prod, q0,      \
-                               blk_prod, blk_orb, orb_idx, blk_val, vals, pb1 + class_off[c], pb2 + class_off[c], \
-                               Rp, Rm, Gh, Sp, Sm);                                                            \
+            hipLaunchKernelGGL((k_sigma_contract<T1, T2, true>), grid, dim3(256), lds, st, n_orb, n_prod, q0,    \
+                               v_cap, blk_prod, blk_orb, orb_idx, blk_val, vals, pb1 + class_off[c],           \
+                               pb2 + class_off[c], Rp, Rm, Gh, Sp, Sm);                                        \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_sigma_contract<T1, T2, false>), grid, dim3(256), 0, st, n_orb, n_prod, q0,     \
-                               blk_prod, blk_orb, orb_idx, blk_val, vals, pb1 + class_off[c], pb2 + class_off[c], \
-                               Rp, (const double *)nullptr, Gh, Sp, (double *)nullptr);                        \
+            hipLaunchKernelGGL((k_sigma_contract<T1, T2, false>), grid, dim3(256), lds, st, n_orb, n_prod, q0,   \
+                               v_cap, blk_prod, blk_orb, orb_idx, blk_val, vals, pb1 + class_off[c],           \
+                               pb2 + class_off[c], Rp, (const double *)nullptr, Gh, Sp, (double *)nullptr);    \
     }
     GW_SC(1, 1, 0)
     GW_SC(1, 2, 1)
