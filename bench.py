@@ -52,12 +52,13 @@ def log(*a):
 def solve_flops(n, n_solved, n_ir=0, mixed=False):
     """Algorithmic flops of the W solve per solved frequency.  FP64: A = 1 -
     v chi0 4N^3, LU 8/3 N^3, forward substitution with N right-hand sides 4N^3,
-    back substitution of the lower triangle of the symmetric W 8/3 N^3.  Mixed:
+    back substitution of the lower triangle of the symmetric W 4/3 N^3
+    (sum over rows r of (r + 1)(N - 1 - r) complex multiply-adds).  Mixed:
     low-precision LU and full solves (8N^3), and per refinement step an FP64
     residual 8N^3 and a low-precision solve 8N^3."""
     n3 = float(n) ** 3
     if not mixed:
-        return {"fp64": n_solved * (4 + 8.0 / 3 + 4 + 8.0 / 3) * n3, "fp32": 0.0}
+        return {"fp64": n_solved * (4 + 8.0 / 3 + 4 + 4.0 / 3) * n3, "fp32": 0.0}
     return {"fp64": n_solved * (4 + 8 * n_ir) * n3, "fp32": n_solved * (8.0 / 3 + 8 * (1 + n_ir)) * n3}
 
 

@@ -809,9 +809,17 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
     const int nblk = (n + NB - 1) / NB;
     const int64_t sI = (int64_t)nblk * NB * NB;
     hipError_t e;
-    // forward: L Y = P B
+    // forward: L Y = P B, left-looking over the outer blocks: block row
+    // [KB, KB + WO) first takes everything already solved above it in one
+    // product (inner dimension KB, long for the later blocks), then is solved
+    // 64 rows at a time
     for (int KB = 0; KB < n; KB += NBO) {
         const int WO = min(NBO, n - KB);
+        if (KB > 0) {
+            e = gemm_t<T>(st, WO, nrhs, KB, T(-1), LU + (int64_t)KB * n, n, sA, B, nrhs, sB, T(1),
+                          B + (int64_t)KB * nrhs, nrhs, sB, batch);
+            if (e != hipSuccess) return e;
+        }
         for (int kb = KB; kb < KB + WO; kb += NB) {
             const int w = min(NB, n - kb);
             Cx<T> *Bk = B + (int64_t)kb * nrhs;
@@ -825,17 +833,19 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
                 if (e != hipSuccess) return e;
             }
         }
-        const int rest = n - KB - WO;
-        if (rest > 0) {
-            e = gemm_t<T>(st, rest, nrhs, WO, T(-1), LU + (int64_t)(KB + WO) * n + KB, n, sA, B + (int64_t)KB * nrhs,
-                          nrhs, sB, T(1), B + (int64_t)(KB + WO) * nrhs, nrhs, sB, batch);
-            if (e != hipSuccess) return e;
-        }
     }
-    // backward: U X = Y.  With sym_lower, rows [r0, r1) are only needed in
-    // columns [0, r1): every product below is cut to those columns.
+    // backward: U X = Y, left-looking from the last outer block up.  With
+    // sym_lower, rows [r0, r1) are only needed in columns [0, r1): every
+    // product is cut to those columns, so the work follows the lower triangle
+    // (a right-looking update would fill whole squares of columns).
     for (int KB = ((n - 1) / NBO) * NBO; KB >= 0; KB -= NBO) {
         const int WO = min(NBO, n - KB);
+        const int below = n - KB - WO;
+        if (below > 0) {
+            e = gemm_t<T>(st, WO, sym_lower ? KB + WO : nrhs, below, T(-1), LU + (int64_t)KB * n + KB + WO, n, sA,
+                          B + (int64_t)(KB + WO) * nrhs, nrhs, sB, T(1), B + (int64_t)KB * nrhs, nrhs, sB, batch);
+            if (e != hipSuccess) return e;
+        }
         for (int kb = KB + ((WO - 1) / NB) * NB; kb >= KB; kb -= NB) {
             const int w = min(NB, n - kb);
             Cx<T> *Bk = B + (int64_t)kb * nrhs;
@@ -849,11 +859,6 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
                               T(1), B + (int64_t)KB * nrhs, nrhs, sB, batch);
                 if (e != hipSuccess) return e;
             }
-        }
-        if (KB > 0) {
-            e = gemm_t<T>(st, KB, sym_lower ? KB : nrhs, WO, T(-1), LU + KB, n, sA, B + (int64_t)KB * nrhs, nrhs, sB,
-                          T(1), B, nrhs, sB, batch);
-            if (e != hipSuccess) return e;
         }
     }
     if (sym_lower && n > 1) {
