@@ -738,11 +738,12 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_hash():
-    """Hash of the sources that define the dominant kernel and its launches."""
+    """Hash of the sources that define the dominant kernel (the GEMM) and the
+    shapes it is launched with (the blocked LU and solves)."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in ("k_gemm.hip", "k_lu.hip", "gw_abi.cpp"):
+    for name in ("k_gemm.hip", "k_lu.hip"):
         with open(os.path.join(HERE, "paper_1101_2065_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -824,6 +825,37 @@ def summarize_profiles(stats_csv, fetch_csv, write_csv, out_json):
                       "dominant_bytes_per_launch": out["bytes_per_launch"]}))
 
 
+def summarize_trace(stats_csv, out_md):
+    """Kernel table from a rocprofv3 --kernel-trace --stats run of the FP64
+    step (one warm-up step and one timed step)."""
+    rows = []
+    for r in _csv_rows(stats_csv):
+        name = r.get("Name") or r.get("KernelName") or ""
+        calls = int(float(r.get("Calls", 0)))
+        tot = float(r.get("TotalDurationNs", 0.0))
+        rows.append((name, calls, tot))
+    rows.sort(key=lambda x: -x[2])
+    total = sum(x[2] for x in rows) or 1.0
+    md = ["# Kernel profile: FP64 step (chi0 build + W solve), 40-atom chain truncated to N_prod=2000, "
+          "1024 frequencies", "",
+          "Command (repository root, one MI355X):", "", "```",
+          "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_n2000 -o run --output-format csv -- python3 bench.py "
+          "--forms fp64 --steps 1 --warmup 1 --no-cpu-baseline",
+          "python bench.py --summarize-trace gpurun_out/prof_n2000/run_kernel_stats.csv", "```", "",
+          "Two steps (one warm-up, one timed) of gw_build_chi0 + gw_solve_W; all kernels from `run_kernel_stats.csv`:",
+          "", "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
+    for name, calls, tot in rows:
+        short = name.replace("(anonymous namespace)::", "")
+        short = short.split("(")[0] if "(" in short else short
+        short = short[5:] if short.startswith("void ") else short
+        md.append("| `%s` | %d | %.1f | %.1f | %.1f%% |" % (short[:70], calls, tot / 1e6, tot / 1e3 / max(calls, 1),
+                                                        100.0 * tot / total))
+    md.append("| **all kernels** | | %.1f | | 100%% |" % (total / 1e6))
+    with open(out_md, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote", out_md)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -842,7 +874,12 @@ def main():
                     help="end with three plain 1 GiB device copies (reference for the HBM counters)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/hbm_traffic.json from rocprofv3 outputs and exit (no GPU)")
+    ap.add_argument("--summarize-trace", metavar="STATS_CSV",
+                    help="write the kernel table of profiles/kernels_fp64_chain40_n2000.md and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, os.path.join(HERE, "profiles", "kernels_fp64_chain40_n2000.md"))
+        return
     if args.summarize_counters:
         summarize_profiles(*args.summarize_counters, TRAFFIC_FILE)
         return
