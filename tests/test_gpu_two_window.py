@@ -149,3 +149,31 @@ def test_two_window_errors(gpu):
         with pytest.raises(gw.GwError) as e:
             ctx.build_chi0_2w(dm.struct, gsml, glrg, a, b)
         assert e.value.status == gw.GW_E_INVALID
+
+
+def test_two_window_in_a_basis(gpu):
+    """Both windows built from pair vectors projected onto a basis (the
+    compressed path): the k x k fine-window chi0 equals the oracle's two-window
+    chi0 of the projected pair vectors."""
+    gw, ctx, torch = gpu
+    mol = gs.chain_molecule(8, 7, orb_per_atom=4, occ_per_atom=2, prod_per_atom=10, prod_per_bond=8,
+                            bond_cutoff=None)
+    k = 40
+    rng = np.random.default_rng(11)
+    Q, _ = np.linalg.qr(rng.standard_normal((mol.n_prod, k)))
+    small, large = _auto(256, 0.5), _auto(256, 4.0)
+    dm = gw.DeviceMolecule(mol)
+    Qd = torch.from_numpy(np.ascontiguousarray(Q)).to("cuda")
+    cs = torch.full((small.n_omega, k, k), float("nan"), dtype=torch.complex128, device="cuda")
+    cl = torch.full((large.n_omega, k, k), float("nan"), dtype=torch.complex128, device="cuda")
+    rep = ctx.build_chi0_2w(dm.struct, _g(gw, small), _g(gw, large), cs, cl, basis=Qd, k=k)
+    torch.cuda.synchronize()
+    Ph = o.project_pairs(o.pair_vectors(mol), Q)
+    s = o.frac_bits(Ph, mol.n_pairs)
+    assert rep.frac_bits_used == s
+    ref = o.unpack_upper(o.chi0_two_window(Ph, mol.eig, mol.n_occ, s,
+                                           (small.n_omega, small.omega_min, small.omega_max, small.eps),
+                                           (large.n_omega, large.omega_min, large.omega_max, large.eps)), k)
+    e = _rel(cs.cpu().numpy(), ref)
+    _say("two windows in a basis of", k, "rel", e)
+    assert e < 1e-10
