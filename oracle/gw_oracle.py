@@ -25,7 +25,9 @@ What the method computes, in the paper's notation (energies in Hartree):
   of rho+- with gamma contracted with the vertex (Section 5.A eq. spectral_3,
   evaluated time by time in Section 8.B), the self-energy as their Cauchy
   transform (eq. Cauchy1), and the instantaneous exchange part (Section 4
-  eq. instantaneous).
+  eq. instantaneous); Dyson's equation and the density of states (Section 2
+  eqs. Dyson and the DOS definition, Section 3 eq. tensorform-dyson, with
+  V_xc subtracted from Sigma as Section 2 prescribes).
 * Compression, Section 7.B eqs. subspace_chi0 and chi_RPA; the paper's own
   subspace, Section 7.A eqs. subsetof_vef, projector0, subspace and
   global-basis-orthogonality.
@@ -86,6 +88,7 @@ __all__ = [
     "self_energy_spectra_by_levels",
     "self_energy_from_spectra",
     "exchange_self_energy",
+    "dyson_dos",
 ]
 
 
@@ -708,3 +711,31 @@ def exchange_self_energy(mol) -> np.ndarray:
     A = V @ D  # (V_mu D)[a][b']
     G = np.einsum("mn,ncd->mcd", mol.v, V)
     return -np.einsum("mab,mbc->ac", A, G)
+
+
+def dyson_dos(mol, n_omega: int, omega_min: float, omega_max: float, eps: float,
+              Sigma_c: Optional[np.ndarray] = None, Sigma_x: Optional[np.ndarray] = None,
+              Vxc: Optional[np.ndarray] = None, js: Optional[Sequence[int]] = None):
+    """G(omega_j + i eps) = [(omega_j + i eps) - H_KS - (Sigma_x + Sigma_c(omega_j) - V_xc)]^{-1}
+    with H_KS = X diag(E) X^T in the (orthonormal, S = 1) orbital basis, and
+    rho(omega_j) = -(1/pi) Im tr G (Section 2 eq. Dyson with the V_xc
+    replacement, Section 3 eq. tensorform-dyson, the DOS definition of
+    Section 2).  Sigma_c: [n_omega][n_orb][n_orb] or None (zero).  Returns
+    (dos [len(js)], G [len(js)][n_orb][n_orb])."""
+    om = grid_omegas(n_omega, omega_min, omega_max)
+    jj = np.arange(n_omega) if js is None else np.asarray(list(js), dtype=np.int64)
+    H = (mol.X * mol.eig[None, :]) @ mol.X.T
+    static = H.copy()
+    if Sigma_x is not None:
+        static = static + Sigma_x
+    if Vxc is not None:
+        static = static - Vxc
+    n = mol.n_orb
+    G = np.empty((len(jj), n, n), dtype=np.complex128)
+    for i, j in enumerate(jj):
+        A = (om[j] + 1j * eps) * np.eye(n) - static
+        if Sigma_c is not None:
+            A = A - Sigma_c[j]
+        G[i] = np.linalg.inv(A)
+    dos = -np.imag(np.trace(G, axis1=1, axis2=2)) / math.pi
+    return dos, G

@@ -717,3 +717,27 @@ def test_exchange_self_energy_by_levels():
     assert np.abs(Sx - ref).max() <= 1e-12 * np.abs(ref).max()
     assert np.abs(Sx - Sx.T).max() <= 1e-12 * np.abs(Sx).max()
     assert np.linalg.eigvalsh(Sx).max() <= 1e-10 * np.abs(Sx).max()
+
+
+def test_dyson_dos_closed_forms():
+    """No self-energy: G = G0 and the DOS is a sum of Lorentzians of width eps
+    at the levels; a constant real shift of the self-energy moves every
+    level; Sigma = V_xc cancels exactly."""
+    mol = gs.make_config(0)
+    n_omega, wmax, eps = 128, 4.0, 0.05
+    om = -wmax + (2 * wmax / n_omega) * np.arange(n_omega)
+    lor = lambda E: (eps / math.pi) / ((om[:, None] - E[None, :]) ** 2 + eps ** 2)
+    dos, G = o.dyson_dos(mol, n_omega, -wmax, wmax, eps)
+    assert np.abs(dos - lor(mol.eig).sum(1)).max() < 1e-10 * dos.max()
+    d = 0.3
+    dos2, _ = o.dyson_dos(mol, n_omega, -wmax, wmax, eps, Sigma_x=d * np.eye(mol.n_orb))
+    assert np.abs(dos2 - lor(mol.eig + d).sum(1)).max() < 1e-10 * dos2.max()
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((mol.n_orb, mol.n_orb))
+    M = M + M.T
+    dos3, G3 = o.dyson_dos(mol, n_omega, -wmax, wmax, eps, Sigma_x=M, Vxc=M)
+    assert np.abs(G3 - G).max() <= 1e-12 * np.abs(G).max()
+    # G0 in the orbital basis is X diag(1/(w - E + i eps)) X^T
+    j = 77
+    ref = (mol.X / (om[j] + 1j * eps - mol.eig)[None, :]) @ mol.X.T
+    assert np.abs(G[j] - ref).max() <= 1e-12 * np.abs(ref).max()
