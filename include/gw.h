@@ -243,6 +243,24 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
                          const void *W, void *stream, double *sigma_out, void *Sigma_out,
                          double *Sigma_x_out, gw_report *rep);
 
+/* Dyson's equation and the density of states (Section 2 eq. Dyson with the
+ * V_xc replacement and the DOS definition; Section 3 eq. tensorform-dyson),
+ * for every point of the mesh g, in the orbital basis of m (orthonormal, S = 1):
+ *   G(omega_j + i eps) = [(omega_j + i eps) 1 - H_KS - Sigma_x - Sigma_c(omega_j) + V_xc]^{-1},
+ *   H_KS = X diag(eig) X^T,  dos[j] = -(1/pi) Im tr G(omega_j + i eps).
+ *   Sigma_c: DEVICE complex128 [n_omega][n_orb][n_orb] (gw_self_energy's
+ *     Sigma_out on the same mesh) or NULL (no correlation part).
+ *   Sigma_x, Vxc: DEVICE double [n_orb][n_orb] or NULL (zero); V_xc is the
+ *     DFT exchange-correlation potential that the self-energy replaces.
+ *   dos_out: DEVICE double [n_omega].
+ *   G_out: DEVICE complex128 [n_omega][n_orb][n_orb] or NULL.
+ *   rep: HOST or NULL: n_solved = n_omega.
+ * One batched LU and solve per frequency (no mirror: G(-omega) is not the
+ * conjugate of G(omega)).  Errors: GW_E_INVALID, GW_E_OOM, GW_E_DEVICE. */
+gw_status gw_dyson_dos(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const void *Sigma_c,
+                       const double *Sigma_x, const double *Vxc, void *stream, double *dos_out,
+                       void *G_out, gw_report *rep);
+
 /* Step 4: W(omega_j) = (1 - v chi0(omega_j))^{-1} v for every mesh point
  * (Section 2 eq. Coulombscreening).  Only j = 0 and j >= n_omega/2 are
  * factorised; W(omega_{n-j}) = conj W(omega_j) fills the rest (retarded

@@ -997,6 +997,70 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
     return GW_OK;
 }
 
+gw_status gw_dyson_dos(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const void *Sigma_c,
+                       const double *Sigma_x, const double *Vxc, void *stream, double *dos_out, void *G_out,
+                       gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    if (!dos_out) return fail(ctx, GW_E_INVALID, "dos_out is NULL");
+    int kbits = 0;
+    gw_status s = check_grid(ctx, g, &kbits);
+    if (s != GW_OK) return s;
+    HostMol h;
+    s = check_molecule(ctx, m, st, &h);
+    if (s != GW_OK) return s;
+    const int n = m->n_orb, N = g->n_omega;
+    const int64_t nn = (int64_t)n * n;
+    const double d = (g->omega_max - g->omega_min) / N;
+    void *q;
+    double *Xe, *Xt, *H, *Hs, *ones;
+#define GW_WS(name, bytes, dst)                                   \
+    do {                                                          \
+        if ((s = ws(ctx, name, (bytes), &q)) != GW_OK) return s;  \
+        dst = (decltype(dst))q;                                   \
+    } while (0)
+    GW_WS("d_Xe", sizeof(double) * nn, Xe);
+    GW_WS("d_Xt", sizeof(double) * nn, Xt);
+    GW_WS("d_H", sizeof(double) * nn, H);
+    GW_WS("d_Hs", sizeof(double) * nn, Hs);
+    GW_WS("d_ones", sizeof(double) * n, ones);
+    gwp::SolvePlan p;
+    s = gwp::solve_plan(ctx, n, N, false, "d_", &p);
+    if (s != GW_OK) return s;
+    zdbl *Gws = nullptr;
+    if (!G_out) GW_WS("d_G", sizeof(zdbl) * (size_t)p.nbmax * nn, Gws);
+#undef GW_WS
+    // H_KS = X diag(E) X^T (orthonormal orbitals), then the static part
+    // H_KS + Sigma_x - V_xc
+    GW_HIP(ctx, gwk::launch_scale_cols(st, n, m->X, m->eig, Xe));
+    GW_HIP(ctx, gwk::launch_transpose_d(st, n, n, m->X, Xt));
+    GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, Xe, n, 0, Xt, n, 0, 0.0, H, n, 0, 1));
+    GW_HIP(ctx, gwk::launch_static_part(st, nn, H, Sigma_x, Vxc, Hs));
+    GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)ones, n, 0x3FF0000000000000ull));  // 1.0
+    gwp::SolveWs &w = p.w;
+    for (int j0 = 0; j0 < N; j0 += p.nbmax) {
+        const int nb = std::min(p.nbmax, N - j0);
+        zdbl *G = G_out ? (zdbl *)G_out + (int64_t)j0 * nn : Gws;
+        GW_HIP(ctx, gwk::launch_dyson_form(st, n, j0, nb, g->omega_min, d, g->eps, Hs, (const zdbl *)Sigma_c, w.A));
+        GW_HIP(ctx, gwk::launch_fill_u32(st, (uint32_t *)w.info, nb, 0u));
+        GW_HIP(ctx, gwk::getrf_batched<zdbl>(st, n, w.A, nn, w.ipiv, (zdbl *)w.Li, (zdbl *)w.Ui, (zdbl *)w.scratch,
+                                             w.info, nb));
+        GW_HIP(ctx, gwk::launch_perm(st, n, w.ipiv, w.perm, nb));
+        GW_HIP(ctx, gwk::launch_init_rhs_perm(st, n, ones, 1, w.perm, G, nn, nb));  // P 1
+        GW_HIP(ctx, gwk::getrs_batched<zdbl>(st, n, n, w.A, nn, w.ipiv, (const zdbl *)w.Li, (const zdbl *)w.Ui, G,
+                                             nn, nb, false));
+        GW_HIP(ctx, gwk::launch_trace_dos(st, n, j0, nb, G, nn, dos_out));
+    }
+    if (rep) {
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_solved = N;
+    }
+    return GW_OK;
+}
+
 gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, const void *chi0, int32_t n_omega,
                      gw_precision prec, double tol, void *stream, void *W_out, gw_report *rep) {
     if (!ctx) return GW_E_INVALID;

@@ -172,6 +172,15 @@ hipError_t launch_pack_upper(hipStream_t st, int n, const double *src, double *d
 // Kp[j][m] = 1/(w_j - m d + i eps), Km[j][m] = 1/(w_j + m d + i eps), w_j = w0 + j d.
 hipError_t launch_cauchy_pm(hipStream_t st, int n_om, int M, double w0, double d, double eps, zdbl *Kp, zdbl *Km);
 hipError_t launch_scale_copy(hipStream_t st, int64_t n, double alpha, const double *src, double *dst);
+// Dyson's equation: Xe = X diag(eig); Hs = H + Sx - Vxc (null terms skipped);
+// A[b] = (w_{j0+b} + i eps) 1 - Hs - Sc[j0+b] (Sc may be null), w_j = w0 + j d;
+// dos[j0+b] = -(1/pi) Im tr G[b].
+hipError_t launch_scale_cols(hipStream_t st, int n, const double *X, const double *eig, double *Xe);
+hipError_t launch_static_part(hipStream_t st, int64_t nn, const double *H, const double *Sx, const double *Vxc,
+                              double *Hs);
+hipError_t launch_dyson_form(hipStream_t st, int n, int j0, int nb, double w0, double d, double eps, const double *Hs,
+                             const zdbl *Sc, zdbl *A);
+hipError_t launch_trace_dos(hipStream_t st, int n, int j0, int nb, const zdbl *G, int64_t sG, double *dos);
 // S+-[2 qq (+1)][a][b] += sum over the listed block pairs of
 // sum_{mu nu} gammahat^{mu nu} (V_mu rho+-(t) V_nu)^{ab} (and the transpose for
 // B1 < B2), time points q0 .. q0 + nq - 1.  Rm == nullptr: one density only.

@@ -51,6 +51,62 @@ __global__ void k_scale_copy(int64_t n, double alpha, const double *__restrict__
         dst[i] = alpha * src[i];
 }
 
+// Xe[a][E] = X[a][E] eig[E]
+__global__ void k_scale_cols(int n, const double *__restrict__ X, const double *__restrict__ eig,
+                             double *__restrict__ Xe) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    Xe[idx] = X[idx] * eig[idx % n];
+}
+
+// Hs = H + Sx - Vxc (either may be null)
+__global__ void k_static_part(int64_t nn, const double *__restrict__ H, const double *__restrict__ Sx,
+                              const double *__restrict__ Vxc, double *__restrict__ Hs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    double h = H[i];
+    if (Sx) h += Sx[i];
+    if (Vxc) h -= Vxc[i];
+    Hs[i] = h;
+}
+
+// A[b] = (w_{j0+b} + i eps) 1 - Hs - Sigma_c[j0+b]   (Sigma_c may be null)
+__global__ void k_dyson_form(int n, int j0, double w0, double d, double eps, const double *__restrict__ Hs,
+                             const zdbl *__restrict__ Sc, zdbl *__restrict__ A) {
+    const int64_t nn = (int64_t)n * n;
+    const int b = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn) return;
+    const int r = (int)(i / n), c = (int)(i % n);
+    zdbl v{-Hs[i], 0.0};
+    if (r == c) {
+        v.re += w0 + (j0 + b) * d;
+        v.im += eps;
+    }
+    if (Sc) {
+        const zdbl s = Sc[(int64_t)(j0 + b) * nn + i];
+        v.re -= s.re;
+        v.im -= s.im;
+    }
+    A[(int64_t)b * nn + i] = v;
+}
+
+// dos[j0 + b] = -(1/pi) Im tr G[b]
+__global__ __launch_bounds__(256) void k_trace_dos(int n, int j0, const zdbl *__restrict__ G, int64_t sG,
+                                                   double *__restrict__ dos) {
+    __shared__ double red[256];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += G[(int64_t)b * sG + (int64_t)i * n + i].im;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dos[j0 + b] = -red[0] / 3.14159265358979323846;
+}
+
 constexpr int SO = TIME_MAX_ORB;
 constexpr int SP = SO + 1;
 
@@ -245,6 +301,32 @@ __global__ __launch_bounds__(256) void k_sigma_contract(
 }
 
 }  // namespace
+
+hipError_t launch_scale_cols(hipStream_t st, int n, const double *X, const double *eig, double *Xe) {
+    const int64_t nn = (int64_t)n * n;
+    hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, n, X, eig, Xe);
+    return hipGetLastError();
+}
+
+hipError_t launch_static_part(hipStream_t st, int64_t nn, const double *H, const double *Sx, const double *Vxc,
+                              double *Hs) {
+    hipLaunchKernelGGL(k_static_part, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, nn, H, Sx, Vxc, Hs);
+    return hipGetLastError();
+}
+
+hipError_t launch_dyson_form(hipStream_t st, int n, int j0, int nb, double w0, double d, double eps, const double *Hs,
+                             const zdbl *Sc, zdbl *A) {
+    const int64_t nn = (int64_t)n * n;
+    ProfScope ps(st, "dyson_form", 0.0, 16.0 * 2.0 * nb * (double)nn);
+    hipLaunchKernelGGL(k_dyson_form, dim3((unsigned)((nn + 255) / 256), (unsigned)nb), dim3(256), 0, st, n, j0, w0,
+                       d, eps, Hs, Sc, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_dos(hipStream_t st, int n, int j0, int nb, const zdbl *G, int64_t sG, double *dos) {
+    hipLaunchKernelGGL(k_trace_dos, dim3((unsigned)nb), dim3(256), 0, st, n, j0, G, sG, dos);
+    return hipGetLastError();
+}
 
 hipError_t launch_w_spectral(hipStream_t st, int n, int n_sb, int j0, double domega, const zdbl *W, double *gam) {
     if (n_sb <= 0) return hipSuccess;

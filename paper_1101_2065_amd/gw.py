@@ -82,6 +82,8 @@ _SIGS = {
                                           ctypes.POINTER(gw_report)]),
     "gw_self_energy": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P, _P, _P,
                                       _P, ctypes.POINTER(gw_report)]),
+    "gw_dyson_dos": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid), _P, _P, _P, _P, _P,
+                                    _P, ctypes.POINTER(gw_report)]),
     "gw_solve_W": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
@@ -202,6 +204,15 @@ class Context:
                                 _stream_handle(stream), _ptr(sigma_out), _ptr(Sigma_out), _ptr(Sigma_x_out),
                                 ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_self_energy")
+        return rep
+
+    def dyson_dos(self, mol: "gw_molecule", grid: "gw_grid", dos_out, Sigma_c=None, Sigma_x=None, Vxc=None,
+                  G_out=None, stream=None, report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_dyson_dos(self.h, ctypes.byref(mol), ctypes.byref(grid), _ptr(Sigma_c), _ptr(Sigma_x), _ptr(Vxc),
+                              _stream_handle(stream), _ptr(dos_out), _ptr(G_out),
+                              ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_dyson_dos")
         return rep
 
     def solve_W(self, v, n: int, chi0, n_omega: int, W_out, prec: int = GW_FP64, tol: float = 1e-7,

@@ -152,3 +152,54 @@ def test_self_energy_errors(gpu):
     with pytest.raises(gw.GwError) as e:  # energies not from the Fermi level
         ctx.self_energy(gw.DeviceMolecule(shifted).struct, _g(gw, g), W, S)
     assert e.value.status == gw.GW_E_INVALID
+
+
+def test_dyson_dos_without_self_energy(gpu):
+    """No self-energy: G = X diag(1/(omega - E + i eps)) X^T and the DOS is the
+    sum of Lorentzians at the levels (closed form)."""
+    gw, ctx, torch = gpu
+    mol = gs.make_config(0)
+    g = _mesh(128, 4.0)
+    dm = gw.DeviceMolecule(mol)
+    dos = torch.full((g.n_omega,), float("nan"), dtype=torch.float64, device="cuda")
+    G = torch.empty((g.n_omega, mol.n_orb, mol.n_orb), dtype=torch.complex128, device="cuda")
+    ctx.dyson_dos(dm.struct, _g(gw, g), dos, G_out=G)
+    torch.cuda.synchronize()
+    om = g.omegas()
+    lor = (g.eps / np.pi) / ((om[:, None] - mol.eig[None, :]) ** 2 + g.eps ** 2)
+    d = dos.cpu().numpy()
+    assert np.abs(d - lor.sum(1)).max() <= 1e-12 * d.max()
+    Gh = G.cpu().numpy()
+    for j in (0, 40, 77, g.n_omega - 1):
+        ref = (mol.X / (om[j] + 1j * g.eps - mol.eig)[None, :]) @ mol.X.T
+        assert _rel(Gh[j], ref) < 1e-12
+
+
+def test_dyson_dos_end_to_end(gpu):
+    """chi0 -> W -> Sigma -> G and the DOS with a V_xc, against the oracle chain."""
+    gw, ctx, torch = gpu
+    mol = gs.chain_molecule(3, 5)
+    g = _mesh(64, 4.0)
+    dm = gw.DeviceMolecule(mol)
+    n, no, N = mol.n_prod, mol.n_orb, g.n_omega
+    chi = torch.empty((N, n, n), dtype=torch.complex128, device="cuda")
+    W = torch.empty_like(chi)
+    ctx.build_chi0(dm.struct, _g(gw, g), chi)
+    ctx.solve_W(dm.v, n, chi, N, W)
+    S = torch.empty((N, no, no), dtype=torch.complex128, device="cuda")
+    Sx = torch.empty((no, no), dtype=torch.float64, device="cuda")
+    ctx.self_energy(dm.struct, _g(gw, g), W, S, v=dm.v, Sigma_x_out=Sx)
+    rng = np.random.default_rng(7)
+    M = 0.05 * rng.standard_normal((no, no))
+    Vxc = M + M.T
+    Vd = torch.from_numpy(Vxc).to("cuda")
+    dos = torch.empty((N,), dtype=torch.float64, device="cuda")
+    G = torch.empty((N, no, no), dtype=torch.complex128, device="cuda")
+    rep = ctx.dyson_dos(dm.struct, _g(gw, g), dos, Sigma_c=S, Sigma_x=Sx, Vxc=Vd, G_out=G)
+    torch.cuda.synchronize()
+    assert rep.n_solved == N
+    _, _, Sref, Sxref = _oracle(mol, g, levels=True)
+    dref, Gref = o.dyson_dos(mol, N, g.omega_min, g.omega_max, g.eps, Sigma_c=Sref, Sigma_x=Sxref, Vxc=Vxc)
+    e = (_rel(dos.cpu().numpy(), dref), _rel(G.cpu().numpy(), Gref))
+    _say("Dyson: dos rel %.2e, G rel %.2e" % e)
+    assert e[0] < 1e-10 and e[1] < 1e-10
