@@ -519,8 +519,10 @@ def run_time_route(args, gw, gs, torch):
 def run_self_energy(args, gw, gs, torch):
     """The 2000-product molecule on the 1024-point mesh carried through to the
     GW self-energy: one step = chi0 + W (FP64, all points) + sigma+- by the
-    time-by-time convolution + Sigma on all points + exchange.  value =
-    Sigma(omega) points per second for the whole step."""
+    time-by-time convolution + Sigma on all points + exchange + Dyson's
+    equation and the DOS on all points (V_xc = 0: the synthetic orbitals carry
+    no DFT potential; the arithmetic is the same).  value = Sigma(omega)
+    points per second for the whole step."""
     log("generating molecule")
     mol = gs.truncate_products(gs.make_config(1), N_PROD)
     grid = gs.config_grid(1)
@@ -533,12 +535,13 @@ def run_self_energy(args, gw, gs, torch):
     W = torch.empty_like(chi)
     S = torch.empty((N, no, no), dtype=torch.complex128, device=dev)
     Sx = torch.empty((no, no), dtype=torch.float64, device=dev)
+    dos = torch.empty((N,), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     ts, roof = [], None
     for it in range(args.warmup + args.steps):
         timed = it >= args.warmup
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         t0 = time.perf_counter()
         ev[0].record(stream)
         ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
@@ -549,22 +552,24 @@ def run_self_energy(args, gw, gs, torch):
             ctx.profile_begin()
         ctx.self_energy(dm.struct, g, W, S, v=dm.v, Sigma_x_out=Sx, stream=stream, report=False)
         ev[3].record(stream)
+        ctx.dyson_dos(dm.struct, g, dos, Sigma_c=S, Sigma_x=Sx, stream=stream, report=False)
+        ev[4].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        parts = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(3)]
+        parts = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(4)]
         if timed and roof is None:
             roof = kernel_roofline(ctx.profile_read())
             ctx.profile_end()
-        log("self-energy step %d: chi0 %.3fs W %.3fs Sigma %.3fs wall %.3fs" % (it, *parts, wall))
+        log("self-energy step %d: chi0 %.3fs W %.3fs Sigma %.3fs Dyson+DOS %.3fs wall %.3fs" % (it, *parts, wall))
         if timed:
             ts.append((wall, *parts))
     a = np.median(np.array(ts), axis=0)
     out = base_record(args, "Sigma(omega)/s, 2000 products, 1024 points (chi0, W, sigma by time-domain convolution, "
-                            "Sigma, exchange)", N / a[0], "Sigma(omega)/s", a[0], "f64",
+                            "Sigma, exchange, Dyson + DOS)", N / a[0], "Sigma(omega)/s", a[0], "f64",
                       {"workload": "chain40_nprod2000_nomega1024_self_energy", "n_prod": n, "n_orb": no,
                        "n_omega": N, "parallelism": "none (1 GPU)"})
-    out["phases_s"] = {"chi0": a[1], "W": a[2], "self_energy": a[3]}
-    out["roofline_self_energy_phase"] = roof
+    out["phases_s"] = {"chi0": a[1], "W": a[2], "self_energy": a[3], "dyson_dos": a[4]}
+    out["roofline_sigma_dyson_phases"] = roof
     ctx.close()
     return out
 

@@ -255,8 +255,12 @@ gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, con
  *   dos_out: DEVICE double [n_omega].
  *   G_out: DEVICE complex128 [n_omega][n_orb][n_orb] or NULL.
  *   rep: HOST or NULL: n_solved = n_omega.
+ *   g: the mesh Sigma_c was computed on (as for gw_build_chi0).
  * One batched LU and solve per frequency (no mirror: G(-omega) is not the
- * conjugate of G(omega)).  Errors: GW_E_INVALID, GW_E_OOM, GW_E_DEVICE. */
+ * conjugate of G(omega)).  With Im Sigma_c negative semidefinite (as the
+ * self-energy is) and eps > 0 the matrix is never singular; a Sigma_c that
+ * makes it singular gives non-finite entries, not an error.
+ * Errors: GW_E_INVALID, GW_E_OOM, GW_E_DEVICE. */
 gw_status gw_dyson_dos(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const void *Sigma_c,
                        const double *Sigma_x, const double *Vxc, void *stream, double *dos_out,
                        void *G_out, gw_report *rep);

@@ -203,3 +203,32 @@ def test_dyson_dos_end_to_end(gpu):
     e = (_rel(dos.cpu().numpy(), dref), _rel(G.cpu().numpy(), Gref))
     _say("Dyson: dos rel %.2e, G rel %.2e" % e)
     assert e[0] < 1e-10 and e[1] < 1e-10
+
+
+def test_dyson_dos_without_G_out_and_errors(gpu):
+    """G_out is optional (the DOS is the same without it); a missing DOS
+    output or a mesh the library does not take is refused."""
+    gw, ctx, torch = gpu
+    mol = gs.make_config(0)
+    g = _mesh(64, 4.0)
+    dm = gw.DeviceMolecule(mol)
+    no, N = mol.n_orb, g.n_omega
+    rng = np.random.default_rng(3)
+    Sc = (0.05 * rng.standard_normal((N, no, no)) - 0.05j * np.abs(rng.standard_normal((N, no, no))))
+    Sc = 0.5 * (Sc + np.transpose(Sc, (0, 2, 1)))
+    Sd = torch.from_numpy(Sc).to("cuda")
+    d1 = torch.empty((N,), dtype=torch.float64, device="cuda")
+    d2 = torch.empty_like(d1)
+    G = torch.empty((N, no, no), dtype=torch.complex128, device="cuda")
+    ctx.dyson_dos(dm.struct, _g(gw, g), d1, Sigma_c=Sd, G_out=G)
+    ctx.dyson_dos(dm.struct, _g(gw, g), d2, Sigma_c=Sd)
+    torch.cuda.synchronize()
+    assert torch.equal(d1, d2)
+    dref, _ = o.dyson_dos(mol, N, g.omega_min, g.omega_max, g.eps, Sigma_c=Sc)
+    assert _rel(d1.cpu().numpy(), dref) < 1e-12
+    with pytest.raises(gw.GwError) as e:
+        ctx.dyson_dos(dm.struct, _g(gw, g), None)
+    assert e.value.status == gw.GW_E_INVALID
+    with pytest.raises(gw.GwError) as e:
+        ctx.dyson_dos(dm.struct, _g(gw, gs.Grid(48, -1.0, 1.0, 0.1)), d1)
+    assert e.value.status == gw.GW_E_INVALID
