@@ -741,3 +741,29 @@ def test_dyson_dos_closed_forms():
     j = 77
     ref = (mol.X / (om[j] + 1j * eps - mol.eig)[None, :]) @ mol.X.T
     assert np.abs(G[j] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_dyson_dos_diagonal_self_energy():
+    """A self-energy diagonal in the Kohn-Sham eigenbasis, Sigma_c(w) =
+    X diag(s(w)) X^T, gives G = X diag(1/(w + i eps - E - s(w))) X^T level by
+    level (fixes the frequency index and the sign of Sigma_c), and V_xc = c 1
+    moves every level by -c (fixes the sign of V_xc)."""
+    mol = gs.make_config(0)
+    n_omega, wmax, eps = 64, 4.0, 0.05
+    om = -wmax + (2 * wmax / n_omega) * np.arange(n_omega)
+    rng = np.random.default_rng(5)
+    # a causal single-pole self-energy per level: s_a(w) = g_a / (w - p_a + i eta)
+    g = rng.uniform(0.01, 0.1, mol.n_orb)
+    p = rng.uniform(-2.0, 2.0, mol.n_orb)
+    s = g[None, :] / (om[:, None] - p[None, :] + 0.2j)
+    Sc = np.einsum("ia,wa,ja->wij", mol.X, s, mol.X)
+    dos, G = o.dyson_dos(mol, n_omega, -wmax, wmax, eps, Sigma_c=Sc)
+    for j in (0, 13, 40, n_omega - 1):
+        ref = (mol.X / (om[j] + 1j * eps - mol.eig - s[j])[None, :]) @ mol.X.T
+        assert np.abs(G[j] - ref).max() <= 1e-12 * np.abs(ref).max()
+    lev = -(1.0 / math.pi) * (1.0 / (om[:, None] + 1j * eps - mol.eig[None, :] - s)).imag.sum(1)
+    assert np.abs(dos - lev).max() <= 1e-12 * np.abs(lev).max()
+    c = 0.25
+    lor = lambda E: (eps / math.pi) / ((om[:, None] - E[None, :]) ** 2 + eps ** 2)
+    dos2, _ = o.dyson_dos(mol, n_omega, -wmax, wmax, eps, Vxc=c * np.eye(mol.n_orb))
+    assert np.abs(dos2 - lor(mol.eig - c).sum(1)).max() < 1e-10 * dos2.max()
