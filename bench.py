@@ -179,7 +179,7 @@ def kernel_roofline(stats):
         achieved = d["bytes"] / sec / 1e9
         rec = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
                "bytes_per_launch": d["bytes"] / d["launches"]}
-    rec.update({"traffic": stored_traffic() if d["name"] == "zgemm_128x64" else None,
+    rec.update({"traffic": stored_traffic() if d["name"] == TRAFFIC_CLASS else None,
                 "kernel": d["name"], "launches": d["launches"],
                 "avg_launch_us": d["ms"] * 1e3 / d["launches"]})
     rec["all_kernels"] = {s["name"]: {"launches": s["launches"], "ms": round(s["ms"], 3),
@@ -737,7 +737,8 @@ def run_c4(args, gw, gs, torch):
 
 # ---------------------------------------------------------------------- profiles
 # Kernel whose HBM traffic the roofline reports, and the source it is built from.
-TRAFFIC_KERNEL = "k_gemm<double, true, true, 4, 2, 8>"
+TRAFFIC_KERNEL = "k_gemm<double, true, true, 4, 1, 8, 4>"
+TRAFFIC_CLASS = "zgemm_128x32"  # the same kernel in the library's live timing
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
 COPY_BYTES = 1 << 30
 
@@ -762,7 +763,7 @@ def stored_traffic():
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("kernel") != TRAFFIC_KERNEL:
         return None
     return t.get("bytes_per_launch")
 

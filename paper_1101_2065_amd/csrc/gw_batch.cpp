@@ -56,10 +56,11 @@ struct gw_batch {
 namespace {
 
 // ------------------------------------------------------------------ autotuner
-// Table: size class (n rounded up to a multiple of 256) and precision -> GEMM
-// tile (0: 64x64 K16, 1: 128x64 K8).  Measured on the trailing-update shape
-// (n x n x 256, complex) the first time a class is seen, kept in memory and in
-// a JSON file ($GW_TUNE_FILE, default $HOME/.cache/gw_tune.json).
+// Table: size class (n rounded up to a multiple of 256) -> tile of the long
+// complex FP64 products (0: 64x64 K16, 1: 128x64 K8, 2: 64x32 K8, 3: 128x32
+// K8).  Measured on the trailing-update shape (n x n x 256, complex) the first
+// time a class is seen, kept in memory and in a JSON file ($GW_TUNE_FILE,
+// default $HOME/.cache/gw_tune.json).
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
@@ -115,15 +116,15 @@ gw_status tune_tile(gw_ctx *ctx, int n, hipStream_t st, int *tile) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load();
     const int cls = ((n + 255) / 256) * 256;
-    const std::string key = "zgemm_n" + std::to_string(cls);
+    const std::string key = "zgemm4_n" + std::to_string(cls);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
         *tile = it->second;
         return GW_OK;
     }
-    if (cls < 128) {
-        *tile = 0;
-        g_tune[key] = 0;
+    if (cls < 256) {  // no long products at this size
+        *tile = 3;
+        g_tune[key] = 3;
         return GW_OK;
     }
     // operands: C (cls x cls), A (cls x 256), B (256 x cls), batch 4
@@ -138,8 +139,8 @@ gw_status tune_tile(gw_ctx *ctx, int n, hipStream_t st, int *tile) {
     GW_HIP(ctx, hipEventCreate(&e0));
     GW_HIP(ctx, hipEventCreate(&e1));
     float best = 1e30f;
-    int best_t = 0;
-    for (int t = 0; t < 2; ++t) {
+    int best_t = 3;
+    for (int t = 3; t >= 0; --t) {
         gwp::set_thread_gemm_tile(t);
         float ms = 0;
         for (int rep = 0; rep < 2; ++rep) {

@@ -5,10 +5,15 @@
 //
 // Complex numbers are interleaved {re, im}.  A complex product is four real
 // MFMA products (no 3M trick: the FP64 residual must keep its accuracy).
-// Tiles: 256-thread workgroups, four 64-wide waves in 2x2; 64x64 outputs
-// (each wave 2x2 MFMA 16x16 blocks, K steps of 16) or 128x64 (4x2 blocks per
-// wave, K steps of 8).  K is staged through a double-buffered LDS tile, the
-// next step prefetched into registers.
+// Tiles: 256-thread workgroups, four 64-wide waves in 2x2.  An FP64 MFMA
+// 16x16x4 occupies the matrix pipe for many cycles, so the complex FP64
+// products are latency-bound by the LDS and global loads around it unless
+// several workgroups share a CU: they use narrow tiles at four waves per SIMD,
+// 128x32 (each wave 4x1 MFMA 16x16 blocks) for long products and 64x32 (2x1)
+// for the thin ones (K = 64 updates inside a block, 64-row products).  The
+// real-times-complex and FP32 products keep 64x64 (K steps of 16) and 128x64
+// (K steps of 8) at two waves per SIMD.  K is staged through a
+// double-buffered LDS tile, the next step prefetched into registers.
 #include "gw_internal.h"
 #include "gw_prof.h"
 
@@ -45,8 +50,8 @@ struct Mfma<float> {
 // Workgroup = 256 threads = 2x2 waves; a wave owns WM x WN MFMA blocks of
 // 16x16, so the workgroup tile is (32 WM) x (32 WN); K advances BK per
 // LDS stage.
-template <typename T, bool AC, bool BC, int WM, int WN, int BK>
-__global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
                                                  int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
                                                  T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
                                                  int64_t sC32) {
@@ -399,23 +404,33 @@ __global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *
     if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
 }
 
-// < 0: choose by shape; 0: 64x64 K16; 1: 128x64 K8.  Per host thread, so the
-// batched driver can record each molecule with its tuned tile.
+// Tile of the long complex FP64 products (M >= 256, K >= 128): < 0 the
+// default (128x32); 0: 64x64 K16; 1: 128x64 K8; 2: 64x32 K8; 3: 128x32 K8.
+// Per host thread, so the batched driver can record each molecule with its
+// tuned tile.  Thin complex FP64 products always take 64x32.
 thread_local int g_gemm_tile = -1;
+
+const char *const kZgemmName[4] = {"zgemm_64x64", "zgemm_128x64", "zgemm_64x32", "zgemm_128x32"};
 
 template <typename T, bool AC, bool BC>
 hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *A, int64_t lda, int64_t sA,
                          const T *B, int64_t ldb, int64_t sB, T beta, T *C, int64_t ldc, int64_t sC, int batch,
                          int add_eye = 0, float *C32 = nullptr, int64_t sC32 = 0) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-    int tile = g_gemm_tile;
-    if (tile < 0) tile = (AC && BC && M >= 128 && K >= 64) ? 1 : 0;
+    constexpr bool Z64 = AC && BC && sizeof(T) == 8;
+    int tile;
+    if constexpr (Z64) {
+        const bool big = M >= 256 && K >= 128;
+        tile = big ? (g_gemm_tile >= 0 && g_gemm_tile <= 3 ? g_gemm_tile : 3) : 2;
+    } else {
+        tile = (AC && BC && M >= 128 && K >= 64) ? 1 : 0;
+    }
     ProfSink *prof = g_prof;
     const char *cls = nullptr;
     double flops = 0, bytes = 0;
     if (prof) {
         const bool dbl = sizeof(T) == 8;
-        if (AC && BC) cls = dbl ? (tile == 1 ? "zgemm_128x64" : "zgemm_64x64") : (tile == 1 ? "cgemm_128x64" : "cgemm_64x64");
+        if (AC && BC) cls = dbl ? kZgemmName[tile] : (tile == 1 ? "cgemm_128x64" : "cgemm_64x64");
         else if (BC) cls = add_eye ? "formA" : "dzgemm";
         else if (AC) cls = "zdgemm";
         else cls = "dgemm";
@@ -425,15 +440,20 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
                 (double)M * N * ec * batch * (beta != T(0) ? 2 : 1);
     }
     ProfScope ps(st, cls ? cls : "", flops, bytes);
-    if (tile == 1) {
-        dim3 grid((N + 63) / 64, (M + 127) / 128, batch);
-        hipLaunchKernelGGL((k_gemm<T, AC, BC, 4, 2, 8>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb,
-                           sB, beta, C, ldc, sC, add_eye, C32, sC32);
+#define GW_GEMM(WM, WN, BK, OCC)                                                                                   \
+    hipLaunchKernelGGL((k_gemm<T, AC, BC, WM, WN, BK, OCC>), dim3((N + 32 * WN - 1) / (32 * WN),                   \
+                       (M + 32 * WM - 1) / (32 * WM), batch), dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, \
+                       sB, beta, C, ldc, sC, add_eye, C32, sC32)
+    if constexpr (Z64) {
+        if (tile == 3) GW_GEMM(4, 1, 8, 4);
+        else if (tile == 2) GW_GEMM(2, 1, 8, 4);
+        else if (tile == 1) GW_GEMM(4, 2, 8, 2);
+        else GW_GEMM(2, 2, 16, 2);
     } else {
-        dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
-        hipLaunchKernelGGL((k_gemm<T, AC, BC, 2, 2, 16>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb,
-                           sB, beta, C, ldc, sC, add_eye, C32, sC32);
+        if (tile == 1) GW_GEMM(4, 2, 8, 2);
+        else GW_GEMM(2, 2, 16, 2);
     }
+#undef GW_GEMM
     return hipGetLastError();
 }
 
