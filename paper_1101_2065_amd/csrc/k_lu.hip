@@ -232,31 +232,87 @@ __global__ __launch_bounds__(512) void k_getf2(int n, int kb, int w, Cx<T> *A, i
 // Left-looking panel factorisation with the active rows in registers.
 // 512 threads; thread t owns panel rows i = t + 512 r (r < R), so the panel
 // height m = n - kb must be at most 512 R.  The 64 columns are processed in
-// blocks of 4: (1) the U rows of the block (rows < j0) by forward
-// substitution with the unit-lower L above it, one wave per column; (2) the
-// block's rows >= j0 loaded into registers and updated with
-// L[:, 0:j0] U[0:j0, block] (left-looking: the panel's L part is read once
-// per block instead of being rewritten after every column); (3) the block
+// chunks of BW (8 while R <= 4, else 4: registers): (1) the U rows of the
+// chunk (rows < j0) by forward substitution with the unit-lower L above it,
+// one wave per column, lane = row, each x_k broadcast from its lane once
+// final (the rows of L join an LDS copy as they become final); (2) the
+// chunk's rows >= j0 loaded into registers and updated with
+// L[:, 0:j0] U[0:j0, chunk] (left-looking: the panel's L part is read once
+// per chunk instead of being rewritten after every column); (3) the chunk
 // factorised column by column in registers (pivot = largest |re| + |im|,
-// ties to the lowest row; row exchanges applied at once to the other panel
-// columns in memory); (4) written back.  The diagonal-block inverses and the
-// composed row exchange list are produced as in k_getf2.
+// ties to the lowest row), its row exchanges composed and applied to the
+// other panel columns in memory once per chunk; (4) written back.  At the
+// end one wave composes all 64 exchanges into a (destination, source) list
+// and the inverses of the 64x64 unit-lower L11 and upper U11 are formed in
+// registers, eight columns per wave, lane = row.
 constexpr int GF_NT = 512;
 
-template <typename T, int R>
+__device__ inline double rlane(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k), hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline float rlane(float v, int k) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k)); }
+__device__ inline int rlane(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+
+// Composes the row exchanges (j, lp[j]), j in [jb, je), applied in order, into
+// (destination, source) pairs: after them, row dst holds what was row src.
+// Run by one whole wave; lane t keeps pair t in (rA, cA) and pair t + 64 in
+// (rB, cB).  Returns the number of pairs.
+__device__ inline int compose_swaps(const int *lp, int jb, int je, int lane, int &rA, int &cA, int &rB, int &cB) {
+    rA = cA = rB = cB = -1;
+    int nt = 0;
+    auto find = [&](int r) -> int {
+        const unsigned long long ma = __ballot(rA == r), mb = __ballot(rB == r);
+        if (ma) return __ffsll((long long)ma) - 1;
+        if (mb) return 64 + __ffsll((long long)mb) - 1;
+        return -1;
+    };
+    auto put = [&](int t, int r, int c) {
+        if (lane == (t & 63)) {
+            if (t < 64) {
+                rA = r;
+                cA = c;
+            } else {
+                rB = r;
+                cB = c;
+            }
+        }
+    };
+    for (int j = jb; j < je; ++j) {
+        const int r1 = j, r2 = lp[j];
+        if (r1 == r2) continue;
+        int i1 = find(r1);
+        if (i1 < 0) {
+            i1 = nt++;
+            put(i1, r1, r1);
+        }
+        int i2 = find(r2);
+        if (i2 < 0) {
+            i2 = nt++;
+            put(i2, r2, r2);
+        }
+        const int c1 = rlane(i1 < 64 ? cA : cB, i1 & 63), c2 = rlane(i2 < 64 ? cA : cB, i2 & 63);
+        put(i1, r1, c2);
+        put(i2, r2, c1);
+    }
+    return nt;
+}
+
+template <typename T, int R, int BW>
 __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A, int64_t sA, int32_t *ipiv,
-                                                 Cx<T> *Linv, Cx<T> *Uinv, int nblk, int32_t *swp, int32_t *info) {
-    constexpr int BW = 4;
-    __shared__ Cx<T> Ts[NB][NB];
-    __shared__ Cx<T> Xs[NB][NB];
+                                                  Cx<T> *Linv, Cx<T> *Uinv, int nblk, int32_t *swp, int32_t *info) {
+    constexpr int NW = GF_NT / 64;
+    static_assert(BW <= NW && NB % BW == 0, "one wave per substituted column");
+    __shared__ Cx<T> Ts[NB][NB + 1];  // the panel's top rows as they become final (padded: column reads)
     __shared__ Cx<T> Ux[NB][BW];
     __shared__ Cx<T> prow[BW];
     __shared__ Cx<T> xch[2][BW];
-    __shared__ T red_v[GF_NT / 64];
-    __shared__ int red_i[GF_NT / 64];
+    __shared__ T red_v[NW];
+    __shared__ int red_i[NW];
     __shared__ int lpiv[NB];
-    __shared__ int piv_s, zero_s;
-    __shared__ int rows[2 * NB], cont[2 * NB];
+    __shared__ int piv_s, zero_s, nsw_s;
+    __shared__ int sw_dst[2 * BW], sw_src[2 * BW];
     __shared__ Cx<T> dinv[NB];
 
     const int b = blockIdx.x;
@@ -272,43 +328,39 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
 
     for (int j0 = 0; j0 < w; j0 += BW) {
         const int bw = min(BW, w - j0);
-        // (1) U rows of the block: x_i = a_i - sum_{k<i} L_ik x_k, i < j0.  The
-        // unit-lower j0 x j0 corner of the panel and the block's rows < j0 are
-        // staged in LDS first (Ts is free until the inverses at the end), so
-        // the sequential substitution waits on LDS, not on memory.
+        // (1) U rows of the chunk: x_i = a_i - sum_{k<i} L_ik x_k for i < j0.  Rows
+        // [j0 - BW, j0) became final in the previous chunk and join the staged
+        // corner; lane i keeps a_i, and x_k is broadcast from lane k once final.
         if (j0 > 0) {
-            for (int idx = tid; idx < j0 * (j0 + BW); idx += GF_NT) {
-                const int i = idx / (j0 + BW), k = idx % (j0 + BW);
-                if (k < j0) Ts[i][k] = P[(int64_t)i * n + k];
-                else if (k - j0 < bw) Ux[i][k - j0] = P[(int64_t)i * n + k];
+            const int r0 = j0 - BW, nT = BW * j0, nU = j0 * bw;
+            for (int idx = tid; idx < nT + nU; idx += GF_NT) {
+                if (idx < nT) {
+                    const int i = r0 + idx / j0, k = idx % j0;
+                    Ts[i][k] = P[(int64_t)i * n + k];
+                } else {
+                    const int q = idx - nT, i = q / bw, c = q % bw;
+                    Ux[i][c] = P[(int64_t)i * n + j0 + c];
+                }
+            }
+            __syncthreads();
+            if (wave < bw) {
+                const int c = wave;
+                Cx<T> x = lane < j0 ? Ux[lane][c] : zero;
+#pragma unroll 4
+                for (int k = 0; k < j0 - 1; ++k) {
+                    const Cx<T> l = (lane > k && lane < j0) ? Ts[lane][k] : zero;
+                    const Cx<T> xk{rlane(x.re, k), rlane(x.im, k)};
+                    x.re -= l.re * xk.re - l.im * xk.im;
+                    x.im -= l.re * xk.im + l.im * xk.re;
+                }
+                if (lane < j0) {
+                    Ux[lane][c] = x;
+                    P[(int64_t)lane * n + j0 + c] = x;
+                }
             }
             __syncthreads();
         }
-        if (j0 > 0 && wave < bw) {
-            const int c = wave;
-            Cx<T> xl = zero;  // lane k keeps x_k
-            for (int i = 0; i < j0; ++i) {
-                T pr = 0, pi = 0;
-                if (lane < i) {
-                    const Cx<T> l = Ts[i][lane];
-                    pr = l.re * xl.re - l.im * xl.im;
-                    pi = l.re * xl.im + l.im * xl.re;
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    pr += __shfl_xor(pr, off);
-                    pi += __shfl_xor(pi, off);
-                }
-                const Cx<T> a = Ux[i][c];
-                const Cx<T> x{a.re - pr, a.im - pi};
-                if (lane == i) xl = x;
-                if (lane == 0) {
-                    Ux[i][c] = x;
-                    P[(int64_t)i * n + j0 + c] = x;
-                }
-            }
-        }
-        __syncthreads();
-        // (2) rows >= j0 of the block into registers, left-looking update
+        // (2) rows >= j0 of the chunk into registers, left-looking update
         Cx<T> a[R][BW];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -331,7 +383,8 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
                 }
             }
         }
-        // (3) factor the block column by column (c compile-time: a[][] stays in registers)
+        // (3) factor the chunk column by column; row exchanges happen in
+        // registers here and in memory (the other panel columns) once per chunk
 #pragma unroll
         for (int c = 0; c < BW; ++c) {
             if (c >= bw) break;
@@ -365,7 +418,7 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
             if (tid == 0) {
                 T bv = red_v[0];
                 int bx = red_i[0];
-                for (int q = 1; q < GF_NT / 64; ++q)
+                for (int q = 1; q < NW; ++q)
                     if (red_v[q] > bv || (red_v[q] == bv && red_i[q] < bx)) {
                         bv = red_v[q];
                         bx = red_i[q];
@@ -378,7 +431,6 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
             }
             __syncthreads();
             const int piv = piv_s;
-            // exchange rows j and piv of the block through LDS
             if (piv != j) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -389,14 +441,6 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
                     if (i == piv)
 #pragma unroll
                         for (int cc = 0; cc < BW; ++cc) xch[1][cc] = a[r][cc];
-                }
-                // the other panel columns, in memory
-                if (tid < w && (tid < j0 || tid >= j0 + bw)) {
-                    Cx<T> *p1 = P + (int64_t)j * n + tid;
-                    Cx<T> *p2 = P + (int64_t)piv * n + tid;
-                    const Cx<T> t = *p1;
-                    *p1 = *p2;
-                    *p2 = t;
                 }
                 __syncthreads();
 #pragma unroll
@@ -410,7 +454,6 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
                         for (int cc = 0; cc < BW; ++cc) a[r][cc] = xch[0][cc];
                 }
             }
-            // pivot row to LDS
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (tid + GF_NT * r == j)
@@ -437,7 +480,40 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
             }
             __syncthreads();
         }
-        // (4) write the block back
+        // the chunk's exchanges, composed, on the panel columns outside it
+        if (wave == 0) {
+            int rA, cA, rB, cB;
+            const int nt = compose_swaps(lpiv, j0, j0 + bw, lane, rA, cA, rB, cB);
+            if (lane < nt) {
+                sw_dst[lane] = rA;
+                sw_src[lane] = cA;
+            }
+            if (lane == 0) nsw_s = nt;
+        }
+        __syncthreads();
+        {
+            const int nt = nsw_s, oc = w - bw;  // columns [0, j0) and [j0 + bw, w)
+            constexpr int MAXP = (2 * BW * NB + GF_NT - 1) / GF_NT;
+            Cx<T> v[MAXP];
+#pragma unroll
+            for (int q = 0; q < MAXP; ++q) {
+                const int idx = tid + GF_NT * q;
+                if (idx < nt * oc) {
+                    const int t = idx / oc, cc = idx % oc, col = cc < j0 ? cc : cc + bw;
+                    v[q] = P[(int64_t)sw_src[t] * n + col];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < MAXP; ++q) {
+                const int idx = tid + GF_NT * q;
+                if (idx < nt * oc) {
+                    const int t = idx / oc, cc = idx % oc, col = cc < j0 ? cc : cc + bw;
+                    P[(int64_t)sw_dst[t] * n + col] = v[q];
+                }
+            }
+        }
+        // (4) the chunk back to memory
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = tid + GF_NT * r;
@@ -450,78 +526,65 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
     }
 
     if (tid < w) ipiv[kb + tid] = kb + lpiv[tid];
-    if (tid == 0) {
-        int nt = 0;
-        for (int j = 0; j < w; ++j) {
-            const int r1 = j, r2 = lpiv[j];
-            if (r1 == r2) continue;
-            int i1 = -1, i2 = -1;
-            for (int t = 0; t < nt; ++t) {
-                if (rows[t] == r1) i1 = t;
-                if (rows[t] == r2) i2 = t;
-            }
-            if (i1 < 0) {
-                rows[nt] = r1;
-                cont[nt] = r1;
-                i1 = nt++;
-            }
-            if (i2 < 0) {
-                rows[nt] = r2;
-                cont[nt] = r2;
-                i2 = nt++;
-            }
-            const int t = cont[i1];
-            cont[i1] = cont[i2];
-            cont[i2] = t;
+    // all of the panel's exchanges as one (destination, source) list
+    if (wave == 0) {
+        int rA, cA, rB, cB;
+        const int nt = compose_swaps(lpiv, 0, w, lane, rA, cA, rB, cB);
+        if (lane == 0) swp[0] = nt;
+        if (lane < nt) {
+            swp[1 + lane] = kb + rA;
+            swp[1 + 2 * NB + lane] = kb + cA;
         }
-        swp[0] = nt;
-        for (int t = 0; t < nt; ++t) {
-            swp[1 + t] = kb + rows[t];
-            swp[1 + 2 * NB + t] = kb + cont[t];
+        if (lane + 64 < nt) {
+            swp[1 + 64 + lane] = kb + rB;
+            swp[1 + 2 * NB + 64 + lane] = kb + cB;
         }
     }
+    // the factored 64 x 64 corner, zero padded, and the inverses of its unit
+    // lower and upper triangles, eight columns per wave with lane = row
     for (int idx = tid; idx < NB * NB; idx += GF_NT) {
         const int i = idx / NB, c = idx % NB;
         Ts[i][c] = (i < w && c < w) ? P[(int64_t)i * n + c] : zero;
-        Xs[i][c] = zero;
     }
     __syncthreads();
-    if (tid < w) {
-        const int c = tid;
-        Xs[c][c] = Cx<T>{T(1), T(0)};
-        for (int i = c + 1; i < w; ++i) {
-            T sr = 0, si = 0;
-            for (int k = c; k < i; ++k) {
-                const Cx<T> l = Ts[i][k], x = Xs[k][c];
-                sr += l.re * x.re - l.im * x.im;
-                si += l.re * x.im + l.im * x.re;
-            }
-            Xs[i][c] = Cx<T>{-sr, -si};
-        }
-    }
     if (tid < w) dinv[tid] = crcp(Ts[tid][tid]);
     __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += GF_NT) {
-        Linv[idx] = Xs[idx / NB][idx % NB];
-        Xs[idx / NB][idx % NB] = zero;
+    constexpr int CPW = NB / NW;
+    Cx<T> x[CPW];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+        const int c = wave * CPW + q;
+        x[q] = (lane == c && c < w) ? Cx<T>{T(1), T(0)} : zero;
     }
-    __syncthreads();
-    if (tid < w) {
-        const int c = tid;
-        Xs[c][c] = dinv[c];
-        for (int i = c - 1; i >= 0; --i) {
-            T sr = 0, si = 0;
-            for (int k = i + 1; k <= c; ++k) {
-                const Cx<T> u = Ts[i][k], x = Xs[k][c];
-                sr += u.re * x.re - u.im * x.im;
-                si += u.re * x.im + u.im * x.re;
-            }
-            const Cx<T> d = dinv[i];
-            Xs[i][c] = Cx<T>{-(sr * d.re - si * d.im), -(sr * d.im + si * d.re)};
+    for (int k = 0; k < w - 1; ++k) {
+        const Cx<T> l = (lane > k && lane < w) ? Ts[lane][k] : zero;
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+            const Cx<T> xk{rlane(x[q].re, k), rlane(x[q].im, k)};
+            x[q].re -= l.re * xk.re - l.im * xk.im;
+            x[q].im -= l.re * xk.im + l.im * xk.re;
         }
     }
-    __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += GF_NT) Uinv[idx] = Xs[idx / NB][idx % NB];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) Linv[lane * NB + wave * CPW + q] = x[q];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+        const int c = wave * CPW + q;
+        x[q] = (lane == c && c < w) ? Cx<T>{T(1), T(0)} : zero;
+    }
+    for (int k = w - 1; k >= 0; --k) {
+        const Cx<T> d = dinv[k];
+        const Cx<T> u = lane < k ? Ts[lane][k] : zero;
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+            if (lane == k) x[q] = cmul(x[q], d);
+            const Cx<T> xk{rlane(x[q].re, k), rlane(x[q].im, k)};
+            x[q].re -= u.re * xk.re - u.im * xk.im;
+            x[q].im -= u.re * xk.im + u.im * xk.re;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) Uinv[lane * NB + wave * CPW + q] = x[q];
 }
 
 // Apply a panel's composed row exchanges to columns [0, kb) and [kb+w, n).
@@ -716,19 +779,19 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
             const int m = n - kb;
             ProfScope ps(st, "lu_panel", 0.0, 2.0 * m * w * sizeof(Cx<T>) * (double)batch);
             if (m <= 512)
-                hipLaunchKernelGGL((k_getf2r<T, 1>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                hipLaunchKernelGGL((k_getf2r<T, 1, 8>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
                                    Uinv, nblk, swp, info);
             else if (m <= 1024)
-                hipLaunchKernelGGL((k_getf2r<T, 2>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                hipLaunchKernelGGL((k_getf2r<T, 2, 8>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
                                    Uinv, nblk, swp, info);
             else if (m <= 2048)
-                hipLaunchKernelGGL((k_getf2r<T, 4>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                hipLaunchKernelGGL((k_getf2r<T, 4, 8>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
                                    Uinv, nblk, swp, info);
             else if (m <= 3072)
-                hipLaunchKernelGGL((k_getf2r<T, 6>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                hipLaunchKernelGGL((k_getf2r<T, 6, 4>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
                                    Uinv, nblk, swp, info);
             else if (m <= 4096)
-                hipLaunchKernelGGL((k_getf2r<T, 8>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
+                hipLaunchKernelGGL((k_getf2r<T, 8, 4>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
                                    Uinv, nblk, swp, info);
             else
                 hipLaunchKernelGGL(k_getf2<T>, dim3(batch), dim3(512), 0, st, n, kb, w, A, sA, ipiv, Linv, Uinv, nblk,

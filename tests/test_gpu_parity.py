@@ -224,3 +224,31 @@ def test_kernel_timing_counts_the_work(gpu):
     assert st["formA"]["flops"] == 4.0 * n ** 3 * rep.n_solved
     assert all(v["ms"] > 0 and v["launches"] > 0 for v in st.values())
     assert any(k.startswith("zgemm") for k in st) and "lu_panel" in st
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n", [2600, 3500, 4200])
+def test_W_tall_panels(gpu, n):
+    """Panels taller than 2048 rows (six and eight rows per thread, and the
+    generic panel kernel above 4096), on a dense random A = 1 - v chi0 far
+    from diagonal dominance, so that rows are exchanged: W at two frequencies
+    against LAPACK."""
+    gw, ctx, torch = gpu
+    rng = np.random.default_rng(n)
+    M = rng.standard_normal((n, n)) / np.sqrt(n)
+    v = M + M.T
+    chi = np.empty((2, n, n), complex)
+    for j in range(2):
+        X = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+        chi[j] = X + X.T
+    _say("tall panels n", n)
+    dv = torch.from_numpy(v).to("cuda")
+    dchi = torch.from_numpy(chi).to("cuda")
+    W = torch.empty_like(dchi)
+    rep = ctx.solve_W(dv, n, dchi, 2, W)
+    torch.cuda.synchronize()
+    assert rep.n_solved == 2
+    for j in range(2):
+        e = _rel(W[j].cpu().numpy(), o.screened_W(v, chi[j]))
+        _say("j", j, "rel", e)
+        assert e < 1e-9
