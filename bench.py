@@ -230,16 +230,6 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
         if form == "fp64":
             roof = kernel_roofline(ctx.profile_read())
             ctx.profile_end()
-            # the same kernels once more with the solve on one stream, so that
-            # no other kernel shares the machine during a launch (not timed)
-            os.environ["GW_SOLVE_STREAMS"] = "1"
-            ctx.profile_begin()
-            ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
-            ctx.solve_W(dm.v, n, chi, N, W, prec=p, tol=1e-7, stream=stream, report=True)
-            torch.cuda.synchronize()
-            roof_iso = kernel_roofline(ctx.profile_read())
-            ctx.profile_end()
-            del os.environ["GW_SOLVE_STREAMS"]
         samp = W[sample_js].cpu().numpy()
         if form == "fp64":
             W_ref = samp
@@ -278,7 +268,6 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
     out["latency_ms"] = {"p50": r["p50_ms"], "p99": r["p99_ms"]}
     if "fp64" in results:
         out["roofline"] = roof
-        out["roofline_one_stream"] = roof_iso
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
@@ -737,7 +726,7 @@ def run_c4(args, gw, gs, torch):
 
 # ---------------------------------------------------------------------- profiles
 # Kernel whose HBM traffic the roofline reports, and the source it is built from.
-TRAFFIC_KERNEL = "k_gemm<double, true, true, 4, 1, 8, 4>"
+TRAFFIC_KERNEL = "k_gemm<double, true, true, 4, 1, 8, 4, true>"
 TRAFFIC_CLASS = "zgemm_128x32"  # the same kernel in the library's live timing
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
 COPY_BYTES = 1 << 30

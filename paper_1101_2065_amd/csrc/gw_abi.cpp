@@ -1084,7 +1084,11 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     int n_solved = 0, n_fallback = 0, max_it = 0;
     double max_rel = 0.0;
     if (!mixed) {
-        int nstreams = 2;
+        // one stream by default: every kernel then has the whole machine (the
+        // panel kernel needs a whole CU, which a second stream's GEMM
+        // workgroups keep occupied); GW_SOLVE_STREAMS=2 overlaps one frequency
+        // batch's panels with the other batch's products
+        int nstreams = 1;
         if (const char *e = std::getenv("GW_SOLVE_STREAMS")) nstreams = std::max(1, std::min(2, std::atoi(e)));
         if (ctx->own_stream || n_omega < 8) nstreams = 1;
         if (nstreams == 1) {

@@ -12,7 +12,8 @@
 // 128x32 (each wave 4x1 MFMA 16x16 blocks) for long products and 64x32 (2x1)
 // for the thin ones (K = 64 updates inside a block, 64-row products).  The
 // real-times-complex and FP32 products keep 64x64 (K steps of 16) and 128x64
-// (K steps of 8) at two waves per SIMD.  K is staged through a
+// (K steps of 8) at two waves per SIMD.  The narrow tiles are dealt to the
+// XCDs in contiguous ranges (each XCD has its own L2).  K is staged through a
 // double-buffered LDS tile, the next step prefetched into registers.
 #include "gw_internal.h"
 #include "gw_prof.h"
@@ -50,7 +51,7 @@ struct Mfma<float> {
 // Workgroup = 256 threads = 2x2 waves; a wave owns WM x WN MFMA blocks of
 // 16x16, so the workgroup tile is (32 WM) x (32 WN); K advances BK per
 // LDS stage.
-template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC>
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool XR>
 __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
                                                  int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
                                                  T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
@@ -71,12 +72,23 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
     __shared__ T Br[2][BK][BN];
     __shared__ T Bi[2][BC ? BK : 1][BC ? BN : 1];
 
-    const int bz = blockIdx.z;
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    if constexpr (XR) {
+        // workgroups are dealt to the eight XCDs in turn, each with its own
+        // L2: give each XCD a contiguous range of tiles (x fastest), so that
+        // tiles sharing an A row band share that XCD's L2
+        const int gx = gridDim.x, gy = gridDim.y;
+        const int64_t nt = (int64_t)gx * gy * gridDim.z, l = bx + (int64_t)gx * (by + (int64_t)gy * bz);
+        const int64_t n8 = nt / 8, t = l < 8 * n8 ? (l % 8) * n8 + l / 8 : l;
+        bx = (int)(t % gx);
+        by = (int)((t / gx) % gy);
+        bz = (int)(t / ((int64_t)gx * gy));
+    }
     A += (int64_t)bz * sA * ea;
     B += (int64_t)bz * sB * eb;
     C += (int64_t)bz * sC * ec;
     if (C32) C32 += (int64_t)bz * sC32 * 2;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int m0 = by * BM, n0 = bx * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
@@ -440,18 +452,18 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
                 (double)M * N * ec * batch * (beta != T(0) ? 2 : 1);
     }
     ProfScope ps(st, cls ? cls : "", flops, bytes);
-#define GW_GEMM(WM, WN, BK, OCC)                                                                                   \
-    hipLaunchKernelGGL((k_gemm<T, AC, BC, WM, WN, BK, OCC>), dim3((N + 32 * WN - 1) / (32 * WN),                   \
+#define GW_GEMM(WM, WN, BK, OCC, XR)                                                                               \
+    hipLaunchKernelGGL((k_gemm<T, AC, BC, WM, WN, BK, OCC, XR>), dim3((N + 32 * WN - 1) / (32 * WN),               \
                        (M + 32 * WM - 1) / (32 * WM), batch), dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, \
                        sB, beta, C, ldc, sC, add_eye, C32, sC32)
     if constexpr (Z64) {
-        if (tile == 3) GW_GEMM(4, 1, 8, 4);
-        else if (tile == 2) GW_GEMM(2, 1, 8, 4);
-        else if (tile == 1) GW_GEMM(4, 2, 8, 2);
-        else GW_GEMM(2, 2, 16, 2);
+        if (tile == 3) GW_GEMM(4, 1, 8, 4, true);
+        else if (tile == 2) GW_GEMM(2, 1, 8, 4, true);
+        else if (tile == 1) GW_GEMM(4, 2, 8, 2, false);
+        else GW_GEMM(2, 2, 16, 2, false);
     } else {
-        if (tile == 1) GW_GEMM(4, 2, 8, 2);
-        else GW_GEMM(2, 2, 16, 2);
+        if (tile == 1) GW_GEMM(4, 2, 8, 2, false);
+        else GW_GEMM(2, 2, 16, 2, false);
     }
 #undef GW_GEMM
     return hipGetLastError();
