@@ -6,7 +6,11 @@
 // as soon as its estimated HBM footprint (workspace + results) fits under the
 // context's budget, next to the results still held and the workspace the
 // other slots keep; admitted requests run concurrently on their slots'
-// streams, so work of different molecules overlaps on the device.  All
+// streams, so work of different molecules overlaps on the device: the
+// compression and chi0 build of one request (vector units, HBM) run beside
+// the W solve of another (matrix cores).  The solves themselves take turns
+// (GW_SERVE_SOLVE_OVERLAP=1 lets them run together): the LU panel kernel needs
+// a whole CU, which a concurrent solve's GEMM workgroups keep occupied.  All
 // serving memory is stream-ordered (hipMallocAsync / hipFreeAsync on the
 // slot's stream, recycled by the device pool), so no allocation or release
 // synchronises the device.  A slot keeps its workspace for the next request
@@ -58,6 +62,7 @@ struct ServeReq {
 
 struct GwServe {
     std::mutex mu;
+    std::mutex solve_mu;  // one W solve on the device at a time
     std::condition_variable cv;
     std::deque<uint64_t> queue;
     std::map<uint64_t, std::unique_ptr<ServeReq>> reqs;
@@ -109,7 +114,15 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
+bool solve_overlap() {
+    static const bool on = [] {
+        const char *e = std::getenv("GW_SERVE_SOLVE_OVERLAP");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+void run_request(gw_ctx *child, hipStream_t st, ServeReq &r, std::mutex *solve_mu) {
     const bool tr = trace_on();
     double t[6] = {now_ms(), 0, 0, 0, 0, 0};
     auto mark = [&](int i) {
@@ -155,9 +168,14 @@ void run_request(gw_ctx *child, hipStream_t st, ServeReq &r) {
     gw_report rb{}, rs{};
     gw_status s = gw_build_chi0(child, &r.mol, &r.grid, (const double *)r.Q, r.k, st, nullptr, r.chi, &rb);
     mark(3);
-    if (s == GW_OK)
+    if (s == GW_OK) {
+        // the solve returns after its stream has drained (it reports), so
+        // holding the lock across it keeps the solves apart on the device
+        std::unique_lock<std::mutex> lk(*solve_mu, std::defer_lock);
+        if (!solve_overlap()) lk.lock();
         s = gw_solve_W(child, r.k ? (const double *)r.S : r.v, 0, r.kk, r.chi, r.grid.n_omega, r.prec, r.tol, st,
                        r.res, &rs);
+    }
     if (s != GW_OK) {
         r.status = s;
         r.err = gw_last_error(child);
@@ -244,7 +262,7 @@ void worker(GwServe *sv, int slot) {
             continue;
         }
         r->stream = st;
-        run_request(child, st, *r);
+        run_request(child, st, *r, &sv->solve_mu);
         const size_t kept = gwk_ctx_bytes(child);
         {
             std::lock_guard<std::mutex> lk(sv->mu);
