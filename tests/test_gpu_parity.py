@@ -141,6 +141,25 @@ def test_W_in_place_equals_out_of_place(gpu, prec):
     assert torch.equal(buf, W)
 
 
+def test_W_two_solve_streams_equal_one(gpu, monkeypatch):
+    """GW_SOLVE_STREAMS=2 (frequency batches alternating between two streams,
+    batched differently) gives bit for bit the one-stream W: every frequency
+    is factorised by the same arithmetic whatever batch it is in."""
+    gw, ctx, torch = gpu
+    mol = gs.chain_molecule(3, 5)
+    grid = gs.config_grid(0)
+    dm, chi, _, _ = _gpu_chi0(gw, ctx, torch, mol, grid, want_hist=False)
+    W1 = torch.empty_like(chi)
+    W2 = torch.full_like(chi, float("nan"))
+    monkeypatch.setenv("GW_SOLVE_STREAMS", "1")
+    ctx.solve_W(dm.v, mol.n_prod, chi, grid.n_omega, W1)
+    monkeypatch.setenv("GW_SOLVE_STREAMS", "2")
+    rep = ctx.solve_W(dm.v, mol.n_prod, chi, grid.n_omega, W2)
+    torch.cuda.synchronize()
+    _say("two streams: solved", rep.n_solved)
+    assert torch.equal(W1, W2)
+
+
 def test_W_is_v_without_vertex(gpu):
     """V = 0: chi0 = 0 and W = v exactly (identity LU, no rounding)."""
     gw, ctx, torch = gpu
