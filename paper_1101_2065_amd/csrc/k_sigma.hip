@@ -111,6 +111,13 @@ constexpr int SO = TIME_MAX_ORB;
 constexpr int SP = SO + 1;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+// value of v in lane k (k wave-uniform)
+__device__ inline double rlane_d(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k), hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 __device__ inline v4d mfma4(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 
 // One wave's share of a (block pair, time point): for its products mu of B1
@@ -144,10 +151,21 @@ __device__ void sigma_wave(int n1, int n2, int p1, int e1, int p2, int e2, bool 
         for (int s = 0; s < 4 * T2; ++s)
 #pragma unroll
             for (int dt = 0; dt < T2; ++dt) gr[s][dt] = gi[s][dt] = 0.0;
+        // the weights gammahat^{mu nu} of 64 products nu at a time, one per
+        // lane (one vector load instead of a dependent load per nu)
+        double lwr = 0.0, lwi = 0.0;
         for (int nu = p2; nu < e2; ++nu) {
-            const int a = min(mu, nu), b = max(mu, nu);
-            const int64_t t = (int64_t)a * n_prod - ((int64_t)a * (a - 1)) / 2 + (b - a);
-            const double wr = ghr[t], wi = ghi[t];
+            const int q = (nu - p2) & 63;
+            if (q == 0) {
+                const int nl = nu + lane;
+                if (nl < e2) {
+                    const int a = min(mu, nl), b = max(mu, nl);
+                    const int64_t t = (int64_t)a * n_prod - ((int64_t)a * (a - 1)) / 2 + (b - a);
+                    lwr = ghr[t];
+                    lwi = ghi[t];
+                }
+            }
+            const double wr = rlane_d(lwr, q), wi = rlane_d(lwi, q);
             const double *vnu = v2 + (int64_t)(nu - p2) * nsq2;  // LDS copy when staged
 #pragma unroll
             for (int s = 0; s < 4 * T2; ++s)
