@@ -820,6 +820,45 @@ def summarize_profiles(stats_csv, fetch_csv, write_csv, out_json):
                       "dominant_bytes_per_launch": out["bytes_per_launch"]}))
 
 
+def summarize_mfma(counter_csv, out_md):
+    """Per-kernel matrix-core figures from one rocprofv3 --pmc MfmaUtil
+    MfmaFlopsF64 run of the FP64 step: average MFMA busy percentage (busy
+    cycles over active cycles of all SIMDs) and executed FP64 matrix flops
+    per dispatch (padded tiles included)."""
+    acc = {}
+    for r in _csv_rows(counter_csv):
+        k, c = r["Kernel_Name"], r.get("Counter_Name")
+        if c not in ("MfmaUtil", "MfmaFlopsF64"):
+            continue
+        a = acc.setdefault(k, {"MfmaUtil": [0.0, 0], "MfmaFlopsF64": [0.0, 0]})
+        a[c][0] += float(r["Counter_Value"])
+        a[c][1] += 1
+    rows = []
+    for k, a in acc.items():
+        fl = a["MfmaFlopsF64"][0] / max(a["MfmaFlopsF64"][1], 1)
+        if fl <= 0:
+            continue
+        rows.append((k, a["MfmaUtil"][1], a["MfmaUtil"][0] / max(a["MfmaUtil"][1], 1), fl))
+    rows.sort(key=lambda x: -x[3] * x[1])
+    md = ["# Matrix-core use per dispatch: FP64 step (chi0 build + W solve), 40-atom chain truncated to "
+          "N_prod=2000, 1024 frequencies", "",
+          "Commands (repository root, one MI355X):", "", "```",
+          "rocprofv3 --pmc MfmaUtil MfmaFlopsF64 -d gpurun_out/pmc_mfma -o run --output-format csv -- python3 "
+          "bench.py --forms fp64 --steps 1 --warmup 0 --no-cpu-baseline",
+          "python bench.py --summarize-mfma gpurun_out/pmc_mfma/run_counter_collection.csv", "```", "",
+          "MfmaUtil = MFMA busy cycles / (active cycles x SIMDs) in percent; MfmaFlopsF64 = executed FP64 matrix "
+          "flops (512 per counted op), padding of partial tiles included.", "",
+          "| kernel | dispatches | MfmaUtil % | MfmaFlopsF64 per dispatch |", "|---|---:|---:|---:|"]
+    for k, cnt, util, fl in rows:
+        short = k.replace("(anonymous namespace)::", "")
+        short = short.split("(")[0] if "(" in short else short
+        short = short[5:] if short.startswith("void ") else short
+        md.append("| `%s` | %d | %.1f | %.3e |" % (short[:70], cnt, util, fl))
+    with open(out_md, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("wrote", out_md)
+
+
 def summarize_trace(stats_csv, out_md):
     """Kernel table from a rocprofv3 --kernel-trace --stats run of the FP64
     step (one warm-up step and one timed step)."""
@@ -869,9 +908,14 @@ def main():
                     help="end with three plain 1 GiB device copies (reference for the HBM counters)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/hbm_traffic.json from rocprofv3 outputs and exit (no GPU)")
+    ap.add_argument("--summarize-mfma", metavar="COUNTER_CSV",
+                    help="write profiles/mfma_chain40_n2000.md from a MfmaUtil/MfmaFlopsF64 counter run")
     ap.add_argument("--summarize-trace", metavar="STATS_CSV",
                     help="write the kernel table of profiles/kernels_fp64_chain40_n2000.md and exit (no GPU)")
     args = ap.parse_args()
+    if args.summarize_mfma:
+        summarize_mfma(args.summarize_mfma, os.path.join(HERE, "profiles", "mfma_chain40_n2000.md"))
+        return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, os.path.join(HERE, "profiles", "kernels_fp64_chain40_n2000.md"))
         return
