@@ -362,3 +362,35 @@ def serving_stream(rate: float = 20.0, duration: float = 60.0, seed: int = 4,
 
 def serving_molecule(i: int, n_atoms: int) -> Molecule:
     return cluster_molecule(n_atoms, 4000 + i, radius=20.0 * (n_atoms / 120.0) ** (1.0 / 3.0))
+
+
+def lowrank_w_factors(n_prod: int, n_omega: int, rank: int = 4, k_max: int = 300, seed: int = 7):
+    """Seeded factors of a synthetic interaction W(k domega) = v + U diag(c[k]) U^T
+    on the positive half of a symmetric n_omega-point mesh (k = 0 .. n_omega/2 - 1):
+    U [n_prod][rank] real, c [n_omega/2][rank] complex with Im c <= 0, a Gaussian
+    bump per rank inside 0 < k < k_max and exactly zero elsewhere (so a
+    convolution with it stays inside a mesh whose bins reach n_omega/2)."""
+    rng = np.random.default_rng(seed)
+    U = rng.standard_normal((n_prod, rank)) / math.sqrt(n_prod)
+    k = np.arange(n_omega // 2, dtype=float)
+    centre = rng.uniform(0.2, 0.8, rank) * k_max
+    width = rng.uniform(0.05, 0.2, rank) * k_max
+    amp = rng.uniform(0.5, 2.0, rank)
+    im = -amp[None, :] * np.exp(-0.5 * ((k[:, None] - centre[None, :]) / width[None, :]) ** 2)
+    im[0] = 0.0
+    im[k_max:] = 0.0
+    re = rng.standard_normal((n_omega // 2, rank))
+    return U, re + 1j * im
+
+
+def lowrank_sigma_factors(n_orb: int, n_omega: int, rank: int = 4, seed: int = 11):
+    """Seeded factors of a synthetic correlation self-energy
+    Sigma_c(omega_j) = Y diag(s[j]) Y^T: Y [n_orb][rank] real, s [n_omega][rank]
+    complex with Im s <= 0 (so Im Sigma_c is negative semidefinite), and a
+    static pair (Sigma_x, V_xc) of small symmetric matrices."""
+    rng = np.random.default_rng(seed)
+    Y = rng.standard_normal((n_orb, rank)) / math.sqrt(n_orb)
+    s = 0.3 * rng.standard_normal((n_omega, rank)) - 0.2j * rng.uniform(0.1, 1.0, (n_omega, rank))
+    A = 0.02 * rng.standard_normal((n_orb, n_orb))
+    B = 0.02 * rng.standard_normal((n_orb, n_orb))
+    return Y, s, A + A.T, B + B.T
