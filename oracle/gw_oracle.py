@@ -66,6 +66,7 @@ __all__ = [
     "packed_index",
     "unpack_upper",
     "chi0_from_hist",
+    "chi0_apply",
     "chi0_poles",
     "screened_W",
     "compress_basis",
@@ -297,6 +298,45 @@ def unpack_upper(packed: np.ndarray, n: int) -> np.ndarray:
 
 # ----------------------------------------------------------------------------
 # chi0 (Section 5.A eq. chi_by_spectra: Cauchy transform of the odd-extended a)
+
+
+def chi0_apply(mol, y: np.ndarray, omega: float, eps: float, domega: float, n_hbins: int) -> np.ndarray:
+    """chi0(omega + i eps) y for y [n_prod] or [n_prod][r], without forming chi0
+    or the pair vectors:
+        chi0 = sum_p 2 V^p (V^p)^T [(1 - frac_p) K(m_p) + frac_p K(m_p + 1)],
+        K(m) = 1/(omega - m domega + i eps) - 1/(omega + m domega + i eps),
+    the same binned spectral function as the histogram (Section 5.A eq.
+    chi_by_spectra, spin factor 2), unquantised, pairs with m_p + 1 >= n_hbins
+    dropped.  The closed form of the pair vertex (Section 7.A) is summed the
+    other way round: V^p . y = X_E^T (sum_mu y_mu V_mu) X_F for every pair
+    p = (E, F) at once, and (chi0 y)_mu = sum_{ab} V_mu^{ab} (X_occ b X_virt^T)_{ab}
+    with b_p = (V^p . y) times the pair's weight."""
+    n_occ, n_orb = mol.n_occ, mol.n_orb
+    Y = np.asarray(y).reshape(mol.n_prod, -1)
+    m, fr = pair_bins(mol.eig, n_occ, domega)
+
+    def K(mm):
+        return 1.0 / (omega - mm * domega + 1j * eps) - 1.0 / (omega + mm * domega + 1j * eps)
+
+    wgt = 2.0 * ((1.0 - fr) * K(m) + fr * K(m + 1))
+    wgt[m + 1 >= n_hbins] = 0.0
+    wgt = wgt.reshape(n_occ, n_orb - n_occ)
+    Xo, Xv = mol.X[:, :n_occ], mol.X[:, n_occ:]
+    blocks = [mol.block_of(b) for b in range(mol.n_blk)]
+    out = np.zeros(Y.shape, dtype=np.complex128)
+    for col in range(Y.shape[1]):
+        Vy = np.zeros((n_orb, n_orb), dtype=np.complex128)
+        for p0, _, orbs, mats in blocks:
+            ix = np.ix_(orbs, orbs)
+            for i, M in enumerate(mats):
+                Vy[ix] += Y[p0 + i, col] * M
+        a = Xo.T @ Vy @ Xv  # V^p . y, p = (E, F)
+        B = Xo @ (a * wgt) @ Xv.T
+        for p0, _, orbs, mats in blocks:
+            Bo = B[np.ix_(orbs, orbs)]
+            for i, M in enumerate(mats):
+                out[p0 + i, col] = np.sum(M * Bo)
+    return out.reshape(np.shape(y))
 
 
 def chi0_from_hist(H: np.ndarray, s: int, n_omega: int, omega_min: float, omega_max: float,

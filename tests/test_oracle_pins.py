@@ -767,3 +767,28 @@ def test_dyson_dos_diagonal_self_energy():
     lor = lambda E: (eps / math.pi) / ((om[:, None] - E[None, :]) ** 2 + eps ** 2)
     dos2, _ = o.dyson_dos(mol, n_omega, -wmax, wmax, eps, Vxc=c * np.eye(mol.n_orb))
     assert np.abs(dos2 - lor(mol.eig - c).sum(1)).max() < 1e-10 * dos2.max()
+
+
+@pytest.mark.parametrize("which", ["config0", "chain3", "narrow_mesh"])
+def test_chi0_apply_equals_histogram_route(which):
+    """chi0 applied to vectors through the pair-vertex closed form summed in
+    orbital space equals chi0 from the integer histogram times the vectors,
+    up to the histogram's 2^-s quantisation (and with the same pairs dropped
+    on a mesh narrower than the spectrum)."""
+    mol = gs.make_config(0) if which != "chain3" else gs.chain_molecule(3, 5)
+    g = gs.Grid(64, -1.0, 1.0, 0.05) if which == "narrow_mesh" else gs.config_grid(0)
+    d = g.domega
+    P = o.pair_vectors(mol)
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, d)
+    nhb = o.hist_bins(mol.eig, g.n_omega, d)
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, nhb)
+    js = [g.n_omega // 2, g.n_omega // 2 + 5, g.n_omega - 1, 3]
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, g.n_omega, g.omega_min, g.omega_max, g.eps, js=js), mol.n_prod)
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal((mol.n_prod, 3)) + 1j * rng.standard_normal((mol.n_prod, 3))
+    om = g.omegas()
+    for i, j in enumerate(js):
+        got = o.chi0_apply(mol, y, om[j], g.eps, d, nhb)
+        ref = chi[i] @ y
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
