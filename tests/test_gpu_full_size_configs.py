@@ -1,0 +1,98 @@
+"""Parity at the full sizes of two more benchmark configurations, through the
+defining equation (1 - v chi0) W = v on sampled columns at sampled
+frequencies, chi0 applied to each column by the oracle's pair-vertex route
+(unquantised: bar 1e-6, the bar of the refined forms):
+
+* the whole 40-atom chain (2304 products, 1024 points; panels taller than
+  2048 rows), FP64 and split-BF16 with FP64 refinement;
+* the largest molecule of the 64-molecule batch (512 points; panels taller
+  than 4096 rows), solved in place through a recorded batch graph, FP64."""
+import sys
+
+import numpy as np
+import pytest
+
+import gw_synth as gs
+import oracle as o
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_2065_amd.gw as gw
+
+    ctx = gw.Context(0)
+    yield gw, ctx, torch
+    ctx.close()
+
+
+def _worst_residual(mol, grid, W, js, cols):
+    om = grid.omegas()
+    nhb = o.hist_bins(mol.eig, grid.n_omega, grid.domega)
+    worst = 0.0
+    for j in js:
+        for c in cols:
+            w = W[j][:, c].cpu().numpy()
+            res = w - mol.v @ o.chi0_apply(mol, w, om[j], grid.eps, grid.domega, nhb) - mol.v[:, c]
+            worst = max(worst, np.linalg.norm(res) / np.linalg.norm(mol.v[:, c]))
+    return worst
+
+
+def test_c1_whole_chain(gpu):
+    gw, ctx, torch = gpu
+    mol = gs.make_config(1)
+    grid = gs.config_grid(1)
+    n, N = mol.n_prod, grid.n_omega
+    _say("C1: n_prod", n, "n_omega", N)
+    assert n > 2048
+    dm = gw.DeviceMolecule(mol)
+    g = gw.make_grid(N, grid.omega_min, grid.omega_max, grid.eps, grid.frac_bits)
+    chi = torch.empty((N, n, n), dtype=torch.complex128, device="cuda")
+    ctx.build_chi0(dm.struct, g, chi)
+    W = torch.empty_like(chi)
+    rng = np.random.default_rng(31)
+    cols = rng.integers(0, n, 3)
+    js = [N // 2, N // 2 + 150, 300]
+    for form, prec in (("fp64", gw.GW_FP64), ("bf16x_ir", gw.GW_BF16X_IR)):
+        rep = ctx.solve_W(dm.v, n, chi, N, W, prec=prec, tol=1e-7)
+        torch.cuda.synchronize()
+        assert rep.n_fallback == 0
+        e = _worst_residual(mol, grid, W, js, cols)
+        _say("C1 %s: max residual %.2e" % (form, e))
+        assert e < 1e-6
+    del chi, W
+    torch.cuda.empty_cache()
+
+
+def test_c3_largest_molecule_batched_in_place(gpu):
+    gw, ctx, torch = gpu
+    mols = gs.batch_molecules()
+    mol = max(mols, key=lambda m: m.n_prod)
+    grid = gs.config_grid(3)
+    n, N = mol.n_prod, grid.n_omega
+    _say("C3 largest: n_prod", n, "n_omega", N)
+    assert n > 4096
+    dm = gw.DeviceMolecule(mol)
+    g = gw.make_grid(N, grid.omega_min, grid.omega_max, grid.eps)
+    buf = torch.zeros((N, n, n), dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    b = ctx.batch_create([dm.struct], [dm.v], g, [buf], [buf], prec=gw.GW_FP64, tol=1e-7, n_refine=3,
+                         stream=stream)
+    b.run(stream=stream)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(32)
+    e = _worst_residual(mol, grid, buf, [N // 2, N // 2 + 80, 100], rng.integers(0, n, 3))
+    _say("C3 largest, batched in place: max residual %.2e" % e)
+    assert e < 1e-6
+    b.close()
+    del buf
+    torch.cuda.empty_cache()
