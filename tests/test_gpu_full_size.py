@@ -35,6 +35,7 @@ def setup():
         pytest.skip("no GPU")
     import paper_1101_2065_amd.gw as gw
 
+    torch.cuda.empty_cache()  # cached blocks of earlier tests: back to the device
     ctx = gw.Context(0)
     mol = gs.truncate_products(gs.make_config(1), N_PROD)
     _say("full size: n_prod", mol.n_prod, "pairs", mol.n_pairs)
@@ -51,6 +52,7 @@ def setup():
     dm = gw.DeviceMolecule(mol)
     yield gw, ctx, torch, mol, dm, P, s, (mu, nu)
     ctx.close()
+    torch.cuda.empty_cache()
 
 
 def _g(gw, g):

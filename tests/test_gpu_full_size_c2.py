@@ -34,7 +34,18 @@ def test_full_size_compressed_c2():
         pytest.skip("no GPU")
     import paper_1101_2065_amd.gw as gw
 
+    # earlier tests' freed tensors stay in torch's cache, which the library's
+    # own workspace allocations cannot use: give them back first
+    torch.cuda.empty_cache()
     ctx = gw.Context(0)
+    try:
+        _run_c2(gw, ctx, torch)
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
+
+
+def _run_c2(gw, ctx, torch):
     mol = gs.make_config(2)
     grid = gs.config_grid(2)
     n, N = mol.n_prod, grid.n_omega
@@ -77,4 +88,3 @@ def test_full_size_compressed_c2():
         _say("%s: max residual of (1 - v chi0) W = v over %d columns x %d frequencies: %.2e"
              % (form, len(cols), len(js), worst))
         assert worst < 1e-6
-    ctx.close()

@@ -30,9 +30,11 @@ def gpu():
         pytest.skip("no GPU")
     import paper_1101_2065_amd.gw as gw
 
+    torch.cuda.empty_cache()  # cached blocks of earlier tests: back to the device
     ctx = gw.Context(0)
     yield gw, ctx, torch
     ctx.close()
+    torch.cuda.empty_cache()
 
 
 def _worst_residual(mol, grid, W, js, cols):

@@ -45,12 +45,14 @@ def setup():
         pytest.skip("no GPU")
     import paper_1101_2065_amd.gw as gw
 
+    torch.cuda.empty_cache()  # cached blocks of earlier tests: back to the device
     ctx = gw.Context(0)
     mol = gs.truncate_products(gs.make_config(1), N_PROD)
     grid = gs.config_grid(1)
     dm = gw.DeviceMolecule(mol)
     yield gw, ctx, torch, mol, grid, dm
     ctx.close()
+    torch.cuda.empty_cache()
 
 
 def _g(gw, g):
