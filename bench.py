@@ -120,10 +120,30 @@ def cpu_baseline(mol, grid, budget_s=20.0):
     total = t_pairs + t_hist + grid.n_omega * (t_chi + t_w)
     omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     nblas = blas_threads()
+    # context: one W solve with a single BLAS thread (the paper's runs used one core)
+    t_w1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            o.screened_W(mol.v, chi)
+            t_w1 = time.perf_counter() - t0
+    except ImportError:
+        pass
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {
         "value": grid.n_omega / total,
         "unit": "W(omega)/s",
         "cores": max(nblas, omp),
+        "host_cpus": os.cpu_count(),
+        "cpu_model": model,
+        "one_thread_W_solve_s": t_w1,
         "kind": "oracle",
         "sample": ("pair vectors in full (%.1fs); int64 histogram (C, %d OpenMP threads) on %d of %d entries "
                    "(scaled); chi0 direct sum at one frequency on the same entries (scaled x%d frequencies); "
