@@ -818,13 +818,13 @@ def summarize_profiles(stats_csv, fetch_csv, write_csv, out_json):
     md = [
         "# HBM traffic per dispatch: FP64 step (chi0 build + W solve), 40-atom chain truncated to N_prod=2000, "
         "1024 frequencies", "",
-        "Commands (repository root, one MI355X; one counter per run):", "", "```",
-        "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o run --output-format csv -- python3 bench.py "
+        "Commands (repository root, one MI355X; one counter per run; OUT is any output directory):", "", "```",
+        "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc_fetch -o run --output-format csv -- python3 bench.py "
         "--forms fp64 --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
-        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o run --output-format csv -- python3 bench.py "
+        "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc_write -o run --output-format csv -- python3 bench.py "
         "--forms fp64 --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
-        "python bench.py --summarize-counters gpurun_out/prof_n2000/run_kernel_stats.csv "
-        "gpurun_out/pmc_fetch/run_counter_collection.csv gpurun_out/pmc_write/run_counter_collection.csv",
+        "python bench.py --summarize-counters $OUT/prof_n2000/run_kernel_stats.csv "
+        "$OUT/pmc_fetch/run_counter_collection.csv $OUT/pmc_write/run_counter_collection.csv",
         "```", "",
         "Calibration: a plain elementwise pass over %d bytes (`%s`) reads FETCH_SIZE %.0f KiB and writes WRITE_SIZE "
         "%.0f KiB per dispatch; factors %.4f (fetch) and %.4f (write) convert the counters to bytes."
@@ -862,10 +862,10 @@ def summarize_mfma(counter_csv, out_md):
     rows.sort(key=lambda x: -x[3] * x[1])
     md = ["# Matrix-core use per dispatch: FP64 step (chi0 build + W solve), 40-atom chain truncated to "
           "N_prod=2000, 1024 frequencies", "",
-          "Commands (repository root, one MI355X):", "", "```",
-          "rocprofv3 --pmc MfmaUtil MfmaFlopsF64 -d gpurun_out/pmc_mfma -o run --output-format csv -- python3 "
+          "Commands (repository root, one MI355X; OUT is any output directory):", "", "```",
+          "rocprofv3 --pmc MfmaUtil MfmaFlopsF64 -d $OUT/pmc_mfma -o run --output-format csv -- python3 "
           "bench.py --forms fp64 --steps 1 --warmup 0 --no-cpu-baseline",
-          "python bench.py --summarize-mfma gpurun_out/pmc_mfma/run_counter_collection.csv", "```", "",
+          "python bench.py --summarize-mfma $OUT/pmc_mfma/run_counter_collection.csv", "```", "",
           "MfmaUtil = MFMA busy cycles / (active cycles x SIMDs) in percent; MfmaFlopsF64 = executed FP64 matrix "
           "flops (512 per counted op), padding of partial tiles included.", "",
           "| kernel | dispatches | MfmaUtil % | MfmaFlopsF64 per dispatch |", "|---|---:|---:|---:|"]
@@ -892,10 +892,10 @@ def summarize_trace(stats_csv, out_md):
     total = sum(x[2] for x in rows) or 1.0
     md = ["# Kernel profile: FP64 step (chi0 build + W solve), 40-atom chain truncated to N_prod=2000, "
           "1024 frequencies", "",
-          "Command (repository root, one MI355X):", "", "```",
-          "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_n2000 -o run --output-format csv -- python3 bench.py "
+          "Command (repository root, one MI355X; OUT is any output directory):", "", "```",
+          "rocprofv3 --kernel-trace --stats -d $OUT/prof_n2000 -o run --output-format csv -- python3 bench.py "
           "--forms fp64 --steps 1 --warmup 1 --no-cpu-baseline",
-          "python bench.py --summarize-trace gpurun_out/prof_n2000/run_kernel_stats.csv", "```", "",
+          "python bench.py --summarize-trace $OUT/prof_n2000/run_kernel_stats.csv", "```", "",
           "Two steps (one warm-up, one timed) of gw_build_chi0 + gw_solve_W; all kernels from `run_kernel_stats.csv`:",
           "", "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
     for name, calls, tot in rows:
@@ -943,7 +943,7 @@ def main():
         summarize_profiles(*args.summarize_counters, TRAFFIC_FILE)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the sharding design is "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the sharding design is "
               "documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.forms is None:
