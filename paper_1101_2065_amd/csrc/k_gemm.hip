@@ -67,10 +67,13 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
     // hit one bank group) and gives each thread B columns TPRB apart
     constexpr int PA = (BK == 16) ? 1 : 0;
     constexpr int SB = (BK == 16) ? TPRB : 1;
-    __shared__ T Ar[2][BK][BM + PA];
-    __shared__ T Ai[2][AC ? BK : 1][AC ? BM + PA : 1];
-    __shared__ T Br[2][BK][BN];
-    __shared__ T Bi[2][BC ? BK : 1][BC ? BN : 1];
+    // complex operands are staged interleaved {re, im}: one 16-byte LDS read
+    // per operand value instead of two 8-byte ones
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    __shared__ T Ar[2][AC ? 1 : BK][AC ? 1 : BM + PA];
+    __shared__ T2 Ac[2][AC ? BK : 1][AC ? BM + PA : 1];
+    __shared__ T Br[2][BC ? 1 : BK][BC ? 1 : BN];
+    __shared__ T2 Bc[2][BC ? BK : 1][BC ? BN : 1];
 
     int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     if constexpr (XR) {
@@ -160,13 +163,13 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
     auto lstore = [&](int b) {
 #pragma unroll
         for (int c = 0; c < EA; ++c) {
-            Ar[b][a_k + c][a_row] = ra_r[c];
-            if constexpr (AC) Ai[b][a_k + c][a_row] = ra_i[c];
+            if constexpr (AC) Ac[b][a_k + c][a_row] = T2{ra_r[c], ra_i[c]};
+            else Ar[b][a_k + c][a_row] = ra_r[c];
         }
 #pragma unroll
         for (int c = 0; c < EB; ++c) {
-            Br[b][b_row][b_col + c * SB] = rb_r[c];
-            if constexpr (BC) Bi[b][b_row][b_col + c * SB] = rb_i[c];
+            if constexpr (BC) Bc[b][b_row][b_col + c * SB] = T2{rb_r[c], rb_i[c]};
+            else Br[b][b_row][b_col + c * SB] = rb_r[c];
         }
     };
     // LDS double buffer: compute on one buffer while the next K step is
@@ -185,16 +188,26 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
 #pragma unroll
             for (int i = 0; i < WM; ++i) {
                 const int r = wm * 16 * WM + i * 16 + (lane & 15);
-                ar[i] = Ar[cur][kl][r];
-                if constexpr (AC) ai[i] = Ai[cur][kl][r];
-                else ai[i] = T(0);
+                if constexpr (AC) {
+                    const T2 a2 = Ac[cur][kl][r];
+                    ar[i] = a2.x;
+                    ai[i] = a2.y;
+                } else {
+                    ar[i] = Ar[cur][kl][r];
+                    ai[i] = T(0);
+                }
             }
 #pragma unroll
             for (int j = 0; j < WN; ++j) {
                 const int c = wn * 16 * WN + j * 16 + (lane & 15);
-                br[j] = Br[cur][kl][c];
-                if constexpr (BC) bi[j] = Bi[cur][kl][c];
-                else bi[j] = T(0);
+                if constexpr (BC) {
+                    const T2 b2 = Bc[cur][kl][c];
+                    br[j] = b2.x;
+                    bi[j] = b2.y;
+                } else {
+                    br[j] = Br[cur][kl][c];
+                    bi[j] = T(0);
+                }
             }
             // two passes so that no MFMA waits on the one issued just before it
 #pragma unroll
