@@ -49,21 +49,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def solve_flops(n, n_solved, n_ir=0, mixed=False):
+def solve_flops(n, n_solved, n_ir=0, mixed=False, form_a=True):
     """Algorithmic flops of the W solve per solved frequency.  FP64: A = 1 -
     v chi0 4N^3, LU 8/3 N^3, forward substitution with N right-hand sides 4N^3,
     back substitution of the lower triangle of the symmetric W 4/3 N^3
     (sum over rows r of (r + 1)(N - 1 - r) complex multiply-adds).  Mixed:
     low-precision LU and full solves (8N^3), and per refinement step an FP64
-    residual 8N^3 and a low-precision solve 8N^3."""
+    residual 8N^3 and a low-precision solve 8N^3.  form_a = False: A is an
+    input (formed with chi0 from v a0), no 4N^3 product."""
     n3 = float(n) ** 3
+    fa = 4.0 if form_a else 0.0
     if not mixed:
-        return {"fp64": n_solved * (4 + 8.0 / 3 + 4 + 4.0 / 3) * n3, "fp32": 0.0}
-    return {"fp64": n_solved * (4 + 8 * n_ir) * n3, "fp32": n_solved * (8.0 / 3 + 8 * (1 + n_ir)) * n3}
+        return {"fp64": n_solved * (fa + 8.0 / 3 + 4 + 4.0 / 3) * n3, "fp32": 0.0}
+    return {"fp64": n_solved * (fa + 8 * n_ir) * n3, "fp32": n_solved * (8.0 / 3 + 8 * (1 + n_ir)) * n3}
 
 
-def solve_roofline(n, n_solved, t_solve, n_ir, mixed):
-    fl = solve_flops(n, n_solved, n_ir, mixed)
+def solve_roofline(n, n_solved, t_solve, n_ir, mixed, form_a=True):
+    fl = solve_flops(n, n_solved, n_ir, mixed, form_a)
     t_roof = fl["fp64"] / PEAK_FP64 + fl["fp32"] / PEAK_FP32
     total = fl["fp64"] + fl["fp32"]
     achieved = total / t_solve / 1e12
@@ -221,13 +223,16 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
     forms = [f for f in args.forms.split(",") if f]
     sample_js = [0, N // 2, N // 2 + 30, N // 2 + 100, N - 1, 200]
     W_ref = None
-    results = {}
+    results, roofs = {}, {}
     for form in forms:
-        p = FORMS[form]
+        # "<precision>_A": A = 1 - v chi0 formed from v a0 (gw_build_A), W from A
+        route_a = form.endswith("_A")
+        base = form[:-2] if route_a else form
+        p = FORMS[base]
         ev, reps = [], []
         for it in range(args.warmup + args.steps):
             timed = it >= args.warmup
-            if timed and form == "fp64":
+            if timed and base == "fp64":
                 ctx.profile_begin()
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -235,9 +240,15 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
             e2 = torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
             e0.record(stream)
-            ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
+            if route_a:  # chi holds A
+                ctx.build_A(dm.struct, dm.v, g, chi, stream=stream, report=False)
+            else:
+                ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
             e1.record(stream)
-            rep = ctx.solve_W(dm.v, n, chi, N, W, prec=p, tol=1e-7, stream=stream, report=True)
+            if route_a:
+                rep = ctx.solve_W_A(dm.v, n, chi, N, W, prec=p, tol=1e-7, stream=stream, report=True)
+            else:
+                rep = ctx.solve_W(dm.v, n, chi, N, W, prec=p, tol=1e-7, stream=stream, report=True)
             e2.record(stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
@@ -247,8 +258,8 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
             log("%s step %d: chi0 %.3fs solve %.3fs wall %.3fs iters %d fallback %d" % (
                 form, it, e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3, wall, rep.max_iter,
                 rep.n_fallback))
-        if form == "fp64":
-            roof = kernel_roofline(ctx.profile_read())
+        if base == "fp64":
+            roofs[form] = kernel_roofline(ctx.profile_read())
             ctx.profile_end()
         samp = W[sample_js].cpu().numpy()
         if form == "fp64":
@@ -268,26 +279,29 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
             "max_iter": int(max(r[0] for r in reps)),
             "fallback": int(max(r[1] for r in reps)),
             "rel_err_vs_fp64": err,
+            "route_a": route_a,
         }
     ok = {f: r for f, r in results.items() if r["rel_err_vs_fp64"] is None or r["rel_err_vs_fp64"] <= 1e-6}
     best = min(ok, key=lambda f: ok[f]["t_step"])
     r = results[best]
     out = base_record(
         args, "W(omega) freq-solves/sec at N_prod=2000 (mixed vs FP64, same GPU); p50/p99 latency",
-        N / r["t_step"], "W(omega)/s", r["t_step"], "f64" if best == "fp64" else "f32+f64",
+        N / r["t_step"], "W(omega)/s", r["t_step"], "f64" if best.startswith("fp64") else "f32+f64",
         {"workload": workload, "n_prod": n, "n_omega": N, "n_pairs": mol.n_pairs, "form": best,
          "parallelism": "none (1 GPU)"})
     out["forms"] = {}
     for f, v in results.items():
-        ach, pk = solve_roofline(n, v["n_solved"], v["t_solve"], v["max_iter"], f != "fp64")
+        ach, pk = solve_roofline(n, v["n_solved"], v["t_solve"], v["max_iter"], not f.startswith("fp64"),
+                                 form_a=not v["route_a"])
         out["forms"][f] = {"W_per_s": N / v["t_step"], "solves_per_s": v["n_solved"] / v["t_step"],
                            "t_chi0_s": v["t_chi0"], "t_solve_s": v["t_solve"], "p50_ms": v["p50_ms"],
                            "p99_ms": v["p99_ms"], "max_ir_steps": v["max_iter"], "fp64_fallbacks": v["fallback"],
                            "rel_err_vs_fp64": v["rel_err_vs_fp64"],
                            "solve_TFLOPs": ach, "solve_roofline_frac": ach / pk}
     out["latency_ms"] = {"p50": r["p50_ms"], "p99": r["p99_ms"]}
-    if "fp64" in results:
-        out["roofline"] = roof
+    if roofs:
+        # the headline form's kernels when they were timed, else the FP64 chi0 route's
+        out["roofline"] = roofs.get(best, roofs.get("fp64", next(iter(roofs.values()))))
     ctx.close()
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
@@ -917,7 +931,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n2000", choices=["n2000", "n2000_2w", "n2000_time", "n2000_sigma", "c1", "c2",
                                                                   "c2pair", "c3", "c4"])
-    ap.add_argument("--forms", default=None, help="comma list of fp64, fp32_ir, bf16x_ir")
+    ap.add_argument("--forms", default=None, help="comma list of fp64, fp32_ir, bf16x_ir; n2000 and c1 also "
+                    "take the same with _A (A = 1 - v chi0 formed from v a0, then W from A)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mols", type=int, default=64, help="c3: number of molecules")
     ap.add_argument("--rate", type=float, default=20.0, help="c4: offered requests/s")

@@ -288,6 +288,41 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
                      const void *chi0, int32_t n_omega, gw_precision prec, double tol,
                      void *stream, void *W_out, gw_report *rep);
 
+/* Steps 3-4 fused at the front: A(omega_j) = 1 - v chi0(omega_j) for every
+ * mesh point, straight from the molecule, without forming chi0.  chi0 is the
+ * Cauchy transform of the spectral function a0 (Section 5.A eq.
+ * chi_by_spectra, evaluated by FFT as in Section 5.A), and the transform is
+ * linear, so v chi0 is the transform of v a0: the exact histogram is built as
+ * for gw_build_chi0 (bin m integrated, integers times 2^-s), each bin is
+ * multiplied by v once (n_hbins - 1 real products of size n), and the FFT
+ * convolution runs on all n^2 entries of v a0.  Equal to forming
+ * 1 - v chi0 from gw_build_chi0's output up to rounding order.
+ *   m: as for gw_build_chi0 (no compression basis).
+ *   v: DEVICE double [n_prod][n_prod], the symmetric Coulomb metric.
+ *   g: as for gw_build_chi0, with 128 <= n_omega <= 1024.
+ *   A_out: DEVICE complex128 [n_omega][n_prod][n_prod], every entry written
+ *      (A is not symmetric).
+ *   rep: HOST or NULL; as for gw_build_chi0.
+ * Workspace: 16 n_hbins n_prod^2 bytes beyond gw_build_chi0's.
+ * Errors: GW_E_INVALID (also for n_omega outside the range above),
+ * GW_E_OOM, GW_E_DEVICE. */
+gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
+                     void *stream, void *A_out, gw_report *rep);
+
+/* Step 4 from A = 1 - v chi0 (gw_build_A's output) instead of chi0:
+ * W(omega_j) = A(omega_j)^{-1} v (Section 2 eq. Coulombscreening), with the
+ * same frequencies, conjugate mirror, precisions, refinement, fallback and
+ * report as gw_solve_W (the refinement residual is r = v - A W in FP64).
+ *   A: DEVICE complex128 [n_omega][n][n].  It is the factorisation's
+ *      storage: under GW_FP64 the solved frequencies (j = 0, j >= n_omega/2)
+ *      hold LU factors on return; the mixed forms leave it unchanged.
+ *   W_out: DEVICE complex128 [n_omega][n][n]; W_out == A is allowed (each
+ *      frequency batch of A is then copied to the workspace first).
+ * Errors: as for gw_solve_W. */
+gw_status gw_solve_W_A(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, void *A,
+                       int32_t n_omega, gw_precision prec, double tol, void *stream, void *W_out,
+                       gw_report *rep);
+
 /* Section 7.B subspace: an orthonormal basis Q of the k-dimensional dominant
  * eigenspace of v (the span of its top-k eigenvectors; shifted subspace
  * iteration, 4 steps) and the metric in that basis, S = Q^T v Q.  The

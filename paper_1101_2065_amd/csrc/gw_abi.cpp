@@ -234,7 +234,8 @@ size_t solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget) {
 gw_status mixed_first_solve(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
                             zdbl *W, int nb, gwp::SolveWs &w) {
     const int64_t nn = (int64_t)n * n;
-    GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, w.A32, nn, nb));
+    if (chi0) GW_HIP(c, gwk::launch_formA(st, n, v, v_is_diag, chi0, nn, w.A, nn, w.A32, nn, nb));
+    else GW_HIP(c, gwk::launch_z2c(st, w.A, w.A32, nn * nb));  // A given: its FP32 copy
     GW_HIP(c, gwk::launch_fill_u32(st, (uint32_t *)w.info, nb, 0u));
     GW_HIP(c, gwk::getrf_batched<zflt>(st, n, w.A32, nn, w.ipiv, (zflt *)w.Li, (zflt *)w.Ui, (zflt *)w.scratch, w.info,
                                        nb));
@@ -386,7 +387,8 @@ gw_status build_plan(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const 
     return GW_OK;
 }
 
-gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
+// a1-a3: pair vectors (projected when a basis is given), bins, exact histogram.
+gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st) {
     const gw_molecule *m = &p.m;
     if (p.basis) {
         GW_HIP(ctx, gwk::launch_transpose_d(st, p.n_prod, p.k, p.basis, p.bt));
@@ -410,6 +412,12 @@ gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *c
                                       p.fsort, p.stat));
     GW_HIP(ctx, gwk::launch_gather(st, p.rows, p.n_pairs, Psrc, p.perm, p.stat, p.Ps));
     GW_HIP(ctx, gwk::launch_hist(st, p.rows, p.n_pairs, p.Ps, p.fsort, p.binoff, p.stat, p.sdev, p.nhb, p.H, p.splits));
+    return GW_OK;
+}
+
+gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
+    gw_status s = build_hist_enqueue(ctx, p, st);
+    if (s != GW_OK) return s;
     if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
     GW_HIP(ctx, gwk::launch_fftconv(st, p.rows, p.g.n_omega, p.nhb, p.H, p.sdev, p.Kt, p.tw, (zdbl *)chi0_out));
     return GW_OK;
@@ -459,20 +467,32 @@ gw_status solve_plan(gw_ctx *ctx, int n, int n_omega, bool mixed, const std::str
     return GW_OK;
 }
 
+gw_status batch_ws(gw_ctx *c, hipStream_t st, const SolveWs &base, zdbl *Ain, const zdbl *W, int64_t nn, int j0,
+                   int nb, SolveWs *out) {
+    *out = base;
+    if (!Ain) return GW_OK;
+    if (Ain == W) GW_HIP(c, hipMemcpyAsync(out->A, Ain + j0 * nn, sizeof(zdbl) * nn * nb, hipMemcpyDeviceToDevice, st));
+    else out->A = Ain + j0 * nn;
+    return GW_OK;
+}
+
 gw_status solve_enqueue_nosync(gw_ctx *ctx, SolvePlan &p, hipStream_t st, const double *v, int v_is_diag,
-                               const zdbl *chi0, zdbl *W, int fixed_ir) {
+                               const zdbl *chi0, zdbl *W, int fixed_ir, zdbl *Ain) {
     const int64_t nn = (int64_t)p.n * p.n;
     gw_status s;
     for (auto &bt : freq_batches(p.n_omega, p.nbmax)) {
         const int j0 = bt.first, nb = bt.second;
+        const zdbl *X = chi0 ? chi0 + j0 * nn : nullptr;
+        SolveWs w;
+        if ((s = batch_ws(ctx, st, p.w, Ain, W, nn, j0, nb, &w)) != GW_OK) return s;
         if (!p.mixed) {
-            s = solve_batch_fp64(ctx, st, p.n, v, v_is_diag, chi0 + j0 * nn, W + j0 * nn, nb, p.w);
+            s = solve_batch_fp64(ctx, st, p.n, v, v_is_diag, X, W + j0 * nn, nb, w);
             if (s != GW_OK) return s;
         } else {
-            s = mixed_first_solve(ctx, st, p.n, v, v_is_diag, chi0 + j0 * nn, W + j0 * nn, nb, p.w);
+            s = mixed_first_solve(ctx, st, p.n, v, v_is_diag, X, W + j0 * nn, nb, w);
             if (s != GW_OK) return s;
             for (int it = 0; it < fixed_ir; ++it) {
-                s = mixed_refine_step(ctx, st, p.n, v, v_is_diag, W + j0 * nn, nb, p.w, nullptr,
+                s = mixed_refine_step(ctx, st, p.n, v, v_is_diag, W + j0 * nn, nb, w, nullptr,
                                       p.final_norms + 2 * j0);
                 if (s != GW_OK) return s;
             }
@@ -1061,12 +1081,16 @@ gw_status gw_dyson_dos(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, cons
     return GW_OK;
 }
 
-gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, const void *chi0, int32_t n_omega,
-                     gw_precision prec, double tol, void *stream, void *W_out, gw_report *rep) {
+}  // extern "C"
+
+namespace {
+// W from chi0 (X0) or from A = 1 - v chi0 (Ain); exactly one is given.
+gw_status solve_W_impl(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, const zdbl *X0, zdbl *Ain,
+                       int32_t n_omega, gw_precision prec, double tol, void *stream, void *W_out, gw_report *rep) {
     if (!ctx) return GW_E_INVALID;
     if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
     GW_HIP(ctx, hipSetDevice(ctx->device));
-    if (!v || !chi0 || !W_out) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
+    if (!v || (!X0 && !Ain) || !W_out) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
     if (n < 1 || n > 32768) return fail(ctx, GW_E_INVALID, "n must be in [1, 32768]");
     if (n_omega < 2 || (n_omega & 1)) return fail(ctx, GW_E_INVALID, "n_omega must be even and >= 2");
     if (prec != GW_FP64 && prec != GW_FP32_IR && prec != GW_BF16X_IR)
@@ -1079,7 +1103,6 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
     gwp::SolvePlan p;
     gw_status s = gwp::solve_plan(ctx, n, n_omega, mixed, "", &p);
     if (s != GW_OK) return s;
-    const zdbl *X0 = (const zdbl *)chi0;
     zdbl *W = (zdbl *)W_out;
     int n_solved = 0, n_fallback = 0, max_it = 0;
     double max_rel = 0.0;
@@ -1092,7 +1115,7 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
         if (const char *e = std::getenv("GW_SOLVE_STREAMS")) nstreams = std::max(1, std::min(2, std::atoi(e)));
         if (ctx->own_stream || n_omega < 8) nstreams = 1;
         if (nstreams == 1) {
-            s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0);
+            s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0, Ain);
             if (s != GW_OK) return s;
             for (auto &bt : freq_batches(n_omega, p.nbmax)) n_solved += bt.second;
         } else {
@@ -1109,7 +1132,10 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
             const auto bts = freq_batches(n_omega, std::max(1, std::min(p2[0].nbmax, (n_omega / 2 + 1) / 2)));
             for (size_t i = 0; i < bts.size(); ++i) {
                 const int j0 = bts[i].first, nb = bts[i].second, q = (int)(i % 2);
-                s = gwp::solve_batch_fp64(ctx, ss[q], n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, p2[q].w);
+                gwp::SolveWs wb;
+                if ((s = gwp::batch_ws(ctx, ss[q], p2[q].w, Ain, W, nn, j0, nb, &wb)) != GW_OK) return s;
+                s = gwp::solve_batch_fp64(ctx, ss[q], n, v, v_is_diag, X0 ? X0 + j0 * nn : nullptr, W + j0 * nn, nb,
+                                          wb);
                 if (s != GW_OK) return s;
                 n_solved += nb;
             }
@@ -1123,7 +1149,10 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
             n_solved += nb;
             std::vector<int> its;
             std::vector<double> rel;
-            s = solve_batch_mixed(ctx, st, n, v, v_is_diag, X0 + j0 * nn, W + j0 * nn, nb, tol, p.w, &its, &rel, 6);
+            gwp::SolveWs wb;
+            if ((s = gwp::batch_ws(ctx, st, p.w, Ain, W, nn, j0, nb, &wb)) != GW_OK) return s;
+            s = solve_batch_mixed(ctx, st, n, v, v_is_diag, X0 ? X0 + j0 * nn : nullptr, W + j0 * nn, nb, tol, wb,
+                                  &its, &rel, 6);
             if (s != GW_OK) return s;
             for (int b = 0; b < nb; ++b) {
                 if (its[b] < 0) {
@@ -1132,7 +1161,7 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
                     ++n_fallback;
                     gwp::SolvePlan p64;
                     if ((s = gwp::solve_plan(ctx, n, 2, false, "fb", &p64)) != GW_OK) return s;
-                    GW_HIP(ctx, hipMemcpyAsync(p64.w.A, p.w.A + (int64_t)b * nn, (size_t)nn * 16,
+                    GW_HIP(ctx, hipMemcpyAsync(p64.w.A, wb.A + (int64_t)b * nn, (size_t)nn * 16,
                                                hipMemcpyDeviceToDevice, st));
                     s = gwp::solve_batch_fp64(ctx, st, n, v, v_is_diag, nullptr, W + (j0 + b) * nn, 1, p64.w);
                     if (s != GW_OK) return s;
@@ -1150,6 +1179,69 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
         rep->n_fallback = n_fallback;
         rep->max_iter = max_it;
         rep->max_rel_update = max_rel;
+    }
+    return GW_OK;
+}
+}  // namespace
+
+extern "C" {
+gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, const void *chi0, int32_t n_omega,
+                     gw_precision prec, double tol, void *stream, void *W_out, gw_report *rep) {
+    if (ctx && !chi0) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
+    return solve_W_impl(ctx, v, v_is_diag, n, (const zdbl *)chi0, nullptr, n_omega, prec, tol, stream, W_out, rep);
+}
+
+gw_status gw_solve_W_A(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, void *A, int32_t n_omega,
+                       gw_precision prec, double tol, void *stream, void *W_out, gw_report *rep) {
+    if (ctx && !A) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
+    return solve_W_impl(ctx, v, v_is_diag, n, nullptr, (zdbl *)A, n_omega, prec, tol, stream, W_out, rep);
+}
+
+gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, void *stream,
+                     void *A_out, gw_report *rep) {
+    if (!ctx) return GW_E_INVALID;
+    if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
+    GW_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = as_stream(stream);
+    if (!v || !A_out || !g) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
+    if (g->n_omega < 128 || g->n_omega > 1024)
+        return fail(ctx, GW_E_INVALID, "gw_build_A needs n_omega in [128, 1024]");
+    gwp::BuildPlan p;
+    gw_status s = gwp::build_plan(ctx, m, g, nullptr, 0, st, "", nullptr, &p);
+    if (s != GW_OK) return s;
+    if (p.nhb - 1 > 65535) return fail(ctx, GW_E_INVALID, "too many spectral bins");
+    const int n = p.n_prod;
+    const int64_t nn = (int64_t)n * n;
+    void *q;
+    if ((s = ws(ctx, "aD", sizeof(double) * p.nhb * nn, &q)) != GW_OK) return s;
+    double *D = (double *)q;
+    if ((s = ws(ctx, "aB", sizeof(double) * p.nhb * nn, &q)) != GW_OK) return s;
+    double *B = (double *)q;
+    const bool kspec = ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != p.dom ||
+                       ctx->ks_eps != g->eps;
+    if ((s = gwp::build_hist_enqueue(ctx, p, st)) != GW_OK) return s;
+    if (kspec) GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, p.j0, p.dom, g->eps, p.Kt, p.tw));
+    // v a0, bin by bin (bins 1 .. nhb-1), then its Cauchy transform is v chi0
+    GW_HIP(ctx, gwk::launch_expand_bins(st, n, p.nhb, p.H, p.n_upper, p.sdev, D));
+    if (p.nhb > 1)
+        GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, D + nn, n, nn, 0.0, B + nn, n, nn, p.nhb - 1));
+    GW_HIP(ctx, gwk::launch_fftconv_A(st, n, g->n_omega, p.nhb, B, p.Kt, p.tw, (zdbl *)A_out));
+    if (kspec) {
+        ctx->ks_n = g->n_omega;
+        ctx->ks_min = g->omega_min;
+        ctx->ks_d = p.dom;
+        ctx->ks_eps = g->eps;
+    }
+    if (rep) {
+        int64_t hs[2];
+        int32_t sv = 0;
+        GW_HIP(ctx, hipMemcpyAsync(hs, p.stat, sizeof(hs), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipMemcpyAsync(&sv, p.sdev, sizeof(sv), hipMemcpyDeviceToHost, st));
+        GW_HIP(ctx, hipStreamSynchronize(st));
+        std::memset(rep, 0, sizeof(*rep));
+        rep->n_hbins = p.nhb;
+        rep->frac_bits_used = sv;
+        rep->n_dropped_pairs = hs[1];
     }
     return GW_OK;
 }

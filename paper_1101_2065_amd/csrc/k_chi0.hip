@@ -405,7 +405,10 @@ struct WPlan {
 // staged through LDS so that every 8 lanes write 128 contiguous bytes of a
 // chi0 row.  Each sequence: forward FFT of the odd extension (purely
 // imaginary spectrum i alpha), times i Kt, inverse FFT, scale 1/L.
-template <typename HT, int L>
+// FULL: the spectral arrays are dense [m][n][n] (n_upper = n^2, every nu, no
+// symmetry) and hold v a0, so the transform is v chi0 and the kernel writes
+// A = 1 - v chi0.
+template <typename HT, int L, bool FULL = false>
 __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, const HT *__restrict__ H,
                                                    int64_t n_upper, const int32_t *__restrict__ s_dev,
                                                    const zdbl *__restrict__ Kt, const zdbl *__restrict__ tw,
@@ -416,18 +419,18 @@ __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, 
     const int nch = (n + 7) / 8;
     const int mu = blockIdx.x / nch;
     const int nu0 = (blockIdx.x % nch) * 8;
-    if (nu0 + 7 < mu) return;
+    if (!FULL && nu0 + 7 < mu) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int s = s_dev ? *s_dev : 0;
     const int64_t nn = (int64_t)n * n;
-    const int64_t trow = (int64_t)mu * n - ((int64_t)mu * (mu - 1)) / 2 - mu;
+    const int64_t trow = FULL ? (int64_t)mu * n : (int64_t)mu * n - ((int64_t)mu * (mu - 1)) / 2 - mu;
     // histogram rows of the 8 sequences, scaled to doubles: Hs[m][w], m < nhb
     double *Hs = lds;
     for (int idx = tid; idx < nhb * 8; idx += 512) {
         const int m = idx >> 3, ww = idx & 7;
         const int nu = nu0 + ww;
         double v = 0.0;
-        if (m >= 1 && nu >= mu && nu < n) v = hval(H, (int64_t)m * n_upper + trow + nu, s);
+        if (m >= 1 && (FULL || nu >= mu) && nu < n) v = hval(H, (int64_t)m * n_upper + trow + nu, s);
         Hs[m * 9 + ww] = v;
     }
     __syncthreads();
@@ -469,9 +472,10 @@ __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, 
     for (int idx = tid; idx < 8 * n_omega; idx += 512) {
         const int ww = idx & 7, j = idx >> 3;
         const int nu = nu0 + ww;
-        if (nu >= mu && nu < n) {
+        if ((FULL || nu >= mu) && nu < n) {
             const double *src = lds + ww * REG + 2 * j;
-            const zdbl v{src[0], src[1]};
+            zdbl v{src[0], src[1]};
+            if (FULL) v = zdbl{(nu == mu ? 1.0 : 0.0) - v.re, -v.im};
             chi0[j * nn + (int64_t)mu * n + nu] = v;
         }
     }
@@ -508,7 +512,78 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int n_omega, int nt, 
     }
 }
 
+// Bins 1..nhb-1 of the packed exact histogram as dense symmetric doubles,
+// D[m][mu][nu] = 2^-s H[m][t(min, max)]; 32 x 32 tiles through LDS as in
+// k_symmetrize.  Workgroup = one upper tile (bi <= bj) of bin blockIdx.y + 1.
+__global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_t *__restrict__ H, int64_t n_upper,
+                                                     const int32_t *__restrict__ s_dev, double *__restrict__ D) {
+    __shared__ double t[32][33];
+    int tile = blockIdx.x, bi = 0;
+    while (tile >= nt - bi) {
+        tile -= nt - bi;
+        ++bi;
+    }
+    const int bj = bi + tile;
+    const int s = *s_dev;
+    const int64_t nn = (int64_t)n * n;
+    const int64_t m = (int64_t)blockIdx.y + 1;
+    const int64_t *Hm = H + m * n_upper;
+    double *Dm = D + m * nn;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = bi * 32 + ty + 8 * q, c = bj * 32 + tx;
+        double val = 0.0;
+        if (r < n && c < n && c >= r) {
+            const int64_t tr = (int64_t)r * n - ((int64_t)r * (r - 1)) / 2 - r;
+            val = ldexp((double)Hm[tr + c], -s);
+            Dm[(int64_t)r * n + c] = val;
+        }
+        t[ty + 8 * q][tx] = val;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = bj * 32 + ty + 8 * q, c = bi * 32 + tx;  // lower (r, c) = upper (c, r)
+        if (r < n && c < n && r > c) Dm[(int64_t)r * n + c] = t[tx][ty + 8 * q];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_expand_bins(hipStream_t st, int n, int nhb, const int64_t *H, int64_t n_upper,
+                              const int32_t *s_dev, double *D) {
+    if (nhb < 2) return hipSuccess;
+    if (nhb - 1 > 65535) return hipErrorInvalidValue;
+    const int nt = (n + 31) / 32;
+    ProfScope pm(st, "expand_bins", 0.0, (8.0 * (nhb - 1)) * ((double)n * (n + 1) / 2 + (double)n * n));
+    hipLaunchKernelGGL(k_expand_bins, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)(nhb - 1)), dim3(256), 0, st, n,
+                       nt, H, n_upper, s_dev, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_fftconv_A(hipStream_t st, int n, int n_omega, int nhb, const double *B, const zdbl *Kt,
+                            const zdbl *tw, zdbl *A) {
+    const int64_t nn = (int64_t)n * n;
+    const int L = 2 * n_omega;
+    ProfScope ps(st, "fftconv_A", 0.0, 8.0 * (nhb - 1) * (double)nn + 16.0 * n_omega * (double)nn);
+    dim3 gw((unsigned)((int64_t)n * ((n + 7) / 8)));
+#define GW_FFTA_CASE(LL)                                                                                            \
+    case LL:                                                                                                        \
+        hipLaunchKernelGGL((k_fftconv_w<double, LL, true>), gw, dim3(512), 0, st, n, n_omega, nhb, B, nn,           \
+                           (const int32_t *)nullptr, Kt, tw, A);                                                    \
+        break;
+    switch (L) {
+        GW_FFTA_CASE(256)
+        GW_FFTA_CASE(512)
+        GW_FFTA_CASE(1024)
+        GW_FFTA_CASE(2048)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef GW_FFTA_CASE
+    return hipGetLastError();
+}
 
 hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, double eps, zdbl *Kt, zdbl *tw) {
     const int L = 2 * n_omega;

@@ -86,6 +86,10 @@ _SIGS = {
                                     _P, ctypes.POINTER(gw_report)]),
     "gw_solve_W": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
+    "gw_solve_W_A": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
+                                    ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
+    "gw_build_A": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P,
+                                  ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "gw_decompress": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "gw_pair_basis": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.c_double, ctypes.c_int32, _P, _P,
@@ -222,6 +226,22 @@ class Context:
                             _stream_handle(stream), _ptr(W_out),
                             ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_solve_W")
+        return rep
+
+    def build_A(self, mol: "gw_molecule", v, grid: "gw_grid", A_out, stream=None, report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_build_A(self.h, ctypes.byref(mol), _ptr(v), ctypes.byref(grid), _stream_handle(stream),
+                            _ptr(A_out), ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_build_A")
+        return rep
+
+    def solve_W_A(self, v, n: int, A, n_omega: int, W_out, prec: int = GW_FP64, tol: float = 1e-7,
+                  v_is_diag: bool = False, stream=None, report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_solve_W_A(self.h, _ptr(v), int(v_is_diag), n, _ptr(A), n_omega, prec, tol,
+                              _stream_handle(stream), _ptr(W_out),
+                              ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_solve_W_A")
         return rep
 
     def compress_basis(self, v, n: int, k: int, Q_out, S_out, stream=None):
