@@ -6,11 +6,14 @@ Default workload (`n2000`): W(omega) per second for one molecule of exactly
 1024-point mesh.  One step = the whole path: pair vertex, mesh bins, exact
 int64 histogram, FFT chi0 on all 1024 mesh points (gw_build_chi0), then
 W(omega) = (1 - v chi0)^{-1} v on all 1024 points (gw_solve_W: 513 factorised,
-the rest by the conjugate mirror).  Inputs are resident in HBM before the
-timed region.  The precision forms are timed in turn (FP64; FP32 LU + FP64
-residual refinement; the same with split-BF16 trailing updates); `value` is
-the fastest form that meets the 1e-6 error target relative to the FP64
-result.
+the rest by the conjugate mirror).  The `_A` forms take the same path with A =
+1 - v chi0 formed at the FFT from v a0 (gw_build_A: one real product by v per
+spectral bin instead of one complex product per solved frequency), then W
+from A (gw_solve_W_A).  Inputs are resident in HBM before the timed region.
+The precision forms are timed in turn (FP64; FP32 LU + FP64 residual
+refinement; the same with split-BF16 trailing updates; each on either route);
+`value` is the fastest form that meets the 1e-6 error target relative to the
+FP64 chi0-route result.
 
 Other workloads (one JSON line each, same keys):
   c1    the 40-atom chain with all of its products
@@ -43,6 +46,10 @@ N_PROD = 2000
 PEAK_FP64 = 78.6e12
 PEAK_FP32 = 157.3e12
 FORMS = {"fp64": 0, "fp32_ir": 1, "bf16x_ir": 2}  # gw_precision values
+# the form the committed profiles were taken on (the default headline form),
+# and the step it times
+PROFILE_FORM = "fp64_A"
+PROFILE_STEP = "FP64 step (A = 1 - v chi0 from v a0 + W solve)"
 
 
 def log(*a):
@@ -830,13 +837,13 @@ def summarize_profiles(stats_csv, fetch_csv, write_csv, out_json):
     with open(out_json, "w") as f:
         json.dump(out, f, indent=1)
     md = [
-        "# HBM traffic per dispatch: FP64 step (chi0 build + W solve), 40-atom chain truncated to N_prod=2000, "
-        "1024 frequencies", "",
+        "# HBM traffic per dispatch: %s, 40-atom chain truncated to N_prod=2000, "
+        "1024 frequencies" % PROFILE_STEP, "",
         "Commands (repository root, one MI355X; one counter per run; OUT is any output directory):", "", "```",
         "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc_fetch -o run --output-format csv -- python3 bench.py "
-        "--forms fp64 --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "--forms %s --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration" % PROFILE_FORM,
         "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc_write -o run --output-format csv -- python3 bench.py "
-        "--forms fp64 --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "--forms %s --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration" % PROFILE_FORM,
         "python bench.py --summarize-counters $OUT/prof_n2000/run_kernel_stats.csv "
         "$OUT/pmc_fetch/run_counter_collection.csv $OUT/pmc_write/run_counter_collection.csv",
         "```", "",
@@ -874,11 +881,11 @@ def summarize_mfma(counter_csv, out_md):
             continue
         rows.append((k, a["MfmaUtil"][1], a["MfmaUtil"][0] / max(a["MfmaUtil"][1], 1), fl))
     rows.sort(key=lambda x: -x[3] * x[1])
-    md = ["# Matrix-core use per dispatch: FP64 step (chi0 build + W solve), 40-atom chain truncated to "
-          "N_prod=2000, 1024 frequencies", "",
+    md = ["# Matrix-core use per dispatch: %s, 40-atom chain truncated to "
+          "N_prod=2000, 1024 frequencies" % PROFILE_STEP, "",
           "Commands (repository root, one MI355X; OUT is any output directory):", "", "```",
           "rocprofv3 --pmc MfmaUtil MfmaFlopsF64 -d $OUT/pmc_mfma -o run --output-format csv -- python3 "
-          "bench.py --forms fp64 --steps 1 --warmup 0 --no-cpu-baseline",
+          "bench.py --forms %s --steps 1 --warmup 0 --no-cpu-baseline" % PROFILE_FORM,
           "python bench.py --summarize-mfma $OUT/pmc_mfma/run_counter_collection.csv", "```", "",
           "MfmaUtil = MFMA busy cycles / (active cycles x SIMDs) in percent; MfmaFlopsF64 = executed FP64 matrix "
           "flops (512 per counted op), padding of partial tiles included.", "",
@@ -894,8 +901,8 @@ def summarize_mfma(counter_csv, out_md):
 
 
 def summarize_trace(stats_csv, out_md):
-    """Kernel table from a rocprofv3 --kernel-trace --stats run of the FP64
-    step (one warm-up step and one timed step)."""
+    """Kernel table from a rocprofv3 --kernel-trace --stats run of the
+    profiled step (one warm-up step and one timed step)."""
     rows = []
     for r in _csv_rows(stats_csv):
         name = r.get("Name") or r.get("KernelName") or ""
@@ -904,13 +911,13 @@ def summarize_trace(stats_csv, out_md):
         rows.append((name, calls, tot))
     rows.sort(key=lambda x: -x[2])
     total = sum(x[2] for x in rows) or 1.0
-    md = ["# Kernel profile: FP64 step (chi0 build + W solve), 40-atom chain truncated to N_prod=2000, "
-          "1024 frequencies", "",
+    md = ["# Kernel profile: %s, 40-atom chain truncated to N_prod=2000, "
+          "1024 frequencies" % PROFILE_STEP, "",
           "Command (repository root, one MI355X; OUT is any output directory):", "", "```",
           "rocprofv3 --kernel-trace --stats -d $OUT/prof_n2000 -o run --output-format csv -- python3 bench.py "
-          "--forms fp64 --steps 1 --warmup 1 --no-cpu-baseline",
+          "--forms %s --steps 1 --warmup 1 --no-cpu-baseline" % PROFILE_FORM,
           "python bench.py --summarize-trace $OUT/prof_n2000/run_kernel_stats.csv", "```", "",
-          "Two steps (one warm-up, one timed) of gw_build_chi0 + gw_solve_W; all kernels from `run_kernel_stats.csv`:",
+          "Two steps (one warm-up, one timed) of gw_build_A + gw_solve_W_A; all kernels from `run_kernel_stats.csv`:",
           "", "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
     for name, calls, tot in rows:
         short = name.replace("(anonymous namespace)::", "")
@@ -946,13 +953,13 @@ def main():
     ap.add_argument("--summarize-mfma", metavar="COUNTER_CSV",
                     help="write profiles/mfma_chain40_n2000.md from a MfmaUtil/MfmaFlopsF64 counter run")
     ap.add_argument("--summarize-trace", metavar="STATS_CSV",
-                    help="write the kernel table of profiles/kernels_fp64_chain40_n2000.md and exit (no GPU)")
+                    help="write the kernel table of profiles/kernels_fp64A_chain40_n2000.md and exit (no GPU)")
     args = ap.parse_args()
     if args.summarize_mfma:
         summarize_mfma(args.summarize_mfma, os.path.join(HERE, "profiles", "mfma_chain40_n2000.md"))
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, os.path.join(HERE, "profiles", "kernels_fp64_chain40_n2000.md"))
+        summarize_trace(args.summarize_trace, os.path.join(HERE, "profiles", "kernels_fp64A_chain40_n2000.md"))
         return
     if args.summarize_counters:
         summarize_profiles(*args.summarize_counters, TRAFFIC_FILE)
@@ -962,8 +969,9 @@ def main():
               "documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.forms is None:
-        args.forms = {"n2000": "fp64,fp32_ir,bf16x_ir", "n2000_2w": "fp64", "n2000_time": "fp64", "n2000_sigma": "fp64",
-                      "c1": "fp64,bf16x_ir",
+        args.forms = {"n2000": "fp64,fp64_A,fp32_ir,bf16x_ir", "n2000_2w": "fp64", "n2000_time": "fp64",
+                      "n2000_sigma": "fp64",
+                      "c1": "fp64,fp64_A,bf16x_ir",
                       "c2": "fp64,bf16x_ir",
                       "c2pair": "fp64", "c3": "fp64", "c4": "fp64"}[args.workload]
 

@@ -1,7 +1,8 @@
 """Parity at the full size of the 2000-product workload (the 40-atom chain
 truncated to 2000 products, 57600 pairs, 1024-point mesh), in the launch
 configuration the benchmark times: every precision form of the solve on all
-mesh points with the default streams.
+mesh points with the default streams, on both routes to A = 1 - v chi0 (from
+chi0, and from v a0 at the FFT).
 
 The oracle cannot hold the whole 2000 x 2000 x 192-bin histogram in seconds,
 so it checks what it can compute one by one: sampled histogram entries bit for
@@ -120,6 +121,50 @@ def test_full_size_chi0_and_W(setup):
         _say("prec", prec, "asymmetry", asym)
         assert asym == 0.0 if prec == gw.GW_FP64 else asym < 1e-9
         assert torch.equal(W[N - (N // 2 + 40)], W[N // 2 + 40].conj())
+
+
+def test_full_size_A_route(setup):
+    """The headline form: A = 1 - v chi0 formed from v a0 (gw_build_A) and W
+    from A (gw_solve_W_A) in FP64, in the benchmark's launch configuration.
+    A on sampled rows against 1 - v chi0 of the chi0 route (whose sampled
+    entries the test above pins to the oracle), W through the defining
+    equation on sampled columns, its symmetry and the conjugate mirror."""
+    gw, ctx, torch, mol, dm, P, s, _ = setup
+    torch.cuda.empty_cache()
+    grid = gs.config_grid(1)
+    N, n = grid.n_omega, mol.n_prod
+    wj = [N // 2, N // 2 + 40, N // 2 + 300, N - 1]
+    buf = torch.empty((N, n, n), dtype=torch.complex128, device="cuda")
+    ctx.build_chi0(dm.struct, _g(gw, grid), buf)
+    chis = {j: buf[j].cpu().numpy() for j in wj}
+    rep = ctx.build_A(dm.struct, dm.v, _g(gw, grid), buf)
+    torch.cuda.synchronize()
+    assert rep.frac_bits_used == s
+    idx = np.array([0, 1, 63, 64, 777, 1500, n - 1])
+    it = torch.as_tensor(idx, device="cuda")
+    for j in wj:
+        Ar = buf[j][it].cpu().numpy()
+        ref = np.eye(n)[idx] - mol.v[idx] @ chis[j]
+        e = np.linalg.norm(Ar - ref) / np.linalg.norm(ref)
+        _say("A j", j, "rel on sampled rows", e)
+        assert e < 1e-12
+    W = torch.full_like(buf, float("nan"))
+    r = ctx.solve_W_A(dm.v, n, buf, N, W, prec=gw.GW_FP64)
+    torch.cuda.synchronize()
+    assert r.n_solved == N // 2 + 1 and r.n_fallback == 0
+    del buf
+    for j in wj:
+        Wc = W[j][:, it].cpu().numpy()
+        lhs = Wc - mol.v @ (chis[j] @ Wc)
+        e = np.linalg.norm(lhs - mol.v[:, idx]) / np.linalg.norm(mol.v[:, idx])
+        _say("A route j", j, "residual of (1 - v chi0) W = v on sampled columns", e)
+        assert e < 1e-10
+    Wr = W[N // 2 + 40][it].cpu().numpy()
+    Wcol = W[N // 2 + 40][:, it].cpu().numpy()
+    assert np.abs(Wr - Wcol.T).max() == 0.0
+    assert torch.equal(W[N - (N // 2 + 40)], W[N // 2 + 40].conj())
+    del W
+    torch.cuda.empty_cache()
 
 
 def test_full_size_two_windows(setup):

@@ -4,7 +4,8 @@ frequencies, chi0 applied to each column by the oracle's pair-vertex route
 (unquantised: bar 1e-6, the bar of the refined forms):
 
 * the whole 40-atom chain (2304 products, 1024 points; panels taller than
-  2048 rows), FP64 and split-BF16 with FP64 refinement;
+  2048 rows), FP64 and split-BF16 with FP64 refinement, and FP64 from A =
+  1 - v chi0 formed from v a0 (equal to the chi0 route's W within 1e-11);
 * the largest molecule of the 64-molecule batch (512 points; panels taller
   than 4096 rows), solved in place through a recorded batch graph, FP64."""
 import sys
@@ -64,6 +65,7 @@ def test_c1_whole_chain(gpu):
     rng = np.random.default_rng(31)
     cols = rng.integers(0, n, 3)
     js = [N // 2, N // 2 + 150, 300]
+    ref = None
     for form, prec in (("fp64", gw.GW_FP64), ("bf16x_ir", gw.GW_BF16X_IR)):
         rep = ctx.solve_W(dm.v, n, chi, N, W, prec=prec, tol=1e-7)
         torch.cuda.synchronize()
@@ -71,6 +73,16 @@ def test_c1_whole_chain(gpu):
         e = _worst_residual(mol, grid, W, js, cols)
         _say("C1 %s: max residual %.2e" % (form, e))
         assert e < 1e-6
+        if form == "fp64":
+            ref = W[js][:, :, cols].cpu().numpy()
+    # A = 1 - v chi0 formed from v a0 at the FFT (over chi0's buffer), W from A
+    ctx.build_A(dm.struct, dm.v, g, chi)
+    rep = ctx.solve_W_A(dm.v, n, chi, N, W, prec=gw.GW_FP64)
+    torch.cuda.synchronize()
+    e = _worst_residual(mol, grid, W, js, cols)
+    d = float(np.linalg.norm(W[js][:, :, cols].cpu().numpy() - ref) / np.linalg.norm(ref))
+    _say("C1 fp64 from A: max residual %.2e, vs the chi0 route %.2e" % (e, d))
+    assert e < 1e-6 and d < 1e-11
     del chi, W
     torch.cuda.empty_cache()
 
