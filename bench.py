@@ -24,7 +24,8 @@ Other workloads (one JSON line each, same keys):
   n2000_time  the 2000-product molecule, a0 by the paper's time-domain route
   n2000_sigma  the same carried through to the GW self-energy on all points
   c3    64 chain molecules (8..80 atoms, 512 points) as recorded hipGraph
-        batches, W written over chi0 in place
+        batches, solved in place (A = 1 - v chi0 formed from v a0 in each
+        molecule's buffer, then W over it)
   c4    serving: Poisson arrivals at 20/s for 60 s (overloaded), then a
         labelled below-capacity run
 
@@ -548,7 +549,8 @@ def run_time_route(args, gw, gs, torch):
 # ---------------------------------------------------------------------- self-energy
 def run_self_energy(args, gw, gs, torch):
     """The 2000-product molecule on the 1024-point mesh carried through to the
-    GW self-energy: one step = chi0 + W (FP64, all points) + sigma+- by the
+    GW self-energy: one step = A = 1 - v chi0 from v a0 + W (FP64, all points;
+    the headline route) + sigma+- by the
     time-by-time convolution + Sigma on all points + exchange + Dyson's
     equation and the DOS on all points (V_xc = 0: the synthetic orbitals carry
     no DFT potential; the arithmetic is the same).  value = Sigma(omega)
@@ -574,9 +576,9 @@ def run_self_energy(args, gw, gs, torch):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
         t0 = time.perf_counter()
         ev[0].record(stream)
-        ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
+        ctx.build_A(dm.struct, dm.v, g, chi, stream=stream, report=False)  # chi holds A
         ev[1].record(stream)
-        ctx.solve_W(dm.v, n, chi, N, W, stream=stream, report=False)
+        ctx.solve_W_A(dm.v, n, chi, N, W, stream=stream, report=False)
         ev[2].record(stream)
         if timed and roof is None:
             ctx.profile_begin()
@@ -590,15 +592,15 @@ def run_self_energy(args, gw, gs, torch):
         if timed and roof is None:
             roof = kernel_roofline(ctx.profile_read())
             ctx.profile_end()
-        log("self-energy step %d: chi0 %.3fs W %.3fs Sigma %.3fs Dyson+DOS %.3fs wall %.3fs" % (it, *parts, wall))
+        log("self-energy step %d: A %.3fs W %.3fs Sigma %.3fs Dyson+DOS %.3fs wall %.3fs" % (it, *parts, wall))
         if timed:
             ts.append((wall, *parts))
     a = np.median(np.array(ts), axis=0)
-    out = base_record(args, "Sigma(omega)/s, 2000 products, 1024 points (chi0, W, sigma by time-domain convolution, "
+    out = base_record(args, "Sigma(omega)/s, 2000 products, 1024 points (A = 1 - v chi0, W, sigma by time-domain convolution, "
                             "Sigma, exchange, Dyson + DOS)", N / a[0], "Sigma(omega)/s", a[0], "f64",
                       {"workload": "chain40_nprod2000_nomega1024_self_energy", "n_prod": n, "n_orb": no,
                        "n_omega": N, "parallelism": "none (1 GPU)"})
-    out["phases_s"] = {"chi0": a[1], "W": a[2], "self_energy": a[3], "dyson_dos": a[4]}
+    out["phases_s"] = {"A_from_v_a0": a[1], "W": a[2], "self_energy": a[3], "dyson_dos": a[4]}
     out["roofline_sigma_dyson_phases"] = roof
     ctx.close()
     return out
@@ -618,10 +620,11 @@ def run_c3(args, gw, gs, torch):
 
     def next_group(start):
         # consecutive molecules whose in-place outputs fit in what is free now,
-        # leaving room for the context's (grow-only) workspaces
+        # leaving room for the context's (grow-only) workspaces (the in-place
+        # molecules' v a0 bins take up to 18 GB of them)
         torch.cuda.empty_cache()
         free, _ = torch.cuda.mem_get_info()
-        cap = free - (64 << 30)
+        cap = free - (88 << 30)
         grp, used = [], 0
         for i in range(start, len(mols)):
             b = N * mols[i].n_prod ** 2 * 16
@@ -661,7 +664,8 @@ def run_c3(args, gw, gs, torch):
             solves += sum(r.n_solved for r in reps)
             worst_fb = max(worst_fb, max(r.n_fallback for r in reps))
             for i in grp:
-                fl = solve_flops(mols[i].n_prod, N // 2 + 1, 2, form != "fp64")
+                # in place: A is formed from v a0 (no 4N^3 product per frequency)
+                fl = solve_flops(mols[i].n_prod, N // 2 + 1, 2, form != "fp64", form_a=False)
                 flops += fl["fp64"] + fl["fp32"]
             log("c3 %s group %d: %d molecules (n_prod %d..%d) create %.2fs replay %.2fs" % (
                 form, gi, len(grp), min(mols[i].n_prod for i in grp), max(mols[i].n_prod for i in grp), tc, tr))

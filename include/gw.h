@@ -383,7 +383,10 @@ gw_status gw_pair_basis(gw_ctx *ctx, const gw_molecule *m, const double *v, doub
  *   whose last step left ||dW||_F > tol ||W||_F (counted in the report).
  *   W_out[i] == chi0_out[i] solves in place; the FP64 re-solve then has no
  *   chi0 to start from, so such a frequency makes gw_batch_run return
- *   GW_E_NOCONV (after filling every report).
+ *   GW_E_NOCONV (after filling every report).  An in-place molecule on a
+ *   mesh of 128 to 1024 points takes the gw_build_A route (A = 1 - v chi0
+ *   formed from v a0 in the buffer, then W over it); its buffer never holds
+ *   chi0.
  *   reps: HOST [n_mol] or NULL (then gw_batch_run does not synchronise for
  *   FP64).  A later gw_batch_create on the same context retires earlier
  *   batches (gw_batch_run on them returns GW_E_STATE).  Not thread-safe with

@@ -415,6 +415,36 @@ gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st) {
     return GW_OK;
 }
 
+gw_status a_route_ws(gw_ctx *c, const std::string &pre, int n, int nhb, ARouteWs *w) {
+    const size_t nn = (size_t)n * n;
+    // dense bins staged at most 2 GiB at a time (at least one bin)
+    w->dchunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(1, nhb - 1), ((size_t)2 << 30) / (8 * nn)));
+    void *q;
+    gw_status s;
+    if ((s = ws(c, pre + "aD", 8 * nn * w->dchunk, &q)) != GW_OK) return s;
+    w->D = (double *)q;
+    if ((s = ws(c, pre + "aB", 8 * nn * std::max(1, nhb), &q)) != GW_OK) return s;
+    w->B = (double *)q;
+    return GW_OK;
+}
+
+gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
+                          bool with_kspec, void *A_out) {
+    gw_status s = build_hist_enqueue(ctx, p, st);
+    if (s != GW_OK) return s;
+    if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
+    // v a0 bin by bin (bins 1 .. nhb-1); its Cauchy transform is v chi0
+    const int n = p.n_prod;
+    const int64_t nn = (int64_t)n * n;
+    for (int m0 = 1; m0 < p.nhb; m0 += w.dchunk) {
+        const int cnt = std::min(w.dchunk, p.nhb - m0);
+        GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, p.H, p.n_upper, p.sdev, w.D));
+        GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
+    }
+    GW_HIP(ctx, gwk::launch_fftconv_A(st, n, p.g.n_omega, p.nhb, w.B, p.Kt, p.tw, (zdbl *)A_out));
+    return GW_OK;
+}
+
 gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
     gw_status s = build_hist_enqueue(ctx, p, st);
     if (s != GW_OK) return s;
@@ -1209,23 +1239,11 @@ gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const g
     gwp::BuildPlan p;
     gw_status s = gwp::build_plan(ctx, m, g, nullptr, 0, st, "", nullptr, &p);
     if (s != GW_OK) return s;
-    if (p.nhb - 1 > 65535) return fail(ctx, GW_E_INVALID, "too many spectral bins");
-    const int n = p.n_prod;
-    const int64_t nn = (int64_t)n * n;
-    void *q;
-    if ((s = ws(ctx, "aD", sizeof(double) * p.nhb * nn, &q)) != GW_OK) return s;
-    double *D = (double *)q;
-    if ((s = ws(ctx, "aB", sizeof(double) * p.nhb * nn, &q)) != GW_OK) return s;
-    double *B = (double *)q;
+    gwp::ARouteWs aw;
+    if ((s = gwp::a_route_ws(ctx, "", p.n_prod, p.nhb, &aw)) != GW_OK) return s;
     const bool kspec = ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != p.dom ||
                        ctx->ks_eps != g->eps;
-    if ((s = gwp::build_hist_enqueue(ctx, p, st)) != GW_OK) return s;
-    if (kspec) GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, p.j0, p.dom, g->eps, p.Kt, p.tw));
-    // v a0, bin by bin (bins 1 .. nhb-1), then its Cauchy transform is v chi0
-    GW_HIP(ctx, gwk::launch_expand_bins(st, n, p.nhb, p.H, p.n_upper, p.sdev, D));
-    if (p.nhb > 1)
-        GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, D + nn, n, nn, 0.0, B + nn, n, nn, p.nhb - 1));
-    GW_HIP(ctx, gwk::launch_fftconv_A(st, n, g->n_omega, p.nhb, B, p.Kt, p.tw, (zdbl *)A_out));
+    if ((s = gwp::a_route_enqueue(ctx, p, st, v, aw, kspec, A_out)) != GW_OK) return s;
     if (kspec) {
         ctx->ks_n = g->n_omega;
         ctx->ks_min = g->omega_min;

@@ -190,6 +190,20 @@ gw_status record(gw_batch *b) {
             sp[i].final_norms = b->norms[i];
         }
     }
+    // in-place molecules never expose chi0: they take the route that forms
+    // A = 1 - v chi0 from v a0 in the buffer (one real product per bin instead
+    // of one complex product per solved frequency); the builds run one after
+    // another on the capture stream, so they share one workspace
+    std::vector<char> route_a(b->n_mol, 0);
+    std::vector<gwp::ARouteWs> aw(b->n_mol);
+    const bool mesh_a = b->g.n_omega >= 128 && b->g.n_omega <= 1024;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < b->n_mol; ++i) {
+            route_a[i] = mesh_a && b->W[i] == b->chi0[i];
+            if (!route_a[i]) continue;
+            gw_status s = gwp::a_route_ws(ctx, "ba", b->n[i], bp[i].nhb, &aw[i]);
+            if (s != GW_OK) return s;
+        }
     GW_HIP(ctx, hipStreamSynchronize(st));
     GW_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     // from here on every failure still ends the capture below
@@ -197,15 +211,18 @@ gw_status record(gw_batch *b) {
     auto hip = [&](hipError_t e, const char *what) {
         if (e != hipSuccess && s == GW_OK) s = fail(ctx, GW_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     };
-    for (int i = 0; i < b->n_mol && s == GW_OK; ++i) s = gwp::build_enqueue(ctx, bp[i], st, b->chi0[i], i == 0);
+    for (int i = 0; i < b->n_mol && s == GW_OK; ++i)
+        s = route_a[i] ? gwp::a_route_enqueue(ctx, bp[i], st, b->v[i], aw[i], i == 0, b->chi0[i])
+                       : gwp::build_enqueue(ctx, bp[i], st, b->chi0[i], i == 0);
     if (s == GW_OK) {
         hip(hipEventRecord(b->events[0], st), "fork");
         for (int r = 0; r < nbr; ++r) hip(hipStreamWaitEvent(b->branches[r], b->events[0], 0), "fork");
         gwp::Bf16xScope bf16x(b->prec == GW_BF16X_IR);
         for (int i = 0; i < b->n_mol && s == GW_OK; ++i) {
             gwp::set_thread_gemm_tile(b->tile[i]);
-            s = gwp::solve_enqueue_nosync(ctx, sp[i], b->branches[i % nbr], b->v[i], 0, (const gwp::zdbl *)b->chi0[i],
-                                          (gwp::zdbl *)b->W[i], mixed ? b->n_refine : 0);
+            gwp::zdbl *buf = (gwp::zdbl *)b->chi0[i];
+            s = gwp::solve_enqueue_nosync(ctx, sp[i], b->branches[i % nbr], b->v[i], 0, route_a[i] ? nullptr : buf,
+                                          (gwp::zdbl *)b->W[i], mixed ? b->n_refine : 0, route_a[i] ? buf : nullptr);
         }
         gwp::set_thread_gemm_tile(-1);
         for (int r = 0; r < nbr; ++r) {

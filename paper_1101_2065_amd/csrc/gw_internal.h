@@ -66,9 +66,9 @@ hipError_t launch_fftconv(hipStream_t st, int n, int n_omega, int nhb, const dou
                           const zdbl *Kt, const zdbl *tw, zdbl *chi0, bool symmetrize = true);
 // chi0[j][nu][mu] = chi0[j][mu][nu] for mu < nu, all j < n_omega.
 hipError_t launch_symmetrize(hipStream_t st, int n, int n_omega, zdbl *chi0);
-// D[m][mu][nu] = 2^-s H[m][t(mu, nu)] for bins 1 <= m < nhb, both triangles
-// (bin 0 of D is not written).
-hipError_t launch_expand_bins(hipStream_t st, int n, int nhb, const int64_t *H, int64_t n_upper,
+// D[m - m0][mu][nu] = 2^-s H[m][t(mu, nu)] for bins m0 <= m < m0 + cnt, both
+// triangles.
+hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const int64_t *H, int64_t n_upper,
                               const int32_t *s_dev, double *D);
 // A[j] = 1 - sum_m B[m] K_m(omega_j) for dense B[nhb][n][n] = v a0 (bins
 // m >= 1 read), every (mu, nu); 256 <= 2 n_omega <= 2048.

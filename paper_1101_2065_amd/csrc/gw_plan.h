@@ -52,6 +52,19 @@ gw_status build_plan(gw_ctx *c, const gw_molecule *m, const gw_grid *g, const do
 // spectrum (once per mesh).
 gw_status build_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec);
 
+// A = 1 - v chi0 formed from v a0: the products v a0 of every bin (B, bins
+// >= 1 used) and the dense bins of one chunk (D, dchunk bins).
+struct ARouteWs {
+    double *D = nullptr, *B = nullptr;
+    int dchunk = 1;
+};
+// Workspace of the route for n products and nhb bins (named `prefix`aD/aB;
+// grow-only, so a run of calls leaves buffers that fit the largest).
+gw_status a_route_ws(gw_ctx *c, const std::string &prefix, int n, int nhb, ARouteWs *w);
+// a1-a3 as build_enqueue, then A[j] = 1 - v chi0(omega_j) for all j into A_out.
+gw_status a_route_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
+                          bool with_kspec, void *A_out);
+
 struct SolveWs {
     zdbl *A = nullptr;
     zflt *A32 = nullptr, *B32 = nullptr;

@@ -512,11 +512,13 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int n_omega, int nt, 
     }
 }
 
-// Bins 1..nhb-1 of the packed exact histogram as dense symmetric doubles,
-// D[m][mu][nu] = 2^-s H[m][t(min, max)]; 32 x 32 tiles through LDS as in
-// k_symmetrize.  Workgroup = one upper tile (bi <= bj) of bin blockIdx.y + 1.
+// Bins m0 .. m0+cnt-1 of the packed exact histogram as dense symmetric
+// doubles, D[m - m0][mu][nu] = 2^-s H[m][t(min, max)]; 32 x 32 tiles through
+// LDS as in k_symmetrize.  Workgroup = one upper tile (bi <= bj) of bin
+// m0 + blockIdx.y.
 __global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_t *__restrict__ H, int64_t n_upper,
-                                                     const int32_t *__restrict__ s_dev, double *__restrict__ D) {
+                                                     const int32_t *__restrict__ s_dev, int m0,
+                                                     double *__restrict__ D) {
     __shared__ double t[32][33];
     int tile = blockIdx.x, bi = 0;
     while (tile >= nt - bi) {
@@ -526,9 +528,8 @@ __global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_
     const int bj = bi + tile;
     const int s = *s_dev;
     const int64_t nn = (int64_t)n * n;
-    const int64_t m = (int64_t)blockIdx.y + 1;
-    const int64_t *Hm = H + m * n_upper;
-    double *Dm = D + m * nn;
+    const int64_t *Hm = H + ((int64_t)m0 + blockIdx.y) * n_upper;
+    double *Dm = D + (int64_t)blockIdx.y * nn;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -551,14 +552,14 @@ __global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_
 
 }  // namespace
 
-hipError_t launch_expand_bins(hipStream_t st, int n, int nhb, const int64_t *H, int64_t n_upper,
+hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const int64_t *H, int64_t n_upper,
                               const int32_t *s_dev, double *D) {
-    if (nhb < 2) return hipSuccess;
-    if (nhb - 1 > 65535) return hipErrorInvalidValue;
+    if (cnt < 1) return hipSuccess;
+    if (cnt > 65535 || m0 < 0) return hipErrorInvalidValue;
     const int nt = (n + 31) / 32;
-    ProfScope pm(st, "expand_bins", 0.0, (8.0 * (nhb - 1)) * ((double)n * (n + 1) / 2 + (double)n * n));
-    hipLaunchKernelGGL(k_expand_bins, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)(nhb - 1)), dim3(256), 0, st, n,
-                       nt, H, n_upper, s_dev, D);
+    ProfScope pm(st, "expand_bins", 0.0, (8.0 * cnt) * ((double)n * (n + 1) / 2 + (double)n * n));
+    hipLaunchKernelGGL(k_expand_bins, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)cnt), dim3(256), 0, st, n, nt, H,
+                       n_upper, s_dev, m0, D);
     return hipGetLastError();
 }
 
