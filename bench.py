@@ -492,8 +492,9 @@ def run_two_window(args, gw, gs, torch):
 def run_time_route(args, gw, gs, torch):
     """The 2000-product molecule on the 1024-point mesh with a0 built by the
     paper's own route (Section 8.A: densities to time, local product per
-    time, back).  One step = gw_build_chi0_time + W on all points (FP64).
-    The pair-route chi0 build is timed beside it for comparison."""
+    time, back).  One step = gw_build_A_time (a0 by the time route, then A =
+    1 - v chi0 from v a0) + W from A on all points (FP64).  The pair-route
+    build of A is timed beside it for comparison."""
     log("generating molecule")
     mol = gs.truncate_products(gs.make_config(1), N_PROD)
     grid = gs.config_grid(1)
@@ -514,9 +515,9 @@ def run_time_route(args, gw, gs, torch):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         t0 = time.perf_counter()
         ev[0].record(stream)
-        ctx.build_chi0_time(dm.struct, g, chi, stream=stream, report=False)
+        ctx.build_A_time(dm.struct, dm.v, g, chi, stream=stream, report=False)  # chi holds A
         ev[1].record(stream)
-        ctx.solve_W(dm.v, n, chi, N, W, stream=stream, report=False)
+        ctx.solve_W_A(dm.v, n, chi, N, W, stream=stream, report=False)
         ev[2].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -524,14 +525,14 @@ def run_time_route(args, gw, gs, torch):
         if timed and roof is None:
             roof = kernel_roofline(ctx.profile_read())
             ctx.profile_end()
-        # the pair-route build of the same chi0, outside the step, for comparison
+        # the pair-route build of the same A, outside the step, for comparison
         ev[3].record(stream)
-        ctx.build_chi0(dm.struct, g, chi, stream=stream, report=False)
+        ctx.build_A(dm.struct, dm.v, g, chi, stream=stream, report=False)
         e5 = torch.cuda.Event(enable_timing=True)
         e5.record(stream)
         torch.cuda.synchronize()
         t_pair = ev[3].elapsed_time(e5) / 1e3
-        log("time-route step %d: chi0 (time route) %.3fs solve %.3fs wall %.3fs | chi0 (pair route) %.3fs" % (
+        log("time-route step %d: A (time route) %.3fs solve %.3fs wall %.3fs | A (pair route) %.3fs" % (
             it, parts[0], parts[1], wall, t_pair))
         if timed:
             ts.append((wall, parts[0], parts[1], t_pair))
@@ -540,7 +541,7 @@ def run_time_route(args, gw, gs, torch):
                       N / a[0], "W(omega)/s", a[0], "f64",
                       {"workload": "chain40_nprod2000_nomega1024_time_route", "n_prod": n, "n_omega": N,
                        "n_orb": mol.n_orb, "parallelism": "none (1 GPU)"})
-    out["phases_s"] = {"chi0_time_route": a[1], "solve": a[2], "chi0_pair_route": a[3]}
+    out["phases_s"] = {"A_time_route": a[1], "solve": a[2], "A_pair_route": a[3]}
     out["roofline"] = roof
     ctx.close()
     return out

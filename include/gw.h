@@ -210,6 +210,19 @@ gw_status gw_build_chi0_2w(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g_s
 gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream,
                              double *a_out, void *chi0_out, gw_report *rep);
 
+/* The time-domain route of gw_build_chi0_time for a0, then A(omega_j) =
+ * 1 - v chi0(omega_j) as in gw_build_A: each bin of the floating-point a0 is
+ * multiplied by v once and the FFT Cauchy transform of v a0 is written as
+ * 1 - result (Section 5.A eq. chi_by_spectra, Section 8.A eq.
+ * sf-of-response-time, Section 2 eq. Coulombscreening).
+ *   m, g, a_out, rep: as for gw_build_chi0_time, with 128 <= n_omega <= 1024.
+ *   v: DEVICE double [n_prod][n_prod], the symmetric Coulomb metric.
+ *   A_out: DEVICE complex128 [n_omega][n_prod][n_prod], every entry written.
+ * Workspace: as gw_build_chi0_time plus that of gw_build_A.  Errors:
+ * GW_E_INVALID, GW_E_OOM, GW_E_DEVICE. */
+gw_status gw_build_A_time(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, void *stream,
+                          double *a_out, void *A_out, gw_report *rep);
+
 /* The GW self-energy downstream of W (Section 5.A eqs. spectral_3 and
  * Cauchy1, time by time as in Section 8.B; exchange by Section 4 eq.
  * instantaneous), on the mesh of g:

@@ -428,21 +428,28 @@ gw_status a_route_ws(gw_ctx *c, const std::string &pre, int n, int nhb, ARouteWs
     return GW_OK;
 }
 
+gw_status a_from_bins_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, int nhb, const int64_t *a_i64,
+                              const int32_t *s_dev, const double *a_f64, const double *v, const ARouteWs &w,
+                              const zdbl *Kt, const zdbl *tw, void *A_out) {
+    // v a0 bin by bin (bins 1 .. nhb-1); its Cauchy transform is v chi0
+    const int64_t nn = (int64_t)n * n;
+    const int64_t n_upper = (int64_t)n * (n + 1) / 2;
+    for (int m0 = 1; m0 < nhb; m0 += w.dchunk) {
+        const int cnt = std::min(w.dchunk, nhb - m0);
+        if (a_i64) GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, a_i64, n_upper, s_dev, w.D));
+        else GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, a_f64, n_upper, w.D));
+        GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
+    }
+    GW_HIP(ctx, gwk::launch_fftconv_A(st, n, n_omega, nhb, w.B, Kt, tw, (zdbl *)A_out));
+    return GW_OK;
+}
+
 gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
                           bool with_kspec, void *A_out) {
     gw_status s = build_hist_enqueue(ctx, p, st);
     if (s != GW_OK) return s;
     if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
-    // v a0 bin by bin (bins 1 .. nhb-1); its Cauchy transform is v chi0
-    const int n = p.n_prod;
-    const int64_t nn = (int64_t)n * n;
-    for (int m0 = 1; m0 < p.nhb; m0 += w.dchunk) {
-        const int cnt = std::min(w.dchunk, p.nhb - m0);
-        GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, p.H, p.n_upper, p.sdev, w.D));
-        GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
-    }
-    GW_HIP(ctx, gwk::launch_fftconv_A(st, n, p.g.n_omega, p.nhb, w.B, p.Kt, p.tw, (zdbl *)A_out));
-    return GW_OK;
+    return a_from_bins_enqueue(ctx, st, p.n_prod, p.g.n_omega, p.nhb, p.H, p.sdev, nullptr, v, w, p.Kt, p.tw, A_out);
 }
 
 gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
@@ -807,16 +814,20 @@ int block_pairs(const HostMol &h, int nblk, std::vector<int32_t> *pbs, int *max_
 
 }  // namespace
 
-gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream, double *a_out,
-                             void *chi0_out, gw_report *rep) {
+// The time-domain route to a0, then chi0 (v = NULL) or A = 1 - v chi0 formed
+// from v a0 (v given) into out.
+static gw_status build_time_impl(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, void *stream,
+                                 double *a_out, void *chi0_out, gw_report *rep) {
     if (!ctx) return GW_E_INVALID;
     if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
     GW_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
-    if (!chi0_out) return fail(ctx, GW_E_INVALID, "chi0_out is NULL");
+    if (!chi0_out) return fail(ctx, GW_E_INVALID, "the output array is NULL");
     int kbits = 0;
     gw_status s = check_grid(ctx, g, &kbits);
     if (s != GW_OK) return s;
+    if (v && (g->n_omega < 128 || g->n_omega > 1024))
+        return fail(ctx, GW_E_INVALID, "gw_build_A_time needs n_omega in [128, 1024]");
     HostMol h;
     s = check_molecule(ctx, m, st, &h);
     if (s != GW_OK) return s;
@@ -906,7 +917,15 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
     }
     const double dom = (g->omega_max - g->omega_min) / g->n_omega;
     GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, (int)std::lround(g->omega_min / dom), dom, g->eps, Kt, tw));
-    GW_HIP(ctx, gwk::launch_fftconv(st, n, g->n_omega, nhb, (const double *)a, Kt, tw, (zdbl *)chi0_out));
+    if (v) {
+        gwp::ARouteWs aw;
+        if ((s = gwp::a_route_ws(ctx, "t_", n, nhb, &aw)) != GW_OK) return s;
+        s = gwp::a_from_bins_enqueue(ctx, st, n, g->n_omega, nhb, nullptr, nullptr, (const double *)a, v, aw, Kt, tw,
+                                     chi0_out);
+        if (s != GW_OK) return s;
+    } else {
+        GW_HIP(ctx, gwk::launch_fftconv(st, n, g->n_omega, nhb, (const double *)a, Kt, tw, (zdbl *)chi0_out));
+    }
     if (rep) {
         GW_HIP(ctx, hipStreamSynchronize(st));
         std::memset(rep, 0, sizeof(*rep));
@@ -915,6 +934,17 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
         rep->n_dropped_pairs = dropped;
     }
     return GW_OK;
+}
+
+gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, void *stream, double *a_out,
+                             void *chi0_out, gw_report *rep) {
+    return build_time_impl(ctx, m, nullptr, g, stream, a_out, chi0_out, rep);
+}
+
+gw_status gw_build_A_time(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, void *stream,
+                          double *a_out, void *A_out, gw_report *rep) {
+    if (ctx && !v) return fail(ctx, GW_E_INVALID, "v is NULL");
+    return build_time_impl(ctx, m, v, g, stream, a_out, A_out, rep);
 }
 
 gw_status gw_self_energy(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, const void *W,

@@ -70,6 +70,8 @@ hipError_t launch_symmetrize(hipStream_t st, int n, int n_omega, zdbl *chi0);
 // triangles.
 hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const int64_t *H, int64_t n_upper,
                               const int32_t *s_dev, double *D);
+// The same from a spectral array already in floating point.
+hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const double *a, int64_t n_upper, double *D);
 // A[j] = 1 - sum_m B[m] K_m(omega_j) for dense B[nhb][n][n] = v a0 (bins
 // m >= 1 read), every (mu, nu); 256 <= 2 n_omega <= 2048.
 hipError_t launch_fftconv_A(hipStream_t st, int n, int n_omega, int nhb, const double *B, const zdbl *Kt,

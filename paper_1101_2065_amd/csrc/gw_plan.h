@@ -64,6 +64,12 @@ gw_status a_route_ws(gw_ctx *c, const std::string &prefix, int n, int nhb, ARout
 // a1-a3 as build_enqueue, then A[j] = 1 - v chi0(omega_j) for all j into A_out.
 gw_status a_route_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
                           bool with_kspec, void *A_out);
+// A[j] = 1 - v chi0(omega_j) for all j from a spectral array a [nhb][n(n+1)/2]
+// already on the mesh (the exact histogram times 2^-s, or a0 in floating
+// point: a_i64 or a_f64), with the Cauchy-kernel spectrum Kt, tw of the mesh.
+gw_status a_from_bins_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const int64_t *a_i64,
+                              const int32_t *s_dev, const double *a_f64, const double *v, const ARouteWs &w,
+                              const zdbl *Kt, const zdbl *tw, void *A_out);
 
 struct SolveWs {
     zdbl *A = nullptr;

@@ -512,11 +512,12 @@ __global__ __launch_bounds__(256) void k_symmetrize(int n, int n_omega, int nt, 
     }
 }
 
-// Bins m0 .. m0+cnt-1 of the packed exact histogram as dense symmetric
-// doubles, D[m - m0][mu][nu] = 2^-s H[m][t(min, max)]; 32 x 32 tiles through
-// LDS as in k_symmetrize.  Workgroup = one upper tile (bi <= bj) of bin
-// m0 + blockIdx.y.
-__global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_t *__restrict__ H, int64_t n_upper,
+// Bins m0 .. m0+cnt-1 of a packed spectral array as dense symmetric doubles,
+// D[m - m0][mu][nu] = H[m][t(min, max)] (times 2^-s for the exact histogram);
+// 32 x 32 tiles through LDS as in k_symmetrize.  Workgroup = one upper tile
+// (bi <= bj) of bin m0 + blockIdx.y.
+template <typename HT>
+__global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const HT *__restrict__ H, int64_t n_upper,
                                                      const int32_t *__restrict__ s_dev, int m0,
                                                      double *__restrict__ D) {
     __shared__ double t[32][33];
@@ -526,9 +527,9 @@ __global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_
         ++bi;
     }
     const int bj = bi + tile;
-    const int s = *s_dev;
+    const int s = s_dev ? *s_dev : 0;
     const int64_t nn = (int64_t)n * n;
-    const int64_t *Hm = H + ((int64_t)m0 + blockIdx.y) * n_upper;
+    const HT *Hm = H + ((int64_t)m0 + blockIdx.y) * n_upper;
     double *Dm = D + (int64_t)blockIdx.y * nn;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
 #pragma unroll
@@ -537,7 +538,7 @@ __global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_
         double val = 0.0;
         if (r < n && c < n && c >= r) {
             const int64_t tr = (int64_t)r * n - ((int64_t)r * (r - 1)) / 2 - r;
-            val = ldexp((double)Hm[tr + c], -s);
+            val = hval(Hm, tr + c, s);
             Dm[(int64_t)r * n + c] = val;
         }
         t[ty + 8 * q][tx] = val;
@@ -552,15 +553,27 @@ __global__ __launch_bounds__(256) void k_expand_bins(int n, int nt, const int64_
 
 }  // namespace
 
-hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const int64_t *H, int64_t n_upper,
-                              const int32_t *s_dev, double *D) {
+namespace {
+template <typename HT>
+hipError_t expand_bins_impl(hipStream_t st, int n, int m0, int cnt, const HT *H, int64_t n_upper,
+                            const int32_t *s_dev, double *D) {
     if (cnt < 1) return hipSuccess;
     if (cnt > 65535 || m0 < 0) return hipErrorInvalidValue;
     const int nt = (n + 31) / 32;
     ProfScope pm(st, "expand_bins", 0.0, (8.0 * cnt) * ((double)n * (n + 1) / 2 + (double)n * n));
-    hipLaunchKernelGGL(k_expand_bins, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)cnt), dim3(256), 0, st, n, nt, H,
-                       n_upper, s_dev, m0, D);
+    hipLaunchKernelGGL((k_expand_bins<HT>), dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)cnt), dim3(256), 0, st, n,
+                       nt, H, n_upper, s_dev, m0, D);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const int64_t *H, int64_t n_upper,
+                              const int32_t *s_dev, double *D) {
+    return expand_bins_impl(st, n, m0, cnt, H, n_upper, s_dev, D);
+}
+
+hipError_t launch_expand_bins(hipStream_t st, int n, int m0, int cnt, const double *a, int64_t n_upper, double *D) {
+    return expand_bins_impl(st, n, m0, cnt, a, n_upper, (const int32_t *)nullptr, D);
 }
 
 hipError_t launch_fftconv_A(hipStream_t st, int n, int n_omega, int nhb, const double *B, const zdbl *Kt,

@@ -80,6 +80,8 @@ _SIGS = {
                                         ctypes.POINTER(gw_report)]),
     "gw_build_chi0_time": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid), _P, _P, _P,
                                           ctypes.POINTER(gw_report)]),
+    "gw_build_A_time": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P, _P,
+                                       ctypes.POINTER(gw_report)]),
     "gw_self_energy": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P, _P, _P,
                                       _P, ctypes.POINTER(gw_report)]),
     "gw_dyson_dos": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), ctypes.POINTER(gw_grid), _P, _P, _P, _P, _P,
@@ -199,6 +201,14 @@ class Context:
         st = lib.gw_build_chi0_time(self.h, ctypes.byref(mol), ctypes.byref(grid), _stream_handle(stream),
                                     _ptr(a_out), _ptr(chi0_out), ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_build_chi0_time")
+        return rep
+
+    def build_A_time(self, mol: "gw_molecule", v, grid: "gw_grid", A_out, a_out=None, stream=None,
+                     report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_build_A_time(self.h, ctypes.byref(mol), _ptr(v), ctypes.byref(grid), _stream_handle(stream),
+                                 _ptr(a_out), _ptr(A_out), ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_build_A_time")
         return rep
 
     def self_energy(self, mol: "gw_molecule", grid: "gw_grid", W, Sigma_out, v=None, sigma_out=None,

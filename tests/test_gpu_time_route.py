@@ -128,3 +128,49 @@ def test_time_route_errors(gpu):
     with pytest.raises(gw.GwError) as e:
         ctx.build_chi0_time(gw.DeviceMolecule(mol).struct, _g(gw, gs.Grid(48, -1.0, 1.0, 0.1)), chi)
     assert e.value.status == gw.GW_E_INVALID
+
+
+@pytest.mark.parametrize("case", ["tiny", "chain8_ragged"])
+def test_time_route_A_matches_oracle(gpu, case):
+    """gw_build_A_time: the same a0, then A = 1 - v chi0 formed from v a0 and
+    W = A^{-1} v, against the oracle's a0, chi0 from it, and LAPACK."""
+    gw, ctx, torch = gpu
+    mk, grid, form = _CASES[case]
+    mol = mk()
+    d = grid.domega
+    dm = gw.DeviceMolecule(mol)
+    n = mol.n_prod
+    nhb = o.level_hist_bins(mol.eig, mol.n_occ, grid.n_omega, d)
+    a = torch.full((nhb, n * (n + 1) // 2), float("nan"), dtype=torch.float64, device="cuda")
+    A = torch.full((grid.n_omega, n, n), float("nan"), dtype=torch.complex128, device="cuda")
+    rep = ctx.build_A_time(dm.struct, dm.v, _g(gw, grid), A, a_out=a)
+    torch.cuda.synchronize()
+    assert rep.n_hbins == nhb
+    if form == "convolution":
+        rho_p, rho_m = o.spectral_densities(mol, d)
+        ref = o.a0_by_convolution(mol, rho_p, rho_m, nhb)
+    else:
+        ref = o.a0_by_pairs(o.pair_vectors(mol), mol.eig, mol.n_occ, d, nhb)
+    assert _rel(a.cpu().numpy(), ref) < 1e-12
+    chi_ref = o.unpack_upper(o.chi0_from_spectrum(ref, grid.n_omega, grid.omega_min, grid.omega_max, grid.eps), n)
+    A_ref = np.eye(n)[None] - np.matmul(mol.v[None], chi_ref)
+    e = _rel(A.cpu().numpy(), A_ref)
+    _say("time route A rel", e)
+    assert e < 1e-12
+    W = torch.empty_like(A)
+    ctx.solve_W_A(dm.v, n, A, grid.n_omega, W)
+    Wg = W.cpu().numpy()
+    worst = max(_rel(Wg[j], o.screened_W(mol.v, chi_ref[j])) for j in range(grid.n_omega))
+    _say("time route W from A, worst rel", worst)
+    assert worst < 1e-10
+
+
+def test_time_route_A_rejects_meshes_out_of_range(gpu):
+    gw, ctx, torch = gpu
+    mol = gs.make_config(0)
+    g0 = gs.config_grid(0)
+    dm = gw.DeviceMolecule(mol)
+    A = torch.empty((1,), dtype=torch.complex128, device="cuda")
+    with pytest.raises(gw.GwError) as ei:
+        ctx.build_A_time(dm.struct, dm.v, gw.make_grid(64, g0.omega_min, g0.omega_max, g0.eps, -1), A)
+    assert ei.value.status == gw.GW_E_INVALID
