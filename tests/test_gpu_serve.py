@@ -109,6 +109,25 @@ def test_results_same_alone_and_in_the_mix(gpu):
     for i, j in enumerate(js):
         Wr = o.screened_W(m.v, chi[i])
         assert np.linalg.norm(alone[0][j] - Wr) <= 1e-10 * np.linalg.norm(Wr)
+    # every served result equals the eager solve (compressed: X of the same
+    # basis) within the FP64 parity bar
+    for ((m, k), dm, got) in zip(mols, dms, alone):
+        kk = k or m.n_prod
+        chi_e = torch.empty((grid.n_omega, kk, kk), dtype=torch.complex128, device="cuda")
+        W_e = torch.empty_like(chi_e)
+        if k:
+            Q = torch.empty((m.n_prod, k), dtype=torch.float64, device="cuda")
+            S = torch.empty((k, k), dtype=torch.float64, device="cuda")
+            ctx.compress_basis(dm.v, m.n_prod, k, Q, S)
+            ctx.build_chi0(dm.struct, g, chi_e, basis=Q, k=k)
+            ctx.solve_W(S, k, chi_e, grid.n_omega, W_e)
+        else:
+            ctx.build_chi0(dm.struct, g, chi_e)
+            ctx.solve_W(dm.v, m.n_prod, chi_e, grid.n_omega, W_e)
+        ref = W_e.cpu().numpy()
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        _say("served n_prod", m.n_prod, "k", k, "rel vs eager", e)
+        assert e < 1e-10
     ctx.close()
 
 
