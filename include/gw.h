@@ -316,7 +316,9 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
  *   A_out: DEVICE complex128 [n_omega][n_prod][n_prod], every entry written
  *      (A is not symmetric).
  *   rep: HOST or NULL; as for gw_build_chi0.
- * Workspace: 16 n_hbins n_prod^2 bytes beyond gw_build_chi0's.
+ * Workspace beyond gw_build_chi0's: the products v a0 of every bin
+ * (8 n_hbins n_prod^2 bytes) and the dense bins of one chunk (at most 2 GiB,
+ * at least one bin).
  * Errors: GW_E_INVALID (also for n_omega outside the range above),
  * GW_E_OOM, GW_E_DEVICE. */
 gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
