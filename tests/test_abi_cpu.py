@@ -21,6 +21,7 @@ def test_library_exports_every_declared_function():
 
     names = _declared()
     assert "gw_build_chi0" in names and "gw_solve_W" in names and "gw_poll" in names
+    assert "gw_build_A" in names and "gw_build_A_time" in names and "gw_solve_W_A" in names
     lib = ctypes.CDLL(gw.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -72,6 +73,10 @@ def test_create_without_gpu_reports_device_error():
     assert gw.lib.gw_create(0, 0, ctypes.byref(h)) == gw.GW_E_DEVICE
     assert gw.lib.gw_destroy(None) == gw.GW_E_INVALID
     assert gw.lib.gw_last_error(None) == b"NULL context"
+    # the A route's entry points reject a NULL context before touching anything
+    assert gw.lib.gw_build_A(None, None, None, None, None, None, None) == gw.GW_E_INVALID
+    assert gw.lib.gw_build_A_time(None, None, None, None, None, None, None, None) == gw.GW_E_INVALID
+    assert gw.lib.gw_solve_W_A(None, None, 0, 1, None, 2, 0, 1e-7, None, None, None) == gw.GW_E_INVALID
 
 
 def test_oracle_is_not_imported_by_the_product():

@@ -91,3 +91,14 @@ def test_counter_summaries(tmp_path):
     text = md.read_text()
     assert "| 2 | 65.0 | 4.500e+11 |" in text
     assert "k_hist" not in text  # no matrix-core work
+
+
+def test_solve_flops_with_A_given():
+    """The A route hands the solve A = 1 - v chi0: no 4N^3 product per
+    frequency (FP64 8N^3: LU 8/3, forward 4, back 4/3; mixed: the residual
+    steps only in FP64)."""
+    n3 = 100.0 ** 3
+    assert bench.solve_flops(100, 1)["fp64"] == pytest.approx(12 * n3)
+    assert bench.solve_flops(100, 1, form_a=False)["fp64"] == pytest.approx(8 * n3)
+    f = bench.solve_flops(100, 2, n_ir=3, mixed=True, form_a=False)
+    assert f["fp64"] == pytest.approx(2 * 24 * n3) and f["fp32"] == pytest.approx(2 * (8.0 / 3 + 32) * n3)
