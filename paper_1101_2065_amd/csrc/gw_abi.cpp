@@ -514,11 +514,12 @@ gw_status batch_ws(gw_ctx *c, hipStream_t st, const SolveWs &base, zdbl *Ain, co
 }
 
 gw_status solve_enqueue_nosync(gw_ctx *ctx, SolvePlan &p, hipStream_t st, const double *v, int v_is_diag,
-                               const zdbl *chi0, zdbl *W, int fixed_ir, zdbl *Ain) {
+                               const zdbl *chi0, zdbl *W, int fixed_ir, zdbl *Ain, bool skip_j0) {
     const int64_t nn = (int64_t)p.n * p.n;
     gw_status s;
     for (auto &bt : freq_batches(p.n_omega, p.nbmax)) {
         const int j0 = bt.first, nb = bt.second;
+        if (skip_j0 && j0 == 0 && nb == 1) continue;
         const zdbl *X = chi0 ? chi0 + j0 * nn : nullptr;
         SolveWs w;
         if ((s = batch_ws(ctx, st, p.w, Ain, W, nn, j0, nb, &w)) != GW_OK) return s;
@@ -1175,8 +1176,24 @@ gw_status solve_W_impl(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t 
         if (const char *e = std::getenv("GW_SOLVE_STREAMS")) nstreams = std::max(1, std::min(2, std::atoi(e)));
         if (ctx->own_stream || n_omega < 8) nstreams = 1;
         if (nstreams == 1) {
-            s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0, Ain);
+            // the lone point j = 0 (no mirror partner) is a batch of one: its
+            // panels would hold one CU each while the rest of the chip idles,
+            // so it runs on the context's second stream beside the batches
+            const bool side = !ctx->own_stream && n_omega >= 8;
+            if (side) {
+                gwp::SolvePlan p0;
+                if ((s = gwp::solve_plan(ctx, n, 2, false, "j0", &p0)) != GW_OK) return s;
+                if ((s = aux_stream(ctx)) != GW_OK) return s;
+                GW_HIP(ctx, hipEventRecord(ctx->fork_ev, st));
+                GW_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+                gwp::SolveWs w0;
+                if ((s = gwp::batch_ws(ctx, ctx->aux, p0.w, Ain, W, nn, 0, 1, &w0)) != GW_OK) return s;
+                if ((s = gwp::solve_batch_fp64(ctx, ctx->aux, n, v, v_is_diag, X0, W, 1, w0)) != GW_OK) return s;
+                GW_HIP(ctx, hipEventRecord(ctx->join_ev, ctx->aux));
+            }
+            s = gwp::solve_enqueue_nosync(ctx, p, st, v, v_is_diag, X0, W, 0, Ain, side);
             if (s != GW_OK) return s;
+            if (side) GW_HIP(ctx, hipStreamWaitEvent(st, ctx->join_ev, 0));
             for (auto &bt : freq_batches(n_omega, p.nbmax)) n_solved += bt.second;
         } else {
             // frequency batches alternate between the caller's stream and a

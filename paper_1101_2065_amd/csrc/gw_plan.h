@@ -97,9 +97,10 @@ gw_status solve_plan(gw_ctx *c, int n, int n_omega, bool mixed, const std::strin
 // refinement steps; the last step's norms go to p.final_norms.  No host
 // synchronisation.
 // Ain: A = 1 - v chi0 given instead of chi0 (chi0 = NULL): each batch is
-// factorised in place in Ain, or from a copy when W aliases Ain.
+// factorised in place in Ain, or from a copy when W aliases Ain.  skip_j0:
+// the lone point j = 0 is solved elsewhere.
 gw_status solve_enqueue_nosync(gw_ctx *c, SolvePlan &p, hipStream_t st, const double *v, int v_is_diag,
-                               const zdbl *chi0, zdbl *W, int fixed_ir, zdbl *Ain = nullptr);
+                               const zdbl *chi0, zdbl *W, int fixed_ir, zdbl *Ain = nullptr, bool skip_j0 = false);
 // The workspace of frequency batch [j0, j0 + nb) for the route above.
 gw_status batch_ws(gw_ctx *c, hipStream_t st, const SolveWs &base, zdbl *Ain, const zdbl *W, int64_t nn, int j0,
                    int nb, SolveWs *out);
