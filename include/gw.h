@@ -294,9 +294,11 @@ gw_status gw_dyson_dos(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, cons
  *   rep: HOST or NULL; if non-NULL the call synchronises and reports.
  * n_omega must be even and at least 2.  The call synchronises the stream
  * once per refinement step for the mixed forms.  The FP64 form runs on the
- * caller's stream; with GW_SOLVE_STREAMS=2 its frequency batches alternate
- * between that stream and a second stream of the context (joined back before
- * the call returns to the stream's order). */
+ * caller's stream, except the lone point j = 0 (a batch of one frequency),
+ * which runs on a second stream of the context beside the first batch when
+ * its workspace fits; with GW_SOLVE_STREAMS=2 the frequency batches alternate
+ * between the two streams.  Either way the second stream is joined back into
+ * the caller's stream's order before the call returns. */
 gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
                      const void *chi0, int32_t n_omega, gw_precision prec, double tol,
                      void *stream, void *W_out, gw_report *rep);

@@ -1179,10 +1179,13 @@ gw_status solve_W_impl(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t 
             // the lone point j = 0 (no mirror partner) is a batch of one: its
             // panels would hold one CU each while the rest of the chip idles,
             // so it runs on the context's second stream beside the batches
-            const bool side = !ctx->own_stream && n_omega >= 8;
+            bool side = !ctx->own_stream && n_omega >= 8;
+            gwp::SolvePlan p0;
+            if (side && (s = gwp::solve_plan(ctx, n, 2, false, "j0", &p0)) != GW_OK) {
+                if (s != GW_E_OOM) return s;
+                side = false;  // no room for a second workspace: j = 0 stays in order
+            }
             if (side) {
-                gwp::SolvePlan p0;
-                if ((s = gwp::solve_plan(ctx, n, 2, false, "j0", &p0)) != GW_OK) return s;
                 if ((s = aux_stream(ctx)) != GW_OK) return s;
                 GW_HIP(ctx, hipEventRecord(ctx->fork_ev, st));
                 GW_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
