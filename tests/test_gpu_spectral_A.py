@@ -203,3 +203,27 @@ def test_A_route_multi_tile_medium(gpu, prec, tol):
     e = float(torch.linalg.norm(W - W2) / torch.linalg.norm(W2))
     _say("A route vs chi0 route", e)
     assert e < (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("n_omega", [128, 512])
+def test_A_route_other_fft_lengths(gpu, n_omega):
+    """The FFT lengths 256 and 1024 (the 128- and 512-point meshes over the
+    same window; the cases above take 512 and 2048): A and the FP64 W at
+    every frequency against the oracle, on the ragged 136-product chain."""
+    gw, ctx, torch = gpu
+    mol = _ragged_chain()
+    grid = gs.Grid(n_omega, -4.0, 4.0, 0.05)
+    _say("A route, n_omega", n_omega)
+    chi, nhb, s = _oracle_chi(mol, grid)
+    dm, A, rep = _gpu_A(gw, ctx, torch, mol, grid)
+    assert rep.n_hbins == nhb and rep.frac_bits_used == s
+    ref = np.eye(mol.n_prod)[None] - np.matmul(mol.v[None], chi)
+    e = _rel(A.cpu().numpy(), ref)
+    _say("A rel", e)
+    assert e < 1e-12
+    W = torch.empty_like(A)
+    ctx.solve_W_A(dm.v, mol.n_prod, A, grid.n_omega, W)
+    Wg = W.cpu().numpy()
+    worst = max(_rel(Wg[j], o.screened_W(mol.v, chi[j])) for j in range(grid.n_omega))
+    _say("W worst rel", worst)
+    assert worst < 1e-10
