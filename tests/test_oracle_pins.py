@@ -630,9 +630,55 @@ def test_w_spectral_is_positive_and_odd():
     scale = np.abs(gam).max()
     for k in range(1, len(gam)):
         assert np.linalg.eigvalsh(gam[k]).min() >= -1e-12 * scale
-    j0 = g.n_omega // 2
-    for k in (1, 5, 17):
-        assert np.array_equal(-(g.domega / math.pi) * np.imag(W[j0 - k]), -gam[k])
+
+
+def test_w_spectral_rebuilds_w_by_the_cauchy_integral():
+    """The weights gamma[k] are the spectral function of W - v on the mesh
+    (Section 5.A: a retarded correlator is the Cauchy integral of minus its
+    imaginary part over pi).  With F(z) = W(z + i eps) - v, analytic above the
+    real axis, F(omega + i eta) = int rho(s) / (omega + i eta - s) ds with
+    rho(s) = -(1/pi) Im W(s + i eps); the trapezoid sum of that integral over
+    the mesh, with the odd extension gamma(-s) = -gamma(s), is
+        sum_k gamma[k] [1/(z - k domega) - 1/(z + k domega)],  z = omega + i eta,
+    and it must equal W(omega + i(eps + eta)) - v solved directly at off-mesh
+    omega (chi0 summed at the larger broadening).  The sum converges
+    exponentially in eps/domega and eta/domega; the vertex is weakened
+    (V -> 0.3 V) so that the weight of W - v stays well inside the window.
+    The same check fails for a lost domega (1/pi), a doubled weight
+    (2 domega/pi) and a zero-frequency bin moved by one mesh point."""
+    mol = gs.make_config(0).scaled_vertex(0.3)
+    n_omega, wmax = 1024, 16.0
+    g = gs.Grid(n_omega, -wmax, wmax, 0.0)
+    d = g.domega
+    g.eps = 1.5 * d
+    eta = 1.5 * d
+    P, m, fr, nhb, s, H = _pipeline(mol, g)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, n_omega, g.omega_min, g.omega_max, g.eps), mol.n_prod)
+    W = np.array([o.screened_W(mol.v, c) for c in chi])
+    gam = o.w_spectral(W, n_omega, g.omega_min, g.omega_max)
+    oms = np.array([0.0, 0.37, 0.91, 1.53, 2.2, 3.1, -0.8])  # off the mesh except 0
+    chiz = o.unpack_upper(o.chi0_from_hist(H, s, n_omega, g.omega_min, g.omega_max, g.eps + eta, omegas=oms),
+                          mol.n_prod)
+    F = np.array([o.screened_W(mol.v, c) for c in chiz]) - mol.v[None]
+
+    def mismatch(gm):
+        k = np.arange(gm.shape[0]) * d
+        z = oms[:, None] + 1j * eta
+        K = 1.0 / (z - k[None, :]) - 1.0 / (z + k[None, :])
+        R = np.einsum("jk,kab->jab", K, gm)
+        return np.linalg.norm(R - F) / np.linalg.norm(F)
+
+    assert mismatch(gam) <= 2e-3
+    # planted mistakes, each built from W on the CPU: they must all fail
+    j0 = n_omega // 2
+
+    def from_bin(jz):
+        gg = -(d / math.pi) * np.imag(W[jz:jz + n_omega // 2])
+        gg[0] = 0.0
+        return gg
+
+    for bad in (gam / d, 2.0 * gam, from_bin(j0 + 1), from_bin(j0 - 1)):
+        assert mismatch(bad) >= 1e-2
 
 
 @pytest.mark.parametrize("which", ["tiny", "chain3"])
