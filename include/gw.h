@@ -388,11 +388,15 @@ gw_status gw_pair_basis(gw_ctx *ctx, const gw_molecule *m, const double *v, doub
 
 /* Batched form: n_mol molecules of different sizes on one mesh (all
  * frequencies of all molecules).  gw_batch_create validates every molecule,
- * sizes the workspaces, chooses GEMM tile shapes per size class with the
- * autotuner (timed once per class, cached in $GW_TUNE_FILE, default
- * $HOME/.cache/gw_tune.json) and records the whole computation once into a
- * hipGraph: every chi0 build, then the W solves on GW_BATCH_STREAMS (default
- * 4) parallel branches.  gw_batch_run replays that graph on `stream`.
+ * sizes the workspaces, chooses GEMM tile shapes per (precision, size class)
+ * with the autotuner (median of five timed launches per candidate tile on the
+ * molecule's first trailing-update shape, once per class; the table is kept
+ * in $GW_TUNE_FILE, default $HOME/.cache/gw_tune.json, whose directories are
+ * created as needed; a table that cannot be read or written is reported by
+ * gw_last_error() while the batch is still created) and records the whole
+ * computation once into a hipGraph: every chi0 build, then the W solves on
+ * GW_BATCH_STREAMS (default 4) parallel branches.  gw_batch_run replays that
+ * graph on `stream`.
  *   v[i]: DEVICE [n_i][n_i]; chi0_out[i], W_out[i]: DEVICE complex128
  *   [n_omega][n_i][n_i], caller-owned, fixed for the life of the batch.
  *   prec GW_FP64, or GW_FP32_IR / GW_BF16X_IR with exactly n_refine (1..6)

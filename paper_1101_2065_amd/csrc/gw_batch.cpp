@@ -11,6 +11,7 @@
 // checks every frequency's last refinement step and re-solves in FP64 (outside
 // the graph) any frequency that did not reach the tolerance.
 #include "gw_plan.h"
+#include "gw_tune.h"
 
 #include <hip/hip_runtime.h>
 
@@ -18,17 +19,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
-#include <fstream>
 #include <map>
 #include <mutex>
-#include <sstream>
 #include <string>
 #include <vector>
 
 namespace gwk {
-hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
-                        const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc, int64_t sC,
-                        int batch);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
 }
 
 using gwp::fail;
@@ -56,111 +53,98 @@ struct gw_batch {
 namespace {
 
 // ------------------------------------------------------------------ autotuner
-// Table: size class (n rounded up to a multiple of 256) -> tile of the long
-// complex FP64 products (0: 64x64 K16, 1: 128x64 K8, 2: 64x32 K8, 3: 128x32
-// K8).  Measured on the trailing-update shape (n x n x 256, complex) the first
-// time a class is seen, kept in memory and in a JSON file ($GW_TUNE_FILE,
-// default $HOME/.cache/gw_tune.json).
+// Table: (precision, size class) -> tile of the long complex products of the
+// LU and the solves (0: 64x64 K16, 1: 128x64 K8, 2: 64x32 K8, 3: 128x32 K8).
+// The size class is n rounded up to a multiple of 256; the precision is that
+// of the factorisation (FP64, or FP32 for both mixed forms: under BF16x the
+// rank-K trailing updates run on the split-BF16 kernel, and the FP32 table
+// entry serves its remaining complex-float products).  A class is measured the
+// first time it is seen, on the molecule's own first trailing update
+// (M = N = n - 256, K = 256, a batch of up to four frequencies): one warm-up
+// launch and five timed ones per tile, the median kept.  The table lives in
+// memory and in a JSON file ($GW_TUNE_FILE, default $HOME/.cache/gw_tune.json).
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
 
-std::string tune_path() {
-    if (const char *e = std::getenv("GW_TUNE_FILE")) return e;
-    const char *h = std::getenv("HOME");
-    return std::string(h ? h : "/tmp") + "/.cache/gw_tune.json";
+std::string tune_key(int cls, gw_precision prec) {
+    return std::string(prec == GW_FP64 ? "zgemm_fp64" : "cgemm_fp32") + "_n" + std::to_string(cls);
 }
 
-void tune_load() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    std::ifstream f(tune_path());
-    if (!f) return;
-    std::stringstream ss;
-    ss << f.rdbuf();
-    const std::string t = ss.str();
-    // flat {"key": value, ...}
-    size_t p = 0;
-    while ((p = t.find('"', p)) != std::string::npos) {
-        const size_t q = t.find('"', p + 1);
-        if (q == std::string::npos) break;
-        const std::string key = t.substr(p + 1, q - p - 1);
-        const size_t c = t.find(':', q);
-        if (c == std::string::npos) break;
-        g_tune[key] = std::atoi(t.c_str() + c + 1);
-        p = t.find_first_of(",}", c);
-        if (p == std::string::npos) break;
-    }
-}
-
-void tune_save() {
-    const std::string path = tune_path();
-    const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        const std::string dir = path.substr(0, slash);
-        std::string cmd = "mkdir -p '" + dir + "'";
-        if (std::system(cmd.c_str()) != 0) return;
-    }
-    std::ofstream f(path);
-    if (!f) return;
-    f << "{";
-    bool first = true;
-    for (auto &kv : g_tune) {
-        f << (first ? "" : ", ") << "\"" << kv.first << "\": " << kv.second;
-        first = false;
-    }
-    f << "}\n";
-}
-
-gw_status tune_tile(gw_ctx *ctx, int n, hipStream_t st, int *tile) {
+gw_status tune_tile(gw_ctx *ctx, int n, gw_precision prec, hipStream_t st, int *tile) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_load();
+    const std::string path = gwt::cache_path();
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        std::string err;
+        if (!gwt::load(path, &g_tune, &err)) ctx->err = "autotuner table not read (" + err + "); measuring afresh";
+    }
     const int cls = ((n + 255) / 256) * 256;
-    const std::string key = "zgemm4_n" + std::to_string(cls);
+    const std::string key = tune_key(cls, prec);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
         *tile = it->second;
         return GW_OK;
     }
-    if (cls < 256) {  // no long products at this size
+    if (n <= 256) {  // no long products at this size
         *tile = 3;
         g_tune[key] = 3;
         return GW_OK;
     }
-    // operands: C (cls x cls), A (cls x 256), B (256 x cls), batch 4
-    const int K = 256, batch = 4;
-    const size_t elems = (size_t)batch * ((size_t)cls * cls + 2 * (size_t)cls * K);
+    const bool dbl = prec == GW_FP64;
+    const int M = n - 256, K = 256, batch = 4;
+    const size_t esz = dbl ? 16 : 8;
+    const size_t elems = (size_t)batch * ((size_t)M * M + 2 * (size_t)M * K);
     void *buf;
-    gw_status s = gwp::ws(ctx, "tune", elems * 16, &buf);
+    gw_status s = gwp::ws(ctx, "tune", elems * esz, &buf);
     if (s != GW_OK) return s;
-    gwk::zdbl *C = (gwk::zdbl *)buf, *A = C + (size_t)batch * cls * cls, *B = A + (size_t)batch * cls * K;
-    GW_HIP(ctx, hipMemsetAsync(buf, 0, elems * 16, st));
+    GW_HIP(ctx, gwk::launch_fill_u32(st, (uint32_t *)buf, (int64_t)(elems * esz / 4), 0u));
     hipEvent_t e0, e1;
     GW_HIP(ctx, hipEventCreate(&e0));
     GW_HIP(ctx, hipEventCreate(&e1));
-    float best = 1e30f;
-    int best_t = 3;
-    for (int t = 3; t >= 0; --t) {
-        gwp::set_thread_gemm_tile(t);
-        float ms = 0;
-        for (int rep = 0; rep < 2; ++rep) {
-            GW_HIP(ctx, hipEventRecord(e0, st));
-            GW_HIP(ctx, gwk::launch_zgemm(st, cls, cls, K, -1.0, A, K, (int64_t)cls * K, B, cls, (int64_t)K * cls, 1.0,
-                                          C, cls, (int64_t)cls * cls, batch));
-            GW_HIP(ctx, hipEventRecord(e1, st));
-            GW_HIP(ctx, hipEventSynchronize(e1));
-            GW_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    auto launch = [&]() -> hipError_t {
+        if (dbl) {
+            gwk::zdbl *C = (gwk::zdbl *)buf, *A = C + (size_t)batch * M * M, *B = A + (size_t)batch * M * K;
+            return gwk::launch_zgemm(st, M, M, K, -1.0, A, K, (int64_t)M * K, B, M, (int64_t)K * M, 1.0, C, M,
+                                     (int64_t)M * M, batch);
         }
-        if (ms < best) {
-            best = ms;
+        gwk::zflt *C = (gwk::zflt *)buf, *A = C + (size_t)batch * M * M, *B = A + (size_t)batch * M * K;
+        return gwk::launch_cgemm(st, M, M, K, -1.f, A, K, (int64_t)M * K, B, M, (int64_t)K * M, 1.f, C, M,
+                                 (int64_t)M * M, batch);
+    };
+    double best = 1e300;
+    int best_t = 3;
+    gwp::Bf16xScope plain(false);  // time the plain complex-float kernel
+    for (int t = 3; t >= 0 && s == GW_OK; --t) {
+        gwp::set_thread_gemm_tile(t);
+        std::vector<double> ms;
+        for (int rep = 0; rep < 6; ++rep) {
+            hipError_t e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float f = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+            if (e != hipSuccess) {
+                s = fail(ctx, GW_E_DEVICE, std::string("autotuner: ") + hipGetErrorString(e));
+                break;
+            }
+            if (rep > 0) ms.push_back(f);  // the first launch warms up
+        }
+        if (s != GW_OK) break;
+        const double med = gwt::median(ms);
+        if (med < best) {
+            best = med;
             best_t = t;
         }
     }
     gwp::set_thread_gemm_tile(-1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (s != GW_OK) return s;
     g_tune[key] = best_t;
-    tune_save();
+    std::string err;
+    if (!gwt::save(path, g_tune, &err)) ctx->err = "autotuner table not saved: " + err;
     *tile = best_t;
     return GW_OK;
 }
@@ -300,7 +284,7 @@ gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, c
         if (s != GW_OK) return bail(s);
         b->norms.push_back((double *)p);
         int tile = 0;
-        s = tune_tile(ctx, mols[i].n_prod, st, &tile);
+        s = tune_tile(ctx, mols[i].n_prod, prec, st, &tile);
         if (s != GW_OK) return bail(s);
         b->tile.push_back(tile);
     }

@@ -429,13 +429,14 @@ __global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *
     if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
 }
 
-// Tile of the long complex FP64 products (M >= 256, K >= 128): < 0 the
-// default (128x32); 0: 64x64 K16; 1: 128x64 K8; 2: 64x32 K8; 3: 128x32 K8.
-// Per host thread, so the batched driver can record each molecule with its
-// tuned tile.  Thin complex FP64 products always take 64x32.
+// Tile of the long complex products (M >= 256, K >= 128): < 0 the default
+// (FP64 128x32, FP32 128x64); 0: 64x64 K16; 1: 128x64 K8; 2: 64x32 K8;
+// 3: 128x32 K8.  Per host thread, so the batched driver can record each
+// molecule with its tuned tile.  Thin complex FP64 products always take 64x32.
 thread_local int g_gemm_tile = -1;
 
 const char *const kZgemmName[4] = {"zgemm_64x64", "zgemm_128x64", "zgemm_64x32", "zgemm_128x32"};
+const char *const kCgemmName[4] = {"cgemm_64x64", "cgemm_128x64", "cgemm_64x32", "cgemm_128x32"};
 
 template <typename T, bool AC, bool BC>
 hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *A, int64_t lda, int64_t sA,
@@ -443,19 +444,24 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
                          int add_eye = 0, float *C32 = nullptr, int64_t sC32 = 0) {
     if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
     constexpr bool Z64 = AC && BC && sizeof(T) == 8;
+    constexpr bool CF32 = AC && BC && sizeof(T) == 4;
+    const bool tuned = g_gemm_tile >= 0 && g_gemm_tile <= 3;
     int tile;
     if constexpr (Z64) {
         const bool big = M >= 256 && K >= 128;
-        tile = big ? (g_gemm_tile >= 0 && g_gemm_tile <= 3 ? g_gemm_tile : 3) : 2;
+        tile = big ? (tuned ? g_gemm_tile : 3) : 2;
+    } else if constexpr (CF32) {
+        const bool big = M >= 256 && K >= 128;
+        tile = big && tuned ? g_gemm_tile : (M >= 128 && K >= 64) ? 1 : 0;
     } else {
-        tile = (AC && BC && M >= 128 && K >= 64) ? 1 : 0;
+        tile = 0;
     }
     ProfSink *prof = g_prof;
     const char *cls = nullptr;
     double flops = 0, bytes = 0;
     if (prof) {
         const bool dbl = sizeof(T) == 8;
-        if (AC && BC) cls = dbl ? kZgemmName[tile] : (tile == 1 ? "cgemm_128x64" : "cgemm_64x64");
+        if (AC && BC) cls = dbl ? kZgemmName[tile] : kCgemmName[tile];
         else if (BC) cls = add_eye ? "formA" : "dzgemm";
         else if (AC) cls = "zdgemm";
         else cls = "dgemm";
@@ -469,7 +475,7 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
     hipLaunchKernelGGL((k_gemm<T, AC, BC, WM, WN, BK, OCC, XR>), dim3((N + 32 * WN - 1) / (32 * WN),               \
                        (M + 32 * WM - 1) / (32 * WM), batch), dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, \
                        sB, beta, C, ldc, sC, add_eye, C32, sC32)
-    if constexpr (Z64) {
+    if constexpr (Z64 || CF32) {
         if (tile == 3) GW_GEMM(4, 1, 8, 4, true);
         else if (tile == 2) GW_GEMM(2, 1, 8, 4, true);
         else if (tile == 1) GW_GEMM(4, 2, 8, 2, false);
