@@ -256,7 +256,7 @@ def build_c() -> str:
     tmp = out + ".tmp%d" % os.getpid()
     subprocess.check_call(
         ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-         "-fno-fast-math", "-std=c99", src, "-o", tmp, "-lm"]
+         "-fno-fast-math", "-fno-math-errno", "-std=c99", src, "-o", tmp, "-lm"]
     )
     os.replace(tmp, out)
     return out

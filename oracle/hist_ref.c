@@ -10,6 +10,9 @@
  *     t_hi = nearbyint((P[mu,p] * ldexp(frac_p, s)) * P[nu,p])
  *     H[m_p]   += 2 (t - t_hi),  H[m_p + 1] += 2 t_hi.
  * Compiled with -ffp-contract=off so every product is rounded on its own.
+ * ldexp(x, s) is written as x times the exact power 2^s (the same correctly
+ * rounded value), and nearbyint as llrint (both round to nearest, ties to
+ * even, in the default rounding mode; every value here is below 2^62).
  * One entry (mu, nu) per loop iteration, pairs in ascending order; the sums
  * are exact integers, so the order does not matter anyway.
  */
@@ -25,6 +28,8 @@ int hist_ref_entries(const double *P, int64_t n_prod, int64_t n_pairs,
     int64_t dropped = 0;
     double *w = (double *)malloc(sizeof(double) * (size_t)(n_pairs > 0 ? n_pairs : 1));
     if (!w) return -1;
+    /* 2^s is exact, and multiplying by it rounds exactly as ldexp does */
+    const double two_s = ldexp(1.0, s);
     for (int64_t p = 0; p < n_pairs; ++p) {
         w[p] = ldexp(frac[p], s);
         if (m[p] + 1 >= nhb) dropped++;
@@ -40,10 +45,10 @@ int hist_ref_entries(const double *P, int64_t n_prod, int64_t n_pairs,
             int64_t mp = m[p];
             if (mp + 1 >= nhb) continue;
             double prod = pm[p] * pn[p];
-            int64_t t = (int64_t)nearbyint(ldexp(prod, s));
+            int64_t t = llrint(prod * two_s);      /* RNE(2^s * fl(P_mu P_nu)) */
             double y = pm[p] * w[p];
             double yy = y * pn[p];
-            int64_t th = (int64_t)nearbyint(yy);
+            int64_t th = llrint(yy);               /* RNE(fl(fl(P_mu 2^s frac) P_nu)) */
             H[mp * n_entries + e] += 2 * (t - th);
             H[(mp + 1) * n_entries + e] += 2 * th;
         }
