@@ -340,6 +340,28 @@ gw_status gw_solve_W_A(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t 
                        int32_t n_omega, gw_precision prec, double tol, void *stream, void *W_out,
                        gw_report *rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the GW_FP64
+ * form of gw_solve_W_A with no allocation of any kind (no hipMalloc, no
+ * hipFree, no stream or event creation).  Its workspace (panel scratch, the
+ * inverted 64 x 64 diagonal blocks of L and U, pivots) lives in one fixed
+ * device array of 64 MiB per GPU, set up by gw_create and held until the
+ * process ends; the frequencies are factorised in batches that fit it.
+ *   v, v_is_diag, n, n_omega, rep: as for gw_solve_W_A.
+ *   A: DEVICE complex128 [n_omega][n][n]; the solved frequencies (j = 0 and
+ *      j >= n_omega/2) hold LU factors on return, as under gw_solve_W_A.
+ *   W_out: DEVICE complex128 [n_omega][n][n]; must not alias A.
+ * Everything runs in order on `stream` (the lone point j = 0 included); the
+ * result equals gw_solve_W_A's FP64 result.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind: calls that overlap in time
+ * on one GPU (other streams or host threads) race and give wrong results.
+ * Kernel timing (gw_profile_begin) is suspended during the call.
+ * Errors: GW_E_INVALID for bad arguments or for an n whose single-frequency
+ * workspace exceeds the array (about 3 KiB per row: n up to ~21000),
+ * GW_E_DEVICE, GW_E_STATE if the array was never set up on this device. */
+gw_status gw_solve_W_A_noalloc(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n, void *A,
+                               int32_t n_omega, void *stream, void *W_out, gw_report *rep);
+
 /* Section 7.B subspace: an orthonormal basis Q of the k-dimensional dominant
  * eigenspace of v (the span of its top-k eigenvectors; shifted subspace
  * iteration, 4 steps) and the metric in that basis, S = Q^T v Q.  The

@@ -550,6 +550,7 @@ gw_status gw_create(int device, size_t hbm_budget_bytes, gw_ctx **out) {
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return GW_E_DEVICE;
     if (device < 0 || device >= count) return GW_E_INVALID;
     if (hipSetDevice(device) != hipSuccess) return GW_E_DEVICE;
+    gwk_noalloc_init(device);
     gw_ctx *c = new gw_ctx();
     c->device = device;
     size_t fr = 0, tot = 0;

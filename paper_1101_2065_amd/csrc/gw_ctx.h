@@ -42,3 +42,6 @@ hipError_t gwk_malloc_async(void **p, size_t bytes, hipStream_t st);
 void gwk_serve_stop(gw_ctx *c);
 void gwk_prof_release(gw_ctx *c);
 size_t gwk_solve_ws_bytes(int n, int n_omega, bool mixed, size_t budget);
+// Device address of the fixed workspace of gw_solve_W_A_noalloc on `device`
+// (current), looked up once per device.
+void gwk_noalloc_init(int device);

@@ -90,6 +90,8 @@ _SIGS = {
                                   ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
     "gw_solve_W_A": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32,
                                     ctypes.c_int, ctypes.c_double, _P, _P, ctypes.POINTER(gw_report)]),
+    "gw_solve_W_A_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int32, _P, _P,
+                                            ctypes.POINTER(gw_report)]),
     "gw_build_A": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P,
                                   ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
@@ -252,6 +254,14 @@ class Context:
                               _stream_handle(stream), _ptr(W_out),
                               ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_solve_W_A")
+        return rep
+
+    def solve_W_A_noalloc(self, v, n: int, A, n_omega: int, W_out, v_is_diag: bool = False, stream=None,
+                          report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_solve_W_A_noalloc(self.h, _ptr(v), int(v_is_diag), n, _ptr(A), n_omega, _stream_handle(stream),
+                                      _ptr(W_out), ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_solve_W_A_noalloc")
         return rep
 
     def compress_basis(self, v, n: int, k: int, Q_out, S_out, stream=None):
