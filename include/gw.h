@@ -287,8 +287,11 @@ gw_status gw_dyson_dos(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, cons
  *      metric S from gw_compress_basis and chi_hat from gw_build_chi0.
  *   chi0: DEVICE complex128 [n_omega][n][n] (e.g. from gw_build_chi0).
  *   prec: GW_FP64, or a mixed form refined with an FP64 residual
- *      r = v - (1 - v chi0) W until ||dW||_F <= tol ||W||_F (at most 6
- *      steps); a frequency that does not converge is re-solved in FP64.
+ *      r = v - (1 - v chi0) W, W_k = W_{k-1} + dW_k, until the error left in
+ *      W_k is estimated below tol ||W_k||_F: ||dW_k||_F <= tol ||W_k||_F, or
+ *      the iteration contracts (rho_k = ||dW_k||_F / ||dW_{k-1}||_F <= 1/2,
+ *      dW_0 = W_0) and ||dW_k||_F rho_k <= tol ||W_k||_F (at most 6 steps);
+ *      a frequency that does not converge is re-solved in FP64.
  *   W_out: DEVICE complex128 [n_omega][n][n].  W_out == chi0 is allowed:
  *      W then overwrites chi0 in place (half the HBM; chi0 is lost).
  *   rep: HOST or NULL; if non-NULL the call synchronises and reports.
@@ -423,7 +426,7 @@ gw_status gw_pair_basis(gw_ctx *ctx, const gw_molecule *m, const double *v, doub
  *   [n_omega][n_i][n_i], caller-owned, fixed for the life of the batch.
  *   prec GW_FP64, or GW_FP32_IR / GW_BF16X_IR with exactly n_refine (1..6)
  *   FP64 refinement steps in the graph; gw_batch_run then re-solves in FP64 every frequency
- *   whose last step left ||dW||_F > tol ||W||_F (counted in the report).
+ *   whose last steps do not meet gw_solve_W's stopping rule (counted in the report).
  *   W_out[i] == chi0_out[i] solves in place; the FP64 re-solve then has no
  *   chi0 to start from, so such a frequency makes gw_batch_run return
  *   GW_E_NOCONV (after filling every report).  An in-place molecule on a

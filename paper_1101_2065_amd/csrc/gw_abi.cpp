@@ -186,6 +186,14 @@ gw_status aux_stream(gw_ctx *c) {
 
 namespace gwp {
 
+bool ir_converged(int k, double dn, double dprev, double wn, double tol) {
+    const double w = std::max(wn, 1e-300);
+    if (!(dn == dn) || !(wn == wn)) return false;  // NaN: not converged
+    if (dn <= tol * w) return true;
+    const double rho = dn / std::max(dprev, 1e-300);
+    return k >= 1 && rho <= 0.5 && dn * rho <= tol * w;
+}
+
 size_t per_freq_bytes(int n, bool mixed) {
     const size_t nn = (size_t)n * n;
     const int nblk = (n + 63) / 64;
@@ -263,15 +271,16 @@ gw_status mixed_refine_step(gw_ctx *c, hipStream_t st, int n, const double *v, i
     return GW_OK;
 }
 
-// Adaptive refinement: stop a frequency once ||dW|| <= tol ||W|| (reads the
-// norms back after every step).
+// Adaptive refinement: after each step the host reads ||dW_k|| and ||W_k|| of
+// every frequency and stops it once gwp::ir_converged says its error is below
+// tol (see there).
 gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
                             zdbl *W, int nb, double tol, gwp::SolveWs &w, std::vector<int> *conv_iters,
                             std::vector<double> *rel, int max_iter) {
     gw_status s = mixed_first_solve(c, st, n, v, v_is_diag, chi0, W, nb, w);
     if (s != GW_OK) return s;
     std::vector<int32_t> act(nb, 1);
-    std::vector<double> hn(2 * nb);
+    std::vector<double> hn(2 * nb), prev(nb, 0.0);
     conv_iters->assign(nb, -1);
     rel->assign(nb, 0.0);
     GW_HIP(c, hipMemcpyAsync(w.active, act.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
@@ -283,14 +292,15 @@ gw_status solve_batch_mixed(gw_ctx *c, hipStream_t st, int n, const double *v, i
         bool any = false;
         for (int b = 0; b < nb; ++b) {
             if (!act[b]) continue;
-            const double r = std::sqrt(hn[2 * b]) / std::max(std::sqrt(hn[2 * b + 1]), 1e-300);
-            (*rel)[b] = r;
-            if (r <= tol) {
+            const double dn = std::sqrt(hn[2 * b]), wn = std::sqrt(hn[2 * b + 1]);
+            (*rel)[b] = dn / std::max(wn, 1e-300);
+            if (gwp::ir_converged(it, dn, it == 1 ? wn : prev[b], wn, tol)) {
                 act[b] = 0;
                 (*conv_iters)[b] = it;
             } else {
                 any = true;
             }
+            prev[b] = dn;
         }
         if (!any) break;
         GW_HIP(c, hipMemcpyAsync(w.active, act.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st));
@@ -491,7 +501,7 @@ gw_status solve_plan(gw_ctx *ctx, int n, int n_omega, bool mixed, const std::str
     w.active = (int32_t *)q;
     if ((s = ws(ctx, pre + "sNorm", (size_t)nbmax * 16, &q)) != GW_OK) return s;
     w.norms = (double *)q;
-    if ((s = ws(ctx, pre + "sFinal", (size_t)n_omega * 16, &q)) != GW_OK) return s;
+    if ((s = ws(ctx, pre + "sFinal", (size_t)n_omega * 32, &q)) != GW_OK) return s;
     p->final_norms = (double *)q;
     if (mixed) {
         if ((s = ws(ctx, pre + "sA32", (size_t)nbmax * nn * 8, &q)) != GW_OK) return s;
@@ -530,8 +540,10 @@ gw_status solve_enqueue_nosync(gw_ctx *ctx, SolvePlan &p, hipStream_t st, const 
             s = mixed_first_solve(ctx, st, p.n, v, v_is_diag, X, W + j0 * nn, nb, w);
             if (s != GW_OK) return s;
             for (int it = 0; it < fixed_ir; ++it) {
-                s = mixed_refine_step(ctx, st, p.n, v, v_is_diag, W + j0 * nn, nb, w, nullptr,
-                                      p.final_norms + 2 * j0);
+                // the last step's norms go to the first half, the step
+                // before it to the second (the stopping rule needs both)
+                double *nrm = p.final_norms + 2 * j0 + (it == fixed_ir - 1 ? 0 : 2 * (int64_t)p.n_omega);
+                s = mixed_refine_step(ctx, st, p.n, v, v_is_diag, W + j0 * nn, nb, w, nullptr, nrm);
                 if (s != GW_OK) return s;
             }
         }

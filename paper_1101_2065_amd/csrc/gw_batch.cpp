@@ -8,7 +8,7 @@
 // stream, then the molecules' W solves spread over parallel stream branches
 // (fork/join through events), so solves of different molecules run
 // concurrently.  gw_batch_run replays the graph; for the mixed form it then
-// checks every frequency's last refinement step and re-solves in FP64 (outside
+// checks every frequency's last refinement steps and re-solves in FP64 (outside
 // the graph) any frequency that did not reach the tolerance.
 #include "gw_plan.h"
 #include "gw_tune.h"
@@ -41,7 +41,7 @@ struct gw_batch {
     gw_precision prec = GW_FP64;
     double tol = 1e-7;
     int n_refine = 0;
-    std::vector<double *> norms;  // per molecule [n_omega][2]
+    std::vector<double *> norms;  // per molecule [2][n_omega][2] (last two refinement steps)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;  // private stream the graph is recorded on
@@ -280,7 +280,7 @@ gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, c
     for (int i = 0; i < n_mol; ++i) {
         b->n.push_back(mols[i].n_prod);
         void *p;
-        gw_status s = gwp::ws(ctx, "bnorm" + std::to_string(i), (size_t)g->n_omega * 16, &p);
+        gw_status s = gwp::ws(ctx, "bnorm" + std::to_string(i), (size_t)g->n_omega * 32, &p);
         if (s != GW_OK) return bail(s);
         b->norms.push_back((double *)p);
         int tile = 0;
@@ -318,8 +318,8 @@ gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
         double worst = 0;
         const bool in_place = b->W[i] == b->chi0[i];
         if (mixed) {
-            std::vector<double> hn(2 * (size_t)N);
-            GW_HIP(ctx, hipMemcpy(hn.data(), b->norms[i], sizeof(double) * 2 * N, hipMemcpyDeviceToHost));
+            std::vector<double> hn(4 * (size_t)N);
+            GW_HIP(ctx, hipMemcpy(hn.data(), b->norms[i], sizeof(double) * 4 * N, hipMemcpyDeviceToHost));
             gwp::SolvePlan p64;
             bool planned = false;
             const int64_t nn = (int64_t)b->n[i] * b->n[i];
@@ -328,8 +328,10 @@ gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
             for (int j = N / 2; j < N; ++j) js.push_back(j);
             for (int j : js) {
                 ++solved;
-                const double r = std::sqrt(hn[2 * j]) / std::max(std::sqrt(hn[2 * j + 1]), 1e-300);
-                if (r <= b->tol) {
+                const double dn = std::sqrt(hn[2 * j]), wn = std::sqrt(hn[2 * j + 1]);
+                const double dprev = b->n_refine >= 2 ? std::sqrt(hn[2 * (size_t)N + 2 * j]) : wn;
+                const double r = dn / std::max(wn, 1e-300);
+                if (gwp::ir_converged(b->n_refine, dn, dprev, wn, b->tol)) {
                     worst = std::max(worst, r);
                     continue;
                 }

@@ -85,8 +85,18 @@ struct SolvePlan {
     int n = 0, n_omega = 0, nbmax = 0;
     bool mixed = false;
     SolveWs w;
-    double *final_norms = nullptr;  // [n_omega][2]: |dW|^2, |W|^2 of the last refinement step
+    // [2][n_omega][2]: |dW|^2, |W|^2 of the last refinement step, then of the
+    // step before it
+    double *final_norms = nullptr;
 };
+
+// Refinement stopping rule.  Step k of W_{k} = W_{k-1} + dW_k contracts the
+// error by about rho_k = ||dW_k|| / ||dW_{k-1}|| (with dW_0 = W_0, the first
+// low-precision solution), so the error left in W_k is about ||dW_k|| rho_k.
+// A frequency has converged when ||dW_k|| <= tol ||W_k||, or when the
+// iteration contracts (rho_k <= 1/2) and ||dW_k|| rho_k <= tol ||W_k||.
+// dn = ||dW_k||, dprev = ||dW_{k-1}|| (||W_0|| for k = 1), wn = ||W_k||.
+bool ir_converged(int k, double dn, double dprev, double wn, double tol);
 
 size_t per_freq_bytes(int n, bool mixed);
 int solve_batch_max(int n, int n_omega, bool mixed, size_t budget);
