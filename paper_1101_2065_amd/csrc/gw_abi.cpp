@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -38,6 +39,16 @@ using gwp::ws;
 
 namespace gwp {
 
+Fault fault() {
+    static const Fault f = [] {
+        const char *e = std::getenv("GW_FAULT");
+        if (!e) return FAULT_NONE;
+        const std::string v(e);
+        return v == "oom" ? FAULT_OOM : v == "device" ? FAULT_DEVICE : v == "noconv" ? FAULT_NOCONV : FAULT_NONE;
+    }();
+    return f;
+}
+
 gw_status fail(gw_ctx *c, gw_status s, const std::string &msg) {
     if (c) {
         c->err = msg;
@@ -53,6 +64,9 @@ gw_status fail(gw_ctx *c, gw_status s, const std::string &msg) {
 gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out) {
     DevBuf &b = c->bufs[name];
     if (bytes == 0) bytes = 256;
+    if (fault() == FAULT_OOM)
+        return fail(c, GW_E_OOM, std::string("workspace ") + name + ": cannot allocate " + std::to_string(bytes) +
+                                     " bytes (GW_FAULT=oom)");
     if (b.bytes < bytes) {
         if (b.ptr) {
             if (c->own_stream) {
@@ -187,6 +201,7 @@ gw_status aux_stream(gw_ctx *c) {
 namespace gwp {
 
 bool ir_converged(int k, double dn, double dprev, double wn, double tol) {
+    if (fault() == FAULT_NOCONV) return false;
     const double w = std::max(wn, 1e-300);
     if (!(dn == dn) || !(wn == wn)) return false;  // NaN: not converged
     if (dn <= tol * w) return true;
@@ -1441,6 +1456,7 @@ void gwk_ctx_trim(gw_ctx *c) {
 // differ) and the device is out of memory, the cache is handed back to the
 // device and the allocation tried once more.
 hipError_t gwk_malloc_async(void **p, size_t bytes, hipStream_t st) {
+    if (gwp::fault() == gwp::FAULT_OOM) return hipErrorOutOfMemory;
     hipError_t e = hipMallocAsync(p, bytes, st);
     if (e != hipErrorOutOfMemory) return e;
     (void)hipGetLastError();

@@ -17,12 +17,22 @@ using gwk::zdbl;
 using gwk::zflt;
 
 gw_status fail(gw_ctx *c, gw_status s, const std::string &msg);
+
+// Host-forced faults, for testing the error paths without breaking anything
+// on the device: the environment variable GW_FAULT (read once per process)
+// set to "oom" makes every workspace allocation fail as out of memory,
+// "device" makes every checked runtime call report a device failure (a
+// sticky error), "noconv" makes every refinement step report that it did not
+// converge.  Unset or anything else: no fault.
+enum Fault { FAULT_NONE = 0, FAULT_OOM = 1, FAULT_DEVICE = 2, FAULT_NOCONV = 3 };
+Fault fault();
 // Grow-only named device buffer of the context.
 gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out);
 
 #define GW_HIP(ctx, call)                                                                                     \
     do {                                                                                                      \
         hipError_t _e = (call);                                                                               \
+        if (_e == hipSuccess && gwp::fault() == gwp::FAULT_DEVICE) _e = hipErrorLaunchFailure;               \
         if (_e != hipSuccess)                                                                                 \
             return gwp::fail((ctx), _e == hipErrorOutOfMemory ? GW_E_OOM : GW_E_DEVICE,                       \
                              std::string(#call) + ": " + hipGetErrorString(_e));                             \

@@ -17,7 +17,9 @@
 // and only gives it back when the head of the queue would not fit otherwise;
 // the results (chi0 and W, plus the compression basis) stay resident until
 // gw_release.  Requests are admitted in arrival order; gw_release on a request
-// still in the queue cancels it.
+// still in the queue cancels it.  A request that runs out of device memory
+// (others' results and workspace in the way) goes back to the head of the
+// queue once, after its slot has given back its workspace.
 #include "../../include/gw.h"
 #include "gw_ctx.h"
 #include "gw_internal.h"
@@ -56,6 +58,7 @@ struct ServeReq {
     gw_report rep{};
     gw_status status = GW_OK;
     std::string err;
+    int retries = 0;  // times it went back to the queue after running out of memory
 };
 
 }  // namespace
@@ -263,14 +266,28 @@ void worker(GwServe *sv, int slot) {
         }
         r->stream = st;
         run_request(child, st, *r, &sv->solve_mu);
+        // out of memory (other requests' results and workspace in the way):
+        // the slot gives its workspace back and the request goes back to the
+        // head of the queue, once; a second failure is reported
+        const bool retry = r->status == GW_E_OOM && r->retries == 0;
+        if (retry) gwk_ctx_trim(child);
         const size_t kept = gwk_ctx_bytes(child);
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             sv->held[slot] = kept;
             if (r->status != GW_OK) {
                 free_results(*r);
-                r->state = Q_FAILED;
                 sv->results -= r->bytes_result;
+                if (retry) {
+                    r->retries = 1;
+                    r->status = GW_OK;
+                    r->err.clear();
+                    r->state = Q_QUEUED;
+                    sv->queue.push_front(r->ticket);
+                } else {
+                    r->state = Q_FAILED;
+                    if (r->retries) r->err += " (after one retry)";
+                }
             } else {
                 r->state = Q_DONE;
             }
