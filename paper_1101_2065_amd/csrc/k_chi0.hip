@@ -220,15 +220,17 @@ __global__ __launch_bounds__(256) void k_fftconv(int n, int n_omega, int nhb, co
 
 
 // ------------------------------------------------------------------ wave FFT convolution
-// One wave per (mu, nu) sequence, E = L / 64 complex values per lane kept in
-// registers; a radix-R Stockham pass works on butterflies j = lane + 64 t
-// (t < E / R), element r of butterfly t in register slot t R + r holding
-// position j + (L / R) r.  Between passes the wave exchanges through its own
-// LDS region (real and imaginary parts in turn, positions padded by one
-// double per 16 against bank conflicts); no workgroup barrier is involved.
-// The last pass leaves position q = lane + 64 sigma in the lane that also
-// owns q in the first pass, so forward output, kernel multiply and inverse
-// input stay in registers.
+// One lane group of P = 64 NW lanes (NW waves) per (mu, nu) sequence, E = L / P
+// complex values per lane kept in registers; a radix-R Stockham pass works on
+// butterflies j = lane + P t (t < E / R), element r of butterfly t in register
+// slot t R + r holding position j + (L / R) r.  Between passes the group
+// exchanges through its own LDS region (real and imaginary parts in turn,
+// positions padded by one double per 16 against bank conflicts); a single
+// wave needs no workgroup barrier, a group of two waits at one.  The last
+// pass leaves position q = lane + P sigma in the lane that also owns q in
+// the first pass, so forward output, kernel multiply and inverse input stay
+// in registers.  At L = 2048 two waves share a sequence (16 values per lane):
+// one wave would need 32 and spill registers to scratch memory.
 __device__ inline int fpad(int pos) { return pos + (pos >> 4); }
 
 template <bool INV>
@@ -276,24 +278,24 @@ __device__ inline void dftR(zdbl *v) {
 // them in the first-pass layout (radix R): canonical slot t R + r is position
 // lane + 64 sg with sg = t + (E / R) r, which the forward transform left in
 // slot (sg % (E / RL)) RL + sg / (E / RL).
-template <int L, int R, int RL, bool PERM>
+template <int L, int R, int RL, bool PERM, int P = 64>
 __device__ constexpr int wslot(int t, int r) {
-    constexpr int E = L / 64;
+    constexpr int E = L / P;
     if constexpr (!PERM) return t * R + r;
     const int sg = t + (E / R) * r;
     return (sg % (E / RL)) * RL + sg / (E / RL);
 }
 
 // Twiddle and butterfly of one pass (radix R, NS points already transformed).
-template <int L, int R, int NS, bool INV, bool PERM = false, int RL = R>
+template <int L, int R, int NS, bool INV, bool PERM = false, int RL = R, int P = 64>
 __device__ inline void wpass(zdbl *x, const zdbl *__restrict__ tw, int lane) {
-    constexpr int E = L / 64, NBF = E / R;
+    constexpr int E = L / P, NBF = E / R;
 #pragma unroll
     for (int t = 0; t < NBF; ++t) {
-        const int j = lane + 64 * t;
+        const int j = lane + P * t;
         zdbl v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = x[wslot<L, R, RL, PERM>(t, r)];
+        for (int r = 0; r < R; ++r) v[r] = x[wslot<L, R, RL, PERM, P>(t, r)];
         if constexpr (NS > 1) {
             // W^(jm r) for r < R from the table entries of r = 1, 2, 4, 8
             // (at most two further roundings per factor)
@@ -322,49 +324,64 @@ __device__ inline void wpass(zdbl *x, const zdbl *__restrict__ tw, int lane) {
         }
         dftR<R, INV>(v);
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[wslot<L, R, RL, PERM>(t, r)] = v[r];
+        for (int r = 0; r < R; ++r) x[wslot<L, R, RL, PERM, P>(t, r)] = v[r];
         __builtin_amdgcn_sched_barrier(0);  // one butterfly's registers at a time
     }
+}
+
+// Waits for the other waves of the lane group (P > 64: the whole workgroup,
+// every wave of which runs the same passes).
+template <int P>
+__device__ inline void wsync() {
+    if constexpr (P == 64) __builtin_amdgcn_wave_barrier();
+    else __syncthreads();
 }
 
 // Outputs of a (R, NS) pass go to y = (j / NS) NS R + j % NS + r NS; the next
 // pass (radix R2) reads position j2 + (L / R2) r2 into slot t2 R2 + r2.  All
 // writes of a part precede its reads, so the reads may land in the same
 // registers.
-template <int L, int R, int NS, int R2, bool PERM = false, int RL = R>
+template <int L, int R, int NS, int R2, bool PERM = false, int RL = R, int P = 64>
 __device__ inline void wexchange(zdbl *x, double *lds, int lane) {
-    constexpr int E = L / 64, NBF = E / R, NBF2 = E / R2;
+    constexpr int E = L / P, NBF = E / R, NBF2 = E / R2;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
 #pragma unroll
         for (int t = 0; t < NBF; ++t) {
-            const int j = lane + 64 * t;
+            const int j = lane + P * t;
             const int base = (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const zdbl &v = x[wslot<L, R, RL, PERM>(t, r)];
+                const zdbl &v = x[wslot<L, R, RL, PERM, P>(t, r)];
                 lds[fpad(base + r * NS)] = part ? v.im : v.re;
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wsync<P>();
 #pragma unroll
         for (int t2 = 0; t2 < NBF2; ++t2)
 #pragma unroll
             for (int r2 = 0; r2 < R2; ++r2) {
-                const double d = lds[fpad(lane + 64 * t2 + (L / R2) * r2)];
+                const double d = lds[fpad(lane + P * t2 + (L / R2) * r2)];
                 if (part) x[t2 * R2 + r2].im = d;
                 else x[t2 * R2 + r2].re = d;
             }
-        __builtin_amdgcn_wave_barrier();
+        wsync<P>();
     }
 }
 
 // Whole FFT of length L in registers + the wave's LDS region; output in the
 // layout of the last pass.  PERM: the input is in the last-pass layout (of a
 // previous transform), else in the first-pass layout.
-template <int L, bool INV, bool PERM>
+template <int L, bool INV, bool PERM, int P = 64>
 __device__ inline void wfft(zdbl *x, double *lds, const zdbl *__restrict__ tw, int lane) {
-    if constexpr (L == 2048) {
+    if constexpr (P == 128) {
+        static_assert(L == 2048, "two waves per sequence only at L = 2048");
+        wpass<L, 16, 1, INV, PERM, 8, P>(x, tw, lane);
+        wexchange<L, 16, 1, 16, PERM, 8, P>(x, lds, lane);
+        wpass<L, 16, 16, INV, false, 16, P>(x, tw, lane);
+        wexchange<L, 16, 16, 8, false, 16, P>(x, lds, lane);
+        wpass<L, 8, 256, INV, false, 8, P>(x, tw, lane);
+    } else if constexpr (L == 2048) {
         wpass<L, 16, 1, INV, PERM, 8>(x, tw, lane);
         wexchange<L, 16, 1, 16, PERM, 8>(x, lds, lane);
         wpass<L, 16, 16, INV>(x, tw, lane);
@@ -398,40 +415,42 @@ template <int L>
 struct WPlan {
     static constexpr int R1 = (L == 2048 || L == 1024) ? 16 : (L == 512 ? 8 : 4);  // first pass radix
     static constexpr int RL = (L == 256) ? 4 : 8;                                  // last pass radix
+    static constexpr int NW = (L == 2048) ? 2 : 1;                                 // waves per sequence
 };
 
-// chi0 from the histogram, one sequence per wave.  Workgroup = 8 waves = row
-// mu and the 8 consecutive nu >= mu of one 8-column group: the outputs are
-// staged through LDS so that every 8 lanes write 128 contiguous bytes of a
-// chi0 row.  Each sequence: forward FFT of the odd extension (purely
-// imaginary spectrum i alpha), times i Kt, inverse FFT, scale 1/L.
-// FULL: the spectral arrays are dense [m][n][n] (n_upper = n^2, every nu, no
-// symmetry) and hold v a0, so the transform is v chi0 and the kernel writes
-// A = 1 - v chi0.
+// chi0 from the histogram, one sequence per lane group.  Workgroup = 8 waves
+// = row mu and SEQ = 8 / NW consecutive nu >= mu of one column group: the
+// outputs are staged through LDS so that every SEQ lanes write SEQ * 16
+// contiguous bytes of a chi0 row.  Each sequence: forward FFT of the odd
+// extension (purely imaginary spectrum i alpha), times i Kt, inverse FFT,
+// scale 1/L.  FULL: the spectral arrays are dense [m][n][n] (n_upper = n^2,
+// every nu, no symmetry) and hold v a0, so the transform is v chi0 and the
+// kernel writes A = 1 - v chi0.
 template <typename HT, int L, bool FULL = false>
 __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, const HT *__restrict__ H,
                                                    int64_t n_upper, const int32_t *__restrict__ s_dev,
                                                    const zdbl *__restrict__ Kt, const zdbl *__restrict__ tw,
                                                    zdbl *__restrict__ chi0) {
-    constexpr int E = L / 64, REG = L + L / 16;  // doubles per wave region
+    constexpr int NW = WPlan<L>::NW, P = 64 * NW, SEQ = 8 / NW;
+    constexpr int E = L / P, REG = L + L / 16;  // doubles per sequence region
     constexpr int R1 = WPlan<L>::R1, RL = WPlan<L>::RL;
-    __shared__ double lds[8 * REG];
-    const int nch = (n + 7) / 8;
+    __shared__ double lds[SEQ * REG];
+    const int nch = (n + SEQ - 1) / SEQ;
     const int mu = blockIdx.x / nch;
-    const int nu0 = (blockIdx.x % nch) * 8;
-    if (!FULL && nu0 + 7 < mu) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nu0 = (blockIdx.x % nch) * SEQ;
+    if (!FULL && nu0 + SEQ - 1 < mu) return;
+    const int tid = threadIdx.x, lane = tid % P, w = tid / P;
     const int s = s_dev ? *s_dev : 0;
     const int64_t nn = (int64_t)n * n;
     const int64_t trow = FULL ? (int64_t)mu * n : (int64_t)mu * n - ((int64_t)mu * (mu - 1)) / 2 - mu;
-    // histogram rows of the 8 sequences, scaled to doubles: Hs[m][w], m < nhb
+    // histogram rows of the SEQ sequences, scaled to doubles: Hs[m][w], m < nhb
     double *Hs = lds;
-    for (int idx = tid; idx < nhb * 8; idx += 512) {
-        const int m = idx >> 3, ww = idx & 7;
+    for (int idx = tid; idx < nhb * SEQ; idx += 512) {
+        const int m = idx / SEQ, ww = idx % SEQ;
         const int nu = nu0 + ww;
         double v = 0.0;
         if (m >= 1 && (FULL || nu >= mu) && nu < n) v = hval(H, (int64_t)m * n_upper + trow + nu, s);
-        Hs[m * 9 + ww] = v;
+        Hs[m * (SEQ + 1) + ww] = v;
     }
     __syncthreads();
     // odd extension a(q) = h(q), a(L - q) = -h(q), in the first pass layout
@@ -440,37 +459,37 @@ __global__ __launch_bounds__(512) void k_fftconv_w(int n, int n_omega, int nhb, 
     for (int t = 0; t < E / R1; ++t)
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
-            const int q = lane + 64 * t + (L / R1) * r;
+            const int q = lane + P * t + (L / R1) * r;
             double a = 0.0;
-            if (q < nhb) a = Hs[q * 9 + w];
-            else if (q > L - nhb) a = -Hs[(L - q) * 9 + w];
+            if (q < nhb) a = Hs[q * (SEQ + 1) + w];
+            else if (q > L - nhb) a = -Hs[(L - q) * (SEQ + 1) + w];
             x[t * R1 + r] = zdbl{a, 0.0};
         }
     __syncthreads();
     double *my = lds + w * REG;
-    wfft<L, false, false>(x, my, tw, lane);
-    // times i Kt at position q = lane + 64 sg, in place in the last-pass layout
+    wfft<L, false, false, P>(x, my, tw, lane);
+    // times i Kt at position q = lane + P sg, in place in the last-pass layout
 #pragma unroll
     for (int sg = 0; sg < E; ++sg) {
         const int sf = (sg % (E / RL)) * RL + sg / (E / RL);
-        const zdbl K = Kt[lane + 64 * sg];
+        const zdbl K = Kt[lane + P * sg];
         const double al = x[sf].im;
         x[sf] = zdbl{-al * K.im, al * K.re};
         if ((sg & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // keep few loads in flight (registers)
     }
-    wfft<L, true, true>(x, my, tw, lane);
-    // stage q < n_omega (last-pass layout) as complex pairs in the wave region
+    wfft<L, true, true, P>(x, my, tw, lane);
+    // stage q < n_omega (last-pass layout) as complex pairs in the sequence's region
     const double inv_l = 1.0 / (double)L;
 #pragma unroll
     for (int sg = 0; sg < E / 2; ++sg) {
         const int sf = (sg % (E / RL)) * RL + sg / (E / RL);
-        const int q = lane + 64 * sg;
+        const int q = lane + P * sg;
         my[2 * q] = x[sf].re * inv_l;
         my[2 * q + 1] = x[sf].im * inv_l;
     }
     __syncthreads();
-    for (int idx = tid; idx < 8 * n_omega; idx += 512) {
-        const int ww = idx & 7, j = idx >> 3;
+    for (int idx = tid; idx < SEQ * n_omega; idx += 512) {
+        const int ww = idx % SEQ, j = idx / SEQ;
         const int nu = nu0 + ww;
         if ((FULL || nu >= mu) && nu < n) {
             const double *src = lds + ww * REG + 2 * j;
@@ -581,7 +600,8 @@ hipError_t launch_fftconv_A(hipStream_t st, int n, int n_omega, int nhb, const d
     const int64_t nn = (int64_t)n * n;
     const int L = 2 * n_omega;
     ProfScope ps(st, "fftconv_A", 0.0, 8.0 * (nhb - 1) * (double)nn + 16.0 * n_omega * (double)nn);
-    dim3 gw((unsigned)((int64_t)n * ((n + 7) / 8)));
+    const int seq = L == 2048 ? 4 : 8;  // sequences per workgroup (two waves each at L = 2048)
+    dim3 gw((unsigned)((int64_t)n * ((n + seq - 1) / seq)));
 #define GW_FFTA_CASE(LL)                                                                                            \
     case LL:                                                                                                        \
         hipLaunchKernelGGL((k_fftconv_w<double, LL, true>), gw, dim3(512), 0, st, n, n_omega, nhb, B, nn,           \
@@ -623,7 +643,8 @@ hipError_t fftconv_impl(hipStream_t st, int n, int n_omega, int nhb, const HT *H
         // wave kernel on the upper triangle, then the lower one by symmetry
         {
             ProfScope ps(st, "fftconv", 0.0, 8.0 * nhb * (double)n_upper + 16.0 * n_omega * (double)n_upper);
-            dim3 gw((unsigned)((int64_t)n * ((n + 7) / 8)));
+            const int seq = L == 2048 ? 4 : 8;  // sequences per workgroup (two waves each at L = 2048)
+            dim3 gw((unsigned)((int64_t)n * ((n + seq - 1) / seq)));
 #define GW_FFTW_CASE(LL)                                                                                     \
     case LL:                                                                                                 \
         hipLaunchKernelGGL((k_fftconv_w<HT, LL>), gw, dim3(512), 0, st, n, n_omega, nhb, H, n_upper, s_dev, Kt, tw, \
