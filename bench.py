@@ -92,7 +92,10 @@ def blas_threads():
 
 def cpu_baseline(mol, grid, budget_s=20.0):
     """Oracle on the host cores over a bounded sample, scaled to whole-job
-    delivered W(omega)/s: T = T_pairs + T_hist + N_omega (T_chi0(w) + T_W(w))."""
+    delivered W(omega)/s.  The oracle uses the same conjugate mirror as the
+    GPU (W(-omega) = W(omega)*, exact for the retarded response on the
+    symmetric mesh), so it pays chi0 and a LAPACK solve at the same N/2 + 1
+    frequencies: T = T_pairs + T_hist + (N/2 + 1) (T_chi0(w) + T_W(w))."""
     sys.path.insert(0, HERE)
     import oracle as o
 
@@ -127,7 +130,8 @@ def cpu_baseline(mol, grid, budget_s=20.0):
         o.screened_W(mol.v, chi)
         ts.append(time.perf_counter() - t0)
     t_w = float(np.median(ts))
-    total = t_pairs + t_hist + grid.n_omega * (t_chi + t_w)
+    n_solved = grid.n_omega // 2 + 1
+    total = t_pairs + t_hist + n_solved * (t_chi + t_w)
     omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     nblas = blas_threads()
     # context: one W solve with a single BLAS thread (the paper's runs used one core)
@@ -150,6 +154,7 @@ def cpu_baseline(mol, grid, budget_s=20.0):
     return {
         "value": grid.n_omega / total,
         "unit": "W(omega)/s",
+        "solves_per_s": n_solved / total,
         "cores": max(nblas, omp),
         "host_cpus": os.cpu_count(),
         "cpu_model": model,
@@ -157,8 +162,9 @@ def cpu_baseline(mol, grid, budget_s=20.0):
         "kind": "oracle",
         "sample": ("pair vectors in full (%.1fs); int64 histogram (C, %d OpenMP threads) on %d of %d entries "
                    "(scaled); chi0 direct sum at one frequency on the same entries (scaled x%d frequencies); "
-                   "LAPACK zgesv W solve (%d BLAS threads) at N=%d on %d frequencies (median %.2fs, scaled x%d)")
-                  % (t_pairs, omp, n_samp, n_upper, grid.n_omega, nblas, n, len(ts), t_w, grid.n_omega),
+                   "LAPACK zgesv W solve (%d BLAS threads) at N=%d on %d frequencies (median %.2fs, scaled x%d); "
+                   "the %d solved frequencies of the conjugate mirror, as on the GPU")
+                  % (t_pairs, omp, n_samp, n_upper, n_solved, nblas, n, len(ts), t_w, n_solved, n_solved),
     }
 
 
@@ -237,9 +243,12 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
         route_a = form.endswith("_A")
         base = form[:-2] if route_a else form
         p = FORMS[base]
+        # the FP64 forms (the headline candidates) take the requested steps;
+        # the refined forms, several times slower on this chip, at most five
+        warm, steps = (args.warmup, args.steps) if base == "fp64" else (min(args.warmup, 1), min(args.steps, 5))
         ev, reps = [], []
-        for it in range(args.warmup + args.steps):
-            timed = it >= args.warmup
+        for it in range(warm + steps):
+            timed = it >= warm
             if timed and base == "fp64":
                 ctx.profile_begin()
             torch.cuda.synchronize()
@@ -288,6 +297,7 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
             "fallback": int(max(r[1] for r in reps)),
             "rel_err_vs_fp64": err,
             "route_a": route_a,
+            "steps": steps,
         }
     ok = {f: r for f, r in results.items() if r["rel_err_vs_fp64"] is None or r["rel_err_vs_fp64"] <= 1e-6}
     best = min(ok, key=lambda f: ok[f]["t_step"])
@@ -304,17 +314,53 @@ def run_single(args, gw, gs, torch, mol, grid, workload):
         out["forms"][f] = {"W_per_s": N / v["t_step"], "solves_per_s": v["n_solved"] / v["t_step"],
                            "t_chi0_s": v["t_chi0"], "t_solve_s": v["t_solve"], "p50_ms": v["p50_ms"],
                            "p99_ms": v["p99_ms"], "max_ir_steps": v["max_iter"], "fp64_fallbacks": v["fallback"],
-                           "rel_err_vs_fp64": v["rel_err_vs_fp64"],
+                           "rel_err_vs_fp64": v["rel_err_vs_fp64"], "steps_timed": v["steps"],
                            "solve_TFLOPs": ach, "solve_roofline_frac": ach / pk}
-    out["latency_ms"] = {"p50": r["p50_ms"], "p99": r["p99_ms"]}
+    out["step_latency_ms"] = {"p50": r["p50_ms"], "p99": r["p99_ms"]}
     if roofs:
         # the headline form's kernels when they were timed, else the FP64 chi0 route's
         out["roofline"] = roofs.get(best, roofs.get("fp64", next(iter(roofs.values()))))
+    out["step_roofline"] = step_roofline(n, N, r["n_solved"], rep_nhb(gw, mol, grid), r["t_step"], r["max_iter"],
+                                         not best.startswith("fp64"), r["route_a"])
     ctx.close()
+    del chi, W, dm
+    torch.cuda.empty_cache()
+    if not args.no_serving and workload.startswith("chain40_nprod2000"):
+        # the serving form of the path (gw_submit .. gw_poll) on a bounded
+        # window of the Poisson workload, so that p50/p99 come from this run
+        legs = serving_legs(args, gw, gs, torch, pool_size=args.serve_pool, duration=args.serve_duration)
+        out["serving"] = legs
+        o = legs["overloaded"]
+        out["latency_ms"] = {"p50": o["p50_ms"], "p99": o["p99_ms"],
+                             "below_capacity_p50": legs["below_capacity"]["p50_ms"],
+                             "below_capacity_p99": legs["below_capacity"]["p99_ms"],
+                             "definition": "gw_submit to gw_poll completion over every arrival; requests still "
+                                           "queued at the end of the arrival window are cancelled and counted at "
+                                           "their age then (a lower bound)"}
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(mol, grid)
     return out
+
+
+def rep_nhb(gw, mol, grid):
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    return gw.query_sizes(mol.n_orb, mol.n_occ, mol.n_prod, np.ascontiguousarray(mol.eig), g).n_hbins
+
+
+def step_roofline(n, N, n_solved, nhb, t_step, n_ir, mixed, route_a):
+    """Whole-step roofline of the headline form: the algorithmic matrix-core
+    work of one step (the solve's products per solved frequency, plus on the A
+    route the n_hbins - 1 real products v a0 of 2 N^3 each) at the FP64 and
+    FP32 matrix peaks, over the measured step time.  The histogram, the FFT
+    and the copies are not counted in the numerator, so the fraction is a
+    lower bound on how close the step is to its matrix-core roofline."""
+    fl = solve_flops(n, n_solved, n_ir, mixed, form_a=not route_a)
+    fp64 = fl["fp64"] + (2.0 * float(n) ** 3 * (nhb - 1) if route_a else 0.0)
+    fp32 = fl["fp32"]
+    t_roof = fp64 / PEAK_FP64 + fp32 / PEAK_FP32
+    return {"bound": "mfma", "flops_fp64": fp64, "flops_fp32": fp32, "t_roof_s": t_roof, "t_step_s": t_step,
+            "achieved_TFLOPs": (fp64 + fp32) / t_step / 1e12, "frac": t_roof / t_step}
 
 
 # ---------------------------------------------------------------------- compressed cluster
@@ -689,84 +735,137 @@ def run_c3(args, gw, gs, torch):
 
 
 # ---------------------------------------------------------------------- serving
-def run_c4(args, gw, gs, torch):
+def serving_pool(gs, gw, torch, n_pool, lo=10, hi=200):
+    """Cluster molecules at n_pool atom counts spaced evenly in log between lo
+    and hi (the midpoints of n_pool equal-probability slices of the
+    log-uniform arrival distribution).  Generating every arrival's own cluster
+    would take about a second each on the host, so each arrival is served the
+    molecule whose atom count is nearest to its own drawn count; the record
+    reports how far that moves the sizes and the cost."""
+    la, lb = math.log(lo), math.log(hi)
+    counts = sorted(set(int(round(math.exp(la + (k + 0.5) * (lb - la) / n_pool))) for k in range(n_pool)))
+    dev = torch.device("cuda:0")
+    pool = []
+    for c in counts:
+        m = gs.serving_molecule(c, c)
+        pool.append((c, m, gw.DeviceMolecule(m, device=dev)))
+    return pool
+
+
+def _nearest(pool, c):
+    return min(range(len(pool)), key=lambda i: (abs(math.log(pool[i][0] / c)), pool[i][0]))
+
+
+def serve_leg(gw, g, N, pool, rate, duration, seed, prec, cancel_at_end):
+    """One Poisson window: submit each arrival on time, poll, release.
+    Latency = gw_submit .. gw_poll completion.  With cancel_at_end, requests
+    still queued when the window closes are cancelled and counted at their age
+    then (censored: a lower bound on their latency)."""
+    times, counts = arrival_stream(rate, duration, seed)
+    picks = [_nearest(pool, int(c)) for c in counts]
+    ctx = gw.Context(0)
+    pending = {}
+    lat, cens = [], []
+    done = cancelled = delivered = 0
+    i = 0
+    t_start = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t_start
+        while i < len(times) and times[i] <= now:
+            _, m, dm = pool[picks[i]]
+            k = min(m.n_prod, 1500)
+            t = ctx.submit(dm.struct, dm.v, g, k_compress=k, prec=prec, tol=1e-7)
+            pending[t] = times[i]
+            i += 1
+        for t in list(pending):
+            r = ctx.poll(t)
+            if r is not None:
+                lat.append(time.perf_counter() - t_start - pending.pop(t))
+                ctx.release(t)
+                done += 1
+                delivered += N
+        if i >= len(times):
+            break
+        time.sleep(0.001)
+    t_window = time.perf_counter() - t_start
+    if cancel_at_end:
+        for t in list(pending):
+            try:
+                ctx.release(t)
+            except gw.GwError:
+                continue  # running: it will complete below
+            cens.append(t_window - pending.pop(t))
+            cancelled += 1
+    while pending:
+        for t in list(pending):
+            r = ctx.poll(t)
+            if r is not None:
+                lat.append(time.perf_counter() - t_start - pending.pop(t))
+                ctx.release(t)
+                done += 1
+                delivered += N
+        time.sleep(0.002)
+    wall = time.perf_counter() - t_start
+    ctx.close()
+    every = np.array(lat + cens) * 1e3
+    lat_ms = np.array(lat) * 1e3
+    served = np.array([pool[p][1].n_prod for p in picks], dtype=float)
+    # size fidelity: the arrivals' own drawn atom counts against the served ones
+    drawn_atoms = np.asarray(counts, dtype=float)
+    served_atoms = np.array([pool[p][0] for p in picks], dtype=float)
+    return {
+        "offered_per_s": rate, "window_s": duration, "arrivals": len(times), "completed": done,
+        "cancelled": cancelled, "completed_fraction": done / max(1, len(times)),
+        "sustained_requests_per_s": done / wall, "sustained_W_per_s": delivered / wall, "wall_s": wall,
+        "p50_ms": float(np.percentile(every, 50)) if len(every) else None,
+        "p99_ms": float(np.percentile(every, 99)) if len(every) else None,
+        "completed_p50_ms": float(np.percentile(lat_ms, 50)) if done else None,
+        "completed_p99_ms": float(np.percentile(lat_ms, 99)) if done else None,
+        "censored_at_window_end": cancelled,
+        "size_fidelity": {
+            "pool_atom_counts": [c for c, _, _ in pool],
+            "mean_abs_rel_atom_error": float(np.mean(np.abs(served_atoms / drawn_atoms - 1.0))) if len(picks) else None,
+            "mean_n_prod_served": float(served.mean()) if len(picks) else None,
+            "cost_ratio_served_vs_drawn": float(np.mean(np.minimum(served_atoms * 60.0, 1500.0) ** 3) /
+                                                np.mean(np.minimum(drawn_atoms * 60.0, 1500.0) ** 3))
+            if len(picks) else None,
+        },
+    }
+
+
+def arrival_stream(rate, duration, seed):
+    sys.path.insert(0, HERE)
+    import gw_synth as gs
+
+    return gs.serving_stream(rate=rate, duration=duration, seed=seed)
+
+
+def serving_legs(args, gw, gs, torch, pool_size, duration):
     grid = gs.config_grid(4)
     N = grid.n_omega
     g = gw.make_grid(N, grid.omega_min, grid.omega_max, grid.eps)
-    dev = torch.device("cuda:0")
-    times, counts = gs.serving_stream(rate=args.rate, duration=args.duration)
-    n_pool = min(args.pool, len(times))
-    log("generating a pool of %d cluster molecules" % n_pool)
-    pool = []
-    for i in range(n_pool):
-        m = gs.serving_molecule(i, int(counts[i]))
-        pool.append((m, gw.DeviceMolecule(m, device=dev)))
-    prec = FORMS[args.forms.split(",")[0]]
+    log("serving: generating a pool of %d cluster molecules" % pool_size)
+    pool = serving_pool(gs, gw, torch, pool_size)
+    prec = 0
     out = {}
-    runs = [("overloaded", args.rate), ("below_capacity", args.low_rate)]
-    for label, rate in runs:
-        times, counts = gs.serving_stream(rate=rate, duration=args.duration)
-        ctx = gw.Context(0)
-        pending = {}
-        lat, done, cancelled = [], 0, 0
-        delivered = 0
-        i = 0
-        t_start = time.perf_counter()
-        while True:
-            now = time.perf_counter() - t_start
-            while i < len(times) and times[i] <= now:
-                m, dm = pool[i % n_pool]
-                k = min(m.n_prod, 1500)
-                t = ctx.submit(dm.struct, dm.v, g, k_compress=k, prec=prec, tol=1e-7)
-                pending[t] = times[i]
-                i += 1
-            for t in list(pending):
-                r = ctx.poll(t)
-                if r is not None:
-                    lat.append(time.perf_counter() - t_start - pending.pop(t))
-                    ctx.release(t)
-                    done += 1
-                    delivered += N
-            if i >= len(times):
-                break
-            time.sleep(0.001)
-        t_window = time.perf_counter() - t_start
-        # end of the arrival window: when overloaded, cancel what is still
-        # queued; in every case finish what was admitted
-        if label == "overloaded":
-            for t in list(pending):
-                try:
-                    ctx.release(t)
-                    pending.pop(t)
-                    cancelled += 1
-                except gw.GwError:
-                    pass
-        while pending:
-            for t in list(pending):
-                r = ctx.poll(t)
-                if r is not None:
-                    lat.append(time.perf_counter() - t_start - pending.pop(t))
-                    ctx.release(t)
-                    done += 1
-                    delivered += N
-            time.sleep(0.002)
-        wall = time.perf_counter() - t_start
-        ctx.close()
-        lat_ms = np.array(lat) * 1e3
-        out[label] = {"offered_per_s": rate, "arrivals": len(times), "completed": done, "cancelled": cancelled,
-                      "sustained_requests_per_s": done / wall, "sustained_W_per_s": delivered / wall,
-                      "window_s": t_window, "wall_s": wall,
-                      "p50_ms": float(np.percentile(lat_ms, 50)) if done else None,
-                      "p99_ms": float(np.percentile(lat_ms, 99)) if done else None}
-        log("c4 %s: %s" % (label, json.dumps(out[label])))
-    o = out["overloaded"]
+    for label, rate, seed, cancel in (("overloaded", args.rate, 4, True), ("below_capacity", args.low_rate, 5, False)):
+        out[label] = serve_leg(gw, g, N, pool, rate, duration, seed, prec, cancel)
+        log("serving %s: %s" % (label, json.dumps({k: v for k, v in out[label].items() if k != "size_fidelity"})))
+    out["form"] = "fp64, k = min(N_prod, 1500) top-k compression, 1024 points"
+    return out
+
+
+def run_c4(args, gw, gs, torch):
+    grid = gs.config_grid(4)
+    N = grid.n_omega
+    legs = serving_legs(args, gw, gs, torch, pool_size=args.pool, duration=args.duration)
+    o = legs["overloaded"]
     rec = base_record(args, "served W(omega)/s (sustained) with p50/p99 latency, Poisson arrivals",
-                      o["sustained_W_per_s"], "W(omega)/s", o["wall_s"],
-                      "f64" if prec == 0 else "f32+f64",
+                      o["sustained_W_per_s"], "W(omega)/s", o["wall_s"], "f64",
                       {"workload": "serve_poisson%g_clusters10to200_k1500_nomega1024" % args.rate,
-                       "duration_s": args.duration, "pool": n_pool, "parallelism": "none (1 GPU)"})
+                       "duration_s": args.duration, "pool": args.pool, "n_omega": N, "parallelism": "none (1 GPU)"})
     rec["latency_ms"] = {"p50": o["p50_ms"], "p99": o["p99_ms"]}
-    rec["serving"] = out
+    rec["serving"] = legs
     return rec
 
 
@@ -950,7 +1049,11 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="c4: offered requests/s")
     ap.add_argument("--low-rate", type=float, default=0.3, help="c4: the below-capacity run")
     ap.add_argument("--duration", type=float, default=60.0, help="c4: arrival window (s)")
-    ap.add_argument("--pool", type=int, default=32, help="c4: distinct molecules drawn by the arrivals")
+    ap.add_argument("--pool", type=int, default=32, help="c4: molecules at log-spaced atom counts (each arrival "
+                    "is served the one nearest its own drawn count)")
+    ap.add_argument("--no-serving", action="store_true", help="n2000: skip the bounded serving legs")
+    ap.add_argument("--serve-duration", type=float, default=20.0, help="n2000: arrival window of each serving leg (s)")
+    ap.add_argument("--serve-pool", type=int, default=16, help="n2000: molecules in the serving pool")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 1 GiB device copies (reference for the HBM counters)")
     ap.add_argument("--summarize-counters", nargs=3, metavar=("STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
@@ -974,7 +1077,8 @@ def main():
               "documented, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.forms is None:
-        args.forms = {"n2000": "fp64,fp64_A,fp32_ir,bf16x_ir", "n2000_2w": "fp64", "n2000_time": "fp64",
+        args.forms = {"n2000": "fp64,fp64_A,fp32_ir,bf16x_ir,fp32_ir_A,bf16x_ir_A", "n2000_2w": "fp64",
+                      "n2000_time": "fp64",
                       "n2000_sigma": "fp64",
                       "c1": "fp64,fp64_A,bf16x_ir",
                       "c2": "fp64,bf16x_ir",
