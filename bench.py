@@ -871,8 +871,8 @@ def run_c4(args, gw, gs, torch):
 
 # ---------------------------------------------------------------------- profiles
 # Kernel whose HBM traffic the roofline reports, and the source it is built from.
-TRAFFIC_KERNEL = "k_gemm<double, true, true, 4, 1, 8, 4, true>"
-TRAFFIC_CLASS = "zgemm_128x32"  # the same kernel in the library's live timing
+TRAFFIC_KERNEL = "k_gemm<double, true, true, 2, 1, 8, 5, true, true>"
+TRAFFIC_CLASS = "zgemm3m_64x32"  # the same kernel in the library's live timing
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
 COPY_BYTES = 1 << 30
 
@@ -945,9 +945,9 @@ def summarize_profiles(stats_csv, fetch_csv, write_csv, out_json):
         "1024 frequencies" % PROFILE_STEP, "",
         "Commands (repository root, one MI355X; one counter per run; OUT is any output directory):", "", "```",
         "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc_fetch -o run --output-format csv -- python3 bench.py "
-        "--forms %s --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration" % PROFILE_FORM,
+        "--forms %s --steps 1 --warmup 0 --no-cpu-baseline --no-serving --copy-calibration" % PROFILE_FORM,
         "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc_write -o run --output-format csv -- python3 bench.py "
-        "--forms %s --steps 1 --warmup 0 --no-cpu-baseline --copy-calibration" % PROFILE_FORM,
+        "--forms %s --steps 1 --warmup 0 --no-cpu-baseline --no-serving --copy-calibration" % PROFILE_FORM,
         "python bench.py --summarize-counters $OUT/prof_n2000/run_kernel_stats.csv "
         "$OUT/pmc_fetch/run_counter_collection.csv $OUT/pmc_write/run_counter_collection.csv",
         "```", "",
@@ -989,7 +989,7 @@ def summarize_mfma(counter_csv, out_md):
           "N_prod=2000, 1024 frequencies" % PROFILE_STEP, "",
           "Commands (repository root, one MI355X; OUT is any output directory):", "", "```",
           "rocprofv3 --pmc MfmaUtil MfmaFlopsF64 -d $OUT/pmc_mfma -o run --output-format csv -- python3 "
-          "bench.py --forms %s --steps 1 --warmup 0 --no-cpu-baseline" % PROFILE_FORM,
+          "bench.py --forms %s --steps 1 --warmup 0 --no-cpu-baseline --no-serving" % PROFILE_FORM,
           "python bench.py --summarize-mfma $OUT/pmc_mfma/run_counter_collection.csv", "```", "",
           "MfmaUtil = MFMA busy cycles / (active cycles x SIMDs) in percent; MfmaFlopsF64 = executed FP64 matrix "
           "flops (512 per counted op), padding of partial tiles included.", "",
@@ -1019,7 +1019,7 @@ def summarize_trace(stats_csv, out_md):
           "1024 frequencies" % PROFILE_STEP, "",
           "Command (repository root, one MI355X; OUT is any output directory):", "", "```",
           "rocprofv3 --kernel-trace --stats -d $OUT/prof_n2000 -o run --output-format csv -- python3 bench.py "
-          "--forms %s --steps 1 --warmup 1 --no-cpu-baseline" % PROFILE_FORM,
+          "--forms %s --steps 1 --warmup 1 --no-cpu-baseline --no-serving" % PROFILE_FORM,
           "python bench.py --summarize-trace $OUT/prof_n2000/run_kernel_stats.csv", "```", "",
           "Two steps (one warm-up, one timed) of gw_build_A + gw_solve_W_A; all kernels from `run_kernel_stats.csv`:",
           "", "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]

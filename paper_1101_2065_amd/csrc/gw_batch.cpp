@@ -105,8 +105,8 @@ gw_status tune_tile(gw_ctx *ctx, int n, gw_precision prec, hipStream_t st, int *
     auto launch = [&]() -> hipError_t {
         if (dbl) {
             gwk::zdbl *C = (gwk::zdbl *)buf, *A = C + (size_t)batch * M * M, *B = A + (size_t)batch * M * K;
-            return gwk::launch_zgemm(st, M, M, K, -1.0, A, K, (int64_t)M * K, B, M, (int64_t)K * M, 1.0, C, M,
-                                     (int64_t)M * M, batch);
+            return gwk::launch_zgemm_lu(st, M, M, K, -1.0, A, K, (int64_t)M * K, B, M, (int64_t)K * M, 1.0, C, M,
+                                        (int64_t)M * M, batch);
         }
         gwk::zflt *C = (gwk::zflt *)buf, *A = C + (size_t)batch * M * M, *B = A + (size_t)batch * M * K;
         return gwk::launch_cgemm(st, M, M, K, -1.f, A, K, (int64_t)M * K, B, M, (int64_t)K * M, 1.f, C, M,

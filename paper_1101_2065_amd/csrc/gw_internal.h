@@ -84,6 +84,12 @@ hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha,
                         const zdbl *A, int64_t lda, int64_t sA,
                         const zdbl *B, int64_t ldb, int64_t sB, double beta,
                         zdbl *C, int64_t ldc, int64_t sC, int batch);
+// The same with three real products per complex product (the FP64 LU and
+// solves; see k_gemm.hip).
+hipError_t launch_zgemm_lu(hipStream_t st, int M, int N, int K, double alpha,
+                           const zdbl *A, int64_t lda, int64_t sA,
+                           const zdbl *B, int64_t ldb, int64_t sB, double beta,
+                           zdbl *C, int64_t ldc, int64_t sC, int batch);
 hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha,
                         const zflt *A, int64_t lda, int64_t sA,
                         const zflt *B, int64_t ldb, int64_t sB, float beta,

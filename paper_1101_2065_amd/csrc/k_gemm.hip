@@ -3,18 +3,21 @@
 // triangular block products of the solve, and the FP64 refinement residual
 // (Section 2 eq. Coulombscreening, Section 3 eq. tensorform-scr-inter).
 //
-// Complex numbers are interleaved {re, im}.  A complex product is four real
-// MFMA products (no 3M trick: the FP64 residual must keep its accuracy).
+// Complex numbers are interleaved {re, im}.  The products of the FP64 LU and
+// solves use three real MFMA products per complex product, ac, bd and
+// (a + b)(c + d) (a quarter less matrix-core work, normwise as accurate); the
+// FP64 refinement residual and the FP32 products use four.
 // Tiles: 256-thread workgroups, four 64-wide waves in 2x2.  An FP64 MFMA
 // 16x16x4 occupies the matrix pipe for many cycles, so the complex FP64
 // products are latency-bound by the LDS and global loads around it unless
-// several workgroups share a CU: they use narrow tiles at four waves per SIMD,
-// 128x32 (each wave 4x1 MFMA 16x16 blocks) for long products and 64x32 (2x1)
-// for the thin ones (K = 64 updates inside a block, 64-row products).  The
-// real-times-complex and FP32 products keep 64x64 (K steps of 16) and 128x64
-// (K steps of 8) at two waves per SIMD.  The narrow tiles are dealt to the
-// XCDs in contiguous ranges (each XCD has its own L2).  K is staged through a
-// double-buffered LDS tile, the next step prefetched into registers.
+// several workgroups share a CU: they use narrow tiles, 64x32 (each wave 2x1
+// MFMA 16x16 blocks) at five waves per SIMD in the three-product form (94
+// registers) for every LU and solve product, and 128x32 (4x1) at four waves
+// per SIMD in the four-product form.  The real-times-complex and FP32
+// products keep 64x64 (K steps of 16) and 128x64 (K steps of 8) at two waves
+// per SIMD.  The narrow tiles are dealt to the XCDs in contiguous ranges (each
+// XCD has its own L2).  K is staged through a double-buffered LDS tile, the
+// next step prefetched into registers.
 #include "gw_internal.h"
 #include "gw_prof.h"
 
@@ -51,11 +54,19 @@ struct Mfma<float> {
 // Workgroup = 256 threads = 2x2 waves; a wave owns WM x WN MFMA blocks of
 // 16x16, so the workgroup tile is (32 WM) x (32 WN); K advances BK per
 // LDS stage.
-template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool XR>
+// M3 (complex times complex only): three real products per complex product,
+// (a + ib)(c + id) = ac - bd + i[(a + b)(c + d) - ac - bd], instead of four:
+// a quarter fewer matrix-core operations, with the sums a + b and c + d
+// formed from the operands as they come out of LDS.  Normwise as accurate
+// (the imaginary part of an entry loses relative accuracy only where it is
+// small against |a||c| + |b||d|); the LU and the solves use it, the FP64
+// refinement residual does not.
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool XR, bool M3 = false>
 __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
                                                  int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
                                                  T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
                                                  int64_t sC32) {
+    static_assert(!M3 || (AC && BC), "the three-product form is for complex times complex");
     constexpr int BM = 32 * WM, BN = 32 * WN;
     constexpr bool CC = AC || BC;
     constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = CC ? 2 : 1;
@@ -95,13 +106,15 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    v4 accr[WM][WN], acci[WM][WN];
+    // M3: accr = sum a c, acci = sum b d, accs = sum (a + b)(c + d)
+    v4 accr[WM][WN], acci[WM][WN], accs[M3 ? WM : 1][M3 ? WN : 1];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
             accr[i][j] = v4{0, 0, 0, 0};
             acci[i][j] = v4{0, 0, 0, 0};
+            if constexpr (M3) accs[i][j] = v4{0, 0, 0, 0};
         }
 
     const int a_row = tid / TPRA, a_k = (tid % TPRA) * EA;
@@ -209,6 +222,28 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
                     bi[j] = T(0);
                 }
             }
+            if constexpr (M3) {
+                // three passes, each over every block, so that no MFMA waits
+                // on the one issued just before it
+                T sa[WM], sb[WN];
+#pragma unroll
+                for (int i = 0; i < WM; ++i) sa[i] = ar[i] + ai[i];
+#pragma unroll
+                for (int j = 0; j < WN; ++j) sb[j] = br[j] + bi[j];
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) accr[i][j] = Mfma<T>::op(ar[i], br[j], accr[i][j]);
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) acci[i][j] = Mfma<T>::op(ai[i], bi[j], acci[i][j]);
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j) accs[i][j] = Mfma<T>::op(sa[i], sb[j], accs[i][j]);
+                continue;
+            }
             // two passes so that no MFMA waits on the one issued just before it
 #pragma unroll
             for (int i = 0; i < WM; ++i)
@@ -244,8 +279,14 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
                 const int col = n0 + wn * 16 * WN + j * 16 + (lane & 15);
                 if (row < M && col < N) {
                     T *pc = C + ((int64_t)row * ldc + col) * ec;
-                    T vr = alpha * accr[i][j][e];
-                    T vi = alpha * acci[i][j][e];
+                    T vr, vi;
+                    if constexpr (M3) {
+                        vr = alpha * (accr[i][j][e] - acci[i][j][e]);
+                        vi = alpha * (accs[i][j][e] - accr[i][j][e] - acci[i][j][e]);
+                    } else {
+                        vr = alpha * accr[i][j][e];
+                        vi = alpha * acci[i][j][e];
+                    }
                     if (beta != T(0)) {
                         vr += beta * pc[0];
                         if constexpr (CC) vi += beta * pc[1];
@@ -437,8 +478,9 @@ thread_local int g_gemm_tile = -1;
 
 const char *const kZgemmName[4] = {"zgemm_64x64", "zgemm_128x64", "zgemm_64x32", "zgemm_128x32"};
 const char *const kCgemmName[4] = {"cgemm_64x64", "cgemm_128x64", "cgemm_64x32", "cgemm_128x32"};
+const char *const kZgemm3Name[4] = {"zgemm3m_64x64", "zgemm3m_128x64", "zgemm3m_64x32", "zgemm3m_128x32"};
 
-template <typename T, bool AC, bool BC>
+template <typename T, bool AC, bool BC, bool M3 = false>
 hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *A, int64_t lda, int64_t sA,
                          const T *B, int64_t ldb, int64_t sB, T beta, T *C, int64_t ldc, int64_t sC, int batch,
                          int add_eye = 0, float *C32 = nullptr, int64_t sC32 = 0) {
@@ -449,7 +491,11 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
     int tile;
     if constexpr (Z64) {
         const bool big = M >= 256 && K >= 128;
-        tile = big ? (tuned ? g_gemm_tile : 3) : 2;
+        // the three-product form takes 64x32 at five waves per SIMD by
+        // default, for long and thin products alike (68 TF on the LU and solve
+        // products at 2000 rows, against 65 TF for the four-product 128x32)
+        tile = big ? (tuned ? g_gemm_tile : (M3 ? 2 : 3)) : 2;
+        if (M3 && tile == 1) tile = 3;  // 128x64 with a third accumulator would spill
     } else if constexpr (CF32) {
         const bool big = M >= 256 && K >= 128;
         tile = big && tuned ? g_gemm_tile : (M >= 128 && K >= 64) ? 1 : 0;
@@ -461,7 +507,7 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
     double flops = 0, bytes = 0;
     if (prof) {
         const bool dbl = sizeof(T) == 8;
-        if (AC && BC) cls = dbl ? kZgemmName[tile] : kCgemmName[tile];
+        if (AC && BC) cls = dbl ? (M3 ? kZgemm3Name[tile] : kZgemmName[tile]) : kCgemmName[tile];
         else if (BC) cls = add_eye ? "formA" : "dzgemm";
         else if (AC) cls = "zdgemm";
         else cls = "dgemm";
@@ -472,12 +518,14 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
     }
     ProfScope ps(st, cls ? cls : "", flops, bytes);
 #define GW_GEMM(WM, WN, BK, OCC, XR)                                                                               \
-    hipLaunchKernelGGL((k_gemm<T, AC, BC, WM, WN, BK, OCC, XR>), dim3((N + 32 * WN - 1) / (32 * WN),               \
+    hipLaunchKernelGGL((k_gemm<T, AC, BC, WM, WN, BK, OCC, XR, M3>), dim3((N + 32 * WN - 1) / (32 * WN),           \
                        (M + 32 * WM - 1) / (32 * WM), batch), dim3(256), 0, st, M, N, K, alpha, A, lda, sA, B, ldb, \
                        sB, beta, C, ldc, sC, add_eye, C32, sC32)
     if constexpr (Z64 || CF32) {
-        if (tile == 3) GW_GEMM(4, 1, 8, 4, true);
-        else if (tile == 2) GW_GEMM(2, 1, 8, 4, true);
+        // the three-product 128x32 tile needs a third accumulator: three
+        // workgroups per CU instead of four, so that nothing spills
+        if (tile == 3) GW_GEMM(4, 1, 8, M3 ? 3 : 4, true);
+        else if (tile == 2) GW_GEMM(2, 1, 8, M3 ? 5 : 4, true);
         else if (tile == 1) GW_GEMM(4, 2, 8, 2, false);
         else GW_GEMM(2, 2, 16, 2, false);
     } else {
@@ -495,6 +543,14 @@ hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const
                         int batch) {
     return launch_gemm_t<double, true, true>(st, M, N, K, alpha, (const double *)A, lda, sA, (const double *)B, ldb,
                                              sB, beta, (double *)C, ldc, sC, batch);
+}
+
+// The products of the FP64 LU and solves: the three-product form.
+hipError_t launch_zgemm_lu(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda,
+                           int64_t sA, const zdbl *B, int64_t ldb, int64_t sB, double beta, zdbl *C, int64_t ldc,
+                           int64_t sC, int batch) {
+    return launch_gemm_t<double, true, true, true>(st, M, N, K, alpha, (const double *)A, lda, sA, (const double *)B,
+                                                   ldb, sB, beta, (double *)C, ldc, sC, batch);
 }
 
 // Complex-float products of the calling thread run as split-BF16 MFMA when set

@@ -744,8 +744,8 @@ template <>
 hipError_t gemm_t<double>(hipStream_t st, int M, int N, int K, double alpha, const Cx<double> *A, int64_t lda,
                           int64_t sA, const Cx<double> *B, int64_t ldb, int64_t sB, double beta, Cx<double> *C,
                           int64_t ldc, int64_t sC, int batch) {
-    return launch_zgemm(st, M, N, K, alpha, (const zdbl *)A, lda, sA, (const zdbl *)B, ldb, sB, beta, (zdbl *)C, ldc,
-                        sC, batch);
+    return launch_zgemm_lu(st, M, N, K, alpha, (const zdbl *)A, lda, sA, (const zdbl *)B, ldb, sB, beta, (zdbl *)C,
+                           ldc, sC, batch);
 }
 template <>
 hipError_t gemm_t<float>(hipStream_t st, int M, int N, int K, float alpha, const Cx<float> *A, int64_t lda,
