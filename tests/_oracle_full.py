@@ -61,3 +61,34 @@ def compare(name, got, ref, bound):
     _say("%s: worst relative error over %d frequencies %.2e (bar %.0e)" % (name, len(ref), worst, bound))
     assert worst <= bound, "%s: %.3e > %.0e" % (name, worst, bound)
     return worst
+
+
+def forward_errors(mol, grid, js, cols, W_apply):
+    """Forward error of computed W(omega_j) columns where the oracle cannot
+    form chi0.  For column c the oracle's residual is
+        r = v e_c - (1 - v chi0) w,   w = W e_c,
+    with chi0 applied by its pair-vertex route, and the error of w is
+    A^-1 r with A = 1 - v chi0.  Since W_true = A^-1 v, A^-1 = 1 + W_true chi0
+    exactly ((1 - v chi0)(1 + W_true chi0) = 1 - v chi0 + v chi0), so the error
+    is estimated by
+        delta = r + W (chi0 r)
+    with the computed W in place of W_true, off only by the (small) relative
+    error of W itself (second order in it).
+      W_apply(j, x): W(omega_j) x for a vector x (W e_c gives the column).
+    Returns (largest ||delta|| / ||w||, largest ||r|| / ||v e_c||)."""
+    om = grid.omegas()
+    nhb = o.hist_bins(mol.eig, grid.n_omega, grid.domega)
+    n = mol.n_prod
+    worst_fwd = worst_res = 0.0
+    for j in js:
+        for c in cols:
+            e = np.zeros(n)
+            e[c] = 1.0
+            w = W_apply(j, e)
+            r = mol.v[:, c] - (w - mol.v @ o.chi0_apply(mol, w, om[j], grid.eps, grid.domega, nhb))
+            d = r + W_apply(j, o.chi0_apply(mol, r, om[j], grid.eps, grid.domega, nhb))
+            worst_fwd = max(worst_fwd, float(np.linalg.norm(d) / np.linalg.norm(w)))
+            worst_res = max(worst_res, float(np.linalg.norm(r) / np.linalg.norm(mol.v[:, c])))
+    _say("forward error over %d columns x %d frequencies: %.2e (residual %.2e)"
+         % (len(cols), len(js), worst_fwd, worst_res))
+    return worst_fwd, worst_res
