@@ -419,9 +419,20 @@ gw_status gw_pair_basis(gw_ctx *ctx, const gw_molecule *m, const double *v, doub
  * in $GW_TUNE_FILE, default $HOME/.cache/gw_tune.json, whose directories are
  * created as needed; a table that cannot be read or written is reported by
  * gw_last_error() while the batch is still created) and records the whole
- * computation once into a hipGraph: every chi0 build, then the W solves on
- * GW_BATCH_STREAMS (default 4) parallel branches.  gw_batch_run replays that
- * graph on `stream`.
+ * computation once into a hipGraph: every chi0 build, then the W solves.
+ * The solves run in lock step (environment GW_BATCH_MODE=lockstep, the
+ * default): every molecule's solve program (its LU factorisations,
+ * substitutions and refinement steps, Section 2 eq. Coulombscreening per
+ * frequency) advances one operation per lock step, the complex products of a
+ * step being one persistent work-queue launch over all molecules (workgroups
+ * take tiles from per-XCD device counters and steal from the others), the
+ * panel factorisations and row exchanges one grouped launch each, the
+ * parallel launches of a step on GW_BATCH_STREAMS (default 4) branches.
+ * Programs are aligned so that they end together (lockstep_left: start
+ * together).  GW_BATCH_MODE=streams instead runs whole molecules on the
+ * parallel branches.  Every molecule then has a workspace of its own, so a
+ * batch needs more device memory than one molecule.  gw_batch_run replays
+ * the graph on `stream`.
  *   v[i]: DEVICE [n_i][n_i]; chi0_out[i], W_out[i]: DEVICE complex128
  *   [n_omega][n_i][n_i], caller-owned, fixed for the life of the batch.
  *   prec GW_FP64, or GW_FP32_IR / GW_BF16X_IR with exactly n_refine (1..6)
@@ -442,6 +453,12 @@ gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, c
                           const gw_grid *g, gw_precision prec, double tol, int32_t n_refine, void *stream,
                           void *const *chi0_out, void *const *W_out, gw_batch **out);
 gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps);
+/* How a batch was recorded: mode 0 (molecules on parallel branches), 1 (lock
+ * steps aligned at the end), 2 (lock steps aligned at the start); for lock
+ * steps their number, the launches they hold and the products queued in
+ * them.  Any output may be NULL.  GW_E_INVALID for a NULL batch. */
+gw_status gw_batch_stats(const gw_batch *b, int32_t *mode, int64_t *n_steps, int64_t *n_launches,
+                         int64_t *n_products);
 gw_status gw_batch_destroy(gw_batch *b);
 
 /* Serving (continuous batching).  gw_submit copies nothing: the molecule's

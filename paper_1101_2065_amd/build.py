@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_exact.hip", "k_chi0.hip", "k_gemm.hip", "k_lu.hip", "k_compress.hip", "k_time.hip", "k_sigma.hip", "gw_abi.cpp", "gw_serve.cpp", "gw_batch.cpp", "gw_prof.cpp", "gw_tune.cpp", "gw_noalloc.cpp"]
+SOURCES = ["k_exact.hip", "k_chi0.hip", "k_gemm.hip", "k_lu.hip", "k_compress.hip", "k_time.hip", "k_sigma.hip", "gw_abi.cpp", "gw_serve.cpp", "gw_batch.cpp", "gw_prof.cpp", "gw_tune.cpp", "gw_noalloc.cpp", "gw_group.cpp"]
 
 # The exact kernels (pair vertex, bins, int64 histogram) must round every
 # product and sum on its own: no FMA contraction anywhere in that file.

@@ -91,6 +91,19 @@ gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out) {
     return GW_OK;
 }
 
+void ws_release(gw_ctx *c, const std::string &prefix) {
+    std::vector<std::string> names;
+    for (auto &kv : c->bufs)
+        if (kv.first.compare(0, prefix.size(), prefix) == 0) names.push_back(kv.first);
+    if (names.empty()) return;
+    if (!c->own_stream) (void)hipDeviceSynchronize();
+    for (auto &nm : names) {
+        void *p = c->bufs[nm].ptr;
+        if (p) (void)(c->own_stream ? hipFreeAsync(p, c->own_stream) : hipFree(p));
+        c->bufs.erase(nm);
+    }
+}
+
 }  // namespace gwp
 
 namespace {
@@ -533,7 +546,7 @@ gw_status batch_ws(gw_ctx *c, hipStream_t st, const SolveWs &base, zdbl *Ain, co
                    int nb, SolveWs *out) {
     *out = base;
     if (!Ain) return GW_OK;
-    if (Ain == W) GW_HIP(c, hipMemcpyAsync(out->A, Ain + j0 * nn, sizeof(zdbl) * nn * nb, hipMemcpyDeviceToDevice, st));
+    if (Ain == W) GW_HIP(c, gwk::launch_copy(st, out->A, Ain + j0 * nn, sizeof(zdbl) * nn * nb));
     else out->A = Ain + j0 * nn;
     return GW_OK;
 }

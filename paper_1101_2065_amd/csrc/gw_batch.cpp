@@ -48,6 +48,8 @@ struct gw_batch {
     std::vector<hipStream_t> branches;
     std::vector<hipEvent_t> events;
     uint64_t generation = 0;  // the context's batch generation this graph was recorded in
+    int mode = 1;             // 0: molecules on parallel branches; 1, 2: lock steps (1: aligned at the end)
+    gwp::LockStepStats ls_stats;
 };
 
 namespace {
@@ -156,20 +158,66 @@ void destroy_graph(gw_batch *b) {
     b->graph = nullptr;
 }
 
+// Record every molecule's solve program (lock-step mode).  The recording runs
+// under a capture of a private stream, so a launch that escaped the recorder
+// would land in that throwaway graph instead of running: it is counted and
+// refused.
+gw_status record_programs(gw_batch *b, std::vector<gwp::SolvePlan> &sp, const std::vector<char> &route_a,
+                          std::vector<std::vector<gwk::RecOp>> *progs) {
+    gw_ctx *ctx = b->ctx;
+    const bool mixed = b->prec != GW_FP64;
+    hipStream_t probe = b->branches[0];
+    GW_HIP(ctx, hipStreamBeginCapture(probe, hipStreamCaptureModeThreadLocal));
+    gw_status s = GW_OK;
+    progs->assign(b->n_mol, {});
+    {
+        gwp::Bf16xScope bf16x(b->prec == GW_BF16X_IR);
+        for (int i = 0; i < b->n_mol && s == GW_OK; ++i) {
+            gwk::OpRecorder rec;
+            gwk::g_rec = &rec;
+            gwp::set_thread_gemm_tile(b->tile[i]);
+            gwp::zdbl *buf = (gwp::zdbl *)b->chi0[i];
+            s = gwp::solve_enqueue_nosync(ctx, sp[i], probe, b->v[i], 0, route_a[i] ? nullptr : buf,
+                                          (gwp::zdbl *)b->W[i], mixed ? b->n_refine : 0, route_a[i] ? buf : nullptr);
+            gwk::g_rec = nullptr;
+            (*progs)[i] = std::move(rec.ops);
+        }
+        gwp::set_thread_gemm_tile(-1);
+    }
+    hipGraph_t pg = nullptr;
+    const hipError_t e = hipStreamEndCapture(probe, &pg);
+    size_t nodes = 0;
+    if (pg) {
+        (void)hipGraphGetNodes(pg, nullptr, &nodes);
+        (void)hipGraphDestroy(pg);
+    }
+    if (s != GW_OK) return s;
+    GW_HIP(ctx, e);
+    if (nodes) return fail(ctx, GW_E_DEVICE, "lock step: a solve launch was not recorded");
+    return GW_OK;
+}
+
 gw_status record(gw_batch *b) {
     gw_ctx *ctx = b->ctx;
     hipStream_t st = b->cap;
     const int nbr = (int)b->branches.size();
     const bool mixed = b->prec != GW_FP64;
-    // planning, pass 1 (grows the shared buffers) and pass 2 (final pointers)
+    const bool lock = b->mode != 0;
+    // planning, pass 1 (grows the shared buffers) and pass 2 (final pointers);
+    // lock-stepped molecules all solve at once: a workspace each
     std::vector<gwp::BuildPlan> bp(b->n_mol);
     std::vector<gwp::SolvePlan> sp(b->n_mol);
+    // the per-molecule workspaces of an earlier lock-step batch (sized for
+    // its molecule count) would otherwise stay beside the new ones
+    if (lock) gwp::ws_release(ctx, "bl");
     for (int pass = 0; pass < 2; ++pass) {
         for (int i = 0; i < b->n_mol; ++i) {
             gw_status s = gwp::build_plan(ctx, &b->mols[i], &b->g, nullptr, 0, st, "bb", nullptr, &bp[i]);
             if (s != GW_OK) return s;
-            s = gwp::solve_plan(ctx, b->n[i], b->g.n_omega, mixed, "bs" + std::to_string(i % nbr), &sp[i],
-                                ctx->budget / nbr);
+            s = lock ? gwp::solve_plan(ctx, b->n[i], b->g.n_omega, mixed, "bl" + std::to_string(i), &sp[i],
+                                       ctx->budget / b->n_mol)
+                     : gwp::solve_plan(ctx, b->n[i], b->g.n_omega, mixed, "bs" + std::to_string(i % nbr), &sp[i],
+                                       ctx->budget / nbr);
             if (s != GW_OK) return s;
             sp[i].final_norms = b->norms[i];
         }
@@ -188,6 +236,20 @@ gw_status record(gw_batch *b) {
             gw_status s = gwp::a_route_ws(ctx, "ba", b->n[i], bp[i].nhb, &aw[i]);
             if (s != GW_OK) return s;
         }
+    gwp::LockStep *ls = nullptr;
+    if (lock) {
+        std::vector<std::vector<gwk::RecOp>> progs;
+        gw_status s = record_programs(b, sp, route_a, &progs);
+        if (s == GW_OK) s = gwp::lockstep_plan(ctx, std::move(progs), b->mode == 1, &ls);
+        if (s != GW_OK) return s;
+        b->ls_stats = gwp::lockstep_stats(ls);
+    }
+    struct Free {
+        gwp::LockStep *p;
+        ~Free() {
+            if (p) gwp::lockstep_free(p);
+        }
+    } free_ls{ls};
     GW_HIP(ctx, hipStreamSynchronize(st));
     GW_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     // from here on every failure still ends the capture below
@@ -198,7 +260,9 @@ gw_status record(gw_batch *b) {
     for (int i = 0; i < b->n_mol && s == GW_OK; ++i)
         s = route_a[i] ? gwp::a_route_enqueue(ctx, bp[i], st, b->v[i], aw[i], i == 0, b->chi0[i])
                        : gwp::build_enqueue(ctx, bp[i], st, b->chi0[i], i == 0);
-    if (s == GW_OK) {
+    if (s == GW_OK && lock) {
+        s = gwp::lockstep_enqueue(ctx, *ls, st, b->branches, b->events);
+    } else if (s == GW_OK) {
         hip(hipEventRecord(b->events[0], st), "fork");
         for (int r = 0; r < nbr; ++r) hip(hipStreamWaitEvent(b->branches[r], b->events[0], 0), "fork");
         gwp::Bf16xScope bf16x(b->prec == GW_BF16X_IR);
@@ -256,9 +320,19 @@ gw_status gw_batch_create(gw_ctx *ctx, int32_t n_mol, const gw_molecule *mols, c
     b->prec = prec;
     b->tol = tol;
     b->n_refine = n_refine;
+    if (const char *e = std::getenv("GW_BATCH_MODE")) {
+        const std::string m = e;
+        if (m == "streams") b->mode = 0;
+        else if (m == "lockstep") b->mode = 1;
+        else if (m == "lockstep_left") b->mode = 2;
+        else {
+            delete b;
+            return fail(ctx, GW_E_INVALID, "GW_BATCH_MODE must be streams, lockstep or lockstep_left");
+        }
+    }
     int nbr = 4;
     if (const char *e = std::getenv("GW_BATCH_STREAMS")) nbr = std::max(1, std::min(16, std::atoi(e)));
-    nbr = std::min(nbr, n_mol);
+    if (b->mode == 0) nbr = std::min(nbr, n_mol);
     auto bail = [&](gw_status s) {
         gw_batch_destroy(b);
         return s;
@@ -372,6 +446,16 @@ gw_status gw_batch_run(gw_batch *b, void *stream, gw_report *reps) {
         }
     }
     return result;
+}
+
+gw_status gw_batch_stats(const gw_batch *b, int32_t *mode, int64_t *n_steps, int64_t *n_launches,
+                         int64_t *n_products) {
+    if (!b) return GW_E_INVALID;
+    if (mode) *mode = b->mode;
+    if (n_steps) *n_steps = b->ls_stats.steps;
+    if (n_launches) *n_launches = b->ls_stats.launches;
+    if (n_products) *n_products = b->ls_stats.products;
+    return GW_OK;
 }
 
 gw_status gw_batch_destroy(gw_batch *b) {

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 namespace gwk {
 
 struct zdbl {
@@ -13,6 +16,97 @@ struct zdbl {
 struct zflt {
     float re, im;
 };
+
+// ---------------------------------------------------------------- lock-step recording
+// One batched product C = alpha A B + beta C of a work-queue launch (device
+// readable): tx x ty tiles per batch entry, tiles t0 .. t0 + tx ty batch - 1
+// of the launch.
+struct GemmItem {
+    const void *A, *B;
+    void *C;
+    int64_t lda, ldb, ldc, sA, sB, sC;
+    double alpha, beta;
+    int M, N, K, batch;
+    int tx, ty;
+    int64_t t0;
+};
+// One batched panel factorisation or row-exchange pass of a grouped launch:
+// its workgroups are wg0 .. wg0 + count - 1 of the launch.
+struct PanelItem {
+    void *A;
+    int64_t sA;
+    int32_t *ipiv, *swp, *info;
+    void *Linv, *Uinv;
+    int n, kb, w, nblk, batch;
+    int64_t wg0;
+};
+// While a recorder is installed on the calling host thread, the launchers of
+// the W solve append their work to it instead of launching (the batched
+// driver runs the recorded programs of many molecules in lock step).
+// kind: GEMM (key = product kind * 4 + tile), PANEL (key = panel variant),
+// LASWP (key = 0 double, 1 float), OTHER (run fn on the lock step's stream),
+// MARK (the factorisation or a substitution starts or ends).
+struct RecOp {
+    enum Kind { GEMM, PANEL, LASWP, OTHER, MARK } kind;
+    int key = 0;
+    GemmItem g{};
+    PanelItem p{};
+    double flops = 0;
+    std::function<hipError_t(hipStream_t)> fn;
+};
+struct OpRecorder {
+    std::vector<RecOp> ops;
+    void other(std::function<hipError_t(hipStream_t)> f) {
+        RecOp o;
+        o.kind = RecOp::OTHER;
+        o.fn = std::move(f);
+        ops.push_back(std::move(o));
+    }
+    void mark() {
+        RecOp o;
+        o.kind = RecOp::MARK;
+        ops.push_back(std::move(o));
+    }
+};
+extern thread_local OpRecorder *g_rec;
+// Element type for device pointers read from a descriptor in memory: the
+// global address space in the device compilation (the compiler cannot infer it
+// for a loaded pointer as it does for a kernel argument, and would emit flat
+// accesses, whose waits also stall on LDS traffic); the host pass only checks
+// the kernels and takes the plain type.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename P>
+using dglobal = __attribute__((address_space(1))) P;
+#else
+template <typename P>
+using dglobal = P;
+#endif
+// In a launcher: while a recorder is installed, run `call` (with `st` its
+// stream) when the recorded program reaches it, instead of now.
+#define GW_DEFER(call)                                                  \
+    do {                                                                \
+        if (::gwk::OpRecorder *rec_ = ::gwk::g_rec) {                   \
+            rec_->other([=](hipStream_t st) { return call; });          \
+            return hipSuccess;                                          \
+        }                                                               \
+    } while (0)
+// product kinds of the work-queue launch
+enum { QK_Z3M = 0, QK_Z4M = 1, QK_C = 2 };
+// One launch of `n_items` products (descriptors on the device), `n_tiles`
+// tiles in all: with `queue` (eight counters, zero) a persistent grid of
+// `grid` workgroups pulling tiles from per-XCD work queues, without it one
+// workgroup per tile handed out by the hardware dispatcher.
+hipError_t launch_gemm_queue(hipStream_t st, int key, const GemmItem *items, int n_items, int64_t n_tiles,
+                             unsigned *queue, int grid, double flops);
+// Device-to-device copy on `st` (deferred like the kernels while recording).
+hipError_t launch_copy(hipStream_t st, void *dst, const void *src, size_t bytes);
+// Grouped panel and row-exchange launches over many batched passes.
+hipError_t launch_panel_group(hipStream_t st, int key, const PanelItem *items, int n_items, int64_t n_wg);
+hipError_t launch_laswp_group(hipStream_t st, int key, const PanelItem *items, int n_items, int64_t n_wg);
+// Resident workgroups per CU of a work-queue launch of this key, and the
+// tile shape (rows, columns) of its tiles.
+int gemm_queue_occupancy(int key);
+void gemm_queue_tile(int key, int *bm, int *bn);
 
 // ---------------------------------------------------------------- chi0 build
 // Pair vertex (Section 7.A): P[mu][(E-e0)*n_virt + F'] = sum_a X_a^E sum_b V_mu^{ab} X_b^{n_occ+F'}
@@ -41,6 +135,7 @@ hipError_t launch_fracbits(hipStream_t st, const uint64_t *vmax_bits, int64_t n_
                            int requested, int32_t *s_out);
 
 hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t value);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
 
 // Exact int64 histogram H[nhb][n_upper] (Section 5.A eq. chi_by_spectra).
 // With a bin range, only pairs whose lower bin lies in [bin_lo, bin_hi) are

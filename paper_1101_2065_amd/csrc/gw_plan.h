@@ -10,6 +10,7 @@
 #include "gw_internal.h"
 
 #include <string>
+#include <vector>
 
 namespace gwp {
 
@@ -28,6 +29,10 @@ enum Fault { FAULT_NONE = 0, FAULT_OOM = 1, FAULT_DEVICE = 2, FAULT_NOCONV = 3 }
 Fault fault();
 // Grow-only named device buffer of the context.
 gw_status ws(gw_ctx *c, const std::string &name, size_t bytes, void **out);
+// Free every buffer whose name starts with `prefix` (after the device has
+// finished its work; for the private context of a serving slot, in its
+// stream's order).
+void ws_release(gw_ctx *c, const std::string &prefix);
 
 #define GW_HIP(ctx, call)                                                                                     \
     do {                                                                                                      \
@@ -128,6 +133,22 @@ gw_status batch_ws(gw_ctx *c, hipStream_t st, const SolveWs &base, zdbl *Ain, co
 // holds A.
 gw_status solve_batch_fp64(gw_ctx *c, hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0,
                            zdbl *W, int nb, SolveWs &w);
+
+// Lock-step execution of recorded solve programs (batched form).
+struct LockStep;
+struct LockStepStats {
+    int64_t steps = 0, ops = 0, launches = 0, products = 0;
+};
+// Group the programs' operations into lock steps (operation k of every
+// program in step k, or, right_align, aligned so that all programs end in the
+// last step), build and upload the descriptor tables.  Host synchronous.
+gw_status lockstep_plan(gw_ctx *c, std::vector<std::vector<gwk::RecOp>> progs, bool right_align, LockStep **out);
+// Enqueue every lock step on st (parallel launches of a step on the branches,
+// joined before the next step; events: 1 + branches.size()).  Recordable.
+gw_status lockstep_enqueue(gw_ctx *c, const LockStep &ls, hipStream_t st, const std::vector<hipStream_t> &branches,
+                           const std::vector<hipEvent_t> &events);
+const LockStepStats &lockstep_stats(const LockStep *ls);
+void lockstep_free(LockStep *ls);
 
 // GEMM tile policy for the launches of the calling host thread (autotuner).
 void set_thread_gemm_tile(int tile);

@@ -378,6 +378,7 @@ hipError_t launch_fracbits(hipStream_t st, const uint64_t *vmax_bits, int64_t n_
 }
 
 hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t value) {
+    GW_DEFER(launch_fill_u64(st, p, n, value));
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;

@@ -61,11 +61,12 @@ struct Mfma<float> {
 // (the imaginary part of an entry loses relative accuracy only where it is
 // small against |a||c| + |b||d|); the LU and the solves use it, the FP64
 // refinement residual does not.
-template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool XR, bool M3 = false>
-__global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
-                                                 int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
-                                                 T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
-                                                 int64_t sC32) {
+// One (32 WM) x (32 WN) tile of C with its top-left corner at (m0, n0); A, B,
+// C (and C32) point at the tile's batch entry.
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, bool M3, typename GT = T>
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, T alpha, const GT *__restrict__ A, int64_t lda,
+                                          const GT *B, int64_t ldb, T beta, GT *C, int64_t ldc, int add_eye,
+                                          float *C32, int m0, int n0) {
     static_assert(!M3 || (AC && BC), "the three-product form is for complex times complex");
     constexpr int BM = 32 * WM, BN = 32 * WN;
     constexpr bool CC = AC || BC;
@@ -86,23 +87,6 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
     __shared__ T Br[2][BC ? 1 : BK][BC ? 1 : BN];
     __shared__ T2 Bc[2][BC ? BK : 1][BC ? BN : 1];
 
-    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    if constexpr (XR) {
-        // workgroups are dealt to the eight XCDs in turn, each with its own
-        // L2: give each XCD a contiguous range of tiles (x fastest), so that
-        // tiles sharing an A row band share that XCD's L2
-        const int gx = gridDim.x, gy = gridDim.y;
-        const int64_t nt = (int64_t)gx * gy * gridDim.z, l = bx + (int64_t)gx * (by + (int64_t)gy * bz);
-        const int64_t n8 = nt / 8, t = l < 8 * n8 ? (l % 8) * n8 + l / 8 : l;
-        bx = (int)(t % gx);
-        by = (int)((t / gx) % gy);
-        bz = (int)(t / ((int64_t)gx * gy));
-    }
-    A += (int64_t)bz * sA * ea;
-    B += (int64_t)bz * sB * eb;
-    C += (int64_t)bz * sC * ec;
-    if (C32) C32 += (int64_t)bz * sC32 * 2;
-    const int m0 = by * BM, n0 = bx * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
@@ -126,7 +110,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
     auto gload = [&](int k0) {
         const int gr = m0 + a_row;
         if (rows_in && k0 + BK <= K) {
-            const T *p = A + ((int64_t)gr * lda + k0 + a_k) * ea;
+            const GT *p = A + ((int64_t)gr * lda + k0 + a_k) * ea;
 #pragma unroll
             for (int c = 0; c < EA; ++c) {
                 ra_r[c] = p[c * ea];
@@ -138,7 +122,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
             for (int c = 0; c < EA; ++c) {
                 const int gk = k0 + a_k + c;
                 if (gr < M && gk < K) {
-                    const T *p = A + ((int64_t)gr * lda + gk) * ea;
+                    const GT *p = A + ((int64_t)gr * lda + gk) * ea;
                     ra_r[c] = p[0];
                     if constexpr (AC) ra_i[c] = p[1];
                     else ra_i[c] = T(0);
@@ -150,7 +134,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
         }
         const int gk = k0 + b_row;
         if (cols_in && gk < K) {
-            const T *p = B + ((int64_t)gk * ldb + n0 + b_col) * eb;
+            const GT *p = B + ((int64_t)gk * ldb + n0 + b_col) * eb;
 #pragma unroll
             for (int c = 0; c < EB; ++c) {
                 rb_r[c] = p[c * SB * eb];
@@ -162,7 +146,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
             for (int c = 0; c < EB; ++c) {
                 const int gc = n0 + b_col + c * SB;
                 if (gk < K && gc < N) {
-                    const T *p = B + ((int64_t)gk * ldb + gc) * eb;
+                    const GT *p = B + ((int64_t)gk * ldb + gc) * eb;
                     rb_r[c] = p[0];
                     if constexpr (BC) rb_i[c] = p[1];
                     else rb_i[c] = T(0);
@@ -278,7 +262,7 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
                 const int row = m0 + wm * 16 * WM + i * 16 + Mfma<T>::row(lane, e);
                 const int col = n0 + wn * 16 * WN + j * 16 + (lane & 15);
                 if (row < M && col < N) {
-                    T *pc = C + ((int64_t)row * ldc + col) * ec;
+                    GT *pc = C + ((int64_t)row * ldc + col) * ec;
                     T vr, vi;
                     if constexpr (M3) {
                         vr = alpha * (accr[i][j][e] - acci[i][j][e]);
@@ -301,6 +285,117 @@ __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha,
                     }
                 }
             }
+}
+
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool XR, bool M3 = false>
+__global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
+                                                 int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
+                                                 T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
+                                                 int64_t sC32) {
+    constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = (AC || BC) ? 2 : 1;
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    if constexpr (XR) {
+        // workgroups are dealt to the eight XCDs in turn, each with its own
+        // L2: give each XCD a contiguous range of tiles (x fastest), so that
+        // tiles sharing an A row band share that XCD's L2
+        const int gx = gridDim.x, gy = gridDim.y;
+        const int64_t nt = (int64_t)gx * gy * gridDim.z, l = bx + (int64_t)gx * (by + (int64_t)gy * bz);
+        const int64_t n8 = nt / 8, t = l < 8 * n8 ? (l % 8) * n8 + l / 8 : l;
+        bx = (int)(t % gx);
+        by = (int)((t / gx) % gy);
+        bz = (int)(t / ((int64_t)gx * gy));
+    }
+    A += (int64_t)bz * sA * ea;
+    B += (int64_t)bz * sB * eb;
+    C += (int64_t)bz * sC * ec;
+    if (C32) C32 += (int64_t)bz * sC32 * 2;
+    gemm_tile<T, AC, BC, WM, WN, BK, M3>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, add_eye, C32, by * 32 * WM,
+                                         bx * 32 * WN);
+}
+
+// Tile t of a multi-product launch: its item (searched from item a up; the
+// items are ordered by their first tile) and the tile within it.
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, bool M3>
+__device__ __forceinline__ void item_tile(const GemmItem *__restrict__ items, int n_items, int64_t t, int &a) {
+    constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = (AC || BC) ? 2 : 1;
+    int b = n_items - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (items[m].t0 <= t) a = m;
+        else b = m - 1;
+    }
+    const GemmItem g = items[a];
+    const int64_t r = t - g.t0, per = (int64_t)g.tx * g.ty;
+    const int bz = (int)(r / per);
+    const int64_t rr = r - bz * per;
+    const int by = (int)(rr / g.tx), bx = (int)(rr % g.tx);
+    // operands through global-address-space pointers (see dglobal)
+    typedef dglobal<T> GT;
+    const GT *Ap = (const GT *)g.A + (int64_t)bz * g.sA * ea;
+    const GT *Bp = (const GT *)g.B + (int64_t)bz * g.sB * eb;
+    GT *Cp = (GT *)g.C + (int64_t)bz * g.sC * ec;
+    gemm_tile<T, AC, BC, WM, WN, BK, M3, GT>(g.M, g.N, g.K, (T)g.alpha, Ap, g.lda, Bp, g.ldb, (T)g.beta, Cp, g.ldc, 0,
+                                             nullptr, by * 32 * WM, bx * 32 * WN);
+}
+
+// Many products in one launch, one tile per workgroup, the hardware
+// dispatcher handing out the tiles: workgroup l (dealt to XCD l mod 8) takes
+// tile (l mod 8) n/8 + l/8, so each XCD works through a contiguous run of
+// tiles (consecutive tiles share an A row band, in that XCD's L2).
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool M3>
+__global__ __launch_bounds__(256, OCC) void k_gemm_group(const GemmItem *__restrict__ items, int n_items,
+                                                       int64_t n_tiles) {
+    const int64_t l = blockIdx.x, n8 = n_tiles / 8;
+    const int64_t t = l < 8 * n8 ? (l % 8) * n8 + l / 8 : l;
+    int a = 0;
+    item_tile<T, AC, BC, WM, WN, BK, M3>(items, n_items, t, a);
+}
+
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for outstanding global stores (a tile's results) to land.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+}
+
+// Persistent form of the same: the tiles are handed out by eight work queues,
+// queue q owning the tiles [q n / 8, (q + 1) n / 8) in order.  A workgroup
+// pulls from the queue of its XCD (workgroups are dealt to the XCDs in turn),
+// then from the others; it leaves when all eight are empty, so every
+// workgroup ends.  queue: eight counters, zero at launch.  On the LU's
+// products it runs about a tenth slower than k_gemm_group, most likely
+// because a wave's memory operations complete in order: the first loads of a
+// workgroup's next tile wait for its previous tile's result stores to drain,
+// which a newly dispatched workgroup does not.
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool M3>
+__global__ __launch_bounds__(256, OCC) void k_gemm_queue(const GemmItem *__restrict__ items, int n_items,
+                                                       int64_t n_tiles, unsigned *__restrict__ queue) {
+    __shared__ int64_t s_t;
+    const int home = blockIdx.x & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int q = (home + k) & 7;
+        const int64_t lo = n_tiles * q / 8, hi = n_tiles * (q + 1) / 8;
+        __syncthreads();  // everyone has read s_t
+        if (threadIdx.x == 0) s_t = lo + (int64_t)atomicAdd(&queue[q], 1u);
+        __syncthreads();
+        int a = 0;  // item of the previous tile: one workgroup's tiles of a queue only grow
+        for (;;) {
+            // uniform over the workgroup: keep the tile index, the item
+            // search and the item's fields in scalar registers
+            const int64_t tv = s_t;
+            const int64_t t = ((int64_t)__builtin_amdgcn_readfirstlane((int)(tv >> 32)) << 32) |
+                              (unsigned)__builtin_amdgcn_readfirstlane((int)tv);
+            if (t >= hi) break;
+            // the next pull goes out now; its latency hides behind this
+            // tile's first loads
+            unsigned nxt = 0;
+            if (threadIdx.x == 0) nxt = atomicAdd(&queue[q], 1u);
+            item_tile<T, AC, BC, WM, WN, BK, M3>(items, n_items, t, a);
+            lds_barrier();  // everyone has read s_t; the tile is done with LDS
+            if (threadIdx.x == 0) s_t = lo + (int64_t)nxt;
+            lds_barrier();
+        }
+    }
 }
 
 // ------------------------------------------------------------------ split-BF16 complex GEMM
@@ -502,6 +597,40 @@ hipError_t launch_gemm_t(hipStream_t st, int M, int N, int K, T alpha, const T *
     } else {
         tile = 0;
     }
+    if (OpRecorder *rec = g_rec) {
+        // lock-step recording: complex products become work-queue items, the
+        // rest run as they are when their lock step comes
+        if constexpr (Z64 || CF32) {
+            RecOp o;
+            o.kind = RecOp::GEMM;
+            o.key = (Z64 ? (M3 ? QK_Z3M : QK_Z4M) : QK_C) * 4 + tile;
+            o.g.A = A;
+            o.g.B = B;
+            o.g.C = C;
+            o.g.lda = lda;
+            o.g.ldb = ldb;
+            o.g.ldc = ldc;
+            o.g.sA = sA;
+            o.g.sB = sB;
+            o.g.sC = sC;
+            o.g.alpha = (double)alpha;
+            o.g.beta = (double)beta;
+            o.g.M = M;
+            o.g.N = N;
+            o.g.K = K;
+            o.g.batch = batch;
+            o.flops = 8.0 * M * N * (double)K * batch;
+            if (!add_eye && !C32) {
+                rec->ops.push_back(std::move(o));
+                return hipSuccess;
+            }
+        }
+        rec->other([=](hipStream_t s2) {
+            return launch_gemm_t<T, AC, BC, M3>(s2, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+                                                add_eye, C32, sC32);
+        });
+        return hipSuccess;
+    }
     ProfSink *prof = g_prof;
     const char *cls = nullptr;
     double flops = 0, bytes = 0;
@@ -562,6 +691,19 @@ hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha, const 
                         int batch) {
     if (g_cgemm_bf16x && K >= 32) {
         if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+        if (OpRecorder *rec = g_rec) {
+            rec->other([=](hipStream_t s2) {
+                OpRecorder *saved = g_rec;
+                g_rec = nullptr;
+                const bool prev = g_cgemm_bf16x;
+                g_cgemm_bf16x = true;
+                const hipError_t e = launch_cgemm(s2, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+                g_cgemm_bf16x = prev;
+                g_rec = saved;
+                return e;
+            });
+            return hipSuccess;
+        }
         dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
         ProfScope ps(st, "cgemm_bf16x", 8.0 * M * N * (double)K * batch,
                      8.0 * ((double)M * K + (double)K * N + (beta != 0.f ? 2.0 : 1.0) * M * N) * batch);
@@ -576,6 +718,7 @@ hipError_t launch_cgemm(hipStream_t st, int M, int N, int K, float alpha, const 
 hipError_t launch_formA(hipStream_t st, int n, const double *v, int v_is_diag, const zdbl *chi0, int64_t s_chi,
                         zdbl *A, int64_t s_A, zflt *A32, int64_t s_A32, int batch) {
     if (v_is_diag) {
+        GW_DEFER(launch_formA(st, n, v, v_is_diag, chi0, s_chi, A, s_A, A32, s_A32, batch));
         dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
         hipLaunchKernelGGL(k_formA_diag, grid, dim3(256), 0, st, n, v, chi0, s_chi, A, s_A, A32, s_A32);
         return hipGetLastError();
@@ -610,6 +753,98 @@ hipError_t launch_dgemm(hipStream_t st, int M, int N, int K, double alpha, const
                         const double *B, int64_t ldb, int64_t sB, double beta, double *C, int64_t ldc, int64_t sC,
                         int batch) {
     return launch_gemm_t<double, false, false>(st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch);
+}
+
+thread_local OpRecorder *g_rec = nullptr;
+
+namespace {
+// (WM, WN, BK, OCC) of each work-queue key: the tiles and occupancies
+// launch_gemm_t picks for the product kind and tile.  The queue loop keeps a
+// few per-lane addresses live across tiles; at these occupancies the
+// three-product tiles (64x32 at five, 128x32 at three per CU) move them to
+// scratch memory, reloaded once per tile, never in the K loop.
+struct QShape {
+    int wm, wn, bk, occ;
+};
+QShape qshape(int key) {
+    const int kind = key / 4, tile = key % 4;
+    if (kind == QK_Z3M) {
+        if (tile == 2) return {2, 1, 8, 5};
+        if (tile == 0) return {2, 2, 16, 2};
+        return {4, 1, 8, 3};  // 3 (and 1, which maps to it)
+    }
+    if (tile == 3) return {4, 1, 8, kind == QK_C ? 4 : 3};  // four-product 128x32 at four would use AGPRs
+    if (tile == 2) return {2, 1, 8, 4};
+    if (tile == 1) return {4, 2, 8, 2};
+    return {2, 2, 16, 2};
+}
+}  // namespace
+
+int gemm_queue_occupancy(int key) {
+    // workgroups of this key resident on one CU, as the runtime computes it
+    // from the kernel's registers and LDS (at least the launch bound's figure)
+    int occ = 0;
+    hipError_t e = hipErrorInvalidValue;
+    const int kind = key / 4, tile = key % 4;
+#define GW_QOCC(T, M3, WM, WN, BK, OCC) \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gemm_queue<T, true, true, WM, WN, BK, OCC, M3>, 256, 0)
+    if (kind == QK_Z3M) {
+        if (tile == 2) GW_QOCC(double, true, 2, 1, 8, 5);
+        else if (tile == 0) GW_QOCC(double, true, 2, 2, 16, 2);
+        else GW_QOCC(double, true, 4, 1, 8, 3);
+    } else if (kind == QK_Z4M) {
+        if (tile == 3) GW_QOCC(double, false, 4, 1, 8, 3);
+        else if (tile == 2) GW_QOCC(double, false, 2, 1, 8, 4);
+        else if (tile == 1) GW_QOCC(double, false, 4, 2, 8, 2);
+        else GW_QOCC(double, false, 2, 2, 16, 2);
+    } else {
+        if (tile == 3) GW_QOCC(float, false, 4, 1, 8, 4);
+        else if (tile == 2) GW_QOCC(float, false, 2, 1, 8, 4);
+        else if (tile == 1) GW_QOCC(float, false, 4, 2, 8, 2);
+        else GW_QOCC(float, false, 2, 2, 16, 2);
+    }
+#undef GW_QOCC
+    return e == hipSuccess && occ > 0 ? occ : qshape(key).occ;
+}
+void gemm_queue_tile(int key, int *bm, int *bn) {
+    const QShape q = qshape(key);
+    *bm = 32 * q.wm;
+    *bn = 32 * q.wn;
+}
+
+hipError_t launch_gemm_queue(hipStream_t st, int key, const GemmItem *items, int n_items, int64_t n_tiles,
+                             unsigned *queue, int grid, double flops) {
+    if (n_items <= 0 || n_tiles <= 0) return hipSuccess;
+    if (key < 0 || key >= 12 || (!queue && n_tiles > INT32_MAX) || (queue && grid <= 0)) return hipErrorInvalidValue;
+    const int kind = key / 4, tile = key % 4;
+    static const char *const names[3] = {"zgemm3m_queue", "zgemm_queue", "cgemm_queue"};
+    ProfScope ps(st, names[kind], flops, 0.0);
+#define GW_QGEMM(T, M3, WM, WN, BK, OCC)                                                                        \
+    do {                                                                                                         \
+        if (queue)                                                                                               \
+            hipLaunchKernelGGL((k_gemm_queue<T, true, true, WM, WN, BK, OCC, M3>), dim3(grid), dim3(256), 0, st, \
+                               items, n_items, n_tiles, queue);                                                  \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_gemm_group<T, true, true, WM, WN, BK, OCC, M3>), dim3((unsigned)n_tiles),      \
+                               dim3(256), 0, st, items, n_items, n_tiles);                                       \
+    } while (0)
+    if (kind == QK_Z3M) {
+        if (tile == 2) GW_QGEMM(double, true, 2, 1, 8, 5);
+        else if (tile == 0) GW_QGEMM(double, true, 2, 2, 16, 2);
+        else GW_QGEMM(double, true, 4, 1, 8, 3);
+    } else if (kind == QK_Z4M) {
+        if (tile == 3) GW_QGEMM(double, false, 4, 1, 8, 3);
+        else if (tile == 2) GW_QGEMM(double, false, 2, 1, 8, 4);
+        else if (tile == 1) GW_QGEMM(double, false, 4, 2, 8, 2);
+        else GW_QGEMM(double, false, 2, 2, 16, 2);
+    } else {
+        if (tile == 3) GW_QGEMM(float, false, 4, 1, 8, 4);
+        else if (tile == 2) GW_QGEMM(float, false, 2, 1, 8, 4);
+        else if (tile == 1) GW_QGEMM(float, false, 4, 2, 8, 2);
+        else GW_QGEMM(float, false, 2, 2, 16, 2);
+    }
+#undef GW_QGEMM
+    return hipGetLastError();
 }
 
 }  // namespace gwk

@@ -299,9 +299,12 @@ __device__ inline int compose_swaps(const int *lp, int jb, int je, int lane, int
     return nt;
 }
 
-template <typename T, int R, int BW>
-__global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A, int64_t sA, int32_t *ipiv,
-                                                  Cx<T> *Linv, Cx<T> *Uinv, int nblk, int32_t *swp, int32_t *info) {
+// GC, GI: the element types the pointers are declared with (global address
+// space for pointers read from a descriptor, so that they are not accessed as
+// flat memory).
+template <typename T, int R, int BW, typename GC = Cx<T>, typename GI = int32_t>
+__device__ __forceinline__ void getf2r_body(int n, int kb, int w, GC *A, int64_t sA, GI *ipiv, GC *Linv, GC *Uinv,
+                                            int nblk, GI *swp, GI *info, const int b) {
     constexpr int NW = GF_NT / 64;
     static_assert(BW <= NW && NB % BW == 0, "one wave per substituted column");
     __shared__ Cx<T> Ts[NB][NB + 1];  // the panel's top rows as they become final (padded: column reads)
@@ -315,7 +318,6 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
     __shared__ int sw_dst[2 * BW], sw_src[2 * BW];
     __shared__ Cx<T> dinv[NB];
 
-    const int b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     A += (int64_t)b * sA;
     ipiv += (int64_t)b * n;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
     Linv += ((int64_t)b * nblk + kb / NB) * NB * NB;
     Uinv += ((int64_t)b * nblk + kb / NB) * NB * NB;
     const int m = n - kb;
-    Cx<T> *P = A + (int64_t)kb * n + kb;  // panel origin, row stride n
+    GC *P = A + (int64_t)kb * n + kb;  // panel origin, row stride n
     const Cx<T> zero{T(0), T(0)};
 
     for (int j0 = 0; j0 < w; j0 += BW) {
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
 #pragma unroll
             for (int c = 0; c < BW; ++c) a[r][c] = zero;
             if (i >= j0 && i < m) {
-                const Cx<T> *row = P + (int64_t)i * n;
+                const GC *row = P + (int64_t)i * n;
 #pragma unroll
                 for (int c = 0; c < BW; ++c)
                     if (c < bw) a[r][c] = row[j0 + c];
@@ -587,19 +589,47 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A
     for (int q = 0; q < CPW; ++q) Uinv[lane * NB + wave * CPW + q] = x[q];
 }
 
+template <typename T, int R, int BW>
+__global__ __launch_bounds__(GF_NT) void k_getf2r(int n, int kb, int w, Cx<T> *A, int64_t sA, int32_t *ipiv,
+                                                  Cx<T> *Linv, Cx<T> *Uinv, int nblk, int32_t *swp, int32_t *info) {
+    getf2r_body<T, R, BW>(n, kb, w, A, sA, ipiv, Linv, Uinv, nblk, swp, info, blockIdx.x);
+}
+
+// The index of the item whose workgroups wg0 .. include g (items ordered by wg0).
+__device__ inline int group_item(const PanelItem *__restrict__ it, int n_items, int64_t g) {
+    int a = 0, b = n_items - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (it[m].wg0 <= g) a = m;
+        else b = m - 1;
+    }
+    return a;
+}
+
+// Many batched panel factorisations in one launch (the batched driver's lock
+// steps): workgroup g factorises batch entry g - wg0 of its item.
+template <typename T, int R, int BW>
+__global__ __launch_bounds__(GF_NT) void k_getf2r_group(const PanelItem *__restrict__ items, int n_items) {
+    const PanelItem p = items[group_item(items, n_items, blockIdx.x)];
+    typedef dglobal<Cx<T>> GC;
+    typedef dglobal<int32_t> GI;
+    getf2r_body<T, R, BW, GC, GI>(p.n, p.kb, p.w, (GC *)p.A, p.sA, (GI *)p.ipiv, (GC *)p.Linv, (GC *)p.Uinv, p.nblk,
+                                  (GI *)p.swp, (GI *)p.info, (int)(blockIdx.x - p.wg0));
+}
+
 // Apply a panel's composed row exchanges to columns [0, kb) and [kb+w, n).
 // Workgroup = 32 columns; all source rows are staged in LDS before any write.
-template <typename T>
-__global__ __launch_bounds__(256) void k_laswp(int n, int kb, int w, Cx<T> *A, int64_t sA, const int32_t *swp) {
+template <typename T, typename GC = Cx<T>, typename GI = const int32_t>
+__device__ __forceinline__ void laswp_body(int n, int kb, int w, GC *A, int64_t sA, GI *swp, const int b,
+                                           const int cg) {
     __shared__ Cx<T> buf[2 * NB][32];
-    const int b = blockIdx.y;
     A += (int64_t)b * sA;
     swp += (int64_t)b * SWP;
     const int nt = swp[0];
     if (nt == 0) return;
     const int ncols = n - w;
     const int cc = threadIdx.x & 31, tr = threadIdx.x >> 5;
-    const int idx = blockIdx.x * 32 + cc;
+    const int idx = cg * 32 + cc;
     const int c = idx < kb ? idx : idx + w;
     const bool ok = idx < ncols;
     for (int t = tr; t < nt; t += 8)
@@ -607,6 +637,23 @@ __global__ __launch_bounds__(256) void k_laswp(int n, int kb, int w, Cx<T> *A, i
     __syncthreads();
     for (int t = tr; t < nt; t += 8)
         if (ok) A[(int64_t)swp[1 + t] * n + c] = buf[t][cc];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_laswp(int n, int kb, int w, Cx<T> *A, int64_t sA, const int32_t *swp) {
+    laswp_body<T>(n, kb, w, A, sA, swp, blockIdx.y, blockIdx.x);
+}
+
+// Many batched row-exchange passes in one launch: an item's workgroups are
+// (batch entry, 32-column group) pairs, column groups fastest.
+template <typename T>
+__global__ __launch_bounds__(256) void k_laswp_group(const PanelItem *__restrict__ items, int n_items) {
+    const PanelItem p = items[group_item(items, n_items, blockIdx.x)];
+    const int ncg = (p.n - p.w + 31) / 32;
+    const int64_t r = blockIdx.x - p.wg0;
+    typedef dglobal<Cx<T>> GC;
+    typedef dglobal<const int32_t> GI;
+    laswp_body<T, GC, GI>(p.n, p.kb, p.w, (GC *)p.A, p.sA, (GI *)p.swp, (int)(r / ncg), (int)(r % ncg));
 }
 
 // Full row permutation of a factorisation: row i of P A is row perm[i] of A.
@@ -772,11 +819,37 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
     const int64_t sI = (int64_t)nblk * NB * NB;
     int32_t *swp = (int32_t *)(scratch + (int64_t)batch * NB * n);
     hipError_t e;
+    OpRecorder *rec = g_rec;
+    if (rec) rec->mark();
     for (int KB = 0; KB < n; KB += NBO) {
         const int WO = min(NBO, n - KB);
         for (int kb = KB; kb < KB + WO; kb += NB) {
             const int w = min(NB, n - kb);
             const int m = n - kb;
+            if (rec) {
+                // lock-step recording: the panel (a grouped launch per
+                // register-row variant) and its row exchanges
+                RecOp o;
+                o.p = PanelItem{A, sA, ipiv, swp, info, Linv, Uinv, n, kb, w, nblk, batch, 0};
+                if (m <= 4096) {
+                    o.kind = RecOp::PANEL;
+                    o.key = (m <= 512 ? 0 : m <= 1024 ? 1 : m <= 2048 ? 2 : m <= 3072 ? 3 : 4) + (sizeof(T) == 4 ? 5 : 0);
+                    rec->ops.push_back(o);
+                } else {
+                    rec->other([=](hipStream_t s2) {
+                        hipLaunchKernelGGL(k_getf2<T>, dim3(batch), dim3(512), 0, s2, n, kb, w, A, sA, ipiv, Linv,
+                                           Uinv, nblk, scratch, swp, info);
+                        return hipGetLastError();
+                    });
+                }
+                if (n - w > 0) {
+                    RecOp l;
+                    l.kind = RecOp::LASWP;
+                    l.key = sizeof(T) == 4 ? 1 : 0;
+                    l.p = o.p;
+                    rec->ops.push_back(l);
+                }
+            } else {
             ProfScope ps(st, "lu_panel", 0.0, 2.0 * m * w * sizeof(Cx<T>) * (double)batch);
             if (m <= 512)
                 hipLaunchKernelGGL((k_getf2r<T, 1, 8>), dim3(batch), dim3(GF_NT), 0, st, n, kb, w, A, sA, ipiv, Linv,
@@ -801,6 +874,7 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
                 ProfScope pl(st, "laswp", 0.0, 2.0 * w * (n - w) * sizeof(Cx<T>) * (double)batch);
                 hipLaunchKernelGGL(k_laswp<T>, dim3((n - w + 31) / 32, batch), dim3(256), 0, st, n, kb, w, A, sA, swp);
                 if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
             }
             const int rb = KB + WO - kb - w;  // columns of this block right of the panel
             if (rb > 0) {
@@ -838,6 +912,7 @@ hipError_t getrf_impl(hipStream_t st, int n, Cx<T> *A, int64_t sA, int32_t *ipiv
             if (e != hipSuccess) return e;
         }
     }
+    if (rec) rec->mark();
     return hipSuccess;
 }
 
@@ -872,6 +947,8 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
     const int nblk = (n + NB - 1) / NB;
     const int64_t sI = (int64_t)nblk * NB * NB;
     hipError_t e;
+    OpRecorder *rec = g_rec;
+    if (rec) rec->mark();
     // forward: L Y = P B, left-looking over the outer blocks: block row
     // [KB, KB + WO) first takes everything already solved above it in one
     // product (inner dimension KB, long for the later blocks), then is solved
@@ -924,8 +1001,17 @@ hipError_t getrs_impl(hipStream_t st, int n, int nrhs, const Cx<T> *LU, int64_t 
             }
         }
     }
+    if (rec) rec->mark();
     if (sym_lower && n > 1) {
         const int nt = (n + 31) / 32;
+        if (rec) {
+            rec->other([=](hipStream_t s2) {
+                hipLaunchKernelGGL(k_mirror_lower<T>, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)batch), dim3(256),
+                                   0, s2, n, nt, B, sB);
+                return hipGetLastError();
+            });
+            return hipSuccess;
+        }
         ProfScope ps(st, "mirror_lower", 0.0, 2.0 * sizeof(Cx<T>) * (double)n * (n - 1) / 2 * batch);
         hipLaunchKernelGGL(k_mirror_lower<T>, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)batch), dim3(256), 0, st,
                            n, nt, B, sB);
@@ -965,12 +1051,14 @@ hipError_t getrs_batched<zflt>(hipStream_t st, int n, int nrhs, const zflt *LU, 
 }
 
 hipError_t launch_perm(hipStream_t st, int n, const int32_t *ipiv, int32_t *perm, int batch) {
+    GW_DEFER(launch_perm(st, n, ipiv, perm, batch));
     hipLaunchKernelGGL(k_perm_from_ipiv, dim3(batch), dim3(256), (size_t)n * sizeof(int32_t), st, n, ipiv, perm);
     return hipGetLastError();
 }
 
 hipError_t launch_rowgather_c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zflt *src, int64_t sS,
                               zflt *dst, int64_t sD, int batch) {
+    GW_DEFER(launch_rowgather_c(st, n, nrhs, perm, src, sS, dst, sD, batch));
     dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
     hipLaunchKernelGGL(k_rowgather<float>, grid, dim3(256), 0, st, n, nrhs, perm, (const Cx<float> *)src, sS,
                        (Cx<float> *)dst, sD);
@@ -978,6 +1066,7 @@ hipError_t launch_rowgather_c(hipStream_t st, int n, int nrhs, const int32_t *pe
 }
 hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
                               zdbl *dst, int64_t sD, int batch) {
+    GW_DEFER(launch_rowgather_z(st, n, nrhs, perm, src, sS, dst, sD, batch));
     dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
     hipLaunchKernelGGL(k_rowgather<double>, grid, dim3(256), 0, st, n, nrhs, perm, (const Cx<double> *)src, sS,
                        (Cx<double> *)dst, sD);
@@ -986,6 +1075,7 @@ hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *pe
 
 hipError_t launch_init_rhs_perm(hipStream_t st, int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
                                 int64_t sB, int batch) {
+    GW_DEFER(launch_init_rhs_perm(st, n, v, v_is_diag, perm, B, sB, batch));
     dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
     ProfScope ps(st, "init_rhs", 0.0, 16.0 * (double)n * n * batch);
     hipLaunchKernelGGL(k_init_rhs, grid, dim3(256), 0, st, n, v, v_is_diag, perm, B, sB);
@@ -997,6 +1087,7 @@ hipError_t launch_init_rhs(hipStream_t st, int n, const double *v, int v_is_diag
 }
 
 hipError_t launch_conj_mirror(hipStream_t st, int64_t nn, int n_omega, zdbl *W) {
+    GW_DEFER(launch_conj_mirror(st, nn, n_omega, W));
     if (n_omega < 4) return hipSuccess;
     dim3 grid((unsigned)((nn + 255) / 256), n_omega / 2 - 1);
     ProfScope ps(st, "conj_mirror", 0.0, 2.0 * 16.0 * (double)nn * (n_omega / 2 - 1));
@@ -1005,6 +1096,7 @@ hipError_t launch_conj_mirror(hipStream_t st, int64_t nn, int n_omega, zdbl *W) 
 }
 
 hipError_t launch_z2c(hipStream_t st, const zdbl *src, zflt *dst, int64_t n) {
+    GW_DEFER(launch_z2c(st, src, dst, n));
     int64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_z2c, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
@@ -1012,6 +1104,7 @@ hipError_t launch_z2c(hipStream_t st, const zdbl *src, zflt *dst, int64_t n) {
 }
 
 hipError_t launch_c2z_add(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch, const int32_t *active) {
+    GW_DEFER(launch_c2z_add(st, d, W, n_per, batch, active));
     int64_t blocks = (n_per + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(k_c2z_add, dim3((unsigned)blocks, batch), dim3(256), 0, st, d, W, n_per, active);
@@ -1019,6 +1112,7 @@ hipError_t launch_c2z_add(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per,
 }
 
 hipError_t launch_norms(hipStream_t st, const zflt *dW, const zdbl *W, int64_t n_per, int batch, double *out) {
+    GW_DEFER(launch_norms(st, dW, W, n_per, batch, out));
     int64_t blocks = (n_per + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_norms, dim3((unsigned)blocks, batch), dim3(256), 0, st, dW, W, n_per, out);
@@ -1027,16 +1121,53 @@ hipError_t launch_norms(hipStream_t st, const zflt *dW, const zdbl *W, int64_t n
 
 hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
                                 zflt *dst, int64_t sD, int batch) {
+    GW_DEFER(launch_rowgather_z2c(st, n, nrhs, perm, src, sS, dst, sD, batch));
     dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
     hipLaunchKernelGGL(k_rowgather_z2c, grid, dim3(256), 0, st, n, nrhs, perm, src, sS, dst, sD);
     return hipGetLastError();
 }
 
 hipError_t launch_c2z_set(hipStream_t st, const zflt *d, zdbl *W, int64_t n_per, int batch) {
+    GW_DEFER(launch_c2z_set(st, d, W, n_per, batch));
     int64_t blocks = (n_per + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(k_c2z_set, dim3((unsigned)blocks, batch), dim3(256), 0, st, d, W, n_per);
     return hipGetLastError();
+}
+
+// Panel keys: (R, BW) = (1, 8), (2, 8), (4, 8), (6, 4), (8, 4) for panels of at
+// most 512, 1024, 2048, 3072, 4096 rows, complex double; +5 complex float.
+hipError_t launch_panel_group(hipStream_t st, int key, const PanelItem *items, int n_items, int64_t n_wg) {
+    if (n_items <= 0 || n_wg <= 0) return hipSuccess;
+    if (key < 0 || key > 9 || n_wg > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)n_wg), blk(GF_NT);
+    switch (key) {
+        case 0: hipLaunchKernelGGL((k_getf2r_group<double, 1, 8>), grid, blk, 0, st, items, n_items); break;
+        case 1: hipLaunchKernelGGL((k_getf2r_group<double, 2, 8>), grid, blk, 0, st, items, n_items); break;
+        case 2: hipLaunchKernelGGL((k_getf2r_group<double, 4, 8>), grid, blk, 0, st, items, n_items); break;
+        case 3: hipLaunchKernelGGL((k_getf2r_group<double, 6, 4>), grid, blk, 0, st, items, n_items); break;
+        case 4: hipLaunchKernelGGL((k_getf2r_group<double, 8, 4>), grid, blk, 0, st, items, n_items); break;
+        case 5: hipLaunchKernelGGL((k_getf2r_group<float, 1, 8>), grid, blk, 0, st, items, n_items); break;
+        case 6: hipLaunchKernelGGL((k_getf2r_group<float, 2, 8>), grid, blk, 0, st, items, n_items); break;
+        case 7: hipLaunchKernelGGL((k_getf2r_group<float, 4, 8>), grid, blk, 0, st, items, n_items); break;
+        case 8: hipLaunchKernelGGL((k_getf2r_group<float, 6, 4>), grid, blk, 0, st, items, n_items); break;
+        default: hipLaunchKernelGGL((k_getf2r_group<float, 8, 4>), grid, blk, 0, st, items, n_items); break;
+    }
+    return hipGetLastError();
+}
+
+// Row-exchange keys: 0 complex double, 1 complex float.
+hipError_t launch_laswp_group(hipStream_t st, int key, const PanelItem *items, int n_items, int64_t n_wg) {
+    if (n_items <= 0 || n_wg <= 0) return hipSuccess;
+    if (key < 0 || key > 1 || n_wg > INT32_MAX) return hipErrorInvalidValue;
+    if (key == 0) hipLaunchKernelGGL(k_laswp_group<double>, dim3((unsigned)n_wg), dim3(256), 0, st, items, n_items);
+    else hipLaunchKernelGGL(k_laswp_group<float>, dim3((unsigned)n_wg), dim3(256), 0, st, items, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t st, void *dst, const void *src, size_t bytes) {
+    GW_DEFER(launch_copy(st, dst, src, bytes));
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
 }
 
 hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *src, double *dst) {
@@ -1046,6 +1177,7 @@ hipError_t launch_transpose_d(hipStream_t st, int rows, int cols, const double *
 }
 
 hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value) {
+    GW_DEFER(launch_fill_u32(st, p, n, value));
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;

@@ -108,6 +108,8 @@ _SIGS = {
                                        ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)]),
     "gw_batch_run": (ctypes.c_int, [_P, _P, ctypes.POINTER(gw_report)]),
     "gw_batch_destroy": (ctypes.c_int, [_P]),
+    "gw_batch_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "gw_profile_begin": (ctypes.c_int, [_P]),
     "gw_profile_read": (ctypes.c_int, [_P, ctypes.POINTER(gw_kernel_stat), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32)]),
@@ -342,6 +344,16 @@ class Batch:
         st = lib.gw_batch_run(self.h, _stream_handle(stream), reps)
         self.ctx._check(st, "gw_batch_run")
         return list(reps) if report else None
+
+    def stats(self):
+        """dict(mode, steps, launches, products): how the batch was recorded
+        (mode 0 molecules on branches, 1 lock steps aligned at the end, 2 at
+        the start)."""
+        m = ctypes.c_int32()
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.ctx._check(lib.gw_batch_stats(self.h, ctypes.byref(m), ctypes.byref(a), ctypes.byref(b),
+                                           ctypes.byref(c)), "gw_batch_stats")
+        return {"mode": m.value, "steps": a.value, "launches": b.value, "products": c.value}
 
     def close(self):
         if self.h:

@@ -27,6 +27,7 @@ typedef struct ihipStream_t *hipStream_t;
 typedef struct ihipEvent_t *hipEvent_t;
 typedef struct ihipGraph *hipGraph_t;
 typedef struct hipGraphExec *hipGraphExec_t;
+typedef struct hipGraphNode *hipGraphNode_t;
 typedef struct ihipMemPoolHandle_t *hipMemPool_t;
 typedef enum { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice } hipMemcpyKind;
 typedef enum { hipStreamCaptureStatusNone, hipStreamCaptureStatusActive } hipStreamCaptureStatus;
@@ -62,6 +63,11 @@ inline hipError_t hipGetDevice(int *d) {
 inline hipError_t hipGetDeviceCount(int *n) {
     *n = 1;
     return hipSuccess;
+}
+typedef enum { hipDeviceAttributeMultiprocessorCount = 63 } hipDeviceAttribute_t;
+inline hipError_t hipDeviceGetAttribute(int *v, hipDeviceAttribute_t, int d) {
+    *v = 256;
+    return d == 0 ? hipSuccess : hipErrorInvalidDevice;
 }
 inline hipError_t hipMemGetInfo(size_t *fr, size_t *tot) {
     *fr = (size_t)64 << 30;
@@ -110,6 +116,17 @@ inline hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus *c) {
     return hipSuccess;
 }
 inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+typedef enum { hipStreamAddCaptureDependencies = 0, hipStreamSetCaptureDependencies } hipStreamUpdateCaptureDependenciesFlags;
+inline hipError_t hipStreamGetCaptureInfo_v2(hipStream_t, hipStreamCaptureStatus *c, unsigned long long *id,
+                                             hipGraph_t *g, const hipGraphNode_t **d, size_t *n) {
+    *c = hipStreamCaptureStatusNone;
+    if (id) *id = 0;
+    if (g) *g = nullptr;
+    if (d) *d = nullptr;
+    if (n) *n = 0;
+    return hipSuccess;
+}
+inline hipError_t hipStreamUpdateCaptureDependencies(hipStream_t, hipGraphNode_t *, size_t, unsigned) { return hipSuccess; }
 inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) {
     *g = (hipGraph_t)hipstub::handle();
     return hipSuccess;
@@ -119,6 +136,10 @@ inline hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t, void *, cha
     return hipSuccess;
 }
 inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipGraphGetNodes(hipGraph_t, hipGraphNode_t *, size_t *n) {
+    *n = 0;  // nothing is ever captured here
+    return hipSuccess;
+}
 inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
 inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
 inline hipError_t hipDeviceGetDefaultMemPool(hipMemPool_t *p, int) {

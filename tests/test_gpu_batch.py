@@ -160,3 +160,57 @@ def test_newer_batch_retires_older(gpu):
     torch.cuda.synchronize()
     b1.close()
     b2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x_ir"])
+def test_lock_steps_equal_molecules_on_branches(gpu, prec, monkeypatch):
+    """The lock-step launch (every molecule's products of a step in one
+    launch, panels and row exchanges grouped) runs the same tile arithmetic
+    as whole molecules on parallel branches: the results are equal bit for
+    bit, aligned at the end or at the start, with the products of a step
+    handed out by the hardware dispatcher or by the persistent work-queue
+    grid.  The molecules span three panel variants (panels of up to 512, 1024
+    and 2048 rows), in place and through chi0."""
+    gw, ctx, torch = gpu
+    grid = gs.config_grid(0)
+    g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
+    mols = [gs.chain_molecule(14, 3), gs.chain_molecule(6, 21), gs.chain_molecule(22, 5), gs.make_config(0)]
+    ns = [m.n_prod for m in mols]
+    _say("lock-step parity: n_prod", ns)
+    assert max(ns) > 1024 and min(ns) <= 512
+    dms = [gw.DeviceMolecule(m) for m in mols]
+    p = {"fp64": gw.GW_FP64, "bf16x_ir": gw.GW_BF16X_IR}[prec]
+    stream = torch.cuda.current_stream()
+    out = {}
+    for mode in ["streams", "lockstep", "lockstep_left", "lockstep_persistent"]:
+        # lockstep_persistent: the products on the persistent work-queue grid
+        monkeypatch.setenv("GW_BATCH_MODE", mode.replace("_persistent", ""))
+        if mode.endswith("_persistent"):
+            monkeypatch.setenv("GW_GEMM_QUEUE", "persistent")
+        else:
+            monkeypatch.delenv("GW_GEMM_QUEUE", raising=False)
+        chis = [torch.zeros((grid.n_omega, n, n), dtype=torch.complex128, device="cuda") for n in ns]
+        Ws = [torch.zeros_like(c) for c in chis]
+        Ws[1] = chis[1]  # in place (A route)
+        b = ctx.batch_create([dm.struct for dm in dms], [dm.v for dm in dms], g, chis, Ws, prec=p, tol=1e-6,
+                             n_refine=2, stream=stream)
+        st = b.stats()
+        _say(prec, mode, st)
+        assert st["mode"] == {"streams": 0, "lockstep": 1, "lockstep_left": 2, "lockstep_persistent": 1}[mode]
+        if mode != "streams":
+            # FP64: every complex product is queued; BF16x: the split-BF16
+            # trailing updates run as launches of their own in the steps
+            assert st["steps"] > 0 and st["products"] > (st["steps"] if prec == "fp64" else 0)
+        for w in Ws:
+            w.fill_(float("nan"))
+        b.run(stream=stream)
+        torch.cuda.synchronize()
+        out[mode] = [w.cpu().numpy() for w in Ws]
+        b.close()
+        del chis, Ws
+    for mode in ["lockstep", "lockstep_left", "lockstep_persistent"]:
+        for i in range(len(mols)):
+            d = np.abs(out[mode][i] - out["streams"][i]).max()
+            _say(prec, mode, "molecule", i, "n", ns[i], "largest difference vs branches", d)
+            assert np.all(np.isfinite(out[mode][i]))
+            assert np.array_equal(out[mode][i], out["streams"][i])

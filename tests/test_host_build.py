@@ -21,7 +21,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1101_2065_amd", "csrc")
 STUB = os.path.join(ROOT, "tests", "hostbuild")
-HOST_SOURCES = ["gw_abi.cpp", "gw_batch.cpp", "gw_serve.cpp", "gw_prof.cpp", "gw_tune.cpp"]
+HOST_SOURCES = ["gw_abi.cpp", "gw_batch.cpp", "gw_serve.cpp", "gw_prof.cpp", "gw_tune.cpp", "gw_group.cpp"]
 
 
 def _strip_defaults(params):
@@ -70,7 +70,11 @@ def _launcher_stubs():
                 defs.append("%s%s %s(%s) { %s }" % (pre, ret, nm, ps, body))
     return ("// generated: every launcher succeeds without doing anything\n"
             "#include \"gw_internal.h\"\n#include \"gw_plan.h\"\n"
-            "namespace gwk {\n" + "\n".join(defs) + "\n}  // namespace gwk\n"
+            "namespace gwk {\n" + "\n".join(defs) + "\n"
+            "thread_local OpRecorder *g_rec = nullptr;\n"
+            "int gemm_queue_occupancy(int key) { return 1 + key % 4; }\n"
+            "void gemm_queue_tile(int key, int *bm, int *bn) { *bm = key % 4 == 2 ? 64 : 128; *bn = 32; }\n"
+            "}  // namespace gwk\n"
             "namespace gwp {\nvoid set_thread_gemm_tile(int) {}\n"
             "bool set_thread_cgemm_bf16x(bool on) { static thread_local bool v = false; bool p = v; v = on; "
             "return p; }\n}  // namespace gwp\n"
@@ -79,6 +83,8 @@ def _launcher_stubs():
 
 DRIVER = r'''
 #include "gw.h"
+#include "gw_ctx.h"
+#include "gw_plan.h"
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -217,6 +223,66 @@ int main(int argc, char **argv) {
         uint64_t tb;
         CHECK(gw_submit(c, &bad, mol.v.data(), &g, 0, GW_FP64, 1e-7, &tb) == GW_E_INVALID);
         CHECK(gw_submit(c, &m, mol.v.data(), &g, 3, GW_FP64, 1e-7, &tb) == GW_E_INVALID);
+    } else if (mode == "lockstep") {
+        // two recorded programs: products, a panel, its row exchanges and a
+        // deferred launch, against two products of a second molecule
+        int ran = 0;
+        auto gemm = [](int M, int N, int K, int batch) {
+            gwk::RecOp o;
+            o.kind = gwk::RecOp::GEMM;
+            o.key = gwk::QK_Z3M * 4 + 2;
+            o.g.M = M; o.g.N = N; o.g.K = K; o.g.batch = batch;
+            o.flops = 8.0 * M * N * K * batch;
+            return o;
+        };
+        gwk::RecOp pan, swp, oth, mark;
+        pan.kind = gwk::RecOp::PANEL; pan.key = 1;
+        pan.p.n = 300; pan.p.w = 64; pan.p.kb = 0; pan.p.batch = 5;
+        swp = pan; swp.kind = gwk::RecOp::LASWP; swp.key = 0;
+        oth.kind = gwk::RecOp::OTHER;
+        oth.fn = [&ran](hipStream_t) { ++ran; return hipSuccess; };
+        mark.kind = gwk::RecOp::MARK;
+        for (int align = 0; align < 2; ++align) {
+            std::vector<std::vector<gwk::RecOp>> progs(2);
+            progs[0] = {mark, gemm(100, 70, 64, 3), pan, swp, oth, mark};
+            progs[1] = {gemm(40, 40, 16, 2), mark, gemm(100, 70, 64, 1)};
+            gwp::LockStep *ls = nullptr;
+            CHECK(gwp::lockstep_plan(c, progs, align == 1, &ls) == GW_OK && ls);
+            const gwp::LockStepStats st = gwp::lockstep_stats(ls);
+            CHECK(st.steps == 4 && st.ops == 6 && st.products == 3);
+            // right-aligned: {G0} {P0} {S0, G1} {O0, G1}; left: {G0 G1} {P0, G1} {S0} {O0}
+            CHECK(st.launches == (align ? 6 : 5));
+            const gwk::GemmItem *gi = (const gwk::GemmItem *)c->bufs["lsGemm"].ptr;
+            const gwk::PanelItem *pi = (const gwk::PanelItem *)c->bufs["lsPanel"].ptr;
+            // 64 x 32 tiles: 100 x 70 in 2 x 3, times the batch
+            CHECK(gi[0].M == 100 && gi[0].tx == 3 && gi[0].ty == 2 && gi[0].t0 == 0);
+            if (align) {
+                CHECK(gi[1].M == 40 && gi[1].t0 == 0 && gi[1].tx == 2 && gi[1].ty == 1);
+                CHECK(gi[2].M == 100 && gi[2].batch == 1 && gi[2].t0 == 0);
+            } else {
+                CHECK(gi[1].M == 40 && gi[1].t0 == 18);  // after the first item's 2 x 3 x 3 tiles
+                CHECK(gi[2].M == 100 && gi[2].batch == 1 && gi[2].t0 == 0);
+            }
+            CHECK(pi[0].batch == 5 && pi[0].wg0 == 0 && pi[1].wg0 == 0 && pi[1].n == 300);
+            std::vector<hipStream_t> br(2);
+            std::vector<hipEvent_t> ev(3);
+            for (auto &x : br) hipStreamCreateWithFlags(&x, 0);
+            for (auto &x : ev) hipEventCreate(&x);
+            CHECK(gwp::lockstep_enqueue(c, *ls, nullptr, br, ev) == GW_OK);
+            CHECK(ran == align + 1);
+            CHECK(gwp::lockstep_enqueue(c, *ls, nullptr, br, {}) == GW_E_INVALID);
+            gwp::lockstep_free(ls);
+        }
+        int32_t md = -1;
+        int64_t nst = -1;
+        const double *vs[1] = {mol.v.data()};
+        void *cs[1] = {chi.data()}, *ws[1] = {W.data()};
+        gw_batch *b = nullptr;
+        CHECK(gw_batch_stats(nullptr, &md, &nst, nullptr, nullptr) == GW_E_INVALID);
+        CHECK(gw_batch_create(c, 1, &m, vs, &g, GW_FP64, 1e-7, 0, nullptr, cs, ws, &b) == GW_OK);
+        CHECK(gw_batch_stats(b, &md, &nst, nullptr, nullptr) == GW_OK && md == 1 && nst == 0);
+        CHECK(gw_batch_run(b, nullptr, &rep) == GW_OK);
+        CHECK(gw_batch_destroy(b) == GW_OK);
     } else {
         std::printf("unknown mode\n");
         return 2;
@@ -263,6 +329,14 @@ def test_argument_checks_and_status_codes(driver):
 @pytest.mark.parametrize("fault", ["oom", "device", "noconv"])
 def test_forced_faults(driver, fault):
     _run(driver, fault, fault)
+
+
+def test_lock_step_grouping(driver):
+    """The batched driver's lock steps: operation k of every recorded program
+    in step k (or aligned at the end), the products of a step in one
+    work-queue launch with consecutive tile ranges, panels and row exchanges
+    grouped with their workgroup offsets, deferred launches run once."""
+    _run(driver, "lockstep")
 
 
 def test_serving_states(driver):
