@@ -618,11 +618,14 @@ __global__ __launch_bounds__(GF_NT) void k_getf2r_group(const PanelItem *__restr
 }
 
 // Apply a panel's composed row exchanges to columns [0, kb) and [kb+w, n).
-// Workgroup = 32 columns; all source rows are staged in LDS before any write.
+// Workgroup = 32 columns, eight threads per column, each holding up to 16 of
+// the (at most 2 NB) source values in registers: all loads are issued before
+// any store, and every source row is read before any row is written (one
+// barrier).  No LDS, so the pass runs at full occupancy.
 template <typename T, typename GC = Cx<T>, typename GI = const int32_t>
 __device__ __forceinline__ void laswp_body(int n, int kb, int w, GC *A, int64_t sA, GI *swp, const int b,
                                            const int cg) {
-    __shared__ Cx<T> buf[2 * NB][32];
+    constexpr int PER = 2 * NB / 8;
     A += (int64_t)b * sA;
     swp += (int64_t)b * SWP;
     const int nt = swp[0];
@@ -632,11 +635,27 @@ __device__ __forceinline__ void laswp_body(int n, int kb, int w, GC *A, int64_t 
     const int idx = cg * 32 + cc;
     const int c = idx < kb ? idx : idx + w;
     const bool ok = idx < ncols;
-    for (int t = tr; t < nt; t += 8)
-        if (ok) buf[t][cc] = A[(int64_t)swp[1 + 2 * NB + t] * n + c];
+    T vr[PER], vi[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int t = tr + 8 * q;
+        vr[q] = vi[q] = T(0);
+        if (ok && t < nt) {
+            const GC &x = A[(int64_t)swp[1 + 2 * NB + t] * n + c];
+            vr[q] = x.re;
+            vi[q] = x.im;
+        }
+    }
     __syncthreads();
-    for (int t = tr; t < nt; t += 8)
-        if (ok) A[(int64_t)swp[1 + t] * n + c] = buf[t][cc];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int t = tr + 8 * q;
+        if (ok && t < nt) {
+            GC &x = A[(int64_t)swp[1 + t] * n + c];
+            x.re = vr[q];
+            x.im = vi[q];
+        }
+    }
 }
 
 template <typename T>
