@@ -453,7 +453,7 @@ gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st) {
     return GW_OK;
 }
 
-gw_status a_route_ws(gw_ctx *c, const std::string &pre, int n, int nhb, ARouteWs *w) {
+gw_status a_route_ws(gw_ctx *c, const std::string &pre, int n, int nhb, int n_omega, ARouteWs *w) {
     const size_t nn = (size_t)n * n;
     // dense bins staged at most 2 GiB at a time (at least one bin)
     w->dchunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::max(1, nhb - 1), ((size_t)2 << 30) / (8 * nn)));
@@ -463,12 +463,14 @@ gw_status a_route_ws(gw_ctx *c, const std::string &pre, int n, int nhb, ARouteWs
     w->D = (double *)q;
     if ((s = ws(c, pre + "aB", 8 * nn * std::max(1, nhb), &q)) != GW_OK) return s;
     w->B = (double *)q;
+    if ((s = ws(c, pre + "aT", 16 * (size_t)(n_omega / 2 + 1) * std::max(1, nhb), &q)) != GW_OK) return s;
+    w->T = (zdbl *)q;
     return GW_OK;
 }
 
 gw_status a_from_bins_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, int nhb, const int64_t *a_i64,
                               const int32_t *s_dev, const double *a_f64, const double *v, const ARouteWs &w,
-                              const zdbl *Kt, const zdbl *tw, void *A_out) {
+                              const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out) {
     // v a0 bin by bin (bins 1 .. nhb-1); its Cauchy transform is v chi0
     const int64_t nn = (int64_t)n * n;
     const int64_t n_upper = (int64_t)n * (n + 1) / 2;
@@ -478,7 +480,9 @@ gw_status a_from_bins_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, i
         else GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, a_f64, n_upper, w.D));
         GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
     }
-    GW_HIP(ctx, gwk::launch_fftconv_A(st, n, n_omega, nhb, w.B, Kt, tw, (zdbl *)A_out));
+    const char *tr = std::getenv("GW_A_TRANSFORM");
+    if (tr && std::string(tr) == "fft") GW_HIP(ctx, gwk::launch_fftconv_A(st, n, n_omega, nhb, w.B, Kt, tw, (zdbl *)A_out));
+    else GW_HIP(ctx, gwk::launch_cauchy_A(st, n, n_omega, nhb, j0, domega, eps, w.B, w.T, (zdbl *)A_out));
     return GW_OK;
 }
 
@@ -487,7 +491,8 @@ gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const
     gw_status s = build_hist_enqueue(ctx, p, st);
     if (s != GW_OK) return s;
     if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
-    return a_from_bins_enqueue(ctx, st, p.n_prod, p.g.n_omega, p.nhb, p.H, p.sdev, nullptr, v, w, p.Kt, p.tw, A_out);
+    return a_from_bins_enqueue(ctx, st, p.n_prod, p.g.n_omega, p.nhb, p.H, p.sdev, nullptr, v, w, p.Kt, p.tw, p.j0,
+                               p.dom, p.g.eps, A_out);
 }
 
 gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
@@ -961,9 +966,9 @@ static gw_status build_time_impl(gw_ctx *ctx, const gw_molecule *m, const double
     GW_HIP(ctx, gwk::launch_kspec(st, g->n_omega, (int)std::lround(g->omega_min / dom), dom, g->eps, Kt, tw));
     if (v) {
         gwp::ARouteWs aw;
-        if ((s = gwp::a_route_ws(ctx, "t_", n, nhb, &aw)) != GW_OK) return s;
+        if ((s = gwp::a_route_ws(ctx, "t_", n, nhb, g->n_omega, &aw)) != GW_OK) return s;
         s = gwp::a_from_bins_enqueue(ctx, st, n, g->n_omega, nhb, nullptr, nullptr, (const double *)a, v, aw, Kt, tw,
-                                     chi0_out);
+                                     (int)std::lround(g->omega_min / dom), dom, g->eps, chi0_out);
         if (s != GW_OK) return s;
     } else {
         GW_HIP(ctx, gwk::launch_fftconv(st, n, g->n_omega, nhb, (const double *)a, Kt, tw, (zdbl *)chi0_out));
@@ -1331,7 +1336,7 @@ gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const g
     gw_status s = gwp::build_plan(ctx, m, g, nullptr, 0, st, "", nullptr, &p);
     if (s != GW_OK) return s;
     gwp::ARouteWs aw;
-    if ((s = gwp::a_route_ws(ctx, "", p.n_prod, p.nhb, &aw)) != GW_OK) return s;
+    if ((s = gwp::a_route_ws(ctx, "", p.n_prod, p.nhb, g->n_omega, &aw)) != GW_OK) return s;
     const bool kspec = ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != p.dom ||
                        ctx->ks_eps != g->eps;
     if ((s = gwp::a_route_enqueue(ctx, p, st, v, aw, kspec, A_out)) != GW_OK) return s;

@@ -233,7 +233,7 @@ gw_status record(gw_batch *b) {
         for (int i = 0; i < b->n_mol; ++i) {
             route_a[i] = mesh_a && b->W[i] == b->chi0[i];
             if (!route_a[i]) continue;
-            gw_status s = gwp::a_route_ws(ctx, "ba", b->n[i], bp[i].nhb, &aw[i]);
+            gw_status s = gwp::a_route_ws(ctx, "ba", b->n[i], bp[i].nhb, b->g.n_omega, &aw[i]);
             if (s != GW_OK) return s;
         }
     gwp::LockStep *ls = nullptr;

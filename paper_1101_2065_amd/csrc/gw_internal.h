@@ -135,6 +135,15 @@ hipError_t launch_fracbits(hipStream_t st, const uint64_t *vmax_bits, int64_t n_
                            int requested, int32_t *s_out);
 
 hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t value);
+// A route: A[j] = 1 - (T X)[j] for all j from the products X = v a0 of the
+// bins ([nhb][n][n] real, bin row 0 is overwritten with the identity), by one
+// complex-times-real product over the solved half of the mesh that also writes
+// the conjugate mirror (T: workspace of (n_omega/2 + 1) nhb complex), and the
+// lone point j = 0.
+hipError_t launch_cauchy_A(hipStream_t st, int n, int n_omega, int nhb, int j0, double domega, double eps,
+                           double *X, zdbl *T, zdbl *A);
+hipError_t launch_zdgemm_wide(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda,
+                              const double *B, int64_t ldb, zdbl *C, int64_t ldc, bool mirror);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t value);
 
 // Exact int64 histogram H[nhb][n_upper] (Section 5.A eq. chi_by_spectra).

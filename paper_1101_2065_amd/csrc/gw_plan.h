@@ -68,23 +68,30 @@ gw_status build_plan(gw_ctx *c, const gw_molecule *m, const gw_grid *g, const do
 gw_status build_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec);
 
 // A = 1 - v chi0 formed from v a0: the products v a0 of every bin (B, bins
-// >= 1 used) and the dense bins of one chunk (D, dchunk bins).
+// >= 1; row 0 takes the identity), the dense bins of one chunk (D, dchunk
+// bins) and the Cauchy-transform matrix T of the solved half of the mesh.
 struct ARouteWs {
     double *D = nullptr, *B = nullptr;
+    zdbl *T = nullptr;
     int dchunk = 1;
 };
-// Workspace of the route for n products and nhb bins (named `prefix`aD/aB;
-// grow-only, so a run of calls leaves buffers that fit the largest).
-gw_status a_route_ws(gw_ctx *c, const std::string &prefix, int n, int nhb, ARouteWs *w);
+// Workspace of the route for n products, nhb bins and n_omega mesh points
+// (named `prefix`aD/aB/aT; grow-only, so a run of calls leaves buffers that
+// fit the largest).
+gw_status a_route_ws(gw_ctx *c, const std::string &prefix, int n, int nhb, int n_omega, ARouteWs *w);
 // a1-a3 as build_enqueue, then A[j] = 1 - v chi0(omega_j) for all j into A_out.
 gw_status a_route_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
                           bool with_kspec, void *A_out);
 // A[j] = 1 - v chi0(omega_j) for all j from a spectral array a [nhb][n(n+1)/2]
 // already on the mesh (the exact histogram times 2^-s, or a0 in floating
-// point: a_i64 or a_f64), with the Cauchy-kernel spectrum Kt, tw of the mesh.
+// point: a_i64 or a_f64): the Cauchy transform of the products v a0 as one
+// complex-times-real matrix product over the solved half of the mesh
+// (omega_j = (j + j0) domega), the rest by the conjugate mirror; with
+// GW_A_TRANSFORM=fft instead the FFT convolution with the Cauchy-kernel
+// spectrum Kt, tw over all mesh points.
 gw_status a_from_bins_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const int64_t *a_i64,
                               const int32_t *s_dev, const double *a_f64, const double *v, const ARouteWs &w,
-                              const zdbl *Kt, const zdbl *tw, void *A_out);
+                              const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out);
 
 struct SolveWs {
     zdbl *A = nullptr;

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 namespace gwk {
 
 namespace {
@@ -617,6 +619,78 @@ hipError_t launch_fftconv_A(hipStream_t st, int n, int n_omega, int nhb, const d
     }
 #undef GW_FFTA_CASE
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ A route: Cauchy transform as a product
+// The Cauchy transform of the odd-extended bins (Section 5.A eq.
+// chi_by_spectra) at mesh point j is a fixed linear map of the bins, the same
+// for every matrix entry:  sum_q T[j][q] x_q  with
+//   T[j][q] = 1/(omega_j - q domega + i eps) - 1/(omega_j + q domega + i eps),
+// omega_j = (j + j0) domega.  On the A route, with x_q = (v a0)_q and the
+// identity in bin row 0 (bin 0 carries no weight in chi0), A = 1 - v chi0 is
+// one complex-times-real product  A = -T' X  with T'[j][0] = -1.
+// Rows of T': r = 0 is mesh point 0 (the lone point), r >= 1 is mesh point
+// n_omega/2 + r - 1 (the solved half); ld = nhb.
+__global__ void k_cauchy_T(int n_omega, int j0, double domega, double eps, int nhb, zdbl *__restrict__ T) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (q >= nhb) return;
+    const int j = r == 0 ? 0 : n_omega / 2 + r - 1;
+    zdbl t{-1.0, 0.0};
+    if (q > 0) {
+        const double xm = (double)(j + j0 - q) * domega, xp = (double)(j + j0 + q) * domega;
+        const double dm = xm * xm + eps * eps, dp = xp * xp + eps * eps;
+        t = zdbl{xm / dm - xp / dp, -eps / dm + eps / dp};
+    }
+    T[(int64_t)r * nhb + q] = t;
+}
+
+// Bin row 0 of X set to the identity pattern (X[0][mu][nu] = delta_{mu nu}).
+__global__ void k_eye_row(int n, int64_t nn, double *__restrict__ X0) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x)
+        X0[e] = (e % (n + 1) == 0) ? 1.0 : 0.0;
+}
+
+// The lone mesh point j = 0 (no mirror partner, one row of the product):
+// A[0][e] = -sum_q T'[0][q] X[q][e], one entry per thread, rows of X read
+// coalesced.
+__global__ __launch_bounds__(256) void k_cauchy_row0(int64_t nn, int nhb, const zdbl *__restrict__ T0,
+                                                     const double *__restrict__ X, zdbl *__restrict__ A0) {
+    extern __shared__ zdbl t0[];
+    for (int q = threadIdx.x; q < nhb; q += blockDim.x) t0[q] = T0[q];
+    __syncthreads();
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nn) return;
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < nhb; ++q) {
+        const double x = X[(int64_t)q * nn + e];
+        re = fma(t0[q].re, x, re);
+        im = fma(t0[q].im, x, im);
+    }
+    A0[e] = zdbl{-re, -im};
+}
+
+hipError_t launch_cauchy_A(hipStream_t st, int n, int n_omega, int nhb, int j0, double domega, double eps,
+                           double *X, zdbl *T, zdbl *A) {
+    const int64_t nn = (int64_t)n * n;
+    const int half = n_omega / 2;
+    hipLaunchKernelGGL(k_cauchy_T, dim3((nhb + 255) / 256, half + 1), dim3(256), 0, st, n_omega, j0, domega, eps, nhb,
+                       T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>((nn + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_eye_row, dim3((unsigned)blocks), dim3(256), 0, st, n, nn, X);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the solved half j = n_omega/2 .. n_omega-1 in one product, which also
+    // writes the other half by A(-omega) = A(omega)* (v real)
+    if ((e = launch_zdgemm_wide(st, half, (int)nn, nhb, -1.0, T + nhb, nhb, X, nn, A + (int64_t)half * nn, nn,
+                                true)) != hipSuccess)
+        return e;
+    {
+        ProfScope ps(st, "cauchy_row0", 4.0 * (double)nn * nhb, 8.0 * (double)nn * nhb + 16.0 * (double)nn);
+        hipLaunchKernelGGL(k_cauchy_row0, dim3((unsigned)((nn + 255) / 256)), dim3(256), sizeof(zdbl) * nhb, st, nn,
+                           nhb, T, X, A);
+        return hipGetLastError();
+    }
 }
 
 hipError_t launch_kspec(hipStream_t st, int n_omega, int j0, double domega, double eps, zdbl *Kt, zdbl *tw) {

@@ -63,7 +63,10 @@ struct Mfma<float> {
 // refinement residual does not.
 // One (32 WM) x (32 WN) tile of C with its top-left corner at (m0, n0); A, B,
 // C (and C32) point at the tile's batch entry.
-template <typename T, bool AC, bool BC, int WM, int WN, int BK, bool M3, typename GT = T>
+// MIR: row r >= 1 of C is also written, conjugated, r rows before C's first
+// row (C(-omega) = C(omega)* for a C whose rows are omega_r on a symmetric
+// mesh starting at omega = 0).
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, bool M3, typename GT = T, bool MIR = false>
 __device__ __forceinline__ void gemm_tile(int M, int N, int K, T alpha, const GT *__restrict__ A, int64_t lda,
                                           const GT *B, int64_t ldb, T beta, GT *C, int64_t ldc, int add_eye,
                                           float *C32, int m0, int n0) {
@@ -278,6 +281,13 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, T alpha, const GT
                     if (add_eye && row == col) vr += T(1);
                     pc[0] = vr;
                     if constexpr (CC) pc[1] = vi;
+                    if constexpr (MIR) {
+                        if (row >= 1) {
+                            GT *pm = C + (col - (int64_t)row * ldc) * ec;
+                            pm[0] = vr;
+                            pm[1] = -vi;
+                        }
+                    }
                     if (C32) {
                         float *q = C32 + ((int64_t)row * ldc + col) * 2;
                         q[0] = (float)vr;
@@ -287,30 +297,37 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, T alpha, const GT
             }
 }
 
-template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, bool XR, bool M3 = false>
+// XR: tile order.  0: as launched; 1 and 2: workgroups are dealt to the
+// eight XCDs in turn, each with its own L2, so each XCD gets a contiguous
+// range of tiles, row band by row band (1: tiles sharing an A row band share
+// that XCD's L2) or column band by column band (2: tiles sharing a B column
+// band do, for products whose B is much larger than A).
+template <typename T, bool AC, bool BC, int WM, int WN, int BK, int OCC, int XR, bool M3 = false, bool MIR = false>
 __global__ __launch_bounds__(256, OCC) void k_gemm(int M, int N, int K, T alpha, const T *__restrict__ A, int64_t lda,
                                                  int64_t sA, const T *B, int64_t ldb, int64_t sB, T beta,
                                                  T *C, int64_t ldc, int64_t sC, int add_eye, float *C32,
                                                  int64_t sC32) {
     constexpr int ea = AC ? 2 : 1, eb = BC ? 2 : 1, ec = (AC || BC) ? 2 : 1;
     int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    if constexpr (XR) {
-        // workgroups are dealt to the eight XCDs in turn, each with its own
-        // L2: give each XCD a contiguous range of tiles (x fastest), so that
-        // tiles sharing an A row band share that XCD's L2
+    if constexpr (XR != 0) {
         const int gx = gridDim.x, gy = gridDim.y;
         const int64_t nt = (int64_t)gx * gy * gridDim.z, l = bx + (int64_t)gx * (by + (int64_t)gy * bz);
         const int64_t n8 = nt / 8, t = l < 8 * n8 ? (l % 8) * n8 + l / 8 : l;
-        bx = (int)(t % gx);
-        by = (int)((t / gx) % gy);
+        if constexpr (XR == 1) {
+            bx = (int)(t % gx);
+            by = (int)((t / gx) % gy);
+        } else {
+            by = (int)(t % gy);
+            bx = (int)((t / gy) % gx);
+        }
         bz = (int)(t / ((int64_t)gx * gy));
     }
     A += (int64_t)bz * sA * ea;
     B += (int64_t)bz * sB * eb;
     C += (int64_t)bz * sC * ec;
     if (C32) C32 += (int64_t)bz * sC32 * 2;
-    gemm_tile<T, AC, BC, WM, WN, BK, M3>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, add_eye, C32, by * 32 * WM,
-                                         bx * 32 * WN);
+    gemm_tile<T, AC, BC, WM, WN, BK, M3, T, MIR>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, add_eye, C32,
+                                                 by * 32 * WM, bx * 32 * WN);
 }
 
 // Tile t of a multi-product launch: its item (searched from item a up; the
@@ -680,6 +697,29 @@ hipError_t launch_zgemm_lu(hipStream_t st, int M, int N, int K, double alpha, co
                            int64_t sC, int batch) {
     return launch_gemm_t<double, true, true, true>(st, M, N, K, alpha, (const double *)A, lda, sA, (const double *)B,
                                                    ldb, sB, beta, (double *)C, ldc, sC, batch);
+}
+
+// C = alpha A B (beta = 0) for complex A (M x K, small) times real B (K x N,
+// N large), tiles ordered column band by column band so each slice of B is
+// read from HBM once: the Cauchy transform of the spectral bins on the
+// A route (M frequencies, N matrix entries, K bins).  mirror: row r >= 1 is
+// also written, conjugated, at row -r (C's rows are the mesh points from
+// omega = 0 up; the rows before C are those of -omega).
+hipError_t launch_zdgemm_wide(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda,
+                              const double *B, int64_t ldb, zdbl *C, int64_t ldc, bool mirror) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    ProfScope ps(st, "cauchy_gemm", 4.0 * M * (double)N * K,
+                 8.0 * (double)K * N + 16.0 * (double)(mirror ? 2 * M - 1 : M) * N);
+    const dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
+    if (mirror)
+        hipLaunchKernelGGL((k_gemm<double, true, false, 2, 2, 16, 2, 2, false, true>), grid, dim3(256), 0, st, M, N, K,
+                           alpha, (const double *)A, lda, (int64_t)0, B, ldb, (int64_t)0, 0.0, (double *)C, ldc,
+                           (int64_t)0, 0, (float *)nullptr, (int64_t)0);
+    else
+        hipLaunchKernelGGL((k_gemm<double, true, false, 2, 2, 16, 2, 2>), grid, dim3(256), 0, st, M, N, K, alpha,
+                           (const double *)A, lda, (int64_t)0, B, ldb, (int64_t)0, 0.0, (double *)C, ldc, (int64_t)0,
+                           0, (float *)nullptr, (int64_t)0);
+    return hipGetLastError();
 }
 
 // Complex-float products of the calling thread run as split-BF16 MFMA when set

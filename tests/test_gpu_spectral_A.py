@@ -70,12 +70,21 @@ def _ragged_chain():
                              bond_cutoff=None)
 
 
+@pytest.mark.parametrize("transform", ["product", "fft"])
 @pytest.mark.parametrize("case", ["tiny_chain", "chain8_ragged"])
-def test_A_matches_oracle(gpu, case):
+def test_A_matches_oracle(gpu, case, transform, monkeypatch):
+    """A at every mesh point against the oracle, with the Cauchy transform of
+    v a0 as one matrix product over the solved half (the lone point j = 0 on
+    its own, the other half written as the conjugate mirror) or as the FFT
+    convolution (GW_A_TRANSFORM=fft)."""
     gw, ctx, torch = gpu
+    if transform == "fft":
+        monkeypatch.setenv("GW_A_TRANSFORM", "fft")
+    else:
+        monkeypatch.delenv("GW_A_TRANSFORM", raising=False)
     mol = gs.make_config(0) if case == "tiny_chain" else _ragged_chain()
     grid = gs.config_grid(0)
-    _say("A route", case, "n_prod", mol.n_prod, "n_omega", grid.n_omega)
+    _say("A route", case, transform, "n_prod", mol.n_prod, "n_omega", grid.n_omega)
     chi, nhb, s = _oracle_chi(mol, grid)
     dm, A, rep = _gpu_A(gw, ctx, torch, mol, grid)
     assert rep.n_hbins == nhb and rep.frac_bits_used == s
@@ -205,15 +214,21 @@ def test_A_route_multi_tile_medium(gpu, prec, tol):
     assert e < (1e-12 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("transform", ["product", "fft"])
 @pytest.mark.parametrize("n_omega", [128, 512])
-def test_A_route_other_fft_lengths(gpu, n_omega):
-    """The FFT lengths 256 and 1024 (the 128- and 512-point meshes over the
-    same window; the cases above take 512 and 2048): A and the FP64 W at
-    every frequency against the oracle, on the ragged 136-product chain."""
+def test_A_route_other_fft_lengths(gpu, n_omega, transform, monkeypatch):
+    """The 128- and 512-point meshes over the same window (FFT lengths 256
+    and 1024; the cases above take 512 and 2048): A and the FP64 W at every
+    frequency against the oracle, on the ragged 136-product chain, with
+    either form of the Cauchy transform."""
     gw, ctx, torch = gpu
+    if transform == "fft":
+        monkeypatch.setenv("GW_A_TRANSFORM", "fft")
+    else:
+        monkeypatch.delenv("GW_A_TRANSFORM", raising=False)
     mol = _ragged_chain()
     grid = gs.Grid(n_omega, -4.0, 4.0, 0.05)
-    _say("A route, n_omega", n_omega)
+    _say("A route, n_omega", n_omega, transform)
     chi, nhb, s = _oracle_chi(mol, grid)
     dm, A, rep = _gpu_A(gw, ctx, torch, mol, grid)
     assert rep.n_hbins == nhb and rep.frac_bits_used == s
