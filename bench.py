@@ -689,6 +689,7 @@ def run_c3(args, gw, gs, torch):
         flops = 0.0
         worst_fb = 0
         start, gi, n_groups = 0, 0, 0
+        rec = {"mode": None, "steps": 0, "launches": 0, "products": 0}
         while start < len(mols):
             grp = next_group(start)
             start = grp[-1] + 1
@@ -702,6 +703,11 @@ def run_c3(args, gw, gs, torch):
                                  tol=1e-6, n_refine=2, stream=stream)
             torch.cuda.synchronize()
             tc = time.perf_counter() - t0
+            st = b.stats()
+            rec["mode"] = {0: "molecules on parallel branches", 1: "lock steps (aligned at the end)",
+                           2: "lock steps (aligned at the start)"}[st["mode"]]
+            for k in ("steps", "launches", "products"):
+                rec[k] += st[k]
             t0 = time.perf_counter()
             reps = b.run(stream=stream)
             torch.cuda.synchronize()
@@ -721,10 +727,12 @@ def run_c3(args, gw, gs, torch):
             gi += 1
         res[form] = {"t_replay_s": t_run, "t_create_s": t_create, "W_per_s": len(mols) * N / t_run,
                      "solves_per_s": solves / t_run, "W_per_s_incl_create": len(mols) * N / (t_run + t_create),
-                     "solve_TFLOPs": flops / t_run / 1e12, "fp64_fallbacks": worst_fb, "groups": n_groups}
+                     "solve_TFLOPs": flops / t_run / 1e12, "fp64_fallbacks": worst_fb, "groups": n_groups,
+                     "recording": rec}
     best = max(res, key=lambda f: res[f]["W_per_s"])
     r = res[best]
-    out = base_record(args, "W(omega)/s, %d chain molecules batched in recorded hipGraphs, 512 points" % len(mols),
+    out = base_record(args, "W(omega)/s, %d chain molecules batched (solves in lock steps) in recorded hipGraphs, "
+                            "512 points" % len(mols),
                       r["W_per_s"], "W(omega)/s", r["t_replay_s"], "f64" if best == "fp64" else "f32+f64",
                       {"workload": "batch%d_chains_8to80_nomega512" % len(mols), "molecules": len(mols),
                        "n_prod_min": min(m.n_prod for m in mols), "n_prod_max": max(m.n_prod for m in mols),

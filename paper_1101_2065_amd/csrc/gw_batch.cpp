@@ -207,9 +207,18 @@ gw_status record(gw_batch *b) {
     // lock-stepped molecules all solve at once: a workspace each
     std::vector<gwp::BuildPlan> bp(b->n_mol);
     std::vector<gwp::SolvePlan> sp(b->n_mol);
-    // the per-molecule workspaces of an earlier lock-step batch (sized for
-    // its molecule count) would otherwise stay beside the new ones
-    if (lock) gwp::ws_release(ctx, "bl");
+    // per-molecule workspaces of earlier lock-step batches are reused where
+    // they fit; they are released first when keeping them beside this
+    // batch's could take more than half the budget (a batch of many small
+    // molecules after one of a few large ones would otherwise keep both)
+    if (lock) {
+        size_t held = 0, need = 0;
+        for (auto &kv : ctx->bufs)
+            if (kv.first.compare(0, 2, "bl") == 0) held += kv.second.bytes;
+        for (int i = 0; i < b->n_mol; ++i)
+            need += gwk_solve_ws_bytes(b->n[i], b->g.n_omega, mixed, ctx->budget / b->n_mol);
+        if (held + need > ctx->budget / 2) gwp::ws_release(ctx, "bl");
+    }
     for (int pass = 0; pass < 2; ++pass) {
         for (int i = 0; i < b->n_mol; ++i) {
             gw_status s = gwp::build_plan(ctx, &b->mols[i], &b->g, nullptr, 0, st, "bb", nullptr, &bp[i]);
