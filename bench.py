@@ -879,7 +879,7 @@ def run_c4(args, gw, gs, torch):
 
 # ---------------------------------------------------------------------- profiles
 # Kernel whose HBM traffic the roofline reports, and the source it is built from.
-TRAFFIC_KERNEL = "k_gemm<double, true, true, 2, 1, 8, 5, true, true>"
+TRAFFIC_KERNEL = "k_gemm<double, true, true, 2, 1, 8, 5, 1, true, false>"
 TRAFFIC_CLASS = "zgemm3m_64x32"  # the same kernel in the library's live timing
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "hbm_traffic.json")
 COPY_BYTES = 1 << 30

@@ -78,9 +78,12 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, T alpha, const GT
     constexpr int EB = BK * BN / 256, TPRB = BN / EB;  // (B)
     static_assert(EA >= 1 && EB >= 1 && TPRA >= 1 && TPRB >= 1, "tile too small");
     typedef typename Mfma<T>::v4 v4;
-    // the 64x64 tile pads the transposed A rows (its stores would otherwise
-    // hit one bank group) and gives each thread B columns TPRB apart
-    constexpr int PA = (BK == 16) ? 1 : 0;
+    // the transposed A rows are padded by one value: unpadded, the K rows of
+    // the tile are a multiple of the LDS bank span apart, so the stores of a
+    // wave (several K rows of few tile rows) pile onto the same banks (3x the
+    // bank-conflict cycles at 64x32); the 64x64 tile also gives each thread B
+    // columns TPRB apart
+    constexpr int PA = 1;
     constexpr int SB = (BK == 16) ? TPRB : 1;
     // complex operands are staged interleaved {re, im}: one 16-byte LDS read
     // per operand value instead of two 8-byte ones
