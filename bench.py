@@ -383,6 +383,9 @@ def run_c2(args, gw, gs, torch):
     sample_js = [0, N // 2, N // 2 + 60, N // 2 + 200, N - 1, 400]
     res, X_ref = {}, None
     for form in forms:
+        # "<precision>_A": A = 1 - S chi_hat formed from S a0_hat (gw_build_A_compressed), X from A
+        route_a = form.endswith("_A")
+        base = form[:-2] if route_a else form
         ts = []
         for it in range(args.warmup + args.steps):
             torch.cuda.synchronize()
@@ -391,9 +394,15 @@ def run_c2(args, gw, gs, torch):
             ev[0].record(stream)
             ctx.compress_basis(dm.v, n, k, Q, S, stream=stream)
             ev[1].record(stream)
-            ctx.build_chi0(dm.struct, g, chi, basis=Q, k=k, stream=stream, report=False)
+            if route_a:  # chi holds A
+                ctx.build_A_compressed(dm.struct, S, Q, k, g, chi, stream=stream, report=False)
+            else:
+                ctx.build_chi0(dm.struct, g, chi, basis=Q, k=k, stream=stream, report=False)
             ev[2].record(stream)
-            rep = ctx.solve_W(S, k, chi, N, X, prec=FORMS[form], tol=1e-7, stream=stream)
+            if route_a:
+                rep = ctx.solve_W_A(S, k, chi, N, X, prec=FORMS[base], tol=1e-7, stream=stream)
+            else:
+                rep = ctx.solve_W(S, k, chi, N, X, prec=FORMS[base], tol=1e-7, stream=stream)
             ev[3].record(stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
@@ -416,12 +425,13 @@ def run_c2(args, gw, gs, torch):
     best = min(ok, key=lambda f: ok[f]["t_step"])
     r = res[best]
     out = base_record(args, "W(omega)/s, 120-atom cluster, top-1500 compressed, 2048 points", N / r["t_step"],
-                      "W(omega)/s", r["t_step"], "f64" if best == "fp64" else "f32+f64",
+                      "W(omega)/s", r["t_step"], "f64" if best.startswith("fp64") else "f32+f64",
                       {"workload": "cluster120_k1500_nomega2048", "n_prod": n, "k": k, "n_omega": N,
                        "n_pairs": mol.n_pairs, "form": best, "parallelism": "none (1 GPU)"})
     out["forms"] = {}
     for f, v in res.items():
-        ach, pk = solve_roofline(k, N // 2 + 1, v["t_solve"], v["max_iter"], f != "fp64")
+        ach, pk = solve_roofline(k, N // 2 + 1, v["t_solve"], v["max_iter"], not f.startswith("fp64"),
+                                 form_a=not f.endswith("_A"))
         out["forms"][f] = dict(v, W_per_s=N / v["t_step"], solve_TFLOPs=ach, solve_roofline_frac=ach / pk)
     ctx.close()
     return out
@@ -1089,7 +1099,7 @@ def main():
                       "n2000_time": "fp64",
                       "n2000_sigma": "fp64",
                       "c1": "fp64,fp64_A,bf16x_ir",
-                      "c2": "fp64,bf16x_ir",
+                      "c2": "fp64,fp64_A,bf16x_ir,bf16x_ir_A",
                       "c2pair": "fp64", "c3": "fp64", "c4": "fp64"}[args.workload]
 
     import torch

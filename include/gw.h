@@ -212,10 +212,11 @@ gw_status gw_build_chi0_time(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g
 
 /* The time-domain route of gw_build_chi0_time for a0, then A(omega_j) =
  * 1 - v chi0(omega_j) as in gw_build_A: each bin of the floating-point a0 is
- * multiplied by v once and the FFT Cauchy transform of v a0 is written as
- * 1 - result (Section 5.A eq. chi_by_spectra, Section 8.A eq.
+ * multiplied by v once and the Cauchy transform of v a0 is written as
+ * 1 - result, as in gw_build_A (Section 5.A eq. chi_by_spectra, Section 8.A eq.
  * sf-of-response-time, Section 2 eq. Coulombscreening).
- *   m, g, a_out, rep: as for gw_build_chi0_time, with 128 <= n_omega <= 1024.
+ *   m, g, a_out, rep: as for gw_build_chi0_time (with GW_A_TRANSFORM=fft,
+ *      128 <= n_omega <= 1024).
  *   v: DEVICE double [n_prod][n_prod], the symmetric Coulomb metric.
  *   A_out: DEVICE complex128 [n_omega][n_prod][n_prod], every entry written.
  * Workspace: as gw_build_chi0_time plus that of gw_build_A.  Errors:
@@ -309,25 +310,43 @@ gw_status gw_solve_W(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t n,
 /* Steps 3-4 fused at the front: A(omega_j) = 1 - v chi0(omega_j) for every
  * mesh point, straight from the molecule, without forming chi0.  chi0 is the
  * Cauchy transform of the spectral function a0 (Section 5.A eq.
- * chi_by_spectra, evaluated by FFT as in Section 5.A), and the transform is
- * linear, so v chi0 is the transform of v a0: the exact histogram is built as
- * for gw_build_chi0 (bin m integrated, integers times 2^-s), each bin is
- * multiplied by v once (n_hbins - 1 real products of size n), and the FFT
- * convolution runs on all n^2 entries of v a0.  Equal to forming
- * 1 - v chi0 from gw_build_chi0's output up to rounding order.
+ * chi_by_spectra), and the transform is linear, so v chi0 is the transform of
+ * v a0: the exact histogram is built as for gw_build_chi0 (bin m integrated,
+ * integers times 2^-s), each bin is multiplied by v once (n_hbins - 1 real
+ * products of size n), and the transform of all n^2 entries of v a0 is one
+ * complex-times-real matrix product with the Cauchy kernel matrix
+ * T[j][q] = 1/(omega_j - q domega + i eps) - 1/(omega_j + q domega + i eps)
+ * over the mesh points j = 0 and j >= n_omega/2; the other points are
+ * written as A(-omega) = A(omega)* (v real).  GW_A_TRANSFORM=fft takes the
+ * FFT convolution of Section 8.A instead (then 128 <= n_omega <= 1024).
+ * Equal to forming 1 - v chi0 from gw_build_chi0's output up to rounding
+ * order.
  *   m: as for gw_build_chi0 (no compression basis).
  *   v: DEVICE double [n_prod][n_prod], the symmetric Coulomb metric.
- *   g: as for gw_build_chi0, with 128 <= n_omega <= 1024.
+ *   g: as for gw_build_chi0.
  *   A_out: DEVICE complex128 [n_omega][n_prod][n_prod], every entry written
  *      (A is not symmetric).
  *   rep: HOST or NULL; as for gw_build_chi0.
  * Workspace beyond gw_build_chi0's: the products v a0 of every bin
- * (8 n_hbins n_prod^2 bytes) and the dense bins of one chunk (at most 2 GiB,
- * at least one bin).
- * Errors: GW_E_INVALID (also for n_omega outside the range above),
+ * (8 n_hbins n_prod^2 bytes), the dense bins of one chunk (at most 2 GiB, at
+ * least one bin) and the kernel matrix (16 (n_omega/2 + 1) n_hbins bytes).
+ * Errors: GW_E_INVALID (also for a mesh outside the FFT form's range),
  * GW_E_OOM, GW_E_DEVICE. */
 gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g,
                      void *stream, void *A_out, gw_report *rep);
+
+/* gw_build_A for the compressed response (Sections 7.B and 8.A): the pair
+ * vectors projected onto the basis before the histogram, as gw_build_chi0
+ * with basis and k does, and A = 1 - S chi_hat with S = Q^T v Q
+ * (gw_compress_basis's outputs); gw_solve_W_A with v = S then gives the
+ * compressed X(omega) = (1 - S chi_hat)^{-1} S, for gw_decompress.
+ *   S: DEVICE double [k][k]; basis: DEVICE double [n_prod][k]; k >= 1.
+ *   A_out: DEVICE complex128 [n_omega][k][k], every entry written.
+ *   m, g, rep: as for gw_build_A.
+ * Workspace: as gw_build_A with k in place of n_prod, plus gw_build_chi0's
+ * projection of the pair vectors.  Errors: as for gw_build_A. */
+gw_status gw_build_A_compressed(gw_ctx *ctx, const gw_molecule *m, const double *S, const double *basis,
+                                int32_t k, const gw_grid *g, void *stream, void *A_out, gw_report *rep);
 
 /* Step 4 from A = 1 - v chi0 (gw_build_A's output) instead of chi0:
  * W(omega_j) = A(omega_j)^{-1} v (Section 2 eq. Coulombscreening), with the

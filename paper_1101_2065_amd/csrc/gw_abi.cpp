@@ -453,6 +453,13 @@ gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st) {
     return GW_OK;
 }
 
+bool a_transform_fft() {
+    const char *tr = std::getenv("GW_A_TRANSFORM");
+    return tr && std::string(tr) == "fft";
+}
+
+bool a_mesh_ok(int n_omega) { return !a_transform_fft() || (n_omega >= 128 && n_omega <= 1024); }
+
 gw_status a_route_ws(gw_ctx *c, const std::string &pre, int n, int nhb, int n_omega, ARouteWs *w) {
     const size_t nn = (size_t)n * n;
     // dense bins staged at most 2 GiB at a time (at least one bin)
@@ -480,8 +487,7 @@ gw_status a_from_bins_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, i
         else GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, a_f64, n_upper, w.D));
         GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
     }
-    const char *tr = std::getenv("GW_A_TRANSFORM");
-    if (tr && std::string(tr) == "fft") GW_HIP(ctx, gwk::launch_fftconv_A(st, n, n_omega, nhb, w.B, Kt, tw, (zdbl *)A_out));
+    if (a_transform_fft()) GW_HIP(ctx, gwk::launch_fftconv_A(st, n, n_omega, nhb, w.B, Kt, tw, (zdbl *)A_out));
     else GW_HIP(ctx, gwk::launch_cauchy_A(st, n, n_omega, nhb, j0, domega, eps, w.B, w.T, (zdbl *)A_out));
     return GW_OK;
 }
@@ -491,7 +497,7 @@ gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const
     gw_status s = build_hist_enqueue(ctx, p, st);
     if (s != GW_OK) return s;
     if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
-    return a_from_bins_enqueue(ctx, st, p.n_prod, p.g.n_omega, p.nhb, p.H, p.sdev, nullptr, v, w, p.Kt, p.tw, p.j0,
+    return a_from_bins_enqueue(ctx, st, p.rows, p.g.n_omega, p.nhb, p.H, p.sdev, nullptr, v, w, p.Kt, p.tw, p.j0,
                                p.dom, p.g.eps, A_out);
 }
 
@@ -873,8 +879,8 @@ static gw_status build_time_impl(gw_ctx *ctx, const gw_molecule *m, const double
     int kbits = 0;
     gw_status s = check_grid(ctx, g, &kbits);
     if (s != GW_OK) return s;
-    if (v && (g->n_omega < 128 || g->n_omega > 1024))
-        return fail(ctx, GW_E_INVALID, "gw_build_A_time needs n_omega in [128, 1024]");
+    if (v && !gwp::a_mesh_ok(g->n_omega))
+        return fail(ctx, GW_E_INVALID, "gw_build_A_time with GW_A_TRANSFORM=fft needs n_omega in [128, 1024]");
     HostMol h;
     s = check_molecule(ctx, m, st, &h);
     if (s != GW_OK) return s;
@@ -1323,20 +1329,21 @@ gw_status gw_solve_W_A(gw_ctx *ctx, const double *v, int32_t v_is_diag, int32_t 
     return solve_W_impl(ctx, v, v_is_diag, n, nullptr, (zdbl *)A, n_omega, prec, tol, stream, W_out, rep);
 }
 
-gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, void *stream,
-                     void *A_out, gw_report *rep) {
+// The A route for gw_build_A (basis = NULL) and gw_build_A_compressed.
+static gw_status build_A_impl(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, const double *basis,
+                       int32_t k, void *stream, void *A_out, gw_report *rep) {
     if (!ctx) return GW_E_INVALID;
     if (ctx->sticky) return fail(ctx, GW_E_DEVICE, "context has a sticky device error: " + ctx->err);
     GW_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = as_stream(stream);
     if (!v || !A_out || !g) return fail(ctx, GW_E_INVALID, "NULL pointer argument");
-    if (g->n_omega < 128 || g->n_omega > 1024)
-        return fail(ctx, GW_E_INVALID, "gw_build_A needs n_omega in [128, 1024]");
+    if (!gwp::a_mesh_ok(g->n_omega))
+        return fail(ctx, GW_E_INVALID, "the A route with GW_A_TRANSFORM=fft needs n_omega in [128, 1024]");
     gwp::BuildPlan p;
-    gw_status s = gwp::build_plan(ctx, m, g, nullptr, 0, st, "", nullptr, &p);
+    gw_status s = gwp::build_plan(ctx, m, g, basis, k, st, "", nullptr, &p);
     if (s != GW_OK) return s;
     gwp::ARouteWs aw;
-    if ((s = gwp::a_route_ws(ctx, "", p.n_prod, p.nhb, g->n_omega, &aw)) != GW_OK) return s;
+    if ((s = gwp::a_route_ws(ctx, "", p.rows, p.nhb, g->n_omega, &aw)) != GW_OK) return s;
     const bool kspec = ctx->ks_n != g->n_omega || ctx->ks_min != g->omega_min || ctx->ks_d != p.dom ||
                        ctx->ks_eps != g->eps;
     if ((s = gwp::a_route_enqueue(ctx, p, st, v, aw, kspec, A_out)) != GW_OK) return s;
@@ -1359,6 +1366,18 @@ gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const g
     }
     return GW_OK;
 }
+
+gw_status gw_build_A(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw_grid *g, void *stream,
+                     void *A_out, gw_report *rep) {
+    return build_A_impl(ctx, m, v, g, nullptr, 0, stream, A_out, rep);
+}
+
+gw_status gw_build_A_compressed(gw_ctx *ctx, const gw_molecule *m, const double *S, const double *basis, int32_t k,
+                                const gw_grid *g, void *stream, void *A_out, gw_report *rep) {
+    if (ctx && (!basis || k < 1)) return fail(ctx, GW_E_INVALID, "gw_build_A_compressed needs a basis and k >= 1");
+    return build_A_impl(ctx, m, S, g, basis, k, stream, A_out, rep);
+}
+
 
 gw_status gw_compress_basis(gw_ctx *ctx, const double *v, int32_t n, int32_t k, void *stream, double *Q_out,
                             double *S_out) {

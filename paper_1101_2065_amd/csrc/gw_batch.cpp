@@ -237,7 +237,7 @@ gw_status record(gw_batch *b) {
     // another on the capture stream, so they share one workspace
     std::vector<char> route_a(b->n_mol, 0);
     std::vector<gwp::ARouteWs> aw(b->n_mol);
-    const bool mesh_a = b->g.n_omega >= 128 && b->g.n_omega <= 1024;
+    const bool mesh_a = gwp::a_mesh_ok(b->g.n_omega);
     for (int pass = 0; pass < 2; ++pass)
         for (int i = 0; i < b->n_mol; ++i) {
             route_a[i] = mesh_a && b->W[i] == b->chi0[i];

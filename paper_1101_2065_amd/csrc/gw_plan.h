@@ -75,6 +75,10 @@ struct ARouteWs {
     zdbl *T = nullptr;
     int dchunk = 1;
 };
+// GW_A_TRANSFORM=fft: the A route's transform by FFT convolution (meshes of
+// 128 to 1024 points) instead of the matrix product (any mesh).
+bool a_transform_fft();
+bool a_mesh_ok(int n_omega);
 // Workspace of the route for n products, nhb bins and n_omega mesh points
 // (named `prefix`aD/aB/aT; grow-only, so a run of calls leaves buffers that
 // fit the largest).

@@ -94,6 +94,8 @@ _SIGS = {
                                             ctypes.POINTER(gw_report)]),
     "gw_build_A": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.POINTER(gw_grid), _P, _P,
                                   ctypes.POINTER(gw_report)]),
+    "gw_build_A_compressed": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, _P, ctypes.c_int32,
+                                             ctypes.POINTER(gw_grid), _P, _P, ctypes.POINTER(gw_report)]),
     "gw_compress_basis": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "gw_decompress": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P]),
     "gw_pair_basis": (ctypes.c_int, [_P, ctypes.POINTER(gw_molecule), _P, ctypes.c_double, ctypes.c_int32, _P, _P,
@@ -247,6 +249,15 @@ class Context:
         st = lib.gw_build_A(self.h, ctypes.byref(mol), _ptr(v), ctypes.byref(grid), _stream_handle(stream),
                             _ptr(A_out), ctypes.byref(rep) if rep is not None else None)
         self._check(st, "gw_build_A")
+        return rep
+
+    def build_A_compressed(self, mol: "gw_molecule", S, basis, k: int, grid: "gw_grid", A_out, stream=None,
+                           report: bool = True):
+        rep = gw_report() if report else None
+        st = lib.gw_build_A_compressed(self.h, ctypes.byref(mol), _ptr(S), _ptr(basis), k, ctypes.byref(grid),
+                                       _stream_handle(stream), _ptr(A_out),
+                                       ctypes.byref(rep) if rep is not None else None)
+        self._check(st, "gw_build_A_compressed")
         return rep
 
     def solve_W_A(self, v, n: int, A, n_omega: int, W_out, prec: int = GW_FP64, tol: float = 1e-7,

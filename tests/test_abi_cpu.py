@@ -75,6 +75,7 @@ def test_create_without_gpu_reports_device_error():
     assert gw.lib.gw_last_error(None) == b"NULL context"
     # the A route's entry points reject a NULL context before touching anything
     assert gw.lib.gw_build_A(None, None, None, None, None, None, None) == gw.GW_E_INVALID
+    assert gw.lib.gw_build_A_compressed(None, None, None, None, 0, None, None, None, None) == gw.GW_E_INVALID
     assert gw.lib.gw_build_A_time(None, None, None, None, None, None, None, None) == gw.GW_E_INVALID
     assert gw.lib.gw_solve_W_A(None, None, 0, 1, None, 2, 0, 1e-7, None, None, None) == gw.GW_E_INVALID
     assert gw.lib.gw_solve_W_A_noalloc(None, None, 0, 1, None, 2, None, None, None) == gw.GW_E_INVALID

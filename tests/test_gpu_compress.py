@@ -188,3 +188,52 @@ def test_pair_basis_errors(gpu):
     with pytest.raises(gw.GwError) as e:
         ctx.pair_basis(dm.struct, dm.v, 10.0, k + 5, Z, U)
     assert e.value.status == gw.GW_E_NOCONV
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x_ir", 1e-6)])
+def test_compressed_A_route(gpu, prec, tol):
+    """gw_build_A_compressed (A = 1 - S chi_hat from S a0_hat, Sections 7.B
+    and 8.A) then gw_solve_W_A with S: X equals the compressed chi0 route's
+    X, and the decompressed W the oracle's top-k form, on the ragged
+    136-product chain (8 atoms and 7 bonds: v has rank 15, so k = 40 keeps
+    its whole range and both equal the full W)."""
+    gw, ctx, torch = gpu
+    mol = gs.chain_molecule(8, 7, orb_per_atom=4, occ_per_atom=2, prod_per_atom=10, prod_per_bond=8,
+                            bond_cutoff=None)
+    grid = gs.config_grid(0)
+    k = 40
+    n, N = mol.n_prod, grid.n_omega
+    dm = gw.DeviceMolecule(mol)
+    Q = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    S = torch.empty((k, k), dtype=torch.float64, device="cuda")
+    ctx.compress_basis(dm.v, n, k, Q, S)
+    g = gw.make_grid(N, grid.omega_min, grid.omega_max, grid.eps)
+    p = {"fp64": gw.GW_FP64, "bf16x_ir": gw.GW_BF16X_IR}[prec]
+    chat = torch.empty((N, k, k), dtype=torch.complex128, device="cuda")
+    ctx.build_chi0(dm.struct, g, chat, basis=Q, k=k)
+    X0 = torch.empty_like(chat)
+    ctx.solve_W(S, k, chat, N, X0, prec=p, tol=1e-9)
+    A = torch.empty_like(chat)
+    rep = ctx.build_A_compressed(dm.struct, S, Q, k, g, A)
+    Sh = S.cpu().numpy()
+    ref_A = np.eye(k)[None] - np.matmul(Sh[None], chat.cpu().numpy())
+    eA = _rel(A.cpu().numpy(), ref_A)
+    X = torch.empty_like(A)
+    ctx.solve_W_A(S, k, A, N, X, prec=p, tol=1e-9)
+    eX = _rel(X.cpu().numpy(), X0.cpu().numpy())
+    _say(prec, "compressed A vs 1 - S chi_hat", eA, "X vs the chi0 route", eX, "n_hbins", rep.n_hbins)
+    assert eA < 1e-12
+    assert eX < tol
+    js = [0, N // 2, N // 2 + 17, N - 1]
+    P = o.pair_vectors(mol)
+    m, fr = o.pair_bins(mol.eig, mol.n_occ, grid.domega)
+    nhb = o.hist_bins(mol.eig, N, grid.domega)
+    s = o.frac_bits(P, mol.n_pairs)
+    H = o.histogram(P, m, fr, s, nhb)
+    chi = o.unpack_upper(o.chi0_from_hist(H, s, N, grid.omega_min, grid.omega_max, grid.eps, js=js), n)
+    for i, j in enumerate(js):
+        W = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+        ctx.decompress(Q, n, k, X[j], W)
+        e = _rel(W.cpu().numpy(), o.screened_W_compressed(mol.v, chi[i], k))
+        _say(prec, "j", j, "W vs oracle", e)
+        assert e < max(tol, 1e-8)

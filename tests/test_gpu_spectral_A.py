@@ -168,15 +168,25 @@ def test_A_route_single_product_closed_form(gpu):
 
 
 @pytest.mark.parametrize("n_omega", [64, 2048])
-def test_A_route_rejects_meshes_out_of_range(gpu, n_omega):
+def test_A_route_other_meshes(gpu, n_omega, monkeypatch):
+    """The matrix-product transform takes any mesh: A at every point of the
+    64- and 2048-point meshes against the oracle on the 64-product chain; the
+    FFT form (periods 256 to 2048) refuses them."""
     gw, ctx, torch = gpu
     mol = gs.make_config(0)
     g0 = gs.config_grid(0)
-    dm = gw.DeviceMolecule(mol)
-    A = torch.empty((1,), dtype=torch.complex128, device="cuda")
-    g = gw.make_grid(n_omega, g0.omega_min, g0.omega_max, g0.eps, -1)
+    grid = gs.Grid(n_omega, g0.omega_min, g0.omega_max, g0.eps)
+    monkeypatch.delenv("GW_A_TRANSFORM", raising=False)
+    chi, nhb, s = _oracle_chi(mol, grid)
+    dm, A, rep = _gpu_A(gw, ctx, torch, mol, grid)
+    assert rep.n_hbins == nhb and rep.frac_bits_used == s
+    ref = np.eye(mol.n_prod)[None] - np.matmul(mol.v[None], chi)
+    e = _rel(A.cpu().numpy(), ref)
+    _say("A route, n_omega", n_omega, "A rel", e)
+    assert e < 1e-12
+    monkeypatch.setenv("GW_A_TRANSFORM", "fft")
     with pytest.raises(gw.GwError) as ei:
-        ctx.build_A(dm.struct, dm.v, g, A)
+        ctx.build_A(dm.struct, dm.v, _grid(gw, grid), A)
     assert ei.value.status == gw.GW_E_INVALID
 
 

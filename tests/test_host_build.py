@@ -86,6 +86,7 @@ DRIVER = r'''
 #include "gw_ctx.h"
 #include "gw_plan.h"
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -145,7 +146,11 @@ int main(int argc, char **argv) {
         CHECK(gw_solve_W(c, mol.v.data(), 0, 0, chi.data(), 64, GW_FP64, 1e-7, nullptr, W.data(), nullptr) == GW_E_INVALID);
         CHECK(gw_solve_W(c, mol.v.data(), 0, 2, chi.data(), 64, (gw_precision)7, 1e-7, nullptr, W.data(), nullptr) == GW_E_INVALID);
         CHECK(gw_solve_W(c, mol.v.data(), 0, 2, chi.data(), 64, GW_FP32_IR, 0.0, nullptr, W.data(), nullptr) == GW_E_INVALID);
-        CHECK(gw_build_A(c, &m, mol.v.data(), &g, nullptr, chi.data(), nullptr) == GW_E_INVALID);  // n_omega < 128
+        setenv("GW_A_TRANSFORM", "fft", 1);  // the FFT form takes 128 to 1024 points only
+        CHECK(gw_build_A(c, &m, mol.v.data(), &g, nullptr, chi.data(), nullptr) == GW_E_INVALID);
+        unsetenv("GW_A_TRANSFORM");
+        CHECK(gw_build_A(c, &m, mol.v.data(), &g, nullptr, chi.data(), nullptr) == GW_OK);
+        CHECK(gw_build_A_compressed(c, &m, mol.v.data(), nullptr, 2, &g, nullptr, chi.data(), nullptr) == GW_E_INVALID);
         CHECK(gw_compress_basis(c, mol.v.data(), 2, 3, nullptr, W.data(), W.data()) == GW_E_INVALID);
         CHECK(gw_decompress(c, mol.v.data(), 2, 0, chi.data(), nullptr, nullptr, W.data()) == GW_E_INVALID);
         // valid calls run through planning and the (stub) launches
