@@ -169,8 +169,9 @@ def test_lock_steps_equal_molecules_on_branches(gpu, prec, monkeypatch):
     as whole molecules on parallel branches: the results are equal bit for
     bit, aligned at the end or at the start, with the products of a step
     handed out by the hardware dispatcher or by the persistent work-queue
-    grid.  The molecules span three panel variants (panels of up to 512, 1024
-    and 2048 rows), in place and through chi0."""
+    grid, and with everything of a step merged and joined step by step.  The
+    molecules span three panel variants (panels of up to 512, 1024 and 2048
+    rows), in place and through chi0."""
     gw, ctx, torch = gpu
     grid = gs.config_grid(0)
     g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
@@ -182,13 +183,23 @@ def test_lock_steps_equal_molecules_on_branches(gpu, prec, monkeypatch):
     p = {"fp64": gw.GW_FP64, "bf16x_ir": gw.GW_BF16X_IR}[prec]
     stream = torch.cuda.current_stream()
     out = {}
-    for mode in ["streams", "lockstep", "lockstep_left", "lockstep_persistent"]:
-        # lockstep_persistent: the products on the persistent work-queue grid
-        monkeypatch.setenv("GW_BATCH_MODE", mode.replace("_persistent", ""))
-        if mode.endswith("_persistent"):
-            monkeypatch.setenv("GW_GEMM_QUEUE", "persistent")
-        else:
-            monkeypatch.delenv("GW_GEMM_QUEUE", raising=False)
+    variants = {
+        "streams": {"GW_BATCH_MODE": "streams"},
+        "lockstep": {"GW_BATCH_MODE": "lockstep"},
+        "lockstep_left": {"GW_BATCH_MODE": "lockstep_left"},
+        # the products on the persistent work-queue grid
+        "lockstep_persistent": {"GW_BATCH_MODE": "lockstep", "GW_GEMM_QUEUE": "persistent"},
+        # every product and panel of a step merged, a join after every step
+        "lockstep_merged": {"GW_BATCH_MODE": "lockstep", "GW_LOCKSTEP_MERGE_WAVES": "1e9",
+                            "GW_LOCKSTEP_MERGE_PANELS": "1", "GW_LOCKSTEP_DEPS": "step"},
+    }
+    knobs = sorted({k for v in variants.values() for k in v})
+    for mode, env in variants.items():
+        for k in knobs:
+            if k in env:
+                monkeypatch.setenv(k, env[k])
+            else:
+                monkeypatch.delenv(k, raising=False)
         chis = [torch.zeros((grid.n_omega, n, n), dtype=torch.complex128, device="cuda") for n in ns]
         Ws = [torch.zeros_like(c) for c in chis]
         Ws[1] = chis[1]  # in place (A route)
@@ -196,7 +207,7 @@ def test_lock_steps_equal_molecules_on_branches(gpu, prec, monkeypatch):
                              n_refine=2, stream=stream)
         st = b.stats()
         _say(prec, mode, st)
-        assert st["mode"] == {"streams": 0, "lockstep": 1, "lockstep_left": 2, "lockstep_persistent": 1}[mode]
+        assert st["mode"] == {"streams": 0, "lockstep_left": 2}.get(mode, 1)
         if mode != "streams":
             # FP64: every complex product is queued; BF16x: the split-BF16
             # trailing updates run as launches of their own in the steps
@@ -208,7 +219,9 @@ def test_lock_steps_equal_molecules_on_branches(gpu, prec, monkeypatch):
         out[mode] = [w.cpu().numpy() for w in Ws]
         b.close()
         del chis, Ws
-    for mode in ["lockstep", "lockstep_left", "lockstep_persistent"]:
+    for mode in variants:
+        if mode == "streams":
+            continue
         for i in range(len(mols)):
             d = np.abs(out[mode][i] - out["streams"][i]).max()
             _say(prec, mode, "molecule", i, "n", ns[i], "largest difference vs branches", d)
