@@ -426,7 +426,7 @@ gw_status build_plan(gw_ctx *ctx, const gw_molecule *m, const gw_grid *g, const 
 }
 
 // a1-a3: pair vectors (projected when a basis is given), bins, exact histogram.
-gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st) {
+gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, bool with_hist) {
     const gw_molecule *m = &p.m;
     if (p.basis) {
         GW_HIP(ctx, gwk::launch_transpose_d(st, p.n_prod, p.k, p.basis, p.bt));
@@ -449,7 +449,9 @@ gw_status build_hist_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st) {
     GW_HIP(ctx, gwk::launch_pair_sort(st, p.n_orb, p.n_occ, m->eig, p.kbits, p.nhb, p.lo, p.rowoff, p.binoff, p.perm,
                                       p.fsort, p.stat));
     GW_HIP(ctx, gwk::launch_gather(st, p.rows, p.n_pairs, Psrc, p.perm, p.stat, p.Ps));
-    GW_HIP(ctx, gwk::launch_hist(st, p.rows, p.n_pairs, p.Ps, p.fsort, p.binoff, p.stat, p.sdev, p.nhb, p.H, p.splits));
+    if (with_hist)
+        GW_HIP(ctx, gwk::launch_hist(st, p.rows, p.n_pairs, p.Ps, p.fsort, p.binoff, p.stat, p.sdev, p.nhb, p.H,
+                                     p.splits));
     return GW_OK;
 }
 
@@ -487,6 +489,11 @@ gw_status a_from_bins_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, i
         else GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, a_f64, n_upper, w.D));
         GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
     }
+    return a_transform_enqueue(ctx, st, n, n_omega, nhb, w, Kt, tw, j0, domega, eps, A_out);
+}
+
+gw_status a_transform_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, int nhb, const ARouteWs &w,
+                              const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out) {
     if (a_transform_fft()) GW_HIP(ctx, gwk::launch_fftconv_A(st, n, n_omega, nhb, w.B, Kt, tw, (zdbl *)A_out));
     else GW_HIP(ctx, gwk::launch_cauchy_A(st, n, n_omega, nhb, j0, domega, eps, w.B, w.T, (zdbl *)A_out));
     return GW_OK;
@@ -494,15 +501,50 @@ gw_status a_from_bins_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, i
 
 gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
                           bool with_kspec, void *A_out) {
-    gw_status s = build_hist_enqueue(ctx, p, st);
+    gw_status s = build_hist_enqueue(ctx, p, st, false);
     if (s != GW_OK) return s;
     if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
-    return a_from_bins_enqueue(ctx, st, p.rows, p.g.n_omega, p.nhb, p.H, p.sdev, nullptr, v, w, p.Kt, p.tw, p.j0,
-                               p.dom, p.g.eps, A_out);
+    // The histogram in chunks of bins on the context's second stream, and the
+    // products v a0 of each chunk's bins on st as soon as those bins are
+    // final (the histogram works on the vector units, the products on the
+    // matrix cores, so the two overlap).  Chunk c adds the pairs whose lower
+    // bin lies in [lo, hi); bin m receives from the pairs of bins m - 1 and
+    // m, so bins [m0, m1) are final once the chunk with hi = m1 is done.  The
+    // integer sums do not depend on their order: H is the same bit for bit.
+    const int n = p.rows, nhb = p.nhb;
+    const int64_t nn = (int64_t)n * n, n_upper = (int64_t)n * (n + 1) / 2;
+    // GW_HIST_CHUNKS chunks (default 4), each at most the staging buffer's bins
+    int want = 4;
+    if (const char *e = std::getenv("GW_HIST_CHUNKS")) want = std::max(1, std::min(64, std::atoi(e)));
+    const int step = nhb > 1 ? std::min(w.dchunk, (nhb - 1 + want - 1) / want) : 1;
+    const int nch = nhb > 1 ? (nhb - 1 + step - 1) / step : 0;
+    if ((s = aux_stream(ctx)) != GW_OK) return s;
+    while ((int)ctx->chunk_ev.size() < nch) {
+        hipEvent_t e;
+        GW_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->chunk_ev.push_back(e);
+    }
+    GW_HIP(ctx, gwk::launch_fill_u64(st, (uint64_t *)p.H, (int64_t)nhb * n_upper, 0ull));
+    GW_HIP(ctx, hipEventRecord(ctx->fork_ev, st));
+    GW_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+    for (int c = 0; c < nch; ++c) {
+        const int m0 = 1 + c * step, m1 = std::min(m0 + step, nhb);
+        GW_HIP(ctx, gwk::launch_hist(ctx->aux, n, p.n_pairs, p.Ps, p.fsort, p.binoff, p.stat, p.sdev, nhb, p.H,
+                                     p.splits, c == 0 ? 0 : m0, c == nch - 1 ? nhb - 1 : m1, false));
+        GW_HIP(ctx, hipEventRecord(ctx->chunk_ev[c], ctx->aux));
+    }
+    for (int c = 0; c < nch; ++c) {
+        const int m0 = 1 + c * step, cnt = std::min(step, nhb - m0);
+        GW_HIP(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[c], 0));
+        GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, p.H, n_upper, p.sdev, w.D));
+        GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));
+    }
+    // st has waited for the last chunk: the second stream is joined
+    return a_transform_enqueue(ctx, st, n, p.g.n_omega, nhb, w, p.Kt, p.tw, p.j0, p.dom, p.g.eps, A_out);
 }
 
 gw_status build_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, void *chi0_out, bool with_kspec) {
-    gw_status s = build_hist_enqueue(ctx, p, st);
+    gw_status s = build_hist_enqueue(ctx, p, st, true);
     if (s != GW_OK) return s;
     if (with_kspec) GW_HIP(ctx, gwk::launch_kspec(st, p.g.n_omega, p.j0, p.dom, p.g.eps, p.Kt, p.tw));
     GW_HIP(ctx, gwk::launch_fftconv(st, p.rows, p.g.n_omega, p.nhb, p.H, p.sdev, p.Kt, p.tw, (zdbl *)chi0_out));
@@ -623,6 +665,7 @@ gw_status gw_destroy(gw_ctx *ctx) {
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    for (hipEvent_t e : ctx->chunk_ev) (void)hipEventDestroy(e);
     for (auto &kv : ctx->bufs)
         if (kv.second.ptr) {
             if (ctx->own_stream) (void)hipFreeAsync(kv.second.ptr, ctx->own_stream);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <vector>
 #include <string>
 
 struct DevBuf {
@@ -34,6 +35,8 @@ struct gw_ctx {
     // the events that fork it from and join it to the caller's stream
     hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    // one event per histogram chunk of the pipelined A route
+    std::vector<hipEvent_t> chunk_ev;
 };
 
 void gwk_ctx_trim(gw_ctx *c);

@@ -152,7 +152,8 @@ hipError_t launch_fill_u32(hipStream_t st, uint32_t *p, int64_t n, uint32_t valu
 // bin_hi < 0 means nhb - 1, i.e. every kept pair.
 hipError_t launch_hist(hipStream_t st, int n, int64_t n_pairs_cap, const double *Ps,
                        const double *fsort, const int32_t *binoff, const int64_t *stat,
-                       const int32_t *s_dev, int nhb, int64_t *H, int splits, int bin_lo = 0, int bin_hi = -1);
+                       const int32_t *s_dev, int nhb, int64_t *H, int splits, int bin_lo = 0, int bin_hi = -1,
+                       bool clear = true);
 
 // Kernel spectrum Kt[q] = DFT of k(r) = 1/((r + j0) domega + i eps) (wrapped) and
 // the twiddle table tw[q] = exp(-2 pi i q / L).

@@ -93,6 +93,9 @@ gw_status a_route_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, const d
 // (omega_j = (j + j0) domega), the rest by the conjugate mirror; with
 // GW_A_TRANSFORM=fft instead the FFT convolution with the Cauchy-kernel
 // spectrum Kt, tw over all mesh points.
+// The transform of the products B of the bins into A (both forms above).
+gw_status a_transform_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const ARouteWs &w,
+                              const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out);
 gw_status a_from_bins_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const int64_t *a_i64,
                               const int32_t *s_dev, const double *a_f64, const double *v, const ARouteWs &w,
                               const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out);

@@ -388,14 +388,17 @@ hipError_t launch_fill_u64(hipStream_t st, uint64_t *p, int64_t n, uint64_t valu
 
 hipError_t launch_hist(hipStream_t st, int n, int64_t n_pairs_cap, const double *Ps, const double *fsort,
                        const int32_t *binoff, const int64_t *stat, const int32_t *s_dev, int nhb, int64_t *H,
-                       int splits, int bin_lo, int bin_hi) {
+                       int splits, int bin_lo, int bin_hi, bool clear) {
     const int64_t n_upper = (int64_t)n * (n + 1) / 2;
     if (bin_hi < 0 || bin_hi > nhb - 1) bin_hi = nhb - 1;
     if (bin_lo < 0 || bin_lo > bin_hi) return hipErrorInvalidValue;
     // only rows [bin_lo, bin_hi] can receive weight; only they are cleared
-    hipError_t e = launch_fill_u64(st, (uint64_t *)H + (int64_t)bin_lo * n_upper,
-                                   (int64_t)(bin_hi - bin_lo + 1) * n_upper, 0);
-    if (e != hipSuccess) return e;
+    // (clear = false: the caller cleared them, and consecutive ranges add up)
+    if (clear) {
+        hipError_t e = launch_fill_u64(st, (uint64_t *)H + (int64_t)bin_lo * n_upper,
+                                       (int64_t)(bin_hi - bin_lo + 1) * n_upper, 0);
+        if (e != hipSuccess) return e;
+    }
     const int ntiles = (n + HT - 1) / HT;
     const int ntp = ntiles * (ntiles + 1) / 2;
     if (splits < 1) splits = 1;

@@ -165,12 +165,42 @@ def test_time_route_A_matches_oracle(gpu, case):
     assert worst < 1e-10
 
 
-def test_time_route_A_rejects_meshes_out_of_range(gpu):
+@pytest.mark.parametrize("n_omega", [64, 2048])
+def test_time_route_A_other_meshes(gpu, n_omega):
+    """The Cauchy transform as a matrix product takes any mesh: A from the
+    time route on 64 and 2048 points against the oracle's a0 and chi0."""
     gw, ctx, torch = gpu
+    g0 = gs.config_grid(0)
+    grid = gs.Grid(n_omega, g0.omega_min, g0.omega_max, g0.eps)
     mol = gs.make_config(0)
+    n = mol.n_prod
+    _say("time route A on", n_omega, "points")
+    dm = gw.DeviceMolecule(mol)
+    A = torch.full((n_omega, n, n), float("nan"), dtype=torch.complex128, device="cuda")
+    ctx.build_A_time(dm.struct, dm.v, _g(gw, grid), A)
+    torch.cuda.synchronize()
+    nhb = o.level_hist_bins(mol.eig, mol.n_occ, n_omega, grid.domega)
+    rho_p, rho_m = o.spectral_densities(mol, grid.domega)
+    ref = o.a0_by_convolution(mol, rho_p, rho_m, nhb)
+    chi_ref = o.unpack_upper(o.chi0_from_spectrum(ref, n_omega, grid.omega_min, grid.omega_max, grid.eps), n)
+    A_ref = np.eye(n)[None] - np.matmul(mol.v[None], chi_ref)
+    e = _rel(A.cpu().numpy(), A_ref)
+    _say("time route A rel", e)
+    assert e < 1e-12
+
+
+def test_time_route_A_fft_transform_rejects_meshes_out_of_range(gpu, monkeypatch):
+    """The FFT form of the transform (GW_A_TRANSFORM=fft) keeps 128..1024
+    points and rejects other meshes before anything is launched.  The output
+    is sized for the full mesh all the same."""
+    gw, ctx, torch = gpu
+    monkeypatch.setenv("GW_A_TRANSFORM", "fft")
+    mol = gs.make_config(0)
+    n = mol.n_prod
     g0 = gs.config_grid(0)
     dm = gw.DeviceMolecule(mol)
-    A = torch.empty((1,), dtype=torch.complex128, device="cuda")
-    with pytest.raises(gw.GwError) as ei:
-        ctx.build_A_time(dm.struct, dm.v, gw.make_grid(64, g0.omega_min, g0.omega_max, g0.eps, -1), A)
-    assert ei.value.status == gw.GW_E_INVALID
+    for n_omega in (64, 2048):
+        A = torch.empty((n_omega, n, n), dtype=torch.complex128, device="cuda")
+        with pytest.raises(gw.GwError) as ei:
+            ctx.build_A_time(dm.struct, dm.v, gw.make_grid(n_omega, g0.omega_min, g0.omega_max, g0.eps, -1), A)
+        assert ei.value.status == gw.GW_E_INVALID
