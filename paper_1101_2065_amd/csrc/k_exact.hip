@@ -210,8 +210,9 @@ __global__ __launch_bounds__(256) void k_hist(int n, int64_t ldp, const double *
                                               unsigned long long *__restrict__ H, int64_t n_upper,
                                               int ntiles, int splits, int bin_lo, int bin_hi) {
 #pragma clang fp contract(off)
-    __shared__ double Pm[HC][HT];
-    __shared__ double Pn[HC][HT];
+    // rows padded by one value: the staging stores walk down a column
+    __shared__ double Pm[HC][HT + 1];
+    __shared__ double Pn[HC][HT + 1];
     __shared__ double wv[HC];
     // decode (ti <= tj) from blockIdx.x, row-major over the upper triangle of tiles
     int t = blockIdx.x;
@@ -223,22 +224,24 @@ __global__ __launch_bounds__(256) void k_hist(int n, int64_t ldp, const double *
     const int tj = ti + t;
     const int mu0 = ti * HT, nu0 = tj * HT;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int64_t n_kept = stat[0];
+    (void)stat;  // the kept-pair count is binoff[nhb - 1]
     const int s = *s_dev;
     const double twos = ldexp(1.0, s);
-    // bin slice [mb, me) of this split
+    // bin slice [mb, me) of this split: only pairs whose lower bin lies in
+    // [bin_lo, bin_hi), cut at bin boundaries into `splits` runs of about
+    // equal length (so a launch over a few bins still fills the grid)
     const int q = blockIdx.y;
     auto first_bin = [&](int64_t target) {
-        int a = 0, b = nhb - 1;  // binoff[nhb-1] = n_kept >= target
+        int a = 0, b = nhb - 1;  // binoff[nhb-1] = the kept pairs >= target
         while (a < b) {
             int mid = (a + b) >> 1;
             if (binoff[mid] >= target) b = mid; else a = mid + 1;
         }
         return a;
     };
-    // only pairs whose lower bin lies in [bin_lo, bin_hi)
-    const int mb = max(bin_lo, (q == 0) ? 0 : first_bin((n_kept * q) / splits));
-    const int me = min(bin_hi, (q == splits - 1) ? nhb - 1 : first_bin((n_kept * (q + 1)) / splits));
+    const int64_t plo = binoff[bin_lo], span = binoff[bin_hi] - plo;
+    const int mb = max(bin_lo, (q == 0) ? bin_lo : first_bin(plo + (span * q) / splits));
+    const int me = min(bin_hi, (q == splits - 1) ? bin_hi : first_bin(plo + (span * (q + 1)) / splits));
     if (mb >= me) return;
 
     uint64_t A[4][4], B[4][4], Bp[4][4];
