@@ -1022,9 +1022,24 @@ def summarize_mfma(counter_csv, out_md):
     print("wrote", out_md)
 
 
-def summarize_trace(stats_csv, out_md):
+TRACE_FORMS = {
+    # form: (step, calls, note, output file)
+    "fp64_A": (PROFILE_STEP, "gw_build_A + gw_solve_W_A",
+               "The histogram's bin ranges run on the context's second stream beside the v a0 products, and the "
+               "lone point j = 0 is factorised there beside the first frequency batch, so those kernels' durations "
+               "include time they share the CUs with each other.", "kernels_fp64A_chain40_n2000.md"),
+    "fp64": ("FP64 step (chi0 build + W solve)", "gw_build_chi0 + gw_solve_W",
+             "The lone point j = 0 is factorised on the context's second stream beside the first frequency batch, "
+             "so the durations of kernels running then include time they share the CUs.",
+             "kernels_fp64_chain40_n2000.md"),
+}
+
+
+def summarize_trace(stats_csv, form=PROFILE_FORM):
     """Kernel table from a rocprofv3 --kernel-trace --stats run of the
-    profiled step (one warm-up step and one timed step)."""
+    profiled step (one warm-up step and one timed step) of one form."""
+    step, calls_text, note, fname = TRACE_FORMS[form]
+    out_md = os.path.join(HERE, "profiles", fname)
     rows = []
     for r in _csv_rows(stats_csv):
         name = r.get("Name") or r.get("KernelName") or ""
@@ -1034,12 +1049,12 @@ def summarize_trace(stats_csv, out_md):
     rows.sort(key=lambda x: -x[2])
     total = sum(x[2] for x in rows) or 1.0
     md = ["# Kernel profile: %s, 40-atom chain truncated to N_prod=2000, "
-          "1024 frequencies" % PROFILE_STEP, "",
+          "1024 frequencies" % step, "",
           "Command (repository root, one MI355X; OUT is any output directory):", "", "```",
           "rocprofv3 --kernel-trace --stats -d $OUT/prof_n2000 -o run --output-format csv -- python3 bench.py "
-          "--forms %s --steps 1 --warmup 1 --no-cpu-baseline --no-serving" % PROFILE_FORM,
-          "python bench.py --summarize-trace $OUT/prof_n2000/run_kernel_stats.csv", "```", "",
-          "Two steps (one warm-up, one timed) of gw_build_A + gw_solve_W_A; all kernels from `run_kernel_stats.csv`:",
+          "--forms %s --steps 1 --warmup 1 --no-cpu-baseline --no-serving" % form,
+          "python bench.py --summarize-trace $OUT/prof_n2000/run_kernel_stats.csv %s" % form, "```", "",
+          "Two steps (one warm-up, one timed) of %s; all kernels from `run_kernel_stats.csv`.  %s" % (calls_text, note),
           "", "| kernel | calls | total ms | avg us | share |", "|---|---:|---:|---:|---:|"]
     for name, calls, tot in rows:
         short = name.replace("(anonymous namespace)::", "")
@@ -1078,14 +1093,15 @@ def main():
                     help="write profiles/hbm_traffic.json from rocprofv3 outputs and exit (no GPU)")
     ap.add_argument("--summarize-mfma", metavar="COUNTER_CSV",
                     help="write profiles/mfma_chain40_n2000.md from a MfmaUtil/MfmaFlopsF64 counter run")
-    ap.add_argument("--summarize-trace", metavar="STATS_CSV",
-                    help="write the kernel table of profiles/kernels_fp64A_chain40_n2000.md and exit (no GPU)")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="STATS_CSV [FORM]",
+                    help="write the kernel table of one form (fp64_A, the default, or fp64) to "
+                         "profiles/kernels_<form>_chain40_n2000.md and exit (no GPU)")
     args = ap.parse_args()
     if args.summarize_mfma:
         summarize_mfma(args.summarize_mfma, os.path.join(HERE, "profiles", "mfma_chain40_n2000.md"))
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, os.path.join(HERE, "profiles", "kernels_fp64A_chain40_n2000.md"))
+        summarize_trace(*args.summarize_trace[:2])
         return
     if args.summarize_counters:
         summarize_profiles(*args.summarize_counters, TRAFFIC_FILE)
