@@ -482,8 +482,12 @@ gw_status gw_batch_destroy(gw_batch *b);
 
 /* Serving (continuous batching).  gw_submit copies nothing: the molecule's
  * DEVICE buffers must stay valid until gw_poll returns GW_OK.  The request is
- * admitted when its estimated HBM footprint fits; its chi0 and W stay on the
- * device, owned by the library, until gw_release.
+ * admitted when its estimated HBM footprint fits; its W (and, compressed, the
+ * basis) stays on the device, owned by the library, until gw_release.  chi0
+ * itself is not kept: A = 1 - v chi0 (compressed: 1 - S chi_hat) is formed
+ * from v a0 in W's buffer (gw_build_A / gw_build_A_compressed) and solved
+ * there in place (gw_solve_W_A); only under GW_A_TRANSFORM=fft, on a mesh
+ * outside 128..1024 points, is chi0 formed in a buffer of its own first.
  *   k_compress: 0 for the full basis, else the rank of the top-k compression
  *   (W_dev then holds X [n_omega][k][k] complex128 followed by Q [n][k]
  *   doubles, W = Q X Q^T).

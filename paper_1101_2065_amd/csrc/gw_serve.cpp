@@ -23,6 +23,7 @@
 #include "../../include/gw.h"
 #include "gw_ctx.h"
 #include "gw_internal.h"
+#include "gw_plan.h"
 
 #include <hip/hip_runtime.h>
 
@@ -49,6 +50,7 @@ struct ServeReq {
     const double *v = nullptr;
     gw_grid grid{};
     int k = 0, kk = 0;
+    bool route_a = true;  // A formed in W's buffer and solved in place (else chi0 first)
     gw_precision prec = GW_FP64;
     double tol = 1e-7;
     size_t bytes_result = 0, bytes_ws = 0, bytes_peak = 0;
@@ -81,12 +83,18 @@ struct GwServe {
 
 namespace {
 
-size_t est_transient(const gw_molecule &m, int k, int n_omega, gw_precision prec, size_t slot_budget) {
+size_t est_transient(const gw_molecule &m, int k, int n_omega, gw_precision prec, size_t slot_budget,
+                     bool route_a) {
     const size_t n_prod = m.n_prod, n_occ = m.n_occ, n_virt = m.n_orb - m.n_occ;
     const size_t n_pairs = n_occ * n_virt;
     const size_t kk = k ? (size_t)k : n_prod;
     const size_t nhb = n_omega / 2;
     size_t b = 0;
+    if (route_a) {
+        b += 8 * nhb * kk * kk;                                        // v a0 per bin
+        b += std::min<size_t>(2ull << 30, 8 * kk * kk * nhb);          // staged dense bins
+        b += 16 * (nhb + 1) * nhb;                                     // Cauchy matrix
+    }
     if (k) {
         const size_t chunk_rows = std::max<size_t>(1, (size_t)(2ull << 30) / (8 * n_prod * n_virt));
         b += 8 * n_prod * std::min(n_occ, chunk_rows) * n_virt;  // pair-vector chunk
@@ -164,20 +172,32 @@ void run_request(gw_ctx *child, hipStream_t st, ServeReq &r, std::mutex *solve_m
         }
     }
     mark(1);
-    if (!hip_ok(gwk_malloc_async((void **)&r.chi, 16 * nn * r.grid.n_omega, st), "chi0")) return;
+    // chi0 is returned to nobody: A = 1 - v chi0 (compressed: 1 - S chi_hat)
+    // is formed from v a0 in W's buffer and solved there in place; only a
+    // mesh the FFT form of the transform cannot take goes through chi0
+    if (!r.route_a && !hip_ok(gwk_malloc_async((void **)&r.chi, 16 * nn * r.grid.n_omega, st), "chi0")) return;
     const size_t res_bytes = 16 * nn * r.grid.n_omega + (r.k ? 8 * n * r.k : 0);
     if (!hip_ok(gwk_malloc_async((void **)&r.res, res_bytes, st), "W")) return;
     mark(2);
     gw_report rb{}, rs{};
-    gw_status s = gw_build_chi0(child, &r.mol, &r.grid, (const double *)r.Q, r.k, st, nullptr, r.chi, &rb);
+    const double *vk = r.k ? (const double *)r.S : r.v;
+    gw_status s;
+    if (!r.route_a)
+        s = gw_build_chi0(child, &r.mol, &r.grid, (const double *)r.Q, r.k, st, nullptr, r.chi, &rb);
+    else if (r.k)
+        s = gw_build_A_compressed(child, &r.mol, vk, (const double *)r.Q, r.k, &r.grid, st, r.res, &rb);
+    else
+        s = gw_build_A(child, &r.mol, r.v, &r.grid, st, r.res, &rb);
     mark(3);
     if (s == GW_OK) {
         // the solve returns after its stream has drained (it reports), so
         // holding the lock across it keeps the solves apart on the device
         std::unique_lock<std::mutex> lk(*solve_mu, std::defer_lock);
         if (!solve_overlap()) lk.lock();
-        s = gw_solve_W(child, r.k ? (const double *)r.S : r.v, 0, r.kk, r.chi, r.grid.n_omega, r.prec, r.tol, st,
-                       r.res, &rs);
+        if (r.route_a)
+            s = gw_solve_W_A(child, vk, 0, r.kk, r.res, r.grid.n_omega, r.prec, r.tol, st, r.res, &rs);
+        else
+            s = gw_solve_W(child, vk, 0, r.kk, r.chi, r.grid.n_omega, r.prec, r.tol, st, r.res, &rs);
     }
     if (s != GW_OK) {
         r.status = s;
@@ -372,9 +392,13 @@ gw_status gw_submit(gw_ctx *ctx, const gw_molecule *m, const double *v, const gw
     r->kk = k_compress ? k_compress : m->n_prod;
     r->prec = prec;
     r->tol = tol;
+    // GW_SERVE_CHI0=1 keeps chi0 in a buffer of its own (the earlier form)
+    const char *ec = std::getenv("GW_SERVE_CHI0");
+    r->route_a = gwp::a_mesh_ok(g->n_omega) && !(ec && *ec && *ec != '0');
     const size_t nn = (size_t)r->kk * r->kk;
-    r->bytes_result = 32 * nn * g->n_omega + (k_compress ? 16ull * m->n_prod * k_compress + 8ull * nn : 0);
-    r->bytes_ws = est_transient(*m, k_compress, g->n_omega, prec, sv->slot_ws_budget);
+    r->bytes_result = (r->route_a ? 16 : 32) * nn * g->n_omega +
+                      (k_compress ? 16ull * m->n_prod * k_compress + 8ull * nn : 0);
+    r->bytes_ws = est_transient(*m, k_compress, g->n_omega, prec, sv->slot_ws_budget, r->route_a);
     r->bytes_peak = r->bytes_result + r->bytes_ws;
     if (r->bytes_peak > sv->budget) {
         ctx->err = "gw_submit: request needs " + std::to_string(r->bytes_peak) + " bytes, more than the budget";

@@ -159,10 +159,12 @@ def test_release_cancels_a_queued_request(gpu):
     grid = gs.config_grid(0)
     g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
     m = gs.chain_molecule(3, 5)  # 152 products
-    # One request keeps 32 * 152^2 * 256 B = 189 MB of results until released
-    # and needs about 300 MB at its peak, so under a 384 MiB budget a second
-    # request cannot be admitted while the first one's results are held.
-    ctx = gw.Context(0, budget_bytes=384 << 20)
+    # One request keeps 16 * 152^2 * 256 B = 95 MB of results (W; A is formed
+    # in its buffer) until released, and the library estimates 145 MB of
+    # workspace for it: 240 MB at its peak, so under a 280 MiB (294 MB)
+    # budget it is admitted, while a second one (95 + 95 + 145 = 335 MB) is
+    # not as long as the first one's results are held.
+    ctx = gw.Context(0, budget_bytes=280 << 20)
     dm = gw.DeviceMolecule(m)
     t1 = ctx.submit(dm.struct, dm.v, g)
     ptr1, _ = _wait(ctx, t1)
