@@ -78,12 +78,15 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, T alpha, const GT
     constexpr int EB = BK * BN / 256, TPRB = BN / EB;  // (B)
     static_assert(EA >= 1 && EB >= 1 && TPRA >= 1 && TPRB >= 1, "tile too small");
     typedef typename Mfma<T>::v4 v4;
-    // the transposed A rows are padded by one value: unpadded, the K rows of
-    // the tile are a multiple of the LDS bank span apart, so the stores of a
-    // wave (several K rows of few tile rows) pile onto the same banks (3x the
-    // bank-conflict cycles at 64x32); the 64x64 tile also gives each thread B
-    // columns TPRB apart
-    constexpr int PA = 1;
+    // in the three-product tile and the Cauchy product's (MIR) the
+    // transposed A rows are padded by one value: unpadded, the K rows of the
+    // tile are a multiple of the LDS bank span apart, so the stores of a wave
+    // (several K rows of few tile rows) pile onto the same banks (3x the
+    // bank-conflict cycles at 64x32; the Cauchy product reads 10% more and
+    // runs 3% slower unpadded).  The other tiles run faster unpadded (the
+    // four-product 128x32 of the FP64 refinement residual lost 9% to the
+    // padding).  The 64x64 tile also gives each thread B columns TPRB apart.
+    constexpr int PA = (M3 || MIR) ? 1 : 0;
     constexpr int SB = (BK == 16) ? TPRB : 1;
     // complex operands are staged interleaved {re, im}: one 16-byte LDS read
     // per operand value instead of two 8-byte ones

@@ -68,8 +68,17 @@ def _workload():
     return grid, mols
 
 
-def test_results_same_alone_and_in_the_mix(gpu):
+@pytest.mark.parametrize("route", ["A", "chi0"])
+def test_results_same_alone_and_in_the_mix(gpu, route, monkeypatch):
+    """Served results (A formed in W's buffer and solved in place, or with
+    GW_SERVE_CHI0=1 through chi0 in a buffer of its own) are the same alone
+    and in a mix, match the oracle on the tiny molecule and the eager
+    chi0-route solve on every molecule."""
     gw, torch = gpu
+    if route == "chi0":
+        monkeypatch.setenv("GW_SERVE_CHI0", "1")
+    else:
+        monkeypatch.delenv("GW_SERVE_CHI0", raising=False)
     grid, mols = _workload()
     g = gw.make_grid(grid.n_omega, grid.omega_min, grid.omega_max, grid.eps)
     dms = [gw.DeviceMolecule(m) for m, _ in mols]
