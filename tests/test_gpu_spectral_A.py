@@ -252,3 +252,34 @@ def test_A_route_other_fft_lengths(gpu, n_omega, transform, monkeypatch):
     worst = max(_rel(Wg[j], o.screened_W(mol.v, chi[j])) for j in range(grid.n_omega))
     _say("W worst rel", worst)
     assert worst < 1e-10
+
+
+def test_A_route_histogram_ranges_bit_identical(gpu, monkeypatch):
+    """The A route histograms its pairs in bin ranges on a second stream
+    (GW_HIST_CHUNKS ranges, default 4) and multiplies each range's bins by v
+    as soon as they are final.  The int64 sums do not depend on the order or
+    the grouping of the pairs, so A is the same bit for bit for one range,
+    three, the default and 64 (45 ranges of two bins for the 91 bins here);
+    and it matches the oracle."""
+    gw, ctx, torch = gpu
+    mol = _ragged_chain()
+    grid = gs.config_grid(0)
+    monkeypatch.delenv("GW_A_TRANSFORM", raising=False)
+    got = {}
+    for chunks in ("1", "3", None, "64"):
+        if chunks is None:
+            monkeypatch.delenv("GW_HIST_CHUNKS", raising=False)
+        else:
+            monkeypatch.setenv("GW_HIST_CHUNKS", chunks)
+        _say("A route, histogram ranges", chunks or "default")
+        _, A, rep = _gpu_A(gw, ctx, torch, mol, grid)
+        got[chunks] = A.cpu().numpy()
+    nhb = rep.n_hbins
+    assert nhb > 64  # "64" gives ranges of two bins
+    for c, a in got.items():
+        assert np.array_equal(a, got["1"]), c
+    chi, _, _ = _oracle_chi(mol, grid, js=[0, grid.n_omega // 2 + 5, grid.n_omega - 1])
+    ref = np.eye(mol.n_prod)[None] - np.matmul(mol.v[None], chi)
+    e = _rel(got[None][[0, grid.n_omega // 2 + 5, grid.n_omega - 1]], ref)
+    _say("A rel vs oracle", e)
+    assert e < 1e-12
