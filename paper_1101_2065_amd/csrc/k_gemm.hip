@@ -23,6 +23,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace gwk {
 
 namespace {
@@ -575,17 +577,20 @@ __global__ __launch_bounds__(256, 1) void k_cgemm_bf16x(int M, int N, int K, flo
 }
 
 // A = 1 - diag(lam) chi0 (compressed metric), optional complex-float copy.
-__global__ void k_formA_diag(int n, const double *__restrict__ lam, const zdbl *__restrict__ chi0, int64_t s_chi,
-                             zdbl *__restrict__ A, int64_t s_A, zflt *A32, int64_t s_A32) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (idx >= (int64_t)n * n) return;
-    const int i = (int)(idx / n), j = (int)(idx % n);
-    const zdbl c = chi0[b * s_chi + idx];
-    zdbl a{-lam[i] * c.re, -lam[i] * c.im};
-    if (i == j) a.re += 1.0;
-    A[b * s_A + idx] = a;
-    if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
+// Grid: x = 256-column blocks, y = rows, z = batch entries (grid strides).
+__global__ void k_formA_diag(int n, int batch, const double *__restrict__ lam, const zdbl *__restrict__ chi0,
+                             int64_t s_chi, zdbl *__restrict__ A, int64_t s_A, zflt *A32, int64_t s_A32) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int b = blockIdx.z; b < batch; b += gridDim.z)
+        for (int i = blockIdx.y; i < n; i += gridDim.y) {
+            const int64_t idx = (int64_t)i * n + j;
+            const zdbl c = chi0[b * s_chi + idx];
+            zdbl a{-lam[i] * c.re, -lam[i] * c.im};
+            if (i == j) a.re += 1.0;
+            A[b * s_A + idx] = a;
+            if (A32) A32[b * s_A32 + idx] = zflt{(float)a.re, (float)a.im};
+        }
 }
 
 // Tile of the long complex products (M >= 256, K >= 128): < 0 the default
@@ -765,8 +770,9 @@ hipError_t launch_formA(hipStream_t st, int n, const double *v, int v_is_diag, c
                         zdbl *A, int64_t s_A, zflt *A32, int64_t s_A32, int batch) {
     if (v_is_diag) {
         GW_DEFER(launch_formA(st, n, v, v_is_diag, chi0, s_chi, A, s_A, A32, s_A32, batch));
-        dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
-        hipLaunchKernelGGL(k_formA_diag, grid, dim3(256), 0, st, n, v, chi0, s_chi, A, s_A, A32, s_A32);
+        const int xb = (n + 255) / 256, zb = std::min(batch, 65535);
+        dim3 grid((unsigned)xb, (unsigned)std::max(1, std::min(n, 65536 / std::max(1, xb * zb))), (unsigned)zb);
+        hipLaunchKernelGGL(k_formA_diag, grid, dim3(256), 0, st, n, batch, v, chi0, s_chi, A, s_A, A32, s_A32);
         return hipGetLastError();
     }
     // A = -v * chi0 + 1 (v real, shared by the batch: batch stride 0)

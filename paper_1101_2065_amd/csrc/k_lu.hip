@@ -17,6 +17,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace gwk {
 
 hipError_t launch_zgemm(hipStream_t st, int M, int N, int K, double alpha, const zdbl *A, int64_t lda, int64_t sA,
@@ -698,28 +700,42 @@ __global__ __launch_bounds__(256) void k_perm_from_ipiv(int n, const int32_t *ip
 }
 
 // B[b][i][c] = src[b][perm[i]][c]  (out of place gather of rows)
+// Grid of the row-wise copies below: x = 256-column blocks, y = rows and
+// z = batch entries, each walked with its grid stride (no division per
+// element).  About 64k workgroups in all, so that each copies many rows
+// (one 4-KB row segment per workgroup left the copies at 3.7 TB/s, bound by
+// launching workgroups).
+inline dim3 rows_grid(int rows, int cols, int batch) {
+    const int xb = (cols + 255) / 256, zb = std::min(batch, 65535);
+    const int yb = std::max(1, std::min(rows, 65536 / std::max(1, xb * zb)));
+    return dim3((unsigned)xb, (unsigned)yb, (unsigned)zb);
+}
+
 template <typename T>
-__global__ void k_rowgather(int n, int nrhs, const int32_t *perm, const Cx<T> *src, int64_t sS, Cx<T> *dst,
-                            int64_t sD) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (idx >= (int64_t)n * nrhs) return;
-    const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
-    dst[(int64_t)b * sD + idx] = src[(int64_t)b * sS + (int64_t)perm[(int64_t)b * n + i] * nrhs + c];
+__global__ void k_rowgather(int n, int nrhs, int batch, const int32_t *perm, const Cx<T> *src, int64_t sS,
+                            Cx<T> *dst, int64_t sD) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    for (int b = blockIdx.z; b < batch; b += gridDim.z)
+        for (int i = blockIdx.y; i < n; i += gridDim.y)
+            dst[(int64_t)b * sD + (int64_t)i * nrhs + c] =
+                src[(int64_t)b * sS + (int64_t)perm[(int64_t)b * n + i] * nrhs + c];
 }
 
 // B[b][i][c] = v[perm[i]][c] (dense real v) or delta(perm[i], c) lam[c] (diagonal);
 // perm may be null (identity).
-__global__ void k_init_rhs(int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B, int64_t sB) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (idx >= (int64_t)n * n) return;
-    const int i = (int)(idx / n), c = (int)(idx % n);
-    const int r = perm ? perm[(int64_t)b * n + i] : i;
-    double x;
-    if (v_is_diag) x = (r == c) ? v[c] : 0.0;
-    else x = v[(int64_t)r * n + c];
-    B[(int64_t)b * sB + idx] = zdbl{x, 0.0};
+__global__ void k_init_rhs(int n, int batch, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
+                           int64_t sB) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    for (int b = blockIdx.z; b < batch; b += gridDim.z)
+        for (int i = blockIdx.y; i < n; i += gridDim.y) {
+            const int r = perm ? perm[(int64_t)b * n + i] : i;
+            double x;
+            if (v_is_diag) x = (r == c) ? v[c] : 0.0;
+            else x = v[(int64_t)r * n + c];
+            B[(int64_t)b * sB + (int64_t)i * n + c] = zdbl{x, 0.0};
+        }
 }
 
 __global__ void k_conj_mirror(int64_t nn, int n_omega, zdbl *W) {
@@ -768,14 +784,15 @@ __global__ void k_norms(const zflt *d, const zdbl *W, int64_t n_per, double *out
 }
 
 
-__global__ void k_rowgather_z2c(int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS, zflt *dst,
-                                int64_t sD) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (idx >= (int64_t)n * nrhs) return;
-    const int i = (int)(idx / nrhs), c = (int)(idx % nrhs);
-    const zdbl x = src[(int64_t)b * sS + (int64_t)perm[(int64_t)b * n + i] * nrhs + c];
-    dst[(int64_t)b * sD + idx] = zflt{(float)x.re, (float)x.im};
+__global__ void k_rowgather_z2c(int n, int nrhs, int batch, const int32_t *perm, const zdbl *src, int64_t sS,
+                                zflt *dst, int64_t sD) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    for (int b = blockIdx.z; b < batch; b += gridDim.z)
+        for (int i = blockIdx.y; i < n; i += gridDim.y) {
+            const zdbl x = src[(int64_t)b * sS + (int64_t)perm[(int64_t)b * n + i] * nrhs + c];
+            dst[(int64_t)b * sD + (int64_t)i * nrhs + c] = zflt{(float)x.re, (float)x.im};
+        }
 }
 
 __global__ void k_c2z_set(const zflt *d, zdbl *W, int64_t n_per) {
@@ -1078,26 +1095,23 @@ hipError_t launch_perm(hipStream_t st, int n, const int32_t *ipiv, int32_t *perm
 hipError_t launch_rowgather_c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zflt *src, int64_t sS,
                               zflt *dst, int64_t sD, int batch) {
     GW_DEFER(launch_rowgather_c(st, n, nrhs, perm, src, sS, dst, sD, batch));
-    dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
-    hipLaunchKernelGGL(k_rowgather<float>, grid, dim3(256), 0, st, n, nrhs, perm, (const Cx<float> *)src, sS,
-                       (Cx<float> *)dst, sD);
+    hipLaunchKernelGGL(k_rowgather<float>, rows_grid(n, nrhs, batch), dim3(256), 0, st, n, nrhs, batch, perm,
+                       (const Cx<float> *)src, sS, (Cx<float> *)dst, sD);
     return hipGetLastError();
 }
 hipError_t launch_rowgather_z(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
                               zdbl *dst, int64_t sD, int batch) {
     GW_DEFER(launch_rowgather_z(st, n, nrhs, perm, src, sS, dst, sD, batch));
-    dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
-    hipLaunchKernelGGL(k_rowgather<double>, grid, dim3(256), 0, st, n, nrhs, perm, (const Cx<double> *)src, sS,
-                       (Cx<double> *)dst, sD);
+    hipLaunchKernelGGL(k_rowgather<double>, rows_grid(n, nrhs, batch), dim3(256), 0, st, n, nrhs, batch, perm,
+                       (const Cx<double> *)src, sS, (Cx<double> *)dst, sD);
     return hipGetLastError();
 }
 
 hipError_t launch_init_rhs_perm(hipStream_t st, int n, const double *v, int v_is_diag, const int32_t *perm, zdbl *B,
                                 int64_t sB, int batch) {
     GW_DEFER(launch_init_rhs_perm(st, n, v, v_is_diag, perm, B, sB, batch));
-    dim3 grid((unsigned)(((int64_t)n * n + 255) / 256), batch);
     ProfScope ps(st, "init_rhs", 0.0, 16.0 * (double)n * n * batch);
-    hipLaunchKernelGGL(k_init_rhs, grid, dim3(256), 0, st, n, v, v_is_diag, perm, B, sB);
+    hipLaunchKernelGGL(k_init_rhs, rows_grid(n, n, batch), dim3(256), 0, st, n, batch, v, v_is_diag, perm, B, sB);
     return hipGetLastError();
 }
 
@@ -1141,8 +1155,8 @@ hipError_t launch_norms(hipStream_t st, const zflt *dW, const zdbl *W, int64_t n
 hipError_t launch_rowgather_z2c(hipStream_t st, int n, int nrhs, const int32_t *perm, const zdbl *src, int64_t sS,
                                 zflt *dst, int64_t sD, int batch) {
     GW_DEFER(launch_rowgather_z2c(st, n, nrhs, perm, src, sS, dst, sD, batch));
-    dim3 grid((unsigned)(((int64_t)n * nrhs + 255) / 256), batch);
-    hipLaunchKernelGGL(k_rowgather_z2c, grid, dim3(256), 0, st, n, nrhs, perm, src, sS, dst, sD);
+    hipLaunchKernelGGL(k_rowgather_z2c, rows_grid(n, nrhs, batch), dim3(256), 0, st, n, nrhs, batch, perm, src, sS,
+                       dst, sD);
     return hipGetLastError();
 }
 
