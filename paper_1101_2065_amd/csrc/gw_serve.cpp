@@ -7,7 +7,7 @@
 // context's budget, next to the results still held and the workspace the
 // other slots keep; admitted requests run concurrently on their slots'
 // streams, so work of different molecules overlaps on the device: the
-// compression and chi0 build of one request (vector units, HBM) run beside
+// compression and A build of one request (vector units, HBM) run beside
 // the W solve of another (matrix cores).  The solves themselves take turns
 // (GW_SERVE_SOLVE_OVERLAP=1 lets them run together): the LU panel kernel needs
 // a whole CU, which a concurrent solve's GEMM workgroups keep occupied.  All
@@ -15,8 +15,9 @@
 // slot's stream, recycled by the device pool), so no allocation or release
 // synchronises the device.  A slot keeps its workspace for the next request
 // and only gives it back when the head of the queue would not fit otherwise;
-// the results (chi0 and W, plus the compression basis) stay resident until
-// gw_release.  Requests are admitted in arrival order; gw_release on a request
+// the results (W, plus the compression basis) stay resident until
+// gw_release; A = 1 - v chi0 is formed in W's buffer and solved there, so
+// chi0 itself is never held (GW_SERVE_CHI0=1 forms it in a buffer of its own).  Requests are admitted in arrival order; gw_release on a request
 // still in the queue cancels it.  A request that runs out of device memory
 // (others' results and workspace in the way) goes back to the head of the
 // queue once, after its slot has given back its workspace.
