@@ -316,13 +316,15 @@ def driver(tmp_path_factory):
     return str(exe), str(d)
 
 
-def _run(drv, mode, fault=None):
+def _run(drv, mode, fault=None, extra_env=None):
     exe, d = drv
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1",
                GW_TUNE_FILE=os.path.join(d, "tune.json"))
     env.pop("GW_FAULT", None)
+    env.pop("GW_SERVE_CHI0", None)
     if fault:
         env["GW_FAULT"] = fault
+    env.update(extra_env or {})
     r = subprocess.run([exe, mode], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout[-3000:] + r.stderr[-3000:]
 
@@ -344,8 +346,11 @@ def test_lock_step_grouping(driver):
     _run(driver, "lockstep")
 
 
-def test_serving_states(driver):
-    _run(driver, "serve")
+@pytest.mark.parametrize("route", ["A", "chi0"])
+def test_serving_states(driver, route):
+    """Served requests form A in W's buffer and solve in place, or with
+    GW_SERVE_CHI0=1 form chi0 in a buffer of their own first."""
+    _run(driver, "serve", extra_env={"GW_SERVE_CHI0": "1"} if route == "chi0" else None)
 
 
 def test_serving_requeues_once_after_running_out_of_memory(driver):
