@@ -499,6 +499,19 @@ gw_status a_transform_enqueue(gw_ctx *ctx, hipStream_t st, int n, int n_omega, i
     return GW_OK;
 }
 
+void hist_ranges(int nhb, int dchunk, int want, std::vector<HistRange> *out) {
+    out->clear();
+    if (nhb <= 1) return;
+    // bins 1 .. nhb-1 in runs of `step`; range c's histogram adds the pairs of
+    // lower bins [m0, m0 + step) (from bin 0 for the first, to the last pair
+    // bin nhb - 2 for the last), after which bins [m0, m0 + step) are final
+    const int step = std::max(1, std::min(dchunk, (nhb - 1 + want - 1) / std::max(1, want)));
+    for (int m0 = 1; m0 < nhb; m0 += step) {
+        const int cnt = std::min(step, nhb - m0);
+        out->push_back(HistRange{m0 == 1 ? 0 : m0, m0 + cnt >= nhb ? nhb - 1 : m0 + cnt, m0, cnt});
+    }
+}
+
 gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
                           bool with_kspec, void *A_out) {
     gw_status s = build_hist_enqueue(ctx, p, st, false);
@@ -513,11 +526,12 @@ gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const
     // integer sums do not depend on their order: H is the same bit for bit.
     const int n = p.rows, nhb = p.nhb;
     const int64_t nn = (int64_t)n * n, n_upper = (int64_t)n * (n + 1) / 2;
-    // GW_HIST_CHUNKS chunks (default 4), each at most the staging buffer's bins
+    // GW_HIST_CHUNKS ranges (default 4), each at most the staging buffer's bins
     int want = 4;
     if (const char *e = std::getenv("GW_HIST_CHUNKS")) want = std::max(1, std::min(64, std::atoi(e)));
-    const int step = nhb > 1 ? std::min(w.dchunk, (nhb - 1 + want - 1) / want) : 1;
-    const int nch = nhb > 1 ? (nhb - 1 + step - 1) / step : 0;
+    std::vector<HistRange> rg;
+    hist_ranges(nhb, w.dchunk, want, &rg);
+    const int nch = (int)rg.size();
     if ((s = aux_stream(ctx)) != GW_OK) return s;
     while ((int)ctx->chunk_ev.size() < nch) {
         hipEvent_t e;
@@ -528,13 +542,12 @@ gw_status a_route_enqueue(gw_ctx *ctx, const BuildPlan &p, hipStream_t st, const
     GW_HIP(ctx, hipEventRecord(ctx->fork_ev, st));
     GW_HIP(ctx, hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
     for (int c = 0; c < nch; ++c) {
-        const int m0 = 1 + c * step, m1 = std::min(m0 + step, nhb);
         GW_HIP(ctx, gwk::launch_hist(ctx->aux, n, p.n_pairs, p.Ps, p.fsort, p.binoff, p.stat, p.sdev, nhb, p.H,
-                                     p.splits, c == 0 ? 0 : m0, c == nch - 1 ? nhb - 1 : m1, false));
+                                     p.splits, rg[c].lo, rg[c].hi, false));
         GW_HIP(ctx, hipEventRecord(ctx->chunk_ev[c], ctx->aux));
     }
     for (int c = 0; c < nch; ++c) {
-        const int m0 = 1 + c * step, cnt = std::min(step, nhb - m0);
+        const int m0 = rg[c].m0, cnt = rg[c].cnt;
         GW_HIP(ctx, hipStreamWaitEvent(st, ctx->chunk_ev[c], 0));
         GW_HIP(ctx, gwk::launch_expand_bins(st, n, m0, cnt, p.H, n_upper, p.sdev, w.D));
         GW_HIP(ctx, gwk::launch_dgemm(st, n, n, n, 1.0, v, n, 0, w.D, n, nn, 0.0, w.B + m0 * nn, n, nn, cnt));

@@ -86,6 +86,19 @@ gw_status a_route_ws(gw_ctx *c, const std::string &prefix, int n, int nhb, int n
 // a1-a3 as build_enqueue, then A[j] = 1 - v chi0(omega_j) for all j into A_out.
 gw_status a_route_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, const double *v, const ARouteWs &w,
                           bool with_kspec, void *A_out);
+// The A route's pipeline over the bins: histogram range c adds the pairs
+// whose lower bin lies in [lo, hi); then the products v a0 of bins
+// [m0, m0 + cnt) (cnt <= dchunk) run, every one of those bins being final
+// (bin m takes weight from the pairs of bins m - 1 and m only).  The ranges
+// cover [0, nhb - 1) and the bins [1, nhb) each exactly once; about `want`
+// ranges.  Empty for nhb <= 1.
+struct HistRange {
+    int lo, hi, m0, cnt;
+};
+void hist_ranges(int nhb, int dchunk, int want, std::vector<HistRange> *out);
+// The transform of the products B of the bins into A (both forms below).
+gw_status a_transform_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const ARouteWs &w,
+                              const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out);
 // A[j] = 1 - v chi0(omega_j) for all j from a spectral array a [nhb][n(n+1)/2]
 // already on the mesh (the exact histogram times 2^-s, or a0 in floating
 // point: a_i64 or a_f64): the Cauchy transform of the products v a0 as one
@@ -93,9 +106,6 @@ gw_status a_route_enqueue(gw_ctx *c, const BuildPlan &p, hipStream_t st, const d
 // (omega_j = (j + j0) domega), the rest by the conjugate mirror; with
 // GW_A_TRANSFORM=fft instead the FFT convolution with the Cauchy-kernel
 // spectrum Kt, tw over all mesh points.
-// The transform of the products B of the bins into A (both forms above).
-gw_status a_transform_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const ARouteWs &w,
-                              const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out);
 gw_status a_from_bins_enqueue(gw_ctx *c, hipStream_t st, int n, int n_omega, int nhb, const int64_t *a_i64,
                               const int32_t *s_dev, const double *a_f64, const double *v, const ARouteWs &w,
                               const zdbl *Kt, const zdbl *tw, int j0, double domega, double eps, void *A_out);

@@ -85,6 +85,7 @@ DRIVER = r'''
 #include "gw.h"
 #include "gw_ctx.h"
 #include "gw_plan.h"
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -228,6 +229,30 @@ int main(int argc, char **argv) {
         uint64_t tb;
         CHECK(gw_submit(c, &bad, mol.v.data(), &g, 0, GW_FP64, 1e-7, &tb) == GW_E_INVALID);
         CHECK(gw_submit(c, &m, mol.v.data(), &g, 3, GW_FP64, 1e-7, &tb) == GW_E_INVALID);
+    } else if (mode == "hist_ranges") {
+        // the A route's bin ranges: pair bins [0, nhb - 1) and product bins
+        // [1, nhb) each covered once and in order, products of at most dchunk
+        // bins, every product bin final when its range is done
+        std::vector<gwp::HistRange> rg;
+        for (int nhb = 0; nhb <= 300; ++nhb)
+            for (int dchunk : {1, 2, 3, 5, 67, 1000})
+                for (int want : {1, 2, 3, 4, 7, 64}) {
+                    gwp::hist_ranges(nhb, dchunk, want, &rg);
+                    if (nhb <= 1) {
+                        CHECK(rg.empty());
+                        continue;
+                    }
+                    int next_lo = 0, next_m = 1;
+                    for (const gwp::HistRange &r : rg) {
+                        CHECK(r.lo == next_lo && r.hi >= r.lo && r.hi <= nhb - 1);
+                        CHECK(r.m0 == next_m && r.cnt >= 1 && r.cnt <= dchunk);
+                        CHECK(r.hi >= std::min(r.m0 + r.cnt, nhb - 1));
+                        next_lo = r.hi;
+                        next_m = r.m0 + r.cnt;
+                    }
+                    CHECK(next_lo == nhb - 1 && next_m == nhb);
+                    CHECK((int)rg.size() <= std::max(want, (nhb - 1 + dchunk - 1) / dchunk));
+                }
     } else if (mode == "lockstep") {
         // two recorded programs: products, a panel, its row exchanges and a
         // deferred launch, against two products of a second molecule
@@ -344,6 +369,13 @@ def test_lock_step_grouping(driver):
     work-queue launch with consecutive tile ranges, panels and row exchanges
     grouped with their workgroup offsets, deferred launches run once."""
     _run(driver, "lockstep")
+
+
+def test_a_route_histogram_ranges(driver):
+    """The A route's histogram ranges and product chunks over 301 bin counts,
+    six staging sizes and six range counts: each bin once, in order, final
+    before its product."""
+    _run(driver, "hist_ranges")
 
 
 @pytest.mark.parametrize("route", ["A", "chi0"])
